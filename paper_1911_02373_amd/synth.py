@@ -1,0 +1,291 @@
+"""Seeded synthetic workloads for the rational-program fit and the launch-configuration search.
+
+This module only draws random inputs and lays them out in flat arrays.  It holds none of the
+method's arithmetic (no design matrix, no least squares, no cost model, no argmin).  The one
+computation it performs is the data-generating process itself: evaluating a seeded ground-truth
+rational function at the sample points to produce the "measured" metric values, which stand in
+for the profiler readings of the paper's data-collection step (section "An Algorithm to Build
+and Deploy a Performance-Predicting Rational Program", step 1).
+
+Both the GPU path and the CPU oracle consume these arrays; neither shares any other code.
+
+Layouts (structure of arrays, all numpy):
+  fits:  X   int32 flat, fit i's samples at X[x0[i] : x0[i] + m[i]*v[i]] as rows of v[i]
+         f   float64 flat, fit i's targets at f[f0[i] : f0[i] + m[i]]
+         exps uint8 [rows][8], exponent tuples; a fit uses rows [num0, num0+n_num) for the
+             numerator and [den0, den0+n_den) for the denominator (row den0 is all-zero: the
+             denominator's constant coefficient is fixed to 1)
+         coef0 offset of the fit's n_num + n_den - 1 coefficients (numerator first)
+         scale_exp int8 [n_fits][8]: variable k enters the monomials as x_k * 2**-scale_exp[k]
+  programs (eval): eight consecutive fits per program in the metric order
+         (I_comp, I_mc, I_mu, U, I_sync, R, Z, B_w); configs int32 rows of v_launch;
+         queries int32 data sizes N.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+MAX_VARS = 8
+N_METRICS = 8
+METRIC_NAMES = ("I_comp", "I_mc", "I_mu", "U", "I_sync", "R", "Z", "B_w")
+# Value ranges [lo, hi] of the synthetic metrics (per-thread instruction counts, transactions
+# per uncoalesced wave access, sync instructions, registers per thread, LDS bytes per block,
+# bytes per wave memory transaction).
+METRIC_RANGES = ((10.0, 4000.0), (1.0, 200.0), (0.0, 50.0), (1.0, 16.0), (0.0, 8.0),
+                 (16.0, 128.0), (0.0, 65536.0), (64.0, 512.0))
+
+
+def monomials(v: int, d: int) -> np.ndarray:
+    """All exponent tuples in v variables of total degree <= d, graded order.
+
+    Within one total degree the tuples are in descending lexicographic order, so the constant
+    monomial is row 0 and, for v=2, d=2 the order is 1, x, y, x^2, xy, y^2.
+    Returned as uint8 [n][MAX_VARS] (unused variables zero)."""
+    rows = []
+    for deg in range(d + 1):
+        tup = [t for t in itertools.product(range(deg + 1), repeat=v) if sum(t) == deg]
+        tup.sort(reverse=True)
+        rows.extend(tup)
+    out = np.zeros((len(rows), MAX_VARS), np.uint8)
+    for i, t in enumerate(rows):
+        out[i, :v] = t
+    return out
+
+
+def _truth_value(xt: np.ndarray, e_num: np.ndarray, e_den: np.ndarray,
+                 c_num: np.ndarray, c_den: np.ndarray) -> np.ndarray:
+    """Ground-truth p/q at scaled points xt [m][v] (data generation only)."""
+    v = xt.shape[1]
+    def poly(E, c):
+        acc = np.zeros(xt.shape[0])
+        for e, ce in zip(E, c):
+            term = np.full(xt.shape[0], ce)
+            for k in range(v):
+                for _ in range(int(e[k])):
+                    term = term * xt[:, k]
+            acc = acc + term
+        return acc
+    return poly(e_num, c_num) / poly(e_den, c_den)
+
+
+@dataclass
+class FitBatch:
+    """A batch of independent rational fits (structure of arrays)."""
+    X: np.ndarray
+    f: np.ndarray
+    exps: np.ndarray
+    x0: np.ndarray
+    f0: np.ndarray
+    m: np.ndarray
+    v: np.ndarray
+    num0: np.ndarray
+    n_num: np.ndarray
+    den0: np.ndarray
+    n_den: np.ndarray
+    coef0: np.ndarray
+    scale_exp: np.ndarray
+    n_coef: int
+    truth_coef: np.ndarray | None = None     # same layout as the fitted coefficients
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_fits(self) -> int:
+        return int(self.m.shape[0])
+
+    def fit_arrays(self, i: int):
+        """(X_i [m][v] int32, f_i [m], E_num, E_den, scale_exp[:v]) of fit i."""
+        v, m = int(self.v[i]), int(self.m[i])
+        Xi = self.X[self.x0[i]: self.x0[i] + m * v].reshape(m, v)
+        fi = self.f[self.f0[i]: self.f0[i] + m]
+        En = self.exps[self.num0[i]: self.num0[i] + self.n_num[i], :v]
+        Ed = self.exps[self.den0[i]: self.den0[i] + self.n_den[i], :v]
+        return Xi, fi, En, Ed, self.scale_exp[i, :v]
+
+
+def _pack_fits(samples, exps, num0, n_num, den0, n_den, scale, truth=None, meta=None) -> FitBatch:
+    n = len(samples)
+    v = np.array([s[0].shape[1] for s in samples], np.int32)
+    m = np.array([s[0].shape[0] for s in samples], np.int32)
+    x0 = np.zeros(n, np.int64)
+    f0 = np.zeros(n, np.int64)
+    x0[1:] = np.cumsum((m.astype(np.int64) * v)[:-1])
+    f0[1:] = np.cumsum(m.astype(np.int64)[:-1])
+    X = np.concatenate([s[0].reshape(-1) for s in samples]).astype(np.int32) if n else np.zeros(0, np.int32)
+    f = np.concatenate([s[1] for s in samples]).astype(np.float64) if n else np.zeros(0)
+    n_num = np.asarray(n_num, np.int32)
+    n_den = np.asarray(n_den, np.int32)
+    ncoef = n_num.astype(np.int64) + n_den - 1
+    coef0 = np.zeros(n, np.int64)
+    coef0[1:] = np.cumsum(ncoef[:-1])
+    tc = None
+    if truth is not None:
+        tc = np.concatenate(truth) if n else np.zeros(0)
+    return FitBatch(X=X, f=f, exps=exps, x0=x0, f0=f0, m=m, v=v,
+                    num0=np.asarray(num0, np.int32), n_num=n_num,
+                    den0=np.asarray(den0, np.int32), n_den=n_den, coef0=coef0,
+                    scale_exp=np.asarray(scale, np.int8), n_coef=int(ncoef.sum()),
+                    truth_coef=tc, meta=meta or {})
+
+
+def config1_fit(seed: int, noise: float = 0.01, n_samples: int = 200) -> FitBatch:
+    """One fit in (N, B): N = 2^10..2^20, B = 32..1024 step 32, total degree <= 2 num and den.
+
+    200 distinct points of the 11 x 32 grid; coefficients U(0.1, 2) in the scaled variables
+    N/2^20, B/2^10; targets times (1 + eps), eps ~ N(0, noise^2)."""
+    rng = np.random.default_rng(seed)
+    Ns = 2 ** np.arange(10, 21)
+    Bs = 32 * np.arange(1, 33)
+    grid = np.array([(n, b) for n in Ns for b in Bs], np.int64)
+    pick = rng.choice(grid.shape[0], size=n_samples, replace=False)
+    Xi = grid[pick].astype(np.int32)
+    E = monomials(2, 2)
+    c_num = rng.uniform(0.1, 2.0, E.shape[0])
+    c_den = np.concatenate([[1.0], rng.uniform(0.1, 2.0, E.shape[0] - 1)])
+    scale = np.zeros((1, MAX_VARS), np.int8)
+    scale[0, :2] = (20, 10)
+    xt = Xi.astype(np.float64) * 2.0 ** -scale[0, :2].astype(np.float64)
+    ftrue = _truth_value(xt, E[:, :2], E[:, :2], c_num, c_den)
+    eps = rng.normal(0.0, 1.0, n_samples) * noise
+    fi = ftrue * (1.0 + eps)
+    exps = np.concatenate([E, E])
+    truth = np.concatenate([c_num, c_den[1:]])
+    return _pack_fits([(Xi, fi)], exps, [0], [E.shape[0]], [E.shape[0]], [E.shape[0]], scale,
+                      truth=[truth], meta={"grid": grid.astype(np.int32), "noise": noise})
+
+
+LITERAL_PAIRS = np.array([(bx, by) for bx in (16, 32, 48, 64) for by in (16, 32, 48, 64)
+                          if bx * by <= 1024], np.int32)
+POW2_PAIRS = np.array([(1 << a, 1 << b) for a in range(11) for b in range(11)
+                       if 16 <= (1 << (a + b)) <= 1024], np.int32)
+
+
+def config2_fits(seed: int, n_fits: int = 4096, domain: str = "2a", noise: float = 0.01,
+                 degree: int = 3, m_range=(64, 512)) -> FitBatch:
+    """Batched uneven fits over (N, bx, by).
+
+    domain "2a": (bx, by) from the 8 pairs of multiples of 16 with bx*by <= 1024;
+    domain "2b": power-of-two (bx, by) with 16 <= bx*by <= 1024.
+    N = round(2^u), u ~ U(8, 24); m ~ U{m_range}; truth of total degree <= `degree` with
+    coefficients U(0.1, 2) in (N/2^24, bx/2^10, by/2^10); f = truth * exp(noise * z)."""
+    rng = np.random.default_rng(seed)
+    pairs = LITERAL_PAIRS if domain == "2a" else POW2_PAIRS
+    E = monomials(3, degree)
+    nm = E.shape[0]
+    scale = np.zeros((n_fits, MAX_VARS), np.int8)
+    scale[:, :3] = (24, 10, 10)
+    sdiv = 2.0 ** -np.array([24.0, 10.0, 10.0])
+    samples, truth = [], []
+    ms = rng.integers(m_range[0], m_range[1] + 1, n_fits)
+    for i in range(n_fits):
+        m = int(ms[i])
+        N = np.rint(2.0 ** rng.uniform(8.0, 24.0, m)).astype(np.int64)
+        pr = pairs[rng.integers(0, pairs.shape[0], m)]
+        Xi = np.stack([N, pr[:, 0], pr[:, 1]], axis=1).astype(np.int32)
+        c_num = rng.uniform(0.1, 2.0, nm)
+        c_den = np.concatenate([[1.0], rng.uniform(0.1, 2.0, nm - 1)])
+        ftrue = _truth_value(Xi.astype(np.float64) * sdiv, E[:, :3], E[:, :3], c_num, c_den)
+        fi = ftrue * np.exp(noise * rng.normal(0.0, 1.0, m))
+        samples.append((Xi, fi))
+        truth.append(np.concatenate([c_num, c_den[1:]]))
+    exps = np.concatenate([E, E])
+    return _pack_fits(samples, exps, [0] * n_fits, [nm] * n_fits, [nm] * n_fits, [nm] * n_fits,
+                      scale, truth=truth, meta={"domain": domain, "noise": noise})
+
+
+# ----------------------------------------------------------------------------------------------
+# Rational programs for the evaluation / argmin sweep.
+
+@dataclass
+class HW:
+    """Hardware parameters H, fixed per call."""
+    n_cu: int = 256
+    wave: int = 64
+    w_max: int = 32          # resident waves per CU
+    b_max: int = 32          # resident workgroups per CU
+    r_max: int = 131072      # register-lanes per CU (512 VGPRs x 64 lanes x 4 SIMDs)
+    z_max: int = 163840      # LDS bytes per CU
+    t_max: int = 1024        # threads per workgroup
+    mem_lat: float = 600.0   # memory latency, cycles
+    dep_delay: float = 40.0  # departure delay between consecutive memory requests, cycles
+    issue_cycles: float = 4.0
+    bw: float = 13.0         # bytes per cycle per CU
+
+
+def config3_launch_configs() -> np.ndarray:
+    """128 launch configs (bx, by): bx = 2^a (a = 0..10), integer by, bx*by in 64*{1..16}
+    (127 tuples), plus one pad (1, 1) that is never admissible."""
+    out = []
+    for a in range(11):
+        bx = 1 << a
+        for k in range(1, 17):
+            t = 64 * k
+            if t % bx == 0:
+                out.append((bx, t // bx))
+    out.append((1, 1))
+    return np.array(out, np.int32)
+
+
+@dataclass
+class ProgramBatch:
+    fits: FitBatch | None      # coefficient holders (8 per program); X/f empty
+    coef: np.ndarray           # float64 coefficients (scaled basis), fits' layout
+    exps: np.ndarray
+    num0: np.ndarray
+    n_num: np.ndarray
+    den0: np.ndarray
+    n_den: np.ndarray
+    coef0: np.ndarray
+    scale_exp: np.ndarray      # [n_fits][8]
+    v_launch: np.ndarray       # per program
+    fit0: np.ndarray
+    cfg0: np.ndarray           # element offset into cfgs
+    n_cfg: np.ndarray
+    grid_kind: np.ndarray      # 0: blocks = ceil(N/prod L); 1: ceil(N/L0)*ceil(N/L1)
+    q0: np.ndarray
+    n_q: np.ndarray
+    cfgs: np.ndarray           # int32 flat
+    queries: np.ndarray        # int32 flat
+    hw: HW
+
+    @property
+    def n_progs(self) -> int:
+        return int(self.fit0.shape[0])
+
+
+def config3_programs(seed: int, n_progs: int = 1024, n_q: int = 65536, degree: int = 2,
+                     log2_range=(8.0, 26.0), cfgs: np.ndarray | None = None) -> ProgramBatch:
+    """Rational programs with 8 fitted metrics each, degree <= `degree` rationals in
+    (N/2^26, bx/2^10, by/2^10).  Metric j is lo_j + s_j * p/q with p, q coefficients U(0.1, 2),
+    q's constant 1, s_j = (hi_j - lo_j)/20 (p/q stays below 20 on the unit cube), so the
+    numerator coefficients are lo_j * q + s_j * p.  Queries N = round(2^u), u ~ U(log2_range)."""
+    rng = np.random.default_rng(seed)
+    E = monomials(3, degree)
+    nm = E.shape[0]
+    n_fits = n_progs * N_METRICS
+    coef = np.empty(n_fits * (2 * nm - 1))
+    for i in range(n_fits):
+        lo, hi = METRIC_RANGES[i % N_METRICS]
+        s = (hi - lo) / 20.0
+        p = rng.uniform(0.1, 2.0, nm)
+        q = np.concatenate([[1.0], rng.uniform(0.1, 2.0, nm - 1)])
+        coef[i * (2 * nm - 1): (i + 1) * (2 * nm - 1)] = np.concatenate([lo * q + s * p, q[1:]])
+    if cfgs is None:
+        cfgs = config3_launch_configs()
+    n_cfg = cfgs.shape[0]
+    queries = np.rint(2.0 ** rng.uniform(log2_range[0], log2_range[1], n_progs * n_q)).astype(np.int32)
+    scale = np.zeros((n_fits, MAX_VARS), np.int8)
+    scale[:, :3] = (26, 10, 10)
+    return ProgramBatch(
+        fits=None, coef=coef, exps=np.concatenate([E, E]),
+        num0=np.zeros(n_fits, np.int32), n_num=np.full(n_fits, nm, np.int32),
+        den0=np.full(n_fits, nm, np.int32), n_den=np.full(n_fits, nm, np.int32),
+        coef0=np.arange(n_fits, dtype=np.int64) * (2 * nm - 1), scale_exp=scale,
+        v_launch=np.full(n_progs, 2, np.int32),
+        fit0=np.arange(n_progs, dtype=np.int32) * N_METRICS,
+        cfg0=np.zeros(n_progs, np.int64), n_cfg=np.full(n_progs, n_cfg, np.int32),
+        grid_kind=np.zeros(n_progs, np.int32),
+        q0=np.arange(n_progs, dtype=np.int64) * n_q, n_q=np.full(n_progs, n_q, np.int32),
+        cfgs=cfgs.reshape(-1).astype(np.int32), queries=queries, hw=HW())
