@@ -1,0 +1,199 @@
+/*
+ * klr.h - C ABI of the MI355X rational-program library.
+ *
+ * The library implements the data-parallel core of the rational-program method for choosing
+ * kernel launch parameters (arXiv 1911.02373):
+ *   - klr_fit_batched   : step 2 of the paper's six-step algorithm ("Rational function
+ *                         estimation") and section "Building a Driver Program: Rational
+ *                         function estimation" - least-squares fits of rational functions
+ *                         p(D,P)/q(D,P) to sampled low-level metrics;
+ *   - klr_eval_argmin   : steps 4 and 5 ("Rational program evaluation", "Selection of optimal
+ *                         values of program parameters") - evaluation of the MWP-CWP-style
+ *                         cycle estimate built from the fitted metrics over every launch
+ *                         configuration, and an exhaustive per-query argmin;
+ *   - klr_surrogate_*   : a learned MLP surrogate of the log-cycle estimate with the exact
+ *                         rational program as fallback (not in the paper).
+ *
+ * Conventions
+ *   - Array arguments are DEVICE pointers (caller-owned, e.g. torch tensors) unless marked
+ *     [host].  The library never frees caller memory.  Every call is asynchronous on `stream`
+ *     (a hipStream_t; NULL = the null stream); results are visible after the stream syncs.
+ *   - Descriptors live in device memory.  Host-detectable errors (NULL pointers, bad sizes,
+ *     invalid hardware constants, too small a workspace) return KLR_E_INVALID or
+ *     KLR_E_WORKSPACE immediately and launch nothing.  Descriptor contents are validated on the
+ *     device against the array lengths passed in; an invalid descriptor is reported per item
+ *     (fit status bit KLR_FIT_BAD_INPUT, program status) and never read out of bounds.
+ *   - HIP errors map to KLR_E_HIP with text from klr_last_error.
+ *   - Identical inputs give bitwise-identical outputs (no atomics in value reductions).
+ *   - One handle per host thread; calls that share a workspace on one stream are ordered by it.
+ */
+#ifndef KLR_H
+#define KLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t klr_status;
+#define KLR_OK 0
+#define KLR_E_INVALID (-1)      /* bad argument detected on the host; nothing launched */
+#define KLR_E_WORKSPACE (-2)    /* workspace too small; nothing launched */
+#define KLR_E_HIP (-3)          /* a HIP runtime call failed; see klr_last_error */
+#define KLR_E_UNSUPPORTED (-4)  /* valid request outside what this build implements */
+
+#define KLR_MAX_VARS 8          /* variables per fit (data parameters first, then launch) */
+#define KLR_N_METRICS 8         /* fitted metrics per rational program */
+#define KLR_MAX_NDEG 3          /* highest power of the data size N in an evaluated metric */
+#define KLR_MAX_UNKNOWNS 128    /* n_num + n_den - 1 per fit */
+#define KLR_MAX_LAUNCH 4        /* launch parameters per configuration */
+#define KLR_MAX_SAMPLES 4096    /* samples per fit */
+
+typedef struct klr_handle_s* klr_handle;
+
+/* Create a handle bound to HIP device `device` (makes it current on the calling thread).
+ * Owns the last-error text and the tuned launch shapes; allocates no device memory. */
+klr_status klr_create(klr_handle* out, int device);
+void klr_destroy(klr_handle h);
+/* [host] text of the last failure on this handle ("" if none); valid until the next call. */
+const char* klr_last_error(klr_handle h);
+
+/* ------------------------------------------------------------------------------------------
+ * Fits.  One fit = one low-level metric g_i of one kernel, modelled as the rational function
+ * p(x~)/q(x~) of the section "Building a Driver Program: Rational function estimation",
+ * with monomial sets given explicitly (this covers the paper's per-variable degree bounds and
+ * total-degree sets alike).  Variables are scaled by powers of two, x~_k = x_k * 2^-s_k
+ * (exact).  The fit solves the linearised least-squares problem
+ *     min_y || A y - f ||_2,   A = [ x~^a (a in numerator set) | -f * x~^b (b in denominator
+ *                                   set without its constant row) ]
+ * i.e. f*q - p = 0 with q's constant coefficient fixed to 1.
+ */
+typedef struct {
+  int64_t x0;             /* element offset of the fit's samples in X: m rows of v int32      */
+  int64_t f0;             /* element offset of its m targets in f (float64)                   */
+  int64_t coef0;          /* element offset of its n_num + n_den - 1 output coefficients:     */
+                          /*   numerator in set order, then denominator without the constant  */
+  int32_t m;              /* samples, 0 <= m <= KLR_MAX_SAMPLES                                */
+  int32_t v;              /* variables, 1..KLR_MAX_VARS                                        */
+  int32_t num0, n_num;    /* numerator exponent rows [num0, num0+n_num) of exps                */
+  int32_t den0, n_den;    /* denominator rows; row den0 must be all-zero (its coefficient = 1) */
+  int8_t scale_exp[KLR_MAX_VARS]; /* s_k; entries beyond v ignored                            */
+} klr_fit_desc;           /* 56 bytes */
+
+/* status bits of klr_fit_info.status */
+#define KLR_FIT_RANK_DEFICIENT 1u   /* numerical rank < n (min-norm-type solution returned)  */
+#define KLR_FIT_UNDERDETERMINED 2u  /* m < n                                                   */
+#define KLR_FIT_NOT_CONVERGED 4u    /* refinement stopped at max_iter above tol                */
+#define KLR_FIT_FELL_BACK_FP64 8u   /* reduced-precision Gram replaced by the FP64 path        */
+#define KLR_FIT_BAD_INPUT 16u       /* bad descriptor, m == 0, or a NaN/Inf sample             */
+#define KLR_FIT_Q_NONPOS 32u        /* fitted q(x~_i) <= 0 at some sample (possible pole)      */
+
+typedef struct {
+  uint32_t status;
+  int32_t rank;           /* numerical rank of the equilibrated Gram factor                   */
+  int32_t iters;          /* refinement iterations used                                        */
+  int32_t q_nonpos;       /* samples with fitted q(x~_i) <= 0                                  */
+  double resid_norm;      /* || A y - f ||_2 in FP64                                            */
+  double err_est;         /* estimated relative error of y (equilibrated norm) vs the FP64 LS  */
+} klr_fit_info;           /* 32 bytes */
+
+typedef enum { KLR_FP64 = 0, KLR_FP32_REFINED = 1, KLR_BF16_REFINED = 2 } klr_precision;
+
+/* Workspace bytes klr_fit_batched needs for n_fits fits. */
+size_t klr_fit_workspace(int32_t n_fits, int32_t precision);
+
+/* Fit n_fits independent rational functions (uneven m and monomial sets in one launch).
+ *   desc[n_fits], exps[n_exp_rows][8] (uint8 exponent tuples), X[x_len] int32,
+ *   f[f_len] float64, coef[coef_len] float64 (out), info[n_fits] (out).
+ *   precision: KLR_FP64 forms the Gram matrix in FP64; KLR_FP32_REFINED / KLR_BF16_REFINED form
+ *   it in reduced precision with FP32 accumulation and recover accuracy by iterative refinement
+ *   against FP64 residuals (max_iter iterations at most, stop when the relative update <= tol).
+ *   The factorisation and residuals are FP64 on every path. */
+klr_status klr_fit_batched(klr_handle h, const klr_fit_desc* desc, int32_t n_fits,
+                           const uint8_t* exps, int32_t n_exp_rows,
+                           const int32_t* X, int64_t x_len, const double* f, int64_t f_len,
+                           int32_t precision, int32_t max_iter, double tol,
+                           double* coef, int64_t coef_len, klr_fit_info* info,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Evaluation and argmin (steps 4 and 5).  A rational program is one kernel: 8 fits in the
+ * metric order I_comp (compute instructions per thread), I_mc (coalesced memory instructions
+ * per thread), I_mu (uncoalesced memory instructions per thread), U (transactions per
+ * uncoalesced wave access), I_sync (synchronisations per thread), R (registers per thread),
+ * Z (LDS bytes per block), B_w (bytes per wave memory transaction).  Each fit has v = 1 +
+ * v_launch variables: the data size N, then the launch parameters.  The cost of configuration
+ * L at data size N is the MWP-CWP-style cycle estimate whose FP32 operation sequence is
+ * fixed by this library's documentation; occupancy follows the paper's flowchart (Example
+ * "Hardware occupancy", eq. occupancy) with the wavefront for the warp.
+ */
+typedef struct {          /* hardware parameters H, fixed per call [host]                     */
+  int32_t n_cu;           /* compute units                                                      */
+  int32_t wave;           /* wavefront width (the paper's warp)                                 */
+  int32_t w_max;          /* resident waves per CU                                              */
+  int32_t b_max;          /* resident workgroups per CU                                         */
+  int32_t r_max;          /* register-lanes per CU                                              */
+  int32_t z_max;          /* LDS bytes per CU                                                   */
+  int32_t t_max;          /* threads per workgroup                                              */
+  int32_t reserved;       /* must be 0                                                          */
+  float mem_lat;          /* memory latency, cycles (> 0)                                       */
+  float dep_delay;        /* departure delay, cycles (> 0)                                      */
+  float issue_cycles;     /* cycles per issued instruction (> 0)                                */
+  float bw;               /* bytes per cycle per CU (> 0)                                       */
+} klr_hw;                 /* 48 bytes */
+
+#define KLR_GRID_1D 0     /* blocks = ceil(N / prod L)                                          */
+#define KLR_GRID_2D 1     /* blocks = ceil(N / L0) * ceil(N / L1) (needs v_launch >= 2)         */
+
+typedef struct {
+  int64_t cfg0;           /* element offset of its n_cfg configurations in cfgs (rows of       */
+                          /*   v_launch int32)                                                  */
+  int64_t q0;             /* offset of its n_q queries in queries, argmin and best_cost        */
+  int64_t cost0;          /* offset of its n_cfg x n_q cost matrix (config-major) in all_costs */
+  int32_t fit0;           /* first of its KLR_N_METRICS consecutive fit descriptors             */
+  int32_t v_launch;       /* launch parameters per configuration, 1..KLR_MAX_LAUNCH             */
+  int32_t n_cfg;          /* configurations, 0..max_cfg                                         */
+  int32_t n_q;            /* queries, 0..max_q                                                  */
+  int32_t grid_kind;      /* KLR_GRID_1D or KLR_GRID_2D                                         */
+  int32_t reserved;       /* must be 0                                                          */
+} klr_program;            /* 48 bytes */
+
+/* program status bits (prog_status) */
+#define KLR_PROG_BAD_DESC 1      /* program descriptor out of range: no output written          */
+#define KLR_PROG_BAD_FIT 2       /* a metric's fit descriptor or exponents invalid: every query */
+                                 /*   of the program reports -1 / +inf                          */
+
+/* Workspace bytes klr_eval_argmin needs. */
+size_t klr_eval_workspace(int32_t n_progs, int32_t max_cfg);
+
+/* Evaluate every program at each of its queries over each of its configurations and take the
+ * argmin: strict "<" in configuration order, so ties keep the lowest index; inadmissible or
+ * non-finite costs never win; a query with no admissible configuration gets -1 and +inf.
+ *   progs[n_progs]; desc[n_fits], exps[n_exp_rows][8], coef[coef_len] (the fitted
+ *   coefficients); cfgs[cfgs_len] int32; queries[q_len] int32 data sizes;
+ *   argmin[q_len] int32 and best_cost[q_len] float (out, at each program's q0 .. q0+n_q);
+ *   all_costs[costs_len] float (optional, may be NULL): the full cost matrix, +inf where
+ *   inadmissible; prog_status[n_progs] int32 (optional, may be NULL).
+ *   max_cfg / max_q bound every program's n_cfg / n_q (launch sizing). */
+klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_progs,
+                           int32_t max_cfg, int32_t max_q, const klr_hw* hw,
+                           const klr_fit_desc* desc, int32_t n_fits,
+                           const uint8_t* exps, int32_t n_exp_rows,
+                           const double* coef, int64_t coef_len,
+                           const int32_t* cfgs, int64_t cfgs_len,
+                           const int32_t* queries, int64_t q_len,
+                           int32_t* argmin, float* best_cost,
+                           float* all_costs, int64_t costs_len, int32_t* prog_status,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* [host] ABI self-description for binding checks: writes up to n entries of
+ * {sizeof(klr_fit_desc), sizeof(klr_fit_info), sizeof(klr_hw), sizeof(klr_program), ...}
+ * and returns the number of entries available. */
+int32_t klr_abi_layout(int64_t* out, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KLR_H */

@@ -1,0 +1,352 @@
+// Rational-program evaluation over launch configurations + per-query argmin, gfx950.
+//
+// Paper: steps 4 ("Rational program evaluation") and 5 ("Selection of optimal values of
+// program parameters") of the section "An Algorithm to Build and Deploy a
+// Performance-Predicting Rational Program"; occupancy by the flowchart of Example "Hardware
+// occupancy" and eq. (occupancy); execution time by an MWP-CWP-style estimate (Example
+// "execution time" names the model without its equations; the operation sequence below is
+// this library's normative definition).
+//
+// Two kernels:
+//   collapse  - one thread per (program, configuration): validates the descriptors, fixes the
+//               launch parameters in each metric's p and q (FP64, monomial order), rounds the
+//               resulting polynomials in N~ to FP32, and precomputes the configuration's
+//               integer occupancy terms.
+//   eval      - one lane per query, looping over the program's configurations in index order;
+//               the configuration's coefficients are wave-uniform (scalar loads), so each lane
+//               keeps its own running (cost, index) minimum with a strict "<" and no cross-lane
+//               reduction is needed.  All decisions are taken in FP32 with the exact operation
+//               order (no contraction: this file is compiled with -ffp-contract=off), correctly
+//               rounded division and compare-select min/max, so a CPU replay reproduces every
+//               cost and index bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace klr {
+namespace {
+
+constexpr int kNdeg = KLR_MAX_NDEG;            // powers 0..3 of N~
+constexpr int kSlotFloats = KLR_N_METRICS * 2 * (kNdeg + 1) + KLR_N_METRICS;   // 72
+constexpr int kEvalBlock = 256;
+constexpr int kCollapseBlock = 128;
+
+struct CfgRec {          // per (program, configuration) integer terms
+  int32_t T;             // threads per block = prod L
+  int32_t Wb;            // waves per block = T / wave
+  int32_t bwarp;         // floor(wave * w_max / T)
+  int32_t rT;            // floor(r_max / T); floor(r_max / (R T)) = floor(rT / R)
+  int32_t Lmax;          // largest launch parameter (admissible only if <= N)
+  int32_t L0, L1;        // first two launch parameters (two-dimensional grid)
+  int32_t ok;            // configuration admissible and the program's fits valid
+};
+
+__device__ __forceinline__ float sel_min(float a, float b) { return b < a ? b : a; }
+__device__ __forceinline__ float sel_max(float a, float b) { return b > a ? b : a; }
+
+__device__ bool program_desc_ok(const klr_program& P, const EvalArgs& a) {
+  if (P.reserved != 0) return false;
+  if (P.fit0 < 0 || (int64_t)P.fit0 + KLR_N_METRICS > a.n_fits) return false;
+  if (P.v_launch < 1 || P.v_launch > KLR_MAX_LAUNCH) return false;
+  if (P.n_cfg < 0 || P.n_cfg > a.max_cfg || P.n_q < 0 || P.n_q > a.max_q) return false;
+  if (P.cfg0 < 0 || P.cfg0 + (int64_t)P.n_cfg * P.v_launch > a.cfgs_len) return false;
+  if (P.q0 < 0 || P.q0 + (int64_t)P.n_q > a.q_len) return false;
+  if (P.grid_kind != KLR_GRID_1D && P.grid_kind != KLR_GRID_2D) return false;
+  if (P.grid_kind == KLR_GRID_2D && P.v_launch < 2) return false;
+  if (a.all_costs && (P.cost0 < 0 || P.cost0 + (int64_t)P.n_cfg * P.n_q > a.costs_len)) return false;
+  return true;
+}
+
+__device__ bool fit_desc_ok(const klr_fit_desc& d, int v_expected, const EvalArgs& a) {
+  if (d.v != v_expected) return false;
+  if (d.n_num < 0 || d.n_den < 1) return false;
+  if (d.num0 < 0 || (int64_t)d.num0 + d.n_num > a.n_exp_rows) return false;
+  if (d.den0 < 0 || (int64_t)d.den0 + d.n_den > a.n_exp_rows) return false;
+  if (d.coef0 < 0 || d.coef0 + (int64_t)d.n_num + d.n_den - 1 > a.coef_len) return false;
+  for (int k = 0; k < d.v; ++k)
+    if (d.scale_exp[k] < -100 || d.scale_exp[k] > 100) return false;
+  const uint8_t* r0 = a.exps + (int64_t)d.den0 * KLR_MAX_VARS;
+  for (int k = 0; k < d.v; ++k)
+    if (r0[k] != 0) return false;
+  return true;
+}
+
+// Polynomial in N~ of one metric polynomial at fixed launch parameters.  FP64, monomials in set
+// order, each monomial value by repeated multiplication in variable order.
+__device__ bool collapse_poly(const uint8_t* exps, int row0, int nrows, int v, const int8_t* s,
+                              const double* coef, bool den, const int32_t* L, double out[kNdeg + 1]) {
+  double Lt[KLR_MAX_LAUNCH];
+  for (int k = 1; k < v; ++k) Lt[k - 1] = ldexp((double)L[k - 1], -(int)s[k]);
+  for (int d = 0; d <= kNdeg; ++d) out[d] = 0.0;
+  for (int t = 0; t < nrows; ++t) {
+    const uint8_t* e = exps + (int64_t)(row0 + t) * KLR_MAX_VARS;
+    if (e[0] > kNdeg) return false;
+    double mono = 1.0;
+    for (int k = 1; k < v; ++k)
+      for (int r = 0; r < e[k]; ++r) mono = mono * Lt[k - 1];
+    double c = den ? (t == 0 ? 1.0 : coef[t - 1]) : coef[t];
+    out[e[0]] = out[e[0]] + c * mono;
+  }
+  return true;
+}
+
+__global__ void __launch_bounds__(kCollapseBlock)
+collapse_kernel(EvalArgs a, int chunks) {
+  const int p = blockIdx.x / chunks;
+  const int c = (blockIdx.x % chunks) * kCollapseBlock + threadIdx.x;
+  if (p >= a.n_progs) return;
+  const klr_program P = a.progs[p];
+  const bool pd_ok = program_desc_ok(P, a);
+  bool fits_ok = pd_ok;
+  const int v = 1 + (pd_ok ? P.v_launch : 0);
+  if (pd_ok) {
+    for (int j = 0; j < KLR_N_METRICS; ++j) {
+      const klr_fit_desc d = a.desc[P.fit0 + j];
+      if (!fit_desc_ok(d, v, a)) { fits_ok = false; break; }
+      for (int t = 0; t < d.n_num && fits_ok; ++t)
+        if (a.exps[(int64_t)(d.num0 + t) * KLR_MAX_VARS] > kNdeg) fits_ok = false;
+      for (int t = 0; t < d.n_den && fits_ok; ++t)
+        if (a.exps[(int64_t)(d.den0 + t) * KLR_MAX_VARS] > kNdeg) fits_ok = false;
+    }
+  }
+  if (c == 0 && a.prog_status)
+    a.prog_status[p] = (pd_ok ? 0 : KLR_PROG_BAD_DESC) | (pd_ok && !fits_ok ? KLR_PROG_BAD_FIT : 0);
+  if (!pd_ok || c >= P.n_cfg || c >= a.max_cfg) return;
+
+  const int64_t slot = (int64_t)p * a.max_cfg + c;
+  float* out = reinterpret_cast<float*>(a.ws) + slot * kSlotFloats;
+  CfgRec* rec = reinterpret_cast<CfgRec*>(reinterpret_cast<char*>(a.ws) +
+                                          (int64_t)a.n_progs * a.max_cfg * kSlotFloats * sizeof(float)) + slot;
+
+  int32_t L[KLR_MAX_LAUNCH] = {1, 1, 1, 1};
+  bool cfg_ok = true;
+  int64_t T = 1;
+  int32_t Lmax = 1;
+  for (int k = 0; k < P.v_launch; ++k) {
+    L[k] = a.cfgs[P.cfg0 + (int64_t)c * P.v_launch + k];
+    if (L[k] < 1) cfg_ok = false;
+    if (L[k] > Lmax) Lmax = L[k];
+    if (cfg_ok) { T *= L[k]; if (T > (int64_t)a.hw.t_max) cfg_ok = false; }
+  }
+  if (cfg_ok && (T % a.hw.wave) != 0) cfg_ok = false;
+  CfgRec r;
+  r.T = cfg_ok ? (int32_t)T : a.hw.wave;
+  r.Wb = r.T / a.hw.wave;
+  r.bwarp = (a.hw.wave * a.hw.w_max) / r.T;
+  r.rT = a.hw.r_max / r.T;
+  r.Lmax = Lmax;
+  r.L0 = L[0] < 1 ? 1 : L[0];
+  r.L1 = L[1] < 1 ? 1 : L[1];
+  r.ok = (cfg_ok && fits_ok) ? 1 : 0;
+  *rec = r;
+
+  for (int j = 0; j < KLR_N_METRICS; ++j) {
+    double num[kNdeg + 1] = {0, 0, 0, 0}, den[kNdeg + 1] = {1, 0, 0, 0};
+    float sc = 1.0f;
+    if (fits_ok) {
+      const klr_fit_desc d = a.desc[P.fit0 + j];
+      collapse_poly(a.exps, d.num0, d.n_num, v, d.scale_exp, a.coef + d.coef0, false, L, num);
+      collapse_poly(a.exps, d.den0, d.n_den, v, d.scale_exp, a.coef + d.coef0 + d.n_num, true, L, den);
+      sc = ldexpf(1.0f, -(int)d.scale_exp[0]);
+    }
+    for (int e = 0; e <= kNdeg; ++e) {
+      out[j * 2 * (kNdeg + 1) + e] = (float)num[e];
+      out[j * 2 * (kNdeg + 1) + (kNdeg + 1) + e] = (float)den[e];
+    }
+    out[KLR_N_METRICS * 2 * (kNdeg + 1) + j] = sc;
+  }
+}
+
+struct Hw32 {
+  int32_t n_cu, wave, w_max, b_max, z_max;
+  float lat, dep, iss, bw;
+};
+
+// Cost of one (query, configuration) point; +inf where inadmissible.
+template <int GRID>
+__device__ __forceinline__ float point_cost(int32_t N, const float* __restrict__ cf, const CfgRec& r,
+                                            const Hw32& hw) {
+  bool ok = (r.ok != 0) & (N >= r.Lmax);
+  const float fN = (float)N;
+  float g[KLR_N_METRICS];
+#pragma unroll
+  for (int j = 0; j < KLR_N_METRICS; ++j) {
+    const float* c = cf + j * 2 * (kNdeg + 1);
+    const float x = fN * cf[KLR_N_METRICS * 2 * (kNdeg + 1) + j];
+    float p = c[kNdeg];
+    float q = c[2 * kNdeg + 1];
+#pragma unroll
+    for (int d = kNdeg - 1; d >= 0; --d) {
+      p = p * x;
+      p = p + c[d];
+      q = q * x;
+      q = q + c[kNdeg + 1 + d];
+    }
+    const float v = p / q;
+    const bool good = (q > 0.0f) & (fabsf(v) <= 3.402823466e38f);
+    ok = ok & good;
+    g[j] = good ? v : 0.0f;
+  }
+  const float Icomp = sel_max(g[0], 0.0f);
+  const float Imc = sel_max(g[1], 0.0f);
+  const float Imu = sel_max(g[2], 0.0f);
+  const float U = sel_max(g[3], 1.0f);
+  const float Isync = sel_max(g[4], 0.0f);
+  const int32_t R = (int32_t)sel_min(sel_max(ceilf(g[5]), 1.0f), 16777216.0f);
+  const int32_t Z = (int32_t)sel_min(sel_max(ceilf(g[6]), 0.0f), 16777216.0f);
+  const float Bw = sel_max(g[7], 1.0f);
+
+  // occupancy: min(b_max, floor(wave w_max / T), floor(r_max / (R T)), floor(z_max / Z))
+  int32_t B = hw.b_max < r.bwarp ? hw.b_max : r.bwarp;
+  const int32_t breg = r.rT / R;
+  B = breg < B ? breg : B;
+  const int32_t blds = Z > 0 ? hw.z_max / Z : hw.b_max;
+  B = blds < B ? blds : B;
+  ok = ok & (B >= 1);
+  const int32_t Bs = B >= 1 ? B : 1;
+  int32_t Nw = Bs * r.Wb;
+  Nw = Nw < hw.w_max ? Nw : hw.w_max;
+  const int32_t Nc = N >= 1 ? N : 1;
+  float repf;
+  if (GRID == KLR_GRID_1D) {
+    const uint32_t blocks = (uint32_t)(Nc - 1) / (uint32_t)r.T + 1u;
+    const uint32_t rep = (blocks - 1u) / (uint32_t)(Bs * hw.n_cu) + 1u;
+    repf = (float)rep;
+  } else {
+    const uint64_t blocks = (uint64_t)((uint32_t)(Nc - 1) / (uint32_t)r.L0 + 1u) *
+                            (uint64_t)((uint32_t)(Nc - 1) / (uint32_t)r.L1 + 1u);
+    const uint64_t rep = (blocks - 1u) / (uint64_t)(Bs * hw.n_cu) + 1u;
+    repf = (float)rep;
+  }
+  const float Nwf = (float)Nw;
+  const float Bf = (float)Bs;
+
+  const float Im = Imc + Imu;
+  float Lu = U - 1.0f;
+  Lu = Lu * hw.dep;
+  Lu = Lu + hw.lat;
+  float mem = hw.lat * Imc;
+  const float tu = Lu * Imu;
+  mem = mem + tu;
+  float comp = Icomp + Im;
+  comp = hw.iss * comp;
+
+  float d1 = U * Imu;
+  d1 = Imc + d1;
+  d1 = hw.dep * d1;
+  const float mwp_lat = mem / d1;
+  const float n2 = hw.bw * mem;
+  const float d2 = Im * Bw;
+  const float mwp_bw = n2 / d2;
+  float mwp = sel_min(mwp_lat, mwp_bw);
+  mwp = sel_min(mwp, Nwf);
+  mwp = sel_max(mwp, 1.0f);
+  const float tot = mem + comp;
+  const bool cwp_full = tot >= Nwf * comp;
+  const bool cwp_ge_mwp = tot >= mwp * comp;
+  const float cpm = comp / Im;
+  float ovl = mwp - 1.0f;
+  ovl = cpm * ovl;
+  const float e1 = tot + ovl;
+  float t2 = mem * Nwf;
+  t2 = t2 / mwp;
+  const float e2 = t2 + ovl;
+  const float t3 = comp * Nwf;
+  const float e3 = hw.lat + t3;
+  const bool case1 = (mwp >= Nwf) & cwp_full;
+  const bool case2 = cwp_ge_mwp | (comp > mem);
+  float ex = case1 ? e1 : (case2 ? e2 : e3);
+  const bool pure = (Im == 0.0f);
+  mwp = pure ? 1.0f : mwp;
+  ex = pure ? comp * Nwf : ex;
+
+  float cost = ex * repf;
+  float sy = mwp - 1.0f;
+  sy = hw.dep * sy;
+  sy = sy * Isync;
+  sy = sy * Bf;
+  sy = sy * repf;
+  cost = cost + sy;
+  ok = ok & (fabsf(cost) <= 3.402823466e38f);
+  return ok ? cost : INFINITY;
+}
+
+struct SweepOut {
+  int32_t* __restrict__ argmin;
+  float* __restrict__ best_cost;
+  float* __restrict__ all_costs;
+};
+
+// One lane per query; all control flow is wave-uniform (lanes past n_q compute a clamped query
+// and skip only the stores), so the per-configuration terms are scalar loads.
+template <int GRID>
+__device__ __forceinline__ void sweep(const float* __restrict__ slot0, const CfgRec* __restrict__ rec0,
+                                      const int32_t* __restrict__ queries, const SweepOut& o,
+                                      const Hw32& hw, const klr_program& P, int qi) {
+  const bool live = qi < P.n_q;
+  const int32_t N = queries[P.q0 + (live ? qi : P.n_q - 1)];
+  float best = INFINITY;
+  int32_t bi = -1;
+  float* costs = o.all_costs ? o.all_costs + P.cost0 + qi : nullptr;
+  for (int c = 0; c < P.n_cfg; ++c) {
+    const CfgRec r = rec0[c];
+    const float cost = point_cost<GRID>(N, slot0 + (int64_t)c * kSlotFloats, r, hw);
+    if (costs && live) costs[(int64_t)c * P.n_q] = cost;
+    if (cost < best) { best = cost; bi = c; }
+  }
+  if (live) {
+    o.argmin[P.q0 + qi] = bi;
+    o.best_cost[P.q0 + qi] = best;
+  }
+}
+
+__global__ void __launch_bounds__(kEvalBlock)
+eval_kernel(const klr_program* __restrict__ progs, const float* __restrict__ coefs,
+            const CfgRec* __restrict__ recs, const int32_t* __restrict__ queries,
+            int32_t* __restrict__ argmin, float* __restrict__ best_cost,
+            float* __restrict__ all_costs, EvalArgs a, Hw32 hw, int chunks) {
+  const int p = blockIdx.x / chunks;
+  const int qb = (blockIdx.x % chunks) * kEvalBlock;
+  if (p >= a.n_progs) return;
+  const klr_program P = progs[p];
+  if (!program_desc_ok(P, a) || qb >= P.n_q) return;
+  const float* slot0 = coefs + (int64_t)p * a.max_cfg * kSlotFloats;
+  const CfgRec* rec0 = recs + (int64_t)p * a.max_cfg;
+  const SweepOut o{argmin, best_cost, all_costs};
+  const int qi = qb + (int)threadIdx.x;
+  if (P.grid_kind == KLR_GRID_1D)
+    sweep<KLR_GRID_1D>(slot0, rec0, queries, o, hw, P, qi);
+  else
+    sweep<KLR_GRID_2D>(slot0, rec0, queries, o, hw, P, qi);
+}
+
+}  // namespace
+
+size_t eval_workspace_bytes(int32_t n_progs, int32_t max_cfg) {
+  const size_t slots = (size_t)(n_progs > 0 ? n_progs : 0) * (size_t)(max_cfg > 0 ? max_cfg : 0);
+  return slots * (kSlotFloats * sizeof(float) + sizeof(CfgRec));
+}
+
+hipError_t launch_eval(const EvalArgs& a) {
+  const int cchunks = a.max_cfg > 0 ? (a.max_cfg + kCollapseBlock - 1) / kCollapseBlock : 1;
+  hipLaunchKernelGGL(collapse_kernel, dim3((unsigned)a.n_progs * cchunks), dim3(kCollapseBlock), 0,
+                     a.stream, a, cchunks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.max_q == 0) return hipSuccess;
+  Hw32 hw{a.hw.n_cu, a.hw.wave, a.hw.w_max, a.hw.b_max, a.hw.z_max,
+          a.hw.mem_lat, a.hw.dep_delay, a.hw.issue_cycles, a.hw.bw};
+  const int qchunks = (a.max_q + kEvalBlock - 1) / kEvalBlock;
+  const dim3 grid((unsigned)a.n_progs * qchunks);
+  const float* coefs = reinterpret_cast<const float*>(a.ws);
+  const CfgRec* recs = reinterpret_cast<const CfgRec*>(
+      reinterpret_cast<const char*>(a.ws) + (int64_t)a.n_progs * a.max_cfg * kSlotFloats * sizeof(float));
+  hipLaunchKernelGGL(eval_kernel, grid, dim3(kEvalBlock), 0, a.stream, a.progs, coefs, recs, a.queries,
+                     a.argmin, a.best_cost, a.all_costs, a, hw, qchunks);
+  return hipGetLastError();
+}
+
+}  // namespace klr

@@ -1,0 +1,284 @@
+"""ctypes binding of libklr.so (include/klr.h): argument marshalling only.
+
+Every step of the fit, evaluation and argmin runs in the HIP library; this module only lays
+out descriptors, uploads arrays with torch (device memory and streams), and calls the C ABI.
+There is no CPU fallback: without the built library or a GPU, `Library.get()` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libklr.so")
+
+KLR_OK, KLR_E_INVALID, KLR_E_WORKSPACE, KLR_E_HIP, KLR_E_UNSUPPORTED = 0, -1, -2, -3, -4
+KLR_FP64, KLR_FP32_REFINED, KLR_BF16_REFINED = 0, 1, 2
+GRID_1D, GRID_2D = 0, 1
+N_METRICS = 8
+MAX_VARS = 8
+
+FIT_DESC = np.dtype([("x0", "<i8"), ("f0", "<i8"), ("coef0", "<i8"), ("m", "<i4"), ("v", "<i4"),
+                     ("num0", "<i4"), ("n_num", "<i4"), ("den0", "<i4"), ("n_den", "<i4"),
+                     ("scale_exp", "i1", (MAX_VARS,))])
+FIT_INFO = np.dtype([("status", "<u4"), ("rank", "<i4"), ("iters", "<i4"), ("q_nonpos", "<i4"),
+                     ("resid_norm", "<f8"), ("err_est", "<f8")])
+HW = np.dtype([("n_cu", "<i4"), ("wave", "<i4"), ("w_max", "<i4"), ("b_max", "<i4"),
+               ("r_max", "<i4"), ("z_max", "<i4"), ("t_max", "<i4"), ("reserved", "<i4"),
+               ("mem_lat", "<f4"), ("dep_delay", "<f4"), ("issue_cycles", "<f4"), ("bw", "<f4")])
+PROGRAM = np.dtype([("cfg0", "<i8"), ("q0", "<i8"), ("cost0", "<i8"), ("fit0", "<i4"),
+                    ("v_launch", "<i4"), ("n_cfg", "<i4"), ("n_q", "<i4"), ("grid_kind", "<i4"),
+                    ("reserved", "<i4")])
+
+EXPORTS = ("klr_create", "klr_destroy", "klr_last_error", "klr_fit_workspace", "klr_fit_batched",
+           "klr_eval_workspace", "klr_eval_argmin", "klr_abi_layout")
+
+
+class KlrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"klr status {status}: {msg}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libklr.so and declare the C signatures (no GPU needed)."""
+    if not os.path.exists(path):
+        raise RuntimeError(f"libklr.so not built at {path}: run `python -m paper_1911_02373_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, SZ, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+    lib.klr_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+    lib.klr_create.restype = I32
+    lib.klr_destroy.argtypes = [P]
+    lib.klr_destroy.restype = None
+    lib.klr_last_error.argtypes = [P]
+    lib.klr_last_error.restype = ctypes.c_char_p
+    lib.klr_abi_layout.argtypes = [ctypes.POINTER(I64), I32]
+    lib.klr_abi_layout.restype = I32
+    lib.klr_fit_workspace.argtypes = [I32, I32]
+    lib.klr_fit_workspace.restype = SZ
+    lib.klr_fit_batched.argtypes = [P, P, I32, P, I32, P, I64, P, I64, I32, I32, D, P, I64, P, P, SZ, P]
+    lib.klr_fit_batched.restype = I32
+    lib.klr_eval_workspace.argtypes = [I32, I32]
+    lib.klr_eval_workspace.restype = SZ
+    lib.klr_eval_argmin.argtypes = [P, P, I32, I32, I32, P, P, I32, P, I32, P, I64, P, I64, P, I64,
+                                    P, P, P, I64, P, P, SZ, P]
+    lib.klr_eval_argmin.restype = I32
+    return lib
+
+
+def abi_layout(lib) -> list:
+    buf = (ctypes.c_int64 * 32)()
+    n = lib.klr_abi_layout(buf, 32)
+    return [int(buf[i]) for i in range(n)]
+
+
+def expected_layout() -> list:
+    return [FIT_DESC.itemsize, FIT_INFO.itemsize, HW.itemsize, PROGRAM.itemsize,
+            FIT_DESC.fields["coef0"][1], FIT_DESC.fields["m"][1], FIT_DESC.fields["scale_exp"][1],
+            FIT_INFO.fields["resid_norm"][1], HW.fields["mem_lat"][1], PROGRAM.fields["fit0"][1],
+            PROGRAM.fields["grid_kind"][1]]
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def to_device(arr: np.ndarray, device="cuda"):
+    """Upload a numpy array (structured arrays as raw bytes) to a torch device tensor."""
+    torch = _torch()
+    a = np.ascontiguousarray(arr)
+    if a.dtype.fields is not None or a.dtype == np.uint8:
+        t = torch.from_numpy(a.view(np.uint8).reshape(-1).copy())
+    else:
+        t = torch.from_numpy(a.reshape(-1).copy())
+    return t.to(device)
+
+
+def hw_struct(hw) -> np.ndarray:
+    h = np.zeros(1, HW)
+    for k in ("n_cu", "wave", "w_max", "b_max", "r_max", "z_max", "t_max"):
+        h[k] = getattr(hw, k)
+    h["mem_lat"], h["dep_delay"] = hw.mem_lat, hw.dep_delay
+    h["issue_cycles"], h["bw"] = hw.issue_cycles, hw.bw
+    return h
+
+
+def fit_descs(fb) -> np.ndarray:
+    d = np.zeros(fb.n_fits, FIT_DESC)
+    d["x0"], d["f0"], d["coef0"] = fb.x0, fb.f0, fb.coef0
+    d["m"], d["v"] = fb.m, fb.v
+    d["num0"], d["n_num"], d["den0"], d["n_den"] = fb.num0, fb.n_num, fb.den0, fb.n_den
+    d["scale_exp"] = fb.scale_exp
+    return d
+
+
+def program_descs(pb, with_costs: bool = False) -> np.ndarray:
+    d = np.zeros(pb.n_progs, PROGRAM)
+    d["cfg0"], d["q0"] = pb.cfg0, pb.q0
+    d["fit0"], d["v_launch"], d["n_cfg"], d["n_q"] = pb.fit0, pb.v_launch, pb.n_cfg, pb.n_q
+    d["grid_kind"] = pb.grid_kind
+    if with_costs:
+        sizes = pb.n_cfg.astype(np.int64) * pb.n_q
+        d["cost0"][1:] = np.cumsum(sizes)[:-1]
+    return d
+
+
+def eval_fit_descs(pb) -> np.ndarray:
+    """Fit descriptors of a ProgramBatch (coefficient holders: no samples)."""
+    n = pb.num0.shape[0]
+    d = np.zeros(n, FIT_DESC)
+    d["coef0"], d["m"] = pb.coef0, 0
+    d["v"] = np.repeat(1 + pb.v_launch, N_METRICS)
+    d["num0"], d["n_num"], d["den0"], d["n_den"] = pb.num0, pb.n_num, pb.den0, pb.n_den
+    d["scale_exp"] = pb.scale_exp
+    return d
+
+
+@dataclass
+class DeviceEval:
+    """Device-resident inputs of klr_eval_argmin for one ProgramBatch."""
+    progs: object
+    n_progs: int
+    max_cfg: int
+    max_q: int
+    desc: object
+    n_fits: int
+    exps: object
+    n_exp_rows: int
+    coef: object
+    cfgs: object
+    queries: object
+    hw: np.ndarray
+    costs_len: int
+    ws: object
+
+    @classmethod
+    def from_batch(cls, lib: "Library", pb, with_costs: bool = False, device="cuda", coef=None):
+        torch = _torch()
+        pd = program_descs(pb, with_costs)
+        costs_len = int((pb.n_cfg.astype(np.int64) * pb.n_q).sum()) if with_costs else 0
+        max_cfg, max_q = int(pb.n_cfg.max()), int(pb.n_q.max())
+        ws_bytes = lib.eval_workspace(pb.n_progs, max_cfg)
+        c = pb.coef if coef is None else coef
+        coef_t = c if hasattr(c, "data_ptr") else to_device(np.asarray(c, np.float64), device)
+        return cls(progs=to_device(pd, device), n_progs=pb.n_progs, max_cfg=max_cfg, max_q=max_q,
+                   desc=to_device(eval_fit_descs(pb), device), n_fits=int(pb.num0.shape[0]),
+                   exps=to_device(pb.exps.astype(np.uint8), device), n_exp_rows=int(pb.exps.shape[0]),
+                   coef=coef_t, cfgs=to_device(pb.cfgs.astype(np.int32), device),
+                   queries=to_device(pb.queries.astype(np.int32), device), hw=hw_struct(pb.hw),
+                   costs_len=costs_len,
+                   ws=torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=device))
+
+
+class Library:
+    _inst = None
+
+    def __init__(self, path: str = LIB_PATH):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the klr product path runs only on the HIP device")
+        self.lib = load_library(path)
+        self.device = torch.cuda.current_device()
+        h = ctypes.c_void_p()
+        st = self.lib.klr_create(ctypes.byref(h), self.device)
+        if st != KLR_OK:
+            raise KlrError(st, "klr_create failed")
+        self.h = h
+
+    @classmethod
+    def get(cls) -> "Library":
+        if cls._inst is None:
+            cls._inst = cls()
+        return cls._inst
+
+    def _check(self, st: int):
+        if st != KLR_OK:
+            raise KlrError(st, self.lib.klr_last_error(self.h).decode())
+
+    @staticmethod
+    def _stream(stream=None) -> int:
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        return s.cuda_stream
+
+    # ---- eval ---------------------------------------------------------------------------
+    def eval_workspace(self, n_progs: int, max_cfg: int) -> int:
+        return int(self.lib.klr_eval_workspace(n_progs, max_cfg))
+
+    def eval_argmin(self, de: DeviceEval, want_costs: bool = False, out=None, stream=None,
+                    want_status: bool = True):
+        """Returns (argmin int32, best_cost float32, all_costs float32 | None, status | None)."""
+        torch = _torch()
+        ql = int(de.queries.numel())
+        if out is None:
+            am = torch.empty(ql, dtype=torch.int32, device=de.queries.device)
+            bc = torch.empty(ql, dtype=torch.float32, device=de.queries.device)
+            costs = torch.empty(de.costs_len, dtype=torch.float32, device=de.queries.device) \
+                if want_costs else None
+            status = torch.empty(de.n_progs, dtype=torch.int32, device=de.queries.device) \
+                if want_status else None
+        else:
+            am, bc, costs, status = out
+        st = self.lib.klr_eval_argmin(
+            self.h, _ptr(de.progs), de.n_progs, de.max_cfg, de.max_q, de.hw.ctypes.data,
+            _ptr(de.desc), de.n_fits, _ptr(de.exps), de.n_exp_rows, _ptr(de.coef),
+            int(de.coef.numel()), _ptr(de.cfgs), int(de.cfgs.numel()), _ptr(de.queries), ql,
+            _ptr(am), _ptr(bc), _ptr(costs), int(costs.numel()) if costs is not None else 0,
+            _ptr(status), _ptr(de.ws), int(de.ws.numel()), self._stream(stream))
+        self._check(st)
+        return am, bc, costs, status
+
+    # ---- fit ----------------------------------------------------------------------------
+    def fit_workspace(self, n_fits: int, precision: int) -> int:
+        return int(self.lib.klr_fit_workspace(n_fits, precision))
+
+    def fit_batched(self, df: "DeviceFit", precision: int = KLR_FP64, max_iter: int = 32,
+                    tol: float = 1e-12, out=None, stream=None):
+        """Returns (coef float64, info bytes [n_fits * 32] uint8 tensor)."""
+        torch = _torch()
+        if out is None:
+            coef = torch.empty(max(df.n_coef, 1), dtype=torch.float64, device=df.f.device)
+            info = torch.empty(max(df.n_fits, 1) * FIT_INFO.itemsize, dtype=torch.uint8, device=df.f.device)
+        else:
+            coef, info = out
+        wsb = self.fit_workspace(df.n_fits, precision)
+        if df.ws is None or df.ws.numel() < wsb:
+            df.ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=df.f.device)
+        st = self.lib.klr_fit_batched(
+            self.h, _ptr(df.desc), df.n_fits, _ptr(df.exps), df.n_exp_rows, _ptr(df.X),
+            int(df.X.numel()), _ptr(df.f), int(df.f.numel()), precision, max_iter, tol,
+            _ptr(coef), df.n_coef, _ptr(info), _ptr(df.ws), int(df.ws.numel()), self._stream(stream))
+        self._check(st)
+        return coef, info
+
+
+@dataclass
+class DeviceFit:
+    desc: object
+    n_fits: int
+    exps: object
+    n_exp_rows: int
+    X: object
+    f: object
+    n_coef: int
+    ws: object = None
+
+    @classmethod
+    def from_batch(cls, fb, device="cuda"):
+        return cls(desc=to_device(fit_descs(fb), device), n_fits=fb.n_fits,
+                   exps=to_device(fb.exps.astype(np.uint8), device), n_exp_rows=int(fb.exps.shape[0]),
+                   X=to_device(fb.X.astype(np.int32), device), f=to_device(fb.f.astype(np.float64), device),
+                   n_coef=int(fb.n_coef))
+
+
+def info_records(info_tensor) -> np.ndarray:
+    """Device info bytes -> numpy structured array of klr_fit_info."""
+    return info_tensor.cpu().numpy().view(FIT_INFO)

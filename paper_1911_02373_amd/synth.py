@@ -289,3 +289,79 @@ def config3_programs(seed: int, n_progs: int = 1024, n_q: int = 65536, degree: i
         grid_kind=np.zeros(n_progs, np.int32),
         q0=np.arange(n_progs, dtype=np.int64) * n_q, n_q=np.full(n_progs, n_q, np.int32),
         cfgs=cfgs.reshape(-1).astype(np.int32), queries=queries, hw=HW())
+
+
+def pow2_launch_tuples(v_launch: int, t_min: int = 64, t_max: int = 1024) -> np.ndarray:
+    """All power-of-two tuples of v_launch launch parameters with product in [t_min, t_max]."""
+    lo, hi = int(np.log2(t_min)), int(np.log2(t_max))
+    out = [tuple(1 << a for a in t) for t in itertools.product(range(hi + 1), repeat=v_launch)
+           if lo <= sum(t) <= hi]
+    return np.array(sorted(out), np.int32).reshape(-1, v_launch)
+
+
+def mixed_programs(seed: int, n_progs: int, n_q_range=(1, 700), n_cfg_range=(1, 160),
+                   degree: int = 3, log2_range=(4.0, 26.0), v_launch_choices=(1, 2, 3, 4),
+                   p_2d: float = 0.3, p_bad_cfg: float = 0.05) -> ProgramBatch:
+    """Uneven programs: v_launch from `v_launch_choices`, n_cfg and n_q uniform in the given
+    ranges, metrics of total degree <= `degree` in (N/2^26, L_k/2^10) with the same lo + s*p/q
+    construction as config3_programs (s = (hi - lo) / (2 * #monomials)).  Configurations are
+    power-of-two tuples with product 64..1024 (the 2-parameter case uses the 127 config-3
+    tuples), plus a few random tuples that may be inadmissible.  Two-dimensional grids are
+    drawn with probability p_2d when v_launch >= 2."""
+    rng = np.random.default_rng(seed)
+    vls = rng.choice(np.asarray(v_launch_choices), n_progs)
+    exps_blocks, exps_index = [], {}
+    row = 0
+    for vl in sorted(set(int(x) for x in vls)):
+        E = monomials(1 + vl, degree)
+        exps_index[vl] = (row, E.shape[0])
+        exps_blocks.append(E)
+        row += E.shape[0]
+    exps = np.concatenate(exps_blocks)
+    fit_num0, fit_nn, coef_parts, coef0 = [], [], [], []
+    scale_rows, fit0, cfg0, n_cfg, gk, q0, n_q = [], [], [], [], [], [], []
+    cfg_parts, q_parts = [], []
+    c_off = q_off = k_off = 0
+    for p in range(n_progs):
+        vl = int(vls[p])
+        r0, nm = exps_index[vl]
+        fit0.append(p * N_METRICS)
+        for j in range(N_METRICS):
+            lo, hi = METRIC_RANGES[j]
+            s = (hi - lo) / (2.0 * nm)
+            pc = rng.uniform(0.1, 2.0, nm)
+            qc = np.concatenate([[1.0], rng.uniform(0.1, 2.0, nm - 1)])
+            coef_parts.append(np.concatenate([lo * qc + s * pc, qc[1:]]))
+            coef0.append(k_off)
+            k_off += 2 * nm - 1
+            fit_num0.append(r0)
+            fit_nn.append(nm)
+            sc = np.zeros(MAX_VARS, np.int8)
+            sc[0] = 26
+            sc[1: 1 + vl] = 10
+            scale_rows.append(sc)
+        base = config3_launch_configs()[:127] if vl == 2 else pow2_launch_tuples(vl)
+        nc = int(rng.integers(n_cfg_range[0], n_cfg_range[1] + 1))
+        pick = base[rng.integers(0, base.shape[0], nc)]
+        bad = rng.random(nc) < p_bad_cfg
+        pick[bad] = rng.integers(1, 96, (int(bad.sum()), vl))
+        cfg_parts.append(pick.reshape(-1))
+        cfg0.append(c_off)
+        c_off += pick.size
+        n_cfg.append(nc)
+        gk.append(1 if (vl >= 2 and rng.random() < p_2d) else 0)
+        nq = int(rng.integers(n_q_range[0], n_q_range[1] + 1))
+        q_parts.append(np.rint(2.0 ** rng.uniform(log2_range[0], log2_range[1], nq)).astype(np.int32))
+        q0.append(q_off)
+        q_off += nq
+        n_q.append(nq)
+    n_fits = n_progs * N_METRICS
+    return ProgramBatch(
+        fits=None, coef=np.concatenate(coef_parts), exps=exps,
+        num0=np.array(fit_num0, np.int32), n_num=np.array(fit_nn, np.int32),
+        den0=np.array(fit_num0, np.int32), n_den=np.array(fit_nn, np.int32),
+        coef0=np.array(coef0, np.int64), scale_exp=np.array(scale_rows, np.int8).reshape(n_fits, MAX_VARS),
+        v_launch=vls.astype(np.int32), fit0=np.array(fit0, np.int32),
+        cfg0=np.array(cfg0, np.int64), n_cfg=np.array(n_cfg, np.int32),
+        grid_kind=np.array(gk, np.int32), q0=np.array(q0, np.int64), n_q=np.array(n_q, np.int32),
+        cfgs=np.concatenate(cfg_parts).astype(np.int32), queries=np.concatenate(q_parts), hw=HW())

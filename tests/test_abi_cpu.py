@@ -1,0 +1,45 @@
+"""The C-ABI library loads without a GPU and exports every symbol include/klr.h declares."""
+import os
+import re
+
+import pytest
+
+from paper_1911_02373_amd import klr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "klr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(klr_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(klr.LIB_PATH):
+        pytest.fail("libklr.so missing: run python -m paper_1911_02373_amd.build (or __graft_entry__.build())")
+    return klr.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert set(klr.EXPORTS) <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layouts_match_binding(lib):
+    assert klr.abi_layout(lib) == klr.expected_layout()
+
+
+def test_workspace_sizes_are_host_computable(lib):
+    assert lib.klr_eval_workspace(0, 128) == 0
+    assert lib.klr_eval_workspace(1024, 128) > 0
+    assert lib.klr_fit_workspace(4096, klr.KLR_FP64) >= 0
+
+
+def test_null_handle_rejected_without_launch(lib):
+    # host-detectable errors return before touching the device
+    assert lib.klr_eval_argmin(None, None, 0, 0, 0, None, None, 0, None, 0, None, 0, None, 0, None,
+                               0, None, None, None, 0, None, None, 0, None) == klr.KLR_E_INVALID

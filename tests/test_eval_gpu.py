@@ -1,0 +1,129 @@
+"""GPU parity of klr_eval_argmin against the oracle's FP32 replay (bit-exact costs and argmin)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cost as oc
+from paper_1911_02373_amd import synth
+from tests.helpers import constant_programs
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "cost_cases.json")
+
+
+def _run(klr, pb, want_costs=True):
+    from paper_1911_02373_amd.klr import DeviceEval
+    de = DeviceEval.from_batch(klr, pb, with_costs=want_costs)
+    am, bc, costs, st = klr.eval_argmin(de, want_costs=want_costs)
+    import torch
+    torch.cuda.synchronize()
+    return (am.cpu().numpy(), bc.cpu().numpy(),
+            None if costs is None else costs.cpu().numpy(), st.cpu().numpy())
+
+
+def _check_program_exact(pb, p, am, bc, costs, cost_off):
+    want = oc.program_costs(pb, p, mode="replay")
+    q0, nq, nc = int(pb.q0[p]), int(pb.n_q[p]), int(pb.n_cfg[p])
+    if costs is not None:
+        got = costs[cost_off: cost_off + nc * nq].reshape(nc, nq)
+        bad = np.argwhere(got.view(np.uint32) != want.view(np.uint32))
+        assert bad.size == 0, (p, bad[:5], got[tuple(bad[0])], want[tuple(bad[0])])
+    wi, wb = oc.argmin_lowest(want)
+    assert np.array_equal(am[q0:q0 + nq], wi), p
+    assert np.array_equal(bc[q0:q0 + nq].view(np.uint32), wb.view(np.uint32)), p
+
+
+def test_hand_derived_costs_on_gpu(klr):
+    cases = json.load(open(GOLDEN))["cases"]
+    for cs in cases:
+        pb = constant_programs([cs["metrics"]], [cs["L"]], [[cs["N"]]], grid_kind=cs["grid"])
+        am, bc, costs, st = _run(klr, pb)
+        want = np.inf if cs["expect"] == "inf" else cs["expect"]
+        assert st[0] == 0
+        assert costs[0] == want, (cs["name"], costs[0], want)
+
+
+def test_config3_small_bit_exact(klr):
+    """8 programs x 1000 queries (ragged against the 256-lane blocks) x 128 configurations."""
+    pb = synth.config3_programs(101, n_progs=8, n_q=1000)
+    am, bc, costs, st = _run(klr, pb)
+    assert np.all(st == 0)
+    off = 0
+    for p in range(pb.n_progs):
+        _check_program_exact(pb, p, am, bc, costs, off)
+        off += int(pb.n_cfg[p]) * int(pb.n_q[p])
+
+
+def test_mixed_uneven_programs_bit_exact(klr):
+    """1-4 launch parameters, degree-3 metrics, 1-D and 2-D grids, uneven n_cfg and n_q,
+    inadmissible configurations, tiny and huge N."""
+    pb = synth.mixed_programs(202, 24)
+    am, bc, costs, st = _run(klr, pb)
+    assert np.all(st == 0)
+    off = 0
+    for p in range(pb.n_progs):
+        _check_program_exact(pb, p, am, bc, costs, off)
+        off += int(pb.n_cfg[p]) * int(pb.n_q[p])
+
+
+def test_config3_full_size_sampled(klr):
+    """1024 programs x 65536 queries x 128 configurations as timed; argmin and best cost of
+    sampled queries against the oracle's replay."""
+    pb = synth.config3_programs(7, n_progs=1024, n_q=65536)
+    am, bc, _, st = _run(klr, pb, want_costs=False)
+    assert np.all(st == 0)
+    rng = np.random.default_rng(0)
+    for p in rng.choice(1024, 24, replace=False):
+        qi = rng.choice(65536, 64, replace=False)
+        wi, wb = oc.argmin_lowest(oc.program_costs(pb, int(p), query_idx=qi))
+        q0 = int(pb.q0[p])
+        assert np.array_equal(am[q0 + qi], wi)
+        assert np.array_equal(bc[q0 + qi].view(np.uint32), wb.view(np.uint32))
+    # properties over every query: an index in range or -1 exactly when the cost is +inf
+    assert np.all((am >= -1) & (am < 128))
+    assert np.array_equal(am == -1, np.isinf(bc))
+    assert np.all(am != 127)            # the pad configuration is never admissible
+
+
+def test_ties_duplicates_and_empty(klr):
+    pb = synth.config3_programs(9, n_progs=3, n_q=300)
+    base = synth.config3_launch_configs()[:50]
+    pb.cfgs = np.concatenate([base, base]).reshape(-1)
+    pb.n_cfg[:] = 100
+    pb.n_cfg[2] = 0                    # a program without configurations
+    am, bc, costs, st = _run(klr, pb)
+    assert np.all(st == 0)
+    assert np.all(am[:600] < 50) and np.all(am[:600] >= 0)
+    assert np.all(am[600:] == -1) and np.all(np.isinf(bc[600:]))
+
+
+def test_all_inadmissible_and_small_N(klr):
+    rows = [[10, 10, 0, 1, 0, 300, 0, 128]]            # R = 300: B_active = 0 for T >= 512
+    cfgs = [[512, 1], [1024, 1], [1, 1], [32, 33]]
+    pb = constant_programs(rows, cfgs, [[1 << 20, 100, 1, 0, -5]])
+    am, bc, costs, st = _run(klr, pb)
+    assert np.all(am == -1) and np.all(np.isinf(bc)) and np.all(np.isinf(costs))
+
+
+def test_bad_descriptors_reported_not_read(klr):
+    pb = synth.config3_programs(5, n_progs=4, n_q=100)
+    pb.fit0[1] = 10 ** 6               # fit range out of bounds: program skipped
+    pb.n_den = pb.n_den.copy()
+    pb.n_den[2 * 8 + 3] = 0            # a metric without a denominator row: fits invalid
+    pb.n_q[3] = 10 ** 6                # query range out of bounds: program skipped
+    pb.q0[3] = 0
+    am, bc, costs, st = _run(klr, pb, want_costs=False)
+    assert st[0] == 0
+    assert st[1] & 1 and st[3] & 1
+    assert st[2] == 2
+    assert np.all(am[200:300] == -1) and np.all(np.isinf(bc[200:300]))
+
+
+def test_deterministic(klr):
+    pb = synth.mixed_programs(77, 16)
+    a = _run(klr, pb)
+    b = _run(klr, pb)
+    for x, y in zip(a, b):
+        assert np.array_equal(np.asarray(x).view(np.uint8), np.asarray(y).view(np.uint8))
