@@ -188,6 +188,21 @@ klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_pro
                            float* all_costs, int64_t costs_len, int32_t* prog_status,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Kernel timing.  When enabled on a handle, every kernel the handle launches is bracketed by a
+ * pair of HIP events recorded on the caller's stream (so the elapsed time is the kernel's own,
+ * on the stream it runs on).  klr_profile_read synchronises the recorded events, returns the
+ * summed milliseconds and launch count of one kernel kind since the last reset, and never
+ * launches work.  Kinds: */
+#define KLR_K_COLLAPSE 0       /* per-(program, configuration) coefficient collapse            */
+#define KLR_K_EVAL 1           /* evaluation + argmin sweep                                    */
+#define KLR_K_FIT_GRAM 2       /* fit: design matrix + Gram                                    */
+#define KLR_K_FIT_SOLVE 3      /* fit: factorisation + refinement + epilogue                   */
+#define KLR_K_MLP 4            /* surrogate network kernels                                    */
+#define KLR_K_COUNT 5
+klr_status klr_profile_enable(klr_handle h, int32_t on);   /* on != 0: enable; 0: disable+reset */
+klr_status klr_profile_read(klr_handle h, int32_t kind, double* total_ms, int64_t* launches);
+
 /* [host] ABI self-description for binding checks: writes up to n entries of
  * {sizeof(klr_fit_desc), sizeof(klr_fit_info), sizeof(klr_hw), sizeof(klr_program), ...}
  * and returns the number of entries available. */

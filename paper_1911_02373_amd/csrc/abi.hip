@@ -21,6 +21,50 @@ klr_status hip_check(klr_handle h, hipError_t e, const char* what) {
   return fail(h, KLR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+hipEvent_t Timer::get() {
+  if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int Timer::begin(int kind, hipStream_t s) {
+  if (!on) return -1;
+  Rec r{kind, get(), get()};
+  if (!r.a || !r.b) return -1;
+  hipEventRecord(r.a, s);
+  pending.push_back(r);
+  return (int)pending.size() - 1;
+}
+
+void Timer::end(int idx, hipStream_t s) {
+  if (idx >= 0) hipEventRecord(pending[idx].b, s);
+}
+
+hipError_t Timer::drain() {
+  hipError_t err = hipSuccess;
+  for (auto& r : pending) {
+    hipError_t e = hipEventSynchronize(r.b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e == hipSuccess) { total_ms[r.kind] += ms; count[r.kind] += 1; } else { err = e; }
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  pending.clear();
+  return err;
+}
+
+void Timer::reset() {
+  drain();
+  for (int k = 0; k < KLR_K_COUNT; ++k) { total_ms[k] = 0.0; count[k] = 0; }
+}
+
+Timer::~Timer() {
+  for (auto& r : pending) { pool.push_back(r.a); pool.push_back(r.b); }
+  for (hipEvent_t e : pool) hipEventDestroy(e);
+}
+
 namespace {
 
 bool hw_ok(const klr_hw& hw, std::string& why) {
@@ -60,6 +104,21 @@ klr_status klr_create(klr_handle* out, int device) {
 void klr_destroy(klr_handle h) { delete h; }
 
 const char* klr_last_error(klr_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+klr_status klr_profile_enable(klr_handle h, int32_t on) {
+  if (!h) return KLR_E_INVALID;
+  h->timer.reset();
+  h->timer.on = on != 0;
+  return KLR_OK;
+}
+
+klr_status klr_profile_read(klr_handle h, int32_t kind, double* total_ms, int64_t* launches) {
+  if (!h || kind < 0 || kind >= KLR_K_COUNT || !total_ms || !launches) return KLR_E_INVALID;
+  klr_status st = klr::hip_check(h, h->timer.drain(), "klr_profile_read");
+  *total_ms = h->timer.total_ms[kind];
+  *launches = h->timer.count[kind];
+  return st;
+}
 
 int32_t klr_abi_layout(int64_t* out, int32_t n) {
   const int64_t v[] = {
@@ -116,7 +175,7 @@ klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_pro
   klr::EvalArgs a{progs, n_progs, max_cfg, max_q, *hw, desc, n_fits, exps, n_exp_rows, coef, coef_len,
                   cfgs, cfgs_len, queries, q_len, argmin, best_cost, all_costs,
                   all_costs ? costs_len : 0, prog_status, ws, ws_bytes,
-                  reinterpret_cast<hipStream_t>(stream)};
+                  reinterpret_cast<hipStream_t>(stream), &h->timer};
   return klr::hip_check(h, klr::launch_eval(a), "klr_eval_argmin launch");
 }
 
@@ -147,7 +206,7 @@ klr_status klr_fit_batched(klr_handle h, const klr_fit_desc* desc, int32_t n_fit
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
     return fail(h, KLR_E_INVALID, "workspace must be 256-byte aligned");
   klr::FitArgs a{desc, n_fits, exps, n_exp_rows, X, x_len, f, f_len, precision, max_iter, tol,
-                 coef, coef_len, info, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream)};
+                 coef, coef_len, info, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream), &h->timer};
   return klr::hip_check(h, klr::launch_fit(a), "klr_fit_batched launch");
 }
 

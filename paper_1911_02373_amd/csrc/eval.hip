@@ -332,8 +332,10 @@ size_t eval_workspace_bytes(int32_t n_progs, int32_t max_cfg) {
 
 hipError_t launch_eval(const EvalArgs& a) {
   const int cchunks = a.max_cfg > 0 ? (a.max_cfg + kCollapseBlock - 1) / kCollapseBlock : 1;
+  int t = a.timer ? a.timer->begin(KLR_K_COLLAPSE, a.stream) : -1;
   hipLaunchKernelGGL(collapse_kernel, dim3((unsigned)a.n_progs * cchunks), dim3(kCollapseBlock), 0,
                      a.stream, a, cchunks);
+  if (a.timer) a.timer->end(t, a.stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.max_q == 0) return hipSuccess;
@@ -344,8 +346,10 @@ hipError_t launch_eval(const EvalArgs& a) {
   const float* coefs = reinterpret_cast<const float*>(a.ws);
   const CfgRec* recs = reinterpret_cast<const CfgRec*>(
       reinterpret_cast<const char*>(a.ws) + (int64_t)a.n_progs * a.max_cfg * kSlotFloats * sizeof(float));
+  t = a.timer ? a.timer->begin(KLR_K_EVAL, a.stream) : -1;
   hipLaunchKernelGGL(eval_kernel, grid, dim3(kEvalBlock), 0, a.stream, a.progs, coefs, recs, a.queries,
                      a.argmin, a.best_cost, a.all_costs, a, hw, qchunks);
+  if (a.timer) a.timer->end(t, a.stream);
   return hipGetLastError();
 }
 

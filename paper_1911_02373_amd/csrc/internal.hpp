@@ -6,12 +6,35 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "klr.h"
+
+namespace klr {
+
+// Optional per-kernel event timing (see klr_profile_enable).
+struct Timer {
+  bool on = false;
+  struct Rec { int kind; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double total_ms[KLR_K_COUNT] = {0};
+  int64_t count[KLR_K_COUNT] = {0};
+  hipEvent_t get();
+  // Record the start event of a kernel of `kind` on `s` (returns the index or -1 when off).
+  int begin(int kind, hipStream_t s);
+  void end(int idx, hipStream_t s);
+  hipError_t drain();
+  void reset();
+  ~Timer();
+};
+
+}  // namespace klr
 
 struct klr_handle_s {
   int device = 0;
   std::string err;
+  klr::Timer timer;
 };
 
 namespace klr {
@@ -43,6 +66,7 @@ struct EvalArgs {
   void* ws;
   size_t ws_bytes;
   hipStream_t stream;
+  Timer* timer;
 };
 
 size_t eval_workspace_bytes(int32_t n_progs, int32_t max_cfg);
@@ -66,6 +90,7 @@ struct FitArgs {
   void* ws;
   size_t ws_bytes;
   hipStream_t stream;
+  Timer* timer;
 };
 
 size_t fit_workspace_bytes(int32_t n_fits, int32_t precision);

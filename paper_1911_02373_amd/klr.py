@@ -34,7 +34,9 @@ PROGRAM = np.dtype([("cfg0", "<i8"), ("q0", "<i8"), ("cost0", "<i8"), ("fit0", "
                     ("reserved", "<i4")])
 
 EXPORTS = ("klr_create", "klr_destroy", "klr_last_error", "klr_fit_workspace", "klr_fit_batched",
-           "klr_eval_workspace", "klr_eval_argmin", "klr_abi_layout")
+           "klr_eval_workspace", "klr_eval_argmin", "klr_abi_layout", "klr_profile_enable",
+           "klr_profile_read")
+K_COLLAPSE, K_EVAL, K_FIT_GRAM, K_FIT_SOLVE, K_MLP = 0, 1, 2, 3, 4
 
 
 class KlrError(RuntimeError):
@@ -66,6 +68,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.klr_eval_argmin.argtypes = [P, P, I32, I32, I32, P, P, I32, P, I32, P, I64, P, I64, P, I64,
                                     P, P, P, I64, P, P, SZ, P]
     lib.klr_eval_argmin.restype = I32
+    lib.klr_profile_enable.argtypes = [P, I32]
+    lib.klr_profile_enable.restype = I32
+    lib.klr_profile_read.argtypes = [P, I32, ctypes.POINTER(D), ctypes.POINTER(I64)]
+    lib.klr_profile_read.restype = I32
     return lib
 
 
@@ -208,6 +214,16 @@ class Library:
         torch = _torch()
         s = stream if stream is not None else torch.cuda.current_stream()
         return s.cuda_stream
+
+    # ---- kernel timing ------------------------------------------------------------------
+    def profile_enable(self, on: bool = True):
+        self._check(self.lib.klr_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self, kind: int):
+        """(summed milliseconds, launches) of one kernel kind since profile_enable."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(self.lib.klr_profile_read(self.h, kind, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
 
     # ---- eval ---------------------------------------------------------------------------
     def eval_workspace(self, n_progs: int, max_cfg: int) -> int:
