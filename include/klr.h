@@ -92,25 +92,41 @@ typedef struct {
 
 typedef struct {
   uint32_t status;
-  int32_t rank;           /* numerical rank of the equilibrated Gram factor                   */
+  int32_t rank;           /* numerical rank of the equilibrated Gram factor at the Gram's own  */
+                          /*   precision (pivots above 4 mu): for FP32/BF16 Grams it counts the */
+                          /*   directions the preconditioner resolves, not the FP64 rank        */
   int32_t iters;          /* refinement iterations used                                        */
   int32_t q_nonpos;       /* samples with fitted q(x~_i) <= 0                                  */
   double resid_norm;      /* || A y - f ||_2 in FP64                                            */
-  double err_est;         /* estimated relative error of y (equilibrated norm) vs the FP64 LS  */
+  double err_est;         /* estimated ||A (y - y*)|| / ||f||: error of the fitted linearised   */
+                          /*   values vs the exact least-squares solution y*                  */
 } klr_fit_info;           /* 32 bytes */
 
 typedef enum { KLR_FP64 = 0, KLR_FP32_REFINED = 1, KLR_BF16_REFINED = 2 } klr_precision;
 
-/* Workspace bytes klr_fit_batched needs for n_fits fits. */
-size_t klr_fit_workspace(int32_t n_fits, int32_t precision);
+/* Workspace bytes klr_fit_batched needs for n_fits fits whose targets span f[0, f_len)
+ * (two FP64 values per sample row for the refinement residuals). */
+size_t klr_fit_workspace(int32_t n_fits, int64_t f_len, int32_t precision);
 
 /* Fit n_fits independent rational functions (uneven m and monomial sets in one launch).
  *   desc[n_fits], exps[n_exp_rows][8] (uint8 exponent tuples), X[x_len] int32,
  *   f[f_len] float64, coef[coef_len] float64 (out), info[n_fits] (out).
- *   precision: KLR_FP64 forms the Gram matrix in FP64; KLR_FP32_REFINED / KLR_BF16_REFINED form
- *   it in reduced precision with FP32 accumulation and recover accuracy by iterative refinement
- *   against FP64 residuals (max_iter iterations at most, stop when the relative update <= tol).
- *   The factorisation and residuals are FP64 on every path. */
+ * Method (one workgroup per fit): the design matrix is built in LDS-staged row chunks from X
+ * and f; the Gram matrix A^T A and A^T f are formed; columns are equilibrated by powers of two;
+ * the equilibrated Gram matrix, shifted by mu = 8 u tr/n (u = unit roundoff of the Gram
+ * precision), is factored by diagonally pivoted Cholesky in FP64 (the numerical rank is the
+ * count of pivots above 4 mu); the normal-equations solution is then refined by conjugate
+ * gradients on the least-squares problem, right-preconditioned by that factor, with residuals
+ * f - A y recomputed from the samples in FP64, until the estimated error of the fitted values,
+ * ||A (y - y*)|| / ||f|| (sum of the last three conjugate-gradient step energies), is <= tol or
+ * max_iter iterations have run.
+ *   precision: KLR_FP64 forms the Gram matrix in FP64; KLR_FP32_REFINED / KLR_BF16_REFINED
+ *   round the design matrix to FP32 / BF16 for the Gram product and accumulate in FP32; a fit
+ *   that does not converge is redone with the FP64 Gram (status KLR_FIT_FELL_BACK_FP64).
+ *   The factorisation and the residuals are FP64 on every path.  Coefficients are in the
+ *   scaled-variable basis x~.  Rank-deficient fits get a least-squares solution (not
+ *   necessarily the minimum-norm one): its values on the samples are the unique
+ *   least-squares values. */
 klr_status klr_fit_batched(klr_handle h, const klr_fit_desc* desc, int32_t n_fits,
                            const uint8_t* exps, int32_t n_exp_rows,
                            const int32_t* X, int64_t x_len, const double* f, int64_t f_len,

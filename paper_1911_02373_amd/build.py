@@ -26,7 +26,6 @@ COMMON = [
 # per-file extra flags: the evaluation's FP32 op sequence is normative, so no contraction
 EXTRA = {
     "eval.hip": ["-ffp-contract=off"],
-    "fit.hip": ["-ffp-contract=off"],
 }
 SOURCES = ["abi.hip", "eval.hip", "fit.hip"]
 

@@ -179,8 +179,8 @@ klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_pro
   return klr::hip_check(h, klr::launch_eval(a), "klr_eval_argmin launch");
 }
 
-size_t klr_fit_workspace(int32_t n_fits, int32_t precision) {
-  return klr::fit_workspace_bytes(n_fits, precision);
+size_t klr_fit_workspace(int32_t n_fits, int64_t f_len, int32_t precision) {
+  return klr::fit_workspace_bytes(n_fits, f_len, precision);
 }
 
 klr_status klr_fit_batched(klr_handle h, const klr_fit_desc* desc, int32_t n_fits,
@@ -200,7 +200,7 @@ klr_status klr_fit_batched(klr_handle h, const klr_fit_desc* desc, int32_t n_fit
   if (n_fits == 0) return KLR_OK;
   if (!desc || !exps || !coef || !info || (x_len > 0 && !X) || (f_len > 0 && !f))
     return fail(h, KLR_E_INVALID, "NULL array argument");
-  const size_t need = klr::fit_workspace_bytes(n_fits, precision);
+  const size_t need = klr::fit_workspace_bytes(n_fits, f_len, precision);
   if (need > 0 && (!ws || ws_bytes < need))
     return fail(h, KLR_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)

@@ -1,18 +1,602 @@
-// Batched rational least-squares fits (placeholder until the kernels land).
+// Batched rational least-squares fits, gfx950.
+//
+// Paper: step 2 ("Rational function estimation") of the section "An Algorithm to Build and
+// Deploy a Performance-Predicting Rational Program" and the section "Building a Driver
+// Program: Rational function estimation": each low-level metric is fitted by a rational
+// function p/q over given monomial sets, as a linear least-squares problem on a Vandermonde-like
+// design matrix (ill-conditioned, possibly rank deficient).
+//
+// One workgroup (4 waves) per fit, one launch per size class of the unknown count n (<= 32,
+// <= 64, <= 128); every workgroup of a launch reads its fit's descriptor and leaves at once when
+// the fit belongs to another class.  Per fit:
+//   1. the design matrix is built in LDS in chunks of CH rows from the staged samples
+//      (x~ = x 2^-s exact in FP64; A_ij = x~^e_j, or -f_i x~^e_j for denominator columns);
+//   2. Gram G = A^T A (4x4 register blocks per thread; FP64, or FP32 / BF16-rounded inputs with
+//      FP32 accumulation) and c = A^T f in FP64;
+//   3. power-of-two column equilibration (exact), diagonal shift mu = 8 u tr/n;
+//   4. diagonally pivoted Cholesky in FP64 in LDS (packed symmetric storage addressed through the
+//      pivot permutation); rank = pivots above 4 mu;
+//   5. z0 = normal-equations solution, then CGLS on min || A D Pi R^-1 w - f ||, i.e. right-
+//      preconditioned by the factor, with the residual f - A D z recomputed and updated in FP64
+//      from the samples every iteration; stop when the delayed Hestenes-Stiefel estimate of
+//      ||A (y - y*)|| (error of the fitted linearised values) is <= tol ||f||;
+//   6. reduced-precision Gram paths that do not converge are redone with the FP64 Gram;
+//   7. epilogue: y = D z, ||f - A y||, count of samples with q(x~_i) <= 0, status.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
 
 #include "internal.hpp"
 
 namespace klr {
+namespace {
 
-size_t fit_workspace_bytes(int32_t n_fits, int32_t precision) {
+constexpr int kFitBlock = 256;
+
+template <int NM>
+struct Chunk { static constexpr int CH = 64; };
+template <>
+struct Chunk<128> { static constexpr int CH = 32; };
+
+template <int NM>
+struct Lds {
+  static constexpr int CH = Chunk<NM>::CH;
+  static constexpr int S = 0;                         // packed symmetric NM x NM (doubles)
+  static constexpr int A = S + NM * (NM + 1) / 2;     // design-matrix chunk CH x NM
+  static constexpr int XT = A + CH * NM;              // scaled variables CH x 8
+  static constexpr int F = XT + CH * 8;               // targets of the chunk
+  static constexpr int R = F + CH;                    // residuals of the chunk
+  static constexpr int V = R + CH;                    // 9 vectors of NM
+  static constexpr int RED = V + 9 * NM;              // reduction scratch
+  static constexpr int NDOUBLE = RED + kFitBlock;
+  static constexpr int BYTES = NDOUBLE * 8 + NM * 8 + NM * 4 + 64;
+};
+
+__device__ __forceinline__ int symi(int a, int b) {
+  return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Deterministic sum over the workgroup (result valid in every thread).
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ float round_bf16(float x) {
+  uint32_t b = __float_as_uint(x);
+  b = (b + 0x7FFFu + ((b >> 16) & 1u)) & 0xFFFF0000u;   // round to nearest even, finite inputs
+  return __uint_as_float(b);
+}
+
+struct FitCtx {
+  int n, n_num, n_den, m, v;
+  int64_t x0, f0;
+  double* S; double* A; double* xt; double* fch; double* rch;
+  double *D, *c, *z, *t, *s, *p, *g, *tp, *piv;
+  double* red;
+  int8_t* ex;
+  int* perm;
+  int* flags;
+};
+
+// Stage rows [i0, i0 + rows) of the fit: scaled variables and targets.  Returns false if a
+// target is not finite.
+template <int NM>
+__device__ bool stage_rows(const FitArgs& a, const FitCtx& C, const int8_t* sc, int i0, int rows,
+                           double* ff = nullptr) {
+  bool bad = false;
+  const int t = threadIdx.x;
+  if (t < rows) {
+    const int32_t* xr = a.X + C.x0 + (int64_t)(i0 + t) * C.v;
+    for (int k = 0; k < C.v; ++k) C.xt[t * 8 + k] = ldexp((double)xr[k], -(int)sc[k]);
+    const double fv = a.f[C.f0 + i0 + t];
+    C.fch[t] = fv;
+    bad = !isfinite(fv);
+    if (ff) *ff += fv * fv;
+  }
+  return bad;
+}
+
+__device__ __forceinline__ double monomial(const double* xr, const int8_t* e, int v) {
+  double mono = 1.0;
+  for (int k = 0; k < v; ++k)
+    for (int r = 0; r < e[k]; ++r) mono *= xr[k];
+  return mono;
+}
+
+// Design-matrix chunk: A[i][j] for j < n, zero up to the 4-padded width.
+template <int NM>
+__device__ void build_chunk(const FitCtx& C, int rows) {
+  const int nb4 = ((C.n + 3) / 4) * 4;
+  for (int e = threadIdx.x; e < rows * nb4; e += kFitBlock) {
+    const int i = e / nb4, j = e - i * nb4;
+    double val = 0.0;
+    if (j < C.n) {
+      const double mono = monomial(C.xt + i * 8, C.ex + j * 8, C.v);
+      val = j < C.n_num ? mono : -C.fch[i] * mono;
+    }
+    C.A[i * NM + j] = val;
+  }
+}
+
+// Gram pass: S (packed lower, unscaled), c = A^T f and ||f||^2 (into *fnorm2).
+// GP: Gram precision.  Returns true if a target is not finite.
+template <int NM, int GP>
+__device__ bool gram_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, double* fnorm2) {
+  constexpr int CH = Chunk<NM>::CH;
+  constexpr int NBMAX = NM / 4;
+  constexpr int BPT = (NBMAX * (NBMAX + 1) / 2 + kFitBlock - 1) / kFitBlock;
+  using acc_t = typename std::conditional<GP == KLR_FP64, double, float>::type;
+  const int nb = (C.n + 3) / 4;
+  const int nbl = nb * (nb + 1) / 2;
+  int bj[BPT], bk[BPT];
+  acc_t acc[BPT][16];
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int blk = threadIdx.x + b * kFitBlock;
+    int r = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= blk) ++r;
+    while (r * (r + 1) / 2 > blk) --r;
+    bj[b] = r;
+    bk[b] = blk - r * (r + 1) / 2;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[b][u] = 0;
+  }
+  double cacc = 0.0, ff = 0.0;
+  bool bad = false;
+  for (int i0 = 0; i0 < C.m; i0 += CH) {
+    const int rows = C.m - i0 < CH ? C.m - i0 : CH;
+    bad |= stage_rows<NM>(a, C, sc, i0, rows, &ff);
+    __syncthreads();
+    build_chunk<NM>(C, rows);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      const int blk = threadIdx.x + b * kFitBlock;
+      if (blk < nbl) {
+        const double* pa = C.A + 4 * bj[b];
+        const double* pb = C.A + 4 * bk[b];
+        for (int i = 0; i < rows; ++i) {
+          acc_t x[4], y[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (GP == KLR_FP64) {
+              x[u] = (acc_t)pa[i * NM + u];
+              y[u] = (acc_t)pb[i * NM + u];
+            } else if (GP == KLR_FP32_REFINED) {
+              x[u] = (acc_t)(float)pa[i * NM + u];
+              y[u] = (acc_t)(float)pb[i * NM + u];
+            } else {
+              x[u] = (acc_t)round_bf16((float)pa[i * NM + u]);
+              y[u] = (acc_t)round_bf16((float)pb[i * NM + u]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) acc[b][u * 4 + w] += x[u] * y[w];
+        }
+      }
+    }
+    if ((int)threadIdx.x < C.n)
+      for (int i = 0; i < rows; ++i) cacc += C.A[i * NM + threadIdx.x] * C.fch[i];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int blk = threadIdx.x + b * kFitBlock;
+    if (blk < nbl) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const int j = 4 * bj[b] + u, k = 4 * bk[b] + w;
+          if (j < C.n && k < C.n && k <= j) C.S[symi(j, k)] = (double)acc[b][u * 4 + w];
+        }
+    }
+  }
+  if ((int)threadIdx.x < C.n) C.c[threadIdx.x] = cacc;
+  if (bad) C.flags[0] = 1;
+  *fnorm2 = block_sum(ff, C.red);
+  return C.flags[0] != 0;
+}
+
+// Forward solve L u = in[perm[.]] (pivoted order), by wave 0.  out is pivot-indexed.
+__device__ void solve_fwd(const FitCtx& C, const double* in, double* out) {
+  const int lane = threadIdx.x & 63;
+  const int n = C.n;
+  double b0 = lane < n ? in[C.perm[lane]] : 0.0;
+  double b1 = lane + 64 < n ? in[C.perm[lane + 64]] : 0.0;
+  for (int k = 0; k < n; ++k) {
+    const int pk = C.perm[k];
+    const double bk = __shfl(k < 64 ? b0 : b1, k & 63);
+    const double uk = bk / C.S[symi(pk, pk)];
+    if (lane == (k & 63)) { if (k < 64) b0 = uk; else b1 = uk; }
+    if (lane > k && lane < n) b0 -= C.S[symi(C.perm[lane], pk)] * uk;
+    if (lane + 64 > k && lane + 64 < n) b1 -= C.S[symi(C.perm[lane + 64], pk)] * uk;
+  }
+  if (lane < n) out[lane] = b0;
+  if (lane + 64 < n) out[lane + 64] = b1;
+}
+
+// Backward solve L^T v = in (pivot-indexed), by wave 0; out[perm[i]] = v_i.
+__device__ void solve_bwd(const FitCtx& C, const double* in, double* out) {
+  const int lane = threadIdx.x & 63;
+  const int n = C.n;
+  double b0 = lane < n ? in[lane] : 0.0;
+  double b1 = lane + 64 < n ? in[lane + 64] : 0.0;
+  for (int k = n - 1; k >= 0; --k) {
+    const int pk = C.perm[k];
+    const double bk = __shfl(k < 64 ? b0 : b1, k & 63);
+    const double vk = bk / C.S[symi(pk, pk)];
+    if (lane == (k & 63)) { if (k < 64) b0 = vk; else b1 = vk; }
+    if (lane < k) b0 -= C.S[symi(pk, C.perm[lane])] * vk;
+    if (lane + 64 < k) b1 -= C.S[symi(pk, C.perm[lane + 64])] * vk;
+  }
+  if (lane < n) out[C.perm[lane]] = b0;
+  if (lane + 64 < n) out[C.perm[lane + 64]] = b1;
+}
+
+// sum_j x_j y_j over n entries, by wave 0 (valid in wave 0).
+__device__ double dot_w0(const double* x, const double* y, int n) {
+  const int lane = threadIdx.x & 63;
+  double v = 0.0;
+  for (int j = lane; j < n; j += 64) v += x[j] * y[j];
+  return wave_sum(v);
+}
+
+enum RowMode { kR0 = 0, kQ = 1, kFinal = 2 };
+
+// Row pass: d_i = sum_j A_ij tp_j.  kR0: r_i = f_i - d_i.  kQ: q_i = d_i, returns sum q_i^2.
+// kFinal: returns sum (f_i - d_i)^2 and counts samples with q(x~_i) <= 0 (tp holds y).
+template <int NM, int MODE>
+__device__ double row_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, double* wsr,
+                           double* wsq, int* qneg_out) {
+  constexpr int CH = Chunk<NM>::CH;
+  constexpr int TPR = kFitBlock / CH;
+  const int i = threadIdx.x / TPR, sub = threadIdx.x % TPR;
+  double acc = 0.0;
+  int qneg = 0;
+  for (int i0 = 0; i0 < C.m; i0 += CH) {
+    const int rows = C.m - i0 < CH ? C.m - i0 : CH;
+    stage_rows<NM>(a, C, sc, i0, rows);
+    __syncthreads();
+    build_chunk<NM>(C, rows);
+    __syncthreads();
+    double dsum = 0.0;
+    if (i < rows)
+      for (int j = sub; j < C.n; j += TPR) dsum += C.A[i * NM + j] * C.tp[j];
+#pragma unroll
+    for (int off = TPR / 2; off >= 1; off >>= 1) dsum += __shfl_xor(dsum, off);
+    if (i < rows && sub == 0) {
+      const int64_t row = C.f0 + i0 + i;
+      if (MODE == kR0) {
+        wsr[row] = C.fch[i] - dsum;
+      } else if (MODE == kQ) {
+        wsq[row] = dsum;
+        acc += dsum * dsum;
+      } else {
+        const double res = C.fch[i] - dsum;
+        acc += res * res;
+        double qv = 1.0;
+        for (int j = C.n_num; j < C.n; ++j) qv += C.tp[j] * monomial(C.xt + i * 8, C.ex + j * 8, C.v);
+        if (!(qv > 0.0)) ++qneg;
+      }
+    }
+    __syncthreads();
+  }
+  if (MODE == kFinal) {
+    const double qn = block_sum((double)qneg, C.red);
+    *qneg_out = (int)qn;
+  }
+  return block_sum(acc, C.red);
+}
+
+// g = D A^T r, with r updated first (r -= alpha q) when `update`.
+template <int NM>
+__device__ void atr_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, double* wsr,
+                         const double* wsq, bool update, double alpha) {
+  constexpr int CH = Chunk<NM>::CH;
+  constexpr int TPC = kFitBlock / NM;
+  const int j = threadIdx.x % NM, sub = threadIdx.x / NM;
+  double acc = 0.0;
+  for (int i0 = 0; i0 < C.m; i0 += CH) {
+    const int rows = C.m - i0 < CH ? C.m - i0 : CH;
+    stage_rows<NM>(a, C, sc, i0, rows);
+    const int t = threadIdx.x;
+    if (t < rows) {
+      const int64_t row = C.f0 + i0 + t;
+      double r = wsr[row];
+      if (update) { r -= alpha * wsq[row]; wsr[row] = r; }
+      C.rch[t] = r;
+    }
+    __syncthreads();
+    build_chunk<NM>(C, rows);
+    __syncthreads();
+    if (j < C.n)
+      for (int i = sub; i < rows; i += TPC) acc += C.A[i * NM + j] * C.rch[i];
+    __syncthreads();
+  }
+  C.red[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < C.n) {
+    double gsum = 0.0;
+    for (int s = 0; s < TPC; ++s) gsum += C.red[threadIdx.x + s * NM];
+    C.g[threadIdx.x] = gsum * C.D[threadIdx.x];
+  }
+  __syncthreads();
+}
+
+// Equilibrate, shift and factor S.  Returns the numerical rank.
+__device__ int factor(const FitCtx& C, double unit) {
+  const int n = C.n;
+  const int tid = threadIdx.x;
+  if (tid < n) {
+    const double gjj = C.S[symi(tid, tid)];
+    int e = 0;
+    if (gjj > 0.0 && isfinite(gjj)) frexp(sqrt(gjj), &e);
+    C.D[tid] = ldexp(1.0, -e);
+    C.perm[tid] = tid;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += kFitBlock) {
+    const int j = e / n, k = e - j * n;
+    if (k <= j) C.S[symi(j, k)] *= C.D[j] * C.D[k];
+  }
+  if (tid < n) C.c[tid] *= C.D[tid];
+  __syncthreads();
+  if (tid < 64) {
+    double tr = 0.0;
+    for (int j = tid; j < n; j += 64) tr += C.S[symi(j, j)];
+    tr = wave_sum(tr);
+    if (tid == 0) C.red[kFitBlock - 1] = 8.0 * unit * tr / n + 1e-300;
+  }
+  __syncthreads();
+  const double mu = C.red[kFitBlock - 1];
+  if (tid < n) C.S[symi(tid, tid)] += mu;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + tid; i < n; i += 64) {
+        const double vv = C.S[symi(C.perm[i], C.perm[i])];
+        if (vv > best || (vv == best && i < bi)) { best = vv; bi = i; }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) {
+        const int pt = C.perm[k];
+        C.perm[k] = C.perm[bi];
+        C.perm[bi] = pt;
+        double dk = C.S[symi(C.perm[k], C.perm[k])];
+        C.piv[k] = dk;
+        if (!(dk > 0.0)) dk = mu;
+        C.S[symi(C.perm[k], C.perm[k])] = sqrt(dk);
+      }
+    }
+    __syncthreads();
+    const int pk = C.perm[k];
+    const double lkk = C.S[symi(pk, pk)];
+    for (int i = k + 1 + tid; i < n; i += kFitBlock) C.S[symi(C.perm[i], pk)] /= lkk;
+    __syncthreads();
+    const int w = n - k - 1;
+    for (int e = tid; e < w * w; e += kFitBlock) {
+      const int ii = e / w, jj = e - ii * w;
+      if (jj <= ii) {
+        const int ra = C.perm[k + 1 + ii], rb = C.perm[k + 1 + jj];
+        C.S[symi(ra, rb)] -= C.S[symi(ra, pk)] * C.S[symi(rb, pk)];
+      }
+    }
+    __syncthreads();
+  }
+  int rank = 0;
+  for (int k = 0; k < n; ++k) rank += C.piv[k] > 4.0 * mu ? 1 : 0;
+  return rank;
+}
+
+template <int NM, int PREC>
+__global__ void __launch_bounds__(kFitBlock)
+fit_kernel(FitArgs a, int nm_lo) {
+  using L = Lds<NM>;
+  extern __shared__ double smem[];
+  const int fi = blockIdx.x;
+  if (fi >= a.n_fits) return;
+  const klr_fit_desc d = a.desc[fi];
+  const int n = d.n_num + d.n_den - 1;
+  const bool shape_ok = d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= KLR_MAX_UNKNOWNS;
+  if (shape_ok ? (n > NM || n <= nm_lo) : (NM != 128)) return;
+  const int tid = threadIdx.x;
+  bool ok = shape_ok && d.v >= 1 && d.v <= KLR_MAX_VARS && d.m >= 1 && d.m <= KLR_MAX_SAMPLES &&
+            d.x0 >= 0 && d.x0 + (int64_t)d.m * d.v <= a.x_len && d.f0 >= 0 &&
+            d.f0 + (int64_t)d.m <= a.f_len && d.num0 >= 0 &&
+            (int64_t)d.num0 + d.n_num <= a.n_exp_rows && d.den0 >= 0 &&
+            (int64_t)d.den0 + d.n_den <= a.n_exp_rows;
+  const bool coef_ok = shape_ok && d.coef0 >= 0 && d.coef0 + (int64_t)n <= a.coef_len;
+  ok = ok && coef_ok;
+  if (ok)
+    for (int k = 0; k < d.v; ++k) {
+      if (d.scale_exp[k] < -100 || d.scale_exp[k] > 100) ok = false;
+      if (a.exps[(int64_t)d.den0 * KLR_MAX_VARS + k] != 0) ok = false;
+    }
+
+  FitCtx C;
+  C.n = n; C.n_num = d.n_num; C.n_den = d.n_den; C.m = d.m; C.v = d.v; C.x0 = d.x0; C.f0 = d.f0;
+  C.S = smem + L::S; C.A = smem + L::A; C.xt = smem + L::XT; C.fch = smem + L::F; C.rch = smem + L::R;
+  double* V = smem + L::V;
+  C.D = V; C.c = V + NM; C.z = V + 2 * NM; C.t = V + 3 * NM; C.s = V + 4 * NM; C.p = V + 5 * NM;
+  C.g = V + 6 * NM; C.tp = V + 7 * NM; C.piv = V + 8 * NM;
+  C.red = smem + L::RED;
+  C.ex = reinterpret_cast<int8_t*>(smem + L::NDOUBLE);
+  C.perm = reinterpret_cast<int*>(C.ex + NM * 8);
+  C.flags = C.perm + NM;
+
+  klr_fit_info info{};
+  if (tid == 0) C.flags[0] = 0;
+  if (ok && tid < n) {
+    const int row = tid < d.n_num ? d.num0 + tid : d.den0 + (tid - d.n_num + 1);
+    for (int k = 0; k < KLR_MAX_VARS; ++k)
+      C.ex[tid * 8 + k] = k < d.v ? (int8_t)a.exps[(int64_t)row * KLR_MAX_VARS + k] : 0;
+  }
+  __syncthreads();
+  int8_t sc[KLR_MAX_VARS];
+  for (int k = 0; k < KLR_MAX_VARS; ++k) sc[k] = d.scale_exp[k];
+  double* wsr = reinterpret_cast<double*>(a.ws);
+  double* wsq = wsr + a.f_len;
+
+  bool bad = !ok;
+  int prec = PREC;
+  int iters = 0, rank = 0;
+  bool converged = false;
+  double err = 0.0;
+  for (int attempt = 0; attempt < 2 && !bad; ++attempt) {
+    bool fbad;
+    double unit, fn2 = 0.0;
+    if (prec == KLR_FP64) { fbad = gram_pass<NM, KLR_FP64>(a, C, sc, &fn2); unit = 0x1p-53; }
+    else if (prec == KLR_FP32_REFINED) { fbad = gram_pass<NM, KLR_FP32_REFINED>(a, C, sc, &fn2); unit = 0x1p-24; }
+    else { fbad = gram_pass<NM, KLR_BF16_REFINED>(a, C, sc, &fn2); unit = 0x1p-8; }
+    const double fnorm = sqrt(fn2);
+    if (fbad) { bad = true; break; }
+    rank = factor(C, unit);
+    // z0 = (G + mu I)^-1 c
+    if (tid < 64) solve_fwd(C, C.c, C.s);
+    __syncthreads();
+    if (tid < 64) solve_bwd(C, C.s, C.z);
+    __syncthreads();
+    if (tid < n) C.tp[tid] = C.D[tid] * C.z[tid];
+    __syncthreads();
+    row_pass<NM, kR0>(a, C, sc, wsr, wsq, nullptr);
+    atr_pass<NM>(a, C, sc, wsr, wsq, false, 0.0);
+    if (tid < 64) solve_fwd(C, C.g, C.s);
+    __syncthreads();
+    if (tid < n) C.p[tid] = C.s[tid];
+    if (tid < 64) { const double gg = dot_w0(C.s, C.s, n); if (tid == 0) C.red[kFitBlock - 2] = gg; }
+    __syncthreads();
+    double gamma = C.red[kFitBlock - 2];
+    iters = 0;
+    converged = a.max_iter == 0 || gamma == 0.0;
+    err = 0.0;
+    // CGLS increments are B^T B-orthogonal, so sum_{j >= k} alpha_j gamma_j = ||A (y* - y_k)||^2:
+    // the last kDelay terms estimate the error of the fitted values (Hestenes-Stiefel).
+    constexpr int kDelay = 3;
+    double hist[kDelay] = {0.0, 0.0, 0.0};
+    const int need = a.max_iter < kDelay ? a.max_iter : kDelay;
+    for (int it = 0; it < a.max_iter && !converged; ++it) {
+      if (tid < 64) solve_bwd(C, C.p, C.t);
+      __syncthreads();
+      if (tid < n) C.tp[tid] = C.D[tid] * C.t[tid];
+      __syncthreads();
+      const double qq = row_pass<NM, kQ>(a, C, sc, wsr, wsq, nullptr);
+      const double alpha = qq > 0.0 ? gamma / qq : 0.0;
+      if (tid < n) C.z[tid] += alpha * C.t[tid];
+      __syncthreads();
+      hist[it % kDelay] = alpha * gamma;
+      ++iters;
+      if (it + 1 >= need) {
+        const double est = sqrt(hist[0] + hist[1] + hist[2]);
+        err = fnorm > 0.0 ? est / fnorm : 0.0;
+        if (est <= a.tol * fnorm) { converged = true; break; }
+      }
+      if (qq == 0.0) { converged = true; break; }
+      atr_pass<NM>(a, C, sc, wsr, wsq, true, alpha);
+      if (tid < 64) solve_fwd(C, C.g, C.s);
+      __syncthreads();
+      if (tid < 64) { const double gg = dot_w0(C.s, C.s, n); if (tid == 0) C.red[kFitBlock - 2] = gg; }
+      __syncthreads();
+      const double gnew = C.red[kFitBlock - 2];
+      const double beta = gamma > 0.0 ? gnew / gamma : 0.0;
+      if (tid < n) C.p[tid] = C.s[tid] + beta * C.p[tid];
+      __syncthreads();
+      gamma = gnew;
+      if (gamma == 0.0) { converged = true; break; }
+    }
+    if (converged || prec == KLR_FP64) break;
+    info.status |= KLR_FIT_FELL_BACK_FP64;
+    prec = KLR_FP64;
+  }
+
+  if (bad) {
+    if (coef_ok)
+      for (int j = tid; j < n; j += kFitBlock) a.coef[d.coef0 + j] = 0.0;
+    if (tid == 0) {
+      info.status = KLR_FIT_BAD_INPUT;
+      info.resid_norm = NAN;
+      info.err_est = NAN;
+      a.info[fi] = info;
+    }
+    return;
+  }
+  if (tid < n) C.tp[tid] = C.D[tid] * C.z[tid];
+  __syncthreads();
+  int qneg = 0;
+  const double rr = row_pass<NM, kFinal>(a, C, sc, wsr, wsq, &qneg);
+  if (tid < n) a.coef[d.coef0 + tid] = C.tp[tid];
+  if (tid == 0) {
+    if (rank < n) info.status |= KLR_FIT_RANK_DEFICIENT;
+    if (d.m < n) info.status |= KLR_FIT_UNDERDETERMINED;
+    if (!converged) info.status |= KLR_FIT_NOT_CONVERGED;
+    if (qneg > 0) info.status |= KLR_FIT_Q_NONPOS;
+    info.rank = rank;
+    info.iters = iters;
+    info.q_nonpos = qneg;
+    info.resid_norm = sqrt(rr);
+    info.err_est = err;
+    a.info[fi] = info;
+  }
+}
+
+template <int NM, int PREC>
+hipError_t launch_class(const FitArgs& a, int nm_lo) {
+  const size_t lds = (size_t)Lds<NM>::BYTES;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_kernel<NM, PREC>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((fit_kernel<NM, PREC>), dim3((unsigned)a.n_fits), dim3(kFitBlock), lds, a.stream, a,
+                     nm_lo);
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_all(const FitArgs& a) {
+  hipError_t e = launch_class<32, PREC>(a, 0);
+  if (e == hipSuccess) e = launch_class<64, PREC>(a, 32);
+  if (e == hipSuccess) e = launch_class<128, PREC>(a, 64);
+  return e;
+}
+
+}  // namespace
+
+size_t fit_workspace_bytes(int32_t n_fits, int64_t f_len, int32_t precision) {
   (void)precision;
-  return (size_t)(n_fits > 0 ? n_fits : 0) * 256;
+  (void)n_fits;
+  return (size_t)(f_len > 0 ? f_len : 0) * 2 * sizeof(double);
 }
 
 hipError_t launch_fit(const FitArgs& a) {
-  (void)a;
-  return hipErrorNotSupported;
+  const int t = a.timer ? a.timer->begin(KLR_K_FIT_SOLVE, a.stream) : -1;
+  hipError_t e;
+  if (a.precision == KLR_FP64) e = launch_all<KLR_FP64>(a);
+  else if (a.precision == KLR_FP32_REFINED) e = launch_all<KLR_FP32_REFINED>(a);
+  else e = launch_all<KLR_BF16_REFINED>(a);
+  if (a.timer) a.timer->end(t, a.stream);
+  return e;
 }
 
 }  // namespace klr

@@ -93,7 +93,7 @@ struct FitArgs {
   Timer* timer;
 };
 
-size_t fit_workspace_bytes(int32_t n_fits, int32_t precision);
+size_t fit_workspace_bytes(int32_t n_fits, int64_t f_len, int32_t precision);
 hipError_t launch_fit(const FitArgs& a);
 
 }  // namespace klr

@@ -59,7 +59,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.klr_last_error.restype = ctypes.c_char_p
     lib.klr_abi_layout.argtypes = [ctypes.POINTER(I64), I32]
     lib.klr_abi_layout.restype = I32
-    lib.klr_fit_workspace.argtypes = [I32, I32]
+    lib.klr_fit_workspace.argtypes = [I32, I64, I32]
     lib.klr_fit_workspace.restype = SZ
     lib.klr_fit_batched.argtypes = [P, P, I32, P, I32, P, I64, P, I64, I32, I32, D, P, I64, P, P, SZ, P]
     lib.klr_fit_batched.restype = I32
@@ -253,8 +253,8 @@ class Library:
         return am, bc, costs, status
 
     # ---- fit ----------------------------------------------------------------------------
-    def fit_workspace(self, n_fits: int, precision: int) -> int:
-        return int(self.lib.klr_fit_workspace(n_fits, precision))
+    def fit_workspace(self, n_fits: int, f_len: int, precision: int) -> int:
+        return int(self.lib.klr_fit_workspace(n_fits, f_len, precision))
 
     def fit_batched(self, df: "DeviceFit", precision: int = KLR_FP64, max_iter: int = 32,
                     tol: float = 1e-12, out=None, stream=None):
@@ -265,7 +265,7 @@ class Library:
             info = torch.empty(max(df.n_fits, 1) * FIT_INFO.itemsize, dtype=torch.uint8, device=df.f.device)
         else:
             coef, info = out
-        wsb = self.fit_workspace(df.n_fits, precision)
+        wsb = self.fit_workspace(df.n_fits, int(df.f.numel()), precision)
         if df.ws is None or df.ws.numel() < wsb:
             df.ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=df.f.device)
         st = self.lib.klr_fit_batched(

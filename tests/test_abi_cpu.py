@@ -36,7 +36,7 @@ def test_struct_layouts_match_binding(lib):
 def test_workspace_sizes_are_host_computable(lib):
     assert lib.klr_eval_workspace(0, 128) == 0
     assert lib.klr_eval_workspace(1024, 128) > 0
-    assert lib.klr_fit_workspace(4096, klr.KLR_FP64) >= 0
+    assert lib.klr_fit_workspace(4096, 1 << 20, klr.KLR_FP64) >= 16 << 20
 
 
 def test_null_handle_rejected_without_launch(lib):
