@@ -2,12 +2,20 @@
 """Throughput of the rational-program hot path on one MI355X.
 
 One step = one pass of the hot path over one batch of synthetic input resident in HBM:
+  fit  : 4096 independent rational fits of uneven sample counts (m ~ U[64, 512]) over
+         (N, bx, by), numerator and denominator of total degree <= 3 (39 unknowns), literal
+         domain (bx, by multiples of 16, bx*by <= 1024), FP64 Gram + pivoted Cholesky + FP64
+         residual refinement to ||A (y - y*)|| <= 1e-10 ||f||;
   eval : 1024 rational programs (8 fitted degree-2 metrics each, in N, bx, by), 65536 data-size
          queries each, 128 launch configurations: collapse + evaluation + per-query argmin
          (8.59e9 (query, configuration) points).
+The reduced-precision Gram paths (FP32, BF16 inputs with FP32 accumulation, same FP64
+refinement) are timed on the same fit batch outside the step, as the comparison the
+precision change is judged by.
 
-Prints ONE JSON line (metric, value = launch-configuration evaluations per second over the
-whole step, roofline of the dominant kernel, CPU-baseline of the oracle on a bounded sample).
+Prints ONE JSON line: value = launch-configuration evaluations per second over the whole step;
+fits/s per precision under "components"; roofline of the dominant kernel (the evaluation
+sweep); CPU baseline = the oracle timed on bounded samples of the same step, scaled to the step.
 Everything else goes to stderr.
 """
 from __future__ import annotations
@@ -26,6 +34,9 @@ METRIC = "rational fits/s + launch-config evals/s; surrogate vs plain at <=1% co
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.32 T lane-operations/s for
 # unpacked VALU instructions (packed FP32 is disabled in every kernel of this library).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+FP64_PEAK_TFLOPS = 78.6
+FIT_TOL = {0: 1e-10, 1: 1e-8, 2: 1e-8}
+FIT_MAX_ITER = 256
 
 
 def eval_ops_per_point(degree: int) -> int:
@@ -38,27 +49,46 @@ def eval_ops_per_point(degree: int) -> int:
     return 8 * (6 + 4 * degree) + 14 + 13 + 14 + 49 + 3 + 1
 
 
+def fit_flops(m, n, iters):
+    """Algorithmic FP64 flops of one fit: Gram m n (n + 1) (symmetric, with A^T f), Cholesky
+    n^3 / 3, refinement per iteration 4 m n (A t and A^T r) + 4 n^2 (two triangular solves),
+    initial residual and A^T r 4 m n + 2 n^2."""
+    return m * n * (n + 1) + n ** 3 / 3 + (iters + 1) * (4 * m * n + 4 * n * n)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pb, budget_s: float):
-    """The oracle's FP32 replay + brute-force argmin, timed on a bounded sample of the same
-    workload: whole programs' first 16384 queries x all 128 configurations, one program after
-    another until the time budget is spent."""
+def cpu_baseline(pb, fb, budget_s: float, points: int, n_fits: int):
+    """The oracle timed on bounded samples of the same step: FP32 replay + brute-force argmin
+    over whole programs' first 16384 queries x all configurations, and pivoted-QR fits over
+    the first fits of the batch, each until its share of the budget is spent; the step time
+    is scaled from the two rates."""
     import numpy as np
     from oracle import cost as oc
-    points, t0, progs = 0, time.perf_counter(), 0
+    from oracle import fit as of
+    ev_pts, t0, progs = 0, time.perf_counter(), 0
     nq = min(16384, int(pb.n_q[0]))
-    while time.perf_counter() - t0 < budget_s and progs < pb.n_progs:
+    while time.perf_counter() - t0 < 0.75 * budget_s and progs < pb.n_progs:
         c = oc.program_costs(pb, progs, query_idx=np.arange(nq))
         oc.argmin_lowest(c)
-        points += c.size
+        ev_pts += c.size
         progs += 1
-    dt = time.perf_counter() - t0
-    return {"value": points / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{progs} programs x {nq} queries x {int(pb.n_cfg[0])} configs "
-                      f"({points} points, {dt:.1f} s, numpy FP32 replay + argmin, 1 thread)"}
+    t_ev = time.perf_counter() - t0
+    t1, nf = time.perf_counter(), 0
+    while time.perf_counter() - t1 < 0.25 * budget_s and nf < fb.n_fits:
+        of.fit_batch(fb, indices=[nf])
+        nf += 1
+    t_fit = time.perf_counter() - t1
+    ev_rate, fit_rate = ev_pts / t_ev, nf / t_fit
+    step_s = n_fits / fit_rate + points / ev_rate
+    return {"value": points / step_s, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "fits_per_s": fit_rate, "evals_per_s": ev_rate,
+            "sample": f"eval: {progs} programs x {nq} queries x {int(pb.n_cfg[0])} configs "
+                      f"({ev_pts} points, {t_ev:.1f} s, numpy FP32 replay + argmin); fit: {nf} fits "
+                      f"({t_fit:.1f} s, numpy pivoted Householder QR); step time scaled from the "
+                      f"two rates to {n_fits} fits + {points} points; 1 thread"}
 
 
 def main() -> int:
@@ -67,8 +97,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=7)
-    ap.add_argument("--cpu-budget-s", type=float, default=12.0)
+    ap.add_argument("--cpu-budget-s", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-sweep", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -83,14 +114,21 @@ def main() -> int:
     lib = klr.Library.get()
     t = time.perf_counter()
     pb = synth.config3_programs(args.seed, n_progs=1024, n_q=65536)
+    fb = synth.config2_fits(args.seed, n_fits=4096, domain="2a")
     de = klr.DeviceEval.from_batch(lib, pb)
-    out = (torch.empty(de.queries.numel(), dtype=torch.int32, device="cuda"),
-           torch.empty(de.queries.numel(), dtype=torch.float32, device="cuda"), None,
-           torch.empty(de.n_progs, dtype=torch.int32, device="cuda"))
+    df = klr.DeviceFit.from_batch(fb)
+    dev = "cuda"
+    out = (torch.empty(de.queries.numel(), dtype=torch.int32, device=dev),
+           torch.empty(de.queries.numel(), dtype=torch.float32, device=dev), None,
+           torch.empty(de.n_progs, dtype=torch.int32, device=dev))
+    fit_out = (torch.empty(df.n_coef, dtype=torch.float64, device=dev),
+               torch.empty(df.n_fits * klr.FIT_INFO.itemsize, dtype=torch.uint8, device=dev))
     points = int((pb.n_cfg.astype(np.int64) * pb.n_q).sum())
-    log(f"workload ready in {time.perf_counter() - t:.1f} s: {pb.n_progs} programs, {points:.3e} points")
+    log(f"workload ready in {time.perf_counter() - t:.1f} s: {fb.n_fits} fits "
+        f"({int(fb.m.sum())} rows), {pb.n_progs} programs, {points:.3e} points")
 
     def step():
+        lib.fit_batched(df, klr.KLR_FP64, FIT_MAX_ITER, FIT_TOL[0], out=fit_out)
         lib.eval_argmin(de, out=out)
 
     for _ in range(args.warmup):
@@ -105,17 +143,48 @@ def main() -> int:
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
-    eval_ms, n_eval = lib.profile_read(klr.K_EVAL)
-    coll_ms, n_coll = lib.profile_read(klr.K_COLLAPSE)
+    kt = {k: lib.profile_read(k) for k in (klr.K_EVAL, klr.K_COLLAPSE, klr.K_FIT_SOLVE)}
     lib.profile_enable(False)
     st = out[3].cpu().numpy()
-    if not np.all(st == 0):
-        log("program status nonzero:", np.unique(st))
+    info = klr.info_records(fit_out[1])
+    if not np.all(st == 0) or np.any(info["status"] & 16):
+        log("bad status:", np.unique(st), np.unique(info["status"]))
         return 1
-    eval_avg = eval_ms / max(n_eval, 1)
+    avg = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
+    eval_avg = avg[klr.K_EVAL]
     ops = eval_ops_per_point(2)
     achieved = ops * points / (eval_avg / 1e3) / 1e12
-    log(f"step {ms:.3f} ms; eval kernel {eval_avg:.3f} ms x {n_eval}; collapse {coll_ms / max(n_coll, 1):.3f} ms")
+    n_unk = (fb.n_num + fb.n_den - 1).astype(np.float64)
+    fit_fl = float(np.sum(fit_flops(fb.m.astype(np.float64), n_unk, info["iters"].astype(np.float64))))
+    comps = {
+        "eval": {"kernel_ms": eval_avg, "collapse_ms": avg[klr.K_COLLAPSE],
+                 "evals_per_s": points / ((eval_avg + avg[klr.K_COLLAPSE]) / 1e3)},
+        "fit_fp64": {"kernel_ms": avg[klr.K_FIT_SOLVE], "fits_per_s": fb.n_fits / (avg[klr.K_FIT_SOLVE] / 1e3),
+                     "iters_mean": float(info["iters"].mean()), "iters_max": int(info["iters"].max()),
+                     "tol": FIT_TOL[0], "err_est_max": float(info["err_est"].max()),
+                     "fp64_tflops": fit_fl / (avg[klr.K_FIT_SOLVE] / 1e3) / 1e12,
+                     "fp64_frac": fit_fl / (avg[klr.K_FIT_SOLVE] / 1e3) / 1e12 / FP64_PEAK_TFLOPS},
+    }
+    log(f"step {ms:.3f} ms; eval {eval_avg:.3f} ms; collapse {avg[klr.K_COLLAPSE]:.3f} ms; "
+        f"fit {avg[klr.K_FIT_SOLVE]:.3f} ms")
+    if not args.no_precision_sweep:
+        for prec, name in ((klr.KLR_FP32_REFINED, "fit_fp32_refined"), (klr.KLR_BF16_REFINED, "fit_bf16_refined")):
+            lib.fit_batched(df, prec, FIT_MAX_ITER, FIT_TOL[prec], out=fit_out)
+            torch.cuda.synchronize()
+            lib.profile_enable(True)
+            reps = 3
+            for _ in range(reps):
+                lib.fit_batched(df, prec, FIT_MAX_ITER, FIT_TOL[prec], out=fit_out)
+            kms, kn = lib.profile_read(klr.K_FIT_SOLVE)
+            lib.profile_enable(False)
+            ir = klr.info_records(fit_out[1])
+            kavg = kms / max(kn, 1)
+            comps[name] = {"kernel_ms": kavg, "fits_per_s": fb.n_fits / (kavg / 1e3), "tol": FIT_TOL[prec],
+                           "iters_mean": float(ir["iters"].mean()), "iters_max": int(ir["iters"].max()),
+                           "fell_back_fp64": float(np.mean((ir["status"] & 8) > 0)),
+                           "err_est_max": float(ir["err_est"].max()),
+                           "speedup_vs_fp64": avg[klr.K_FIT_SOLVE] / kavg}
+            log(f"{name}: {kavg:.3f} ms, iters mean {ir['iters'].mean():.1f}")
 
     res = {
         "metric": METRIC,
@@ -124,18 +193,21 @@ def main() -> int:
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic (seeded)",
-        "config": {"workload": "eval/argmin: 1024 rational programs x 65536 queries x 128 launch "
-                               "configs, 8 degree-2 fitted metrics each, MWP-CWP-style cycle estimate",
+        "dtype": "f32 eval / f64 fit", "data": "synthetic (seeded)",
+        "config": {"workload": "fit 4096 uneven degree-3 rational fits over (N, bx, by) + eval/argmin "
+                               "of 1024 rational programs x 65536 queries x 128 launch configs",
+                   "fits": int(fb.n_fits), "fit_rows": int(fb.m.sum()), "unknowns": 39,
                    "programs": int(pb.n_progs), "queries_per_program": 65536, "configs": 128,
                    "points": points},
-        "components": {"eval_kernel_ms": eval_avg, "collapse_kernel_ms": coll_ms / max(n_coll, 1)},
+        "fits_per_s": comps["fit_fp64"]["fits_per_s"],
+        "evals_per_s": comps["eval"]["evals_per_s"],
+        "components": comps,
         "roofline": {"bound": "alu", "kernel": "eval_kernel", "achieved": achieved,
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
                      "ops_per_point": ops, "traffic": None},
     }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(pb, args.cpu_budget_s)
+        res["cpu_baseline"] = cpu_baseline(pb, fb, args.cpu_budget_s, points, fb.n_fits)
     print(json.dumps(res), flush=True)
     return 0
 
