@@ -205,6 +205,78 @@ klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_pro
                            void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Learned surrogate (not in the paper): one network shared by all kernels (programs),
+ * conditioned on a learned scalar embedding e_k per kernel, predicting standardised log-cycles:
+ *   x = (log2 N / 26, log2 bx / 10, log2 by / 10, e_k); h1 = relu(W1 x + b1) [256];
+ *   h2 = relu(W2 h1 + b2) [256]; y = w3 . h2 + b3;  ln C ~ mu + sigma y.
+ * The 256 x 256 layer runs on BF16 MFMA (BF16 weights and activations, FP32 accumulation);
+ * layers 1 and 3 run in FP32.  FP32 master weights, Adam moments in FP32.
+ *
+ * Parameter blob (caller-owned device memory of klr_surrogate_param_bytes(n_kernels) bytes):
+ *   float hdr[16]      : hdr[0] = mu, hdr[1] = sigma (set by klr_surrogate_train)
+ *   float P[NP], M[NP], V[NP]: parameters, Adam first and second moments, each laid out as
+ *                        W2[256][256] | W1[256][4] | b1[256] | b2[256] | w3[256] | b3 | pad(15)
+ *                        | emb[n_kernels] | pad to a multiple of 64 floats (NP)
+ *   bf16 W2b[256][256], W2Tb[256][256]: working copies of W2 and its transpose
+ * klr_surrogate_layout returns these offsets for bindings. */
+#define KLR_MLP_HIDDEN 256
+#define KLR_MLP_IN 4
+
+typedef struct {
+  float lr;               /* peak learning rate (cosine decay to 0 over all steps)             */
+  float beta1, beta2, eps;
+  int32_t batch;          /* samples per step, multiple of 128, 128..65536                      */
+  int32_t epochs;         /* full passes; each pass visits floor(n / batch) batches             */
+  uint64_t seed;          /* seeds the per-epoch sample permutation                             */
+} klr_train_cfg;
+
+size_t klr_surrogate_param_bytes(int32_t n_kernels);
+/* Write the BF16 working copies (W2b, W2Tb) from P; call after filling P from the host. */
+klr_status klr_surrogate_init(klr_handle h, void* params, int32_t n_kernels, void* stream);
+/* [host] writes up to n of {NP, P offset, M offset, V offset (floats), W2b offset, W2Tb offset,
+ * total (bytes), offsets of W2, W1, b1, b2, w3, b3, emb inside P (floats)}; returns the count. */
+int32_t klr_surrogate_layout(int32_t n_kernels, int64_t* out, int32_t n);
+/* Workspace bytes of klr_surrogate_train for this batch size and kernel count. */
+size_t klr_surrogate_train_workspace(int32_t n_kernels, int32_t batch);
+/* Train on n samples (sample i: kernel kernel_id[i] in [0, n_kernels), data size N[i] >= 1,
+ * launch (launch[2i], launch[2i+1]) >= 1, exact cost cost[i] > 0; samples whose cost is not
+ * finite and positive get zero weight).  mu, sigma of ln cost are computed first and stored in
+ * the blob; params must hold initial P with zero M and V.  loss_per_epoch[epochs] (device, out):
+ * mean training loss of each epoch on the standardised scale. */
+klr_status klr_surrogate_train(klr_handle h, void* params, int32_t n_kernels,
+                               const int32_t* kernel_id, const int32_t* N, const int32_t* launch,
+                               const float* cost, int64_t n, const klr_train_cfg* cfg /*[host]*/,
+                               float* loss_per_epoch, void* ws, size_t ws_bytes, void* stream);
+/* Forward pass only: pred[i] = mu + sigma y(sample i) for n samples (ln C predictions). */
+klr_status klr_surrogate_predict(klr_handle h, const void* params, int32_t n_kernels,
+                                 const int32_t* kernel_id, const int32_t* N, const int32_t* launch,
+                                 int64_t n, float* pred, void* stream);
+/* One training step on one batch without the permutation (samples [0, batch) in order), for
+ * gradient checks: writes the mean loss and, when grads != NULL, the gradient of every
+ * parameter in the P layout (float[NP]) before applying Adam with (lr, step). */
+klr_status klr_surrogate_step(klr_handle h, void* params, int32_t n_kernels,
+                              const int32_t* kernel_id, const int32_t* N, const int32_t* launch,
+                              const float* target_std, int32_t batch, float lr, int32_t step,
+                              float beta1, float beta2, float eps, float* grads, float* loss,
+                              void* ws, size_t ws_bytes, void* stream);
+/* Surrogate selection over the same programs, configurations and queries as klr_eval_argmin:
+ * program p uses embedding p (p < n_kernels).  For each query the network predicts ln C of
+ * every statically admissible configuration (T <= t_max, T % wave == 0, every L <= N); the
+ * pick is the lowest prediction (lowest index on ties).  If the predicted margin to the second
+ * best is below ln(1 + margin), the query falls back to the exact rational program
+ * (klr_eval_argmin semantics) and fell_back[q] = 1.  pred_cost[q] = exp(predicted ln C) of the
+ * pick, or the exact cost on fallback.  Needs klr_surrogate_eval_workspace bytes. */
+size_t klr_surrogate_eval_workspace(int32_t n_progs, int32_t max_cfg, int64_t q_len);
+klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernels,
+                              const klr_program* progs, int32_t n_progs, int32_t max_cfg,
+                              int32_t max_q, const klr_hw* hw, const klr_fit_desc* desc,
+                              int32_t n_fits, const uint8_t* exps, int32_t n_exp_rows,
+                              const double* coef, int64_t coef_len, const int32_t* cfgs,
+                              int64_t cfgs_len, const int32_t* queries, int64_t q_len,
+                              float margin, int32_t* argmin, float* pred_cost, uint8_t* fell_back,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------------
  * Kernel timing.  When enabled on a handle, every kernel the handle launches is bracketed by a
  * pair of HIP events recorded on the caller's stream (so the elapsed time is the kernel's own,
  * on the stream it runs on).  klr_profile_read synchronises the recorded events, returns the
@@ -214,8 +286,10 @@ klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_pro
 #define KLR_K_EVAL 1           /* evaluation + argmin sweep                                    */
 #define KLR_K_FIT_GRAM 2       /* fit: design matrix + Gram                                    */
 #define KLR_K_FIT_SOLVE 3      /* fit: factorisation + refinement + epilogue                   */
-#define KLR_K_MLP 4            /* surrogate network kernels                                    */
-#define KLR_K_COUNT 5
+#define KLR_K_MLP 4            /* surrogate network training kernels                           */
+#define KLR_K_SURR 5           /* surrogate selection (forward over the query x config grid)   */
+#define KLR_K_FALLBACK 6       /* compaction + exact re-evaluation of low-margin queries       */
+#define KLR_K_COUNT 7
 klr_status klr_profile_enable(klr_handle h, int32_t on);   /* on != 0: enable; 0: disable+reset */
 klr_status klr_profile_read(klr_handle h, int32_t kind, double* total_ms, int64_t* launches);
 

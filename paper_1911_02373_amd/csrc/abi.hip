@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -208,6 +209,219 @@ klr_status klr_fit_batched(klr_handle h, const klr_fit_desc* desc, int32_t n_fit
   klr::FitArgs a{desc, n_fits, exps, n_exp_rows, X, x_len, f, f_len, precision, max_iter, tol,
                  coef, coef_len, info, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream), &h->timer};
   return klr::hip_check(h, klr::launch_fit(a), "klr_fit_batched launch");
+}
+
+size_t klr_surrogate_param_bytes(int32_t n_kernels) {
+  return n_kernels < 0 ? 0 : klr::mlp_param_bytes(n_kernels);
+}
+
+klr_status klr_surrogate_init(klr_handle h, void* params, int32_t n_kernels, void* stream) {
+  if (!h) return KLR_E_INVALID;
+  h->err.clear();
+  if (!params || n_kernels < 1) return fail(h, KLR_E_INVALID, "bad arguments");
+  if (reinterpret_cast<uintptr_t>(params) % 256 != 0) return fail(h, KLR_E_INVALID, "params must be 256-byte aligned");
+  return klr::hip_check(h, klr::launch_refresh(klr::blob_of(params, n_kernels), reinterpret_cast<hipStream_t>(stream)),
+                        "klr_surrogate_init");
+}
+
+int32_t klr_surrogate_layout(int32_t n_kernels, int64_t* out, int32_t n) {
+  const int64_t np = klr::mlp_np(n_kernels);
+  const int64_t v[] = {np, 16, 16 + np, 16 + 2 * np, (16 + 3 * np) * 4,
+                       (16 + 3 * np) * 4 + 2 * KLR_MLP_HIDDEN * KLR_MLP_HIDDEN,
+                       (int64_t)klr::mlp_param_bytes(n_kernels), klr::kO_W2, klr::kO_W1, klr::kO_B1,
+                       klr::kO_B2, klr::kO_W3, klr::kO_B3, klr::kO_EMB};
+  const int32_t cnt = (int32_t)(sizeof(v) / sizeof(v[0]));
+  for (int32_t i = 0; i < n && i < cnt; ++i) out[i] = v[i];
+  return cnt;
+}
+
+size_t klr_surrogate_train_workspace(int32_t n_kernels, int32_t batch) {
+  if (n_kernels < 0 || batch <= 0) return 0;
+  return klr::mlp_train_ws_bytes(n_kernels, batch);
+}
+
+}  // extern "C"
+
+namespace klr {
+
+size_t mlp_train_ws_bytes(int32_t nk, int32_t B) {
+  const size_t t = (size_t)KLR_MLP_HIDDEN * B * sizeof(uint16_t);
+  const size_t part = (size_t)(B / 64) * kPartialStride * sizeof(float);
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  return 2 * al(t) + al(part) + al((size_t)nk * 8) + 256;
+}
+
+namespace {
+
+TrainTile tile_args(void* ws, int32_t nk, int32_t B) {
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  char* c = reinterpret_cast<char*>(ws);
+  const size_t t = (size_t)KLR_MLP_HIDDEN * B * sizeof(uint16_t);
+  TrainTile tt{};
+  tt.H1T = reinterpret_cast<uint16_t*>(c);
+  tt.dH2T = reinterpret_cast<uint16_t*>(c + al(t));
+  tt.partial = reinterpret_cast<float*>(c + 2 * al(t));
+  tt.emb_acc = reinterpret_cast<unsigned long long*>(c + 2 * al(t) + al((size_t)(B / 64) * kPartialStride * 4));
+  tt.B = B;
+  tt.nk = nk;
+  return tt;
+}
+
+float* loss_slot(void* ws, int32_t nk, int32_t B) {
+  return reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + mlp_train_ws_bytes(nk, B) - 256);
+}
+
+AdamArgs adam_args(float lr, float b1, float b2, float eps, int64_t step) {
+  AdamArgs a{lr, b1, b2, eps, (float)(1.0 - std::pow((double)b1, (double)step)),
+             (float)(1.0 - std::pow((double)b2, (double)step))};
+  return a;
+}
+
+bool batch_ok(int32_t B) { return B >= 128 && B <= 65536 && B % 128 == 0; }
+
+}  // namespace
+}  // namespace klr
+
+extern "C" {
+
+klr_status klr_surrogate_train(klr_handle h, void* params, int32_t n_kernels,
+                               const int32_t* kernel_id, const int32_t* N, const int32_t* launch,
+                               const float* cost, int64_t n, const klr_train_cfg* cfg,
+                               float* loss_per_epoch, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return KLR_E_INVALID;
+  h->err.clear();
+  if (!cfg || !params || n_kernels < 1 || n < 0) return fail(h, KLR_E_INVALID, "bad arguments");
+  if (!klr::batch_ok(cfg->batch)) return fail(h, KLR_E_INVALID, "batch must be a multiple of 128 in [128, 65536]");
+  if (cfg->epochs < 0 || !(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
+      !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f))
+    return fail(h, KLR_E_INVALID, "bad optimiser settings");
+  if (n > 0 && (!kernel_id || !N || !launch || !cost)) return fail(h, KLR_E_INVALID, "NULL sample array");
+  if (cfg->epochs > 0 && !loss_per_epoch) return fail(h, KLR_E_INVALID, "loss_per_epoch is NULL");
+  const size_t need = klr::mlp_train_ws_bytes(n_kernels, cfg->batch);
+  if (!ws || ws_bytes < need) return fail(h, KLR_E_WORKSPACE, "workspace too small: need " + std::to_string(need));
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0 || reinterpret_cast<uintptr_t>(params) % 256 != 0)
+    return fail(h, KLR_E_INVALID, "params and workspace must be 256-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  klr::Blob w = klr::blob_of(params, n_kernels);
+  klr::TrainTile t = klr::tile_args(ws, n_kernels, cfg->batch);
+  t.kid = kernel_id; t.N = N; t.L = launch; t.cost = cost; t.tstd = nullptr; t.n = n;
+  int bits = 1;
+  while (bits < 62 && (int64_t(1) << bits) < n) ++bits;
+  t.perm_bits = bits;
+  const int64_t nb = n / cfg->batch;
+  const int64_t total = nb * cfg->epochs;
+  const int tm = h->timer.begin(KLR_K_MLP, s);
+  hipError_t e = klr::launch_stats(cost, n, w.hdr, s);
+  if (e == hipSuccess) e = klr::launch_refresh(w, s);
+  if (e == hipSuccess) e = hipMemsetAsync(t.emb_acc, 0, (size_t)n_kernels * 8, s);
+  if (e == hipSuccess && cfg->epochs > 0) e = hipMemsetAsync(loss_per_epoch, 0, (size_t)cfg->epochs * 4, s);
+  int64_t step = 0;
+  for (int ep = 0; ep < cfg->epochs && e == hipSuccess; ++ep) {
+    uint64_t z = cfg->seed * 0x9E3779B97F4A7C15ull + (uint64_t)ep * 0xD1B54A32D192ED03ull + 0x1234567ull;
+    t.perm_key = z;
+    for (int64_t b = 0; b < nb && e == hipSuccess; ++b) {
+      ++step;
+      const double prog = total > 1 ? (double)(step - 1) / (double)(total - 1) : 0.0;
+      const float lr = (float)(cfg->lr * 0.5 * (1.0 + std::cos(3.14159265358979323846 * prog)));
+      t.batch_start = b * cfg->batch;
+      e = klr::launch_train_step(t, w, klr::adam_args(lr, cfg->beta1, cfg->beta2, cfg->eps, step), nullptr,
+                                 nullptr, loss_per_epoch + ep, 1.0f / (float)nb, s);
+    }
+  }
+  h->timer.end(tm, s);
+  return klr::hip_check(h, e, "klr_surrogate_train");
+}
+
+klr_status klr_surrogate_predict(klr_handle h, const void* params, int32_t n_kernels,
+                                 const int32_t* kernel_id, const int32_t* N, const int32_t* launch,
+                                 int64_t n, float* pred, void* stream) {
+  if (!h) return KLR_E_INVALID;
+  h->err.clear();
+  if (!params || n_kernels < 1 || n < 0) return fail(h, KLR_E_INVALID, "bad arguments");
+  if (n == 0) return KLR_OK;
+  if (!kernel_id || !N || !launch || !pred) return fail(h, KLR_E_INVALID, "NULL array");
+  if ((n + 63) / 64 >= (int64_t(1) << 31)) return fail(h, KLR_E_UNSUPPORTED, "too many samples");
+  klr::Blob w = klr::blob_of(const_cast<void*>(params), n_kernels);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return klr::hip_check(h, klr::launch_predict(kernel_id, N, launch, n, n_kernels, w, pred, s),
+                        "klr_surrogate_predict");
+}
+
+klr_status klr_surrogate_step(klr_handle h, void* params, int32_t n_kernels,
+                              const int32_t* kernel_id, const int32_t* N, const int32_t* launch,
+                              const float* target_std, int32_t batch, float lr, int32_t step,
+                              float beta1, float beta2, float eps, float* grads, float* loss,
+                              void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return KLR_E_INVALID;
+  h->err.clear();
+  if (!params || n_kernels < 1 || !klr::batch_ok(batch) || step < 1 || !kernel_id || !N || !launch ||
+      !target_std)
+    return fail(h, KLR_E_INVALID, "bad arguments (batch must be a multiple of 128, step >= 1)");
+  const size_t need = klr::mlp_train_ws_bytes(n_kernels, batch);
+  if (!ws || ws_bytes < need) return fail(h, KLR_E_WORKSPACE, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0 || reinterpret_cast<uintptr_t>(params) % 256 != 0)
+    return fail(h, KLR_E_INVALID, "params and workspace must be 256-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  klr::Blob w = klr::blob_of(params, n_kernels);
+  klr::TrainTile t = klr::tile_args(ws, n_kernels, batch);
+  t.kid = kernel_id; t.N = N; t.L = launch; t.cost = nullptr; t.tstd = target_std; t.n = batch;
+  t.perm_bits = 0; t.batch_start = 0;
+  float* ls = loss ? loss : klr::loss_slot(ws, n_kernels, batch);
+  hipError_t e = klr::launch_refresh(w, s);
+  if (e == hipSuccess) e = hipMemsetAsync(t.emb_acc, 0, (size_t)n_kernels * 8, s);
+  if (e == hipSuccess)
+    e = klr::launch_train_step(t, w, klr::adam_args(lr, beta1, beta2, eps, step), grads, ls, nullptr, 0.0f, s);
+  return klr::hip_check(h, e, "klr_surrogate_step");
+}
+
+size_t klr_surrogate_eval_workspace(int32_t n_progs, int32_t max_cfg, int64_t q_len) {
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  return al(klr::eval_workspace_bytes(n_progs, max_cfg)) + al(klr::fallback_ws_bytes(n_progs, q_len));
+}
+
+klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernels,
+                              const klr_program* progs, int32_t n_progs, int32_t max_cfg,
+                              int32_t max_q, const klr_hw* hw, const klr_fit_desc* desc,
+                              int32_t n_fits, const uint8_t* exps, int32_t n_exp_rows,
+                              const double* coef, int64_t coef_len, const int32_t* cfgs,
+                              int64_t cfgs_len, const int32_t* queries, int64_t q_len,
+                              float margin, int32_t* argmin, float* pred_cost, uint8_t* fell_back,
+                              void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return KLR_E_INVALID;
+  h->err.clear();
+  if (!hw) return fail(h, KLR_E_INVALID, "hw is NULL");
+  std::string why;
+  if (!klr::hw_ok(*hw, why)) return fail(h, KLR_E_INVALID, why);
+  if (!params || n_kernels < 1 || n_progs < 0 || max_cfg < 0 || max_q < 0 || q_len < 0 || cfgs_len < 0 ||
+      coef_len < 0 || n_fits < 0 || n_exp_rows < 0 || !(margin >= 0.0f))
+    return fail(h, KLR_E_INVALID, "bad arguments");
+  if (n_progs == 0) return KLR_OK;
+  if (max_cfg > 65536) return fail(h, KLR_E_UNSUPPORTED, "max_cfg above 65536");
+  if (!progs || !desc || !exps || !coef || !cfgs || !queries || !argmin || !pred_cost || !fell_back)
+    return fail(h, KLR_E_INVALID, "NULL array argument");
+  const size_t need = klr_surrogate_eval_workspace(n_progs, max_cfg, q_len);
+  if (!ws || ws_bytes < need) return fail(h, KLR_E_WORKSPACE, "workspace too small: need " + std::to_string(need));
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0 || reinterpret_cast<uintptr_t>(params) % 256 != 0)
+    return fail(h, KLR_E_INVALID, "params and workspace must be 256-byte aligned");
+  const int64_t items = (int64_t)n_progs * (((int64_t)max_q + 255) / 256) * 256;
+  const int64_t items_c = (int64_t)n_progs * (((int64_t)max_cfg + 127) / 128) * 128;
+  if (items >= (int64_t(1) << 32) || items_c >= (int64_t(1) << 32))
+    return fail(h, KLR_E_UNSUPPORTED, "launch grid above 2^32 work-items; split the batch");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  klr::Blob w = klr::blob_of(const_cast<void*>(params), n_kernels);
+  klr::SelectArgs sa{progs, n_progs, max_cfg, max_q, n_kernels, hw->t_max, hw->wave, cfgs, cfgs_len,
+                     queries, q_len, margin, argmin, pred_cost, fell_back};
+  const int t0 = h->timer.begin(KLR_K_SURR, s);
+  hipError_t e = klr::launch_select(sa, w, s);
+  h->timer.end(t0, s);
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t ews = klr::eval_workspace_bytes(n_progs, max_cfg);
+  klr::EvalArgs a{progs, n_progs, max_cfg, max_q, *hw, desc, n_fits, exps, n_exp_rows, coef, coef_len,
+                  cfgs, cfgs_len, queries, q_len, argmin, pred_cost, nullptr, 0, nullptr, ws, ews, s,
+                  &h->timer};
+  if (e == hipSuccess) e = klr::launch_collapse_only(a);
+  if (e == hipSuccess) e = klr::launch_fallback(a, fell_back, pred_cost, reinterpret_cast<char*>(ws) + al(ews));
+  return klr::hip_check(h, e, "klr_surrogate_eval");
 }
 
 }  // extern "C"

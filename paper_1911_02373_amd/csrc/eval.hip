@@ -280,14 +280,13 @@ struct SweepOut {
   float* __restrict__ all_costs;
 };
 
-// One lane per query; all control flow is wave-uniform (lanes past n_q compute a clamped query
-// and skip only the stores), so the per-configuration terms are scalar loads.
+// One lane per query; all control flow is wave-uniform (lanes without a query compute a
+// clamped one and skip only the stores), so the per-configuration terms are scalar loads.
 template <int GRID>
 __device__ __forceinline__ void sweep(const float* __restrict__ slot0, const CfgRec* __restrict__ rec0,
                                       const int32_t* __restrict__ queries, const SweepOut& o,
-                                      const Hw32& hw, const klr_program& P, int qi) {
-  const bool live = qi < P.n_q;
-  const int32_t N = queries[P.q0 + (live ? qi : P.n_q - 1)];
+                                      const Hw32& hw, const klr_program& P, int qi, bool live) {
+  const int32_t N = queries[P.q0 + qi];
   float best = INFINITY;
   int32_t bi = -1;
   float* costs = o.all_costs ? o.all_costs + P.cost0 + qi : nullptr;
@@ -317,10 +316,97 @@ eval_kernel(const klr_program* __restrict__ progs, const float* __restrict__ coe
   const CfgRec* rec0 = recs + (int64_t)p * a.max_cfg;
   const SweepOut o{argmin, best_cost, all_costs};
   const int qi = qb + (int)threadIdx.x;
+  const bool live = qi < P.n_q;
+  const int qc = live ? qi : P.n_q - 1;
   if (P.grid_kind == KLR_GRID_1D)
-    sweep<KLR_GRID_1D>(slot0, rec0, queries, o, hw, P, qi);
+    sweep<KLR_GRID_1D>(slot0, rec0, queries, o, hw, P, qc, live);
   else
-    sweep<KLR_GRID_2D>(slot0, rec0, queries, o, hw, P, qi);
+    sweep<KLR_GRID_2D>(slot0, rec0, queries, o, hw, P, qc, live);
+}
+
+// ---- exact re-evaluation of flagged queries --------------------------------------------------
+// fb_count: flagged queries per program; fb_scan: exclusive offsets of queries and of 256-query
+// chunks; fb_compact: order-preserving list of flagged query indices per program; fb_exact: one
+// workgroup per chunk, the exact sweep over the listed queries (all lanes of a workgroup belong
+// to one program, so the configuration loop stays wave-uniform).
+__global__ void __launch_bounds__(kEvalBlock)
+fb_count(EvalArgs a, const uint8_t* __restrict__ flags, int32_t* cnt) {
+  __shared__ int red[kEvalBlock / 64];
+  const int p = blockIdx.x;
+  const klr_program P = a.progs[p];
+  int c = 0;
+  if (program_desc_ok(P, a))
+    for (int qi = threadIdx.x; qi < P.n_q; qi += kEvalBlock) c += flags[P.q0 + qi] != 0 ? 1 : 0;
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[p] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void fb_scan(int32_t n_progs, const int32_t* __restrict__ cnt, int32_t* off, int32_t* choff,
+                        int32_t* total) {
+  if (threadIdx.x != 0) return;
+  int32_t o = 0, ch = 0;
+  for (int p = 0; p < n_progs; ++p) {
+    off[p] = o;
+    choff[p] = ch;
+    o += cnt[p];
+    ch += (cnt[p] + kEvalBlock - 1) / kEvalBlock;
+  }
+  *total = ch;
+}
+
+__global__ void __launch_bounds__(kEvalBlock)
+fb_compact(EvalArgs a, const uint8_t* __restrict__ flags, const int32_t* __restrict__ off, int32_t* list) {
+  __shared__ int wsum[kEvalBlock / 64];
+  const int p = blockIdx.x;
+  const klr_program P = a.progs[p];
+  if (!program_desc_ok(P, a)) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int running = off[p];
+  for (int q0 = 0; q0 < P.n_q; q0 += kEvalBlock) {
+    const int qi = q0 + (int)threadIdx.x;
+    const bool f = qi < P.n_q && flags[P.q0 + qi] != 0;
+    const unsigned long long m = __ballot(f);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wv] = __popcll(m);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    if (f) list[running + before + rank] = qi;
+    running += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kEvalBlock)
+fb_exact(const klr_program* __restrict__ progs, const float* __restrict__ coefs,
+         const CfgRec* __restrict__ recs, const int32_t* __restrict__ queries,
+         int32_t* __restrict__ argmin, float* __restrict__ best_cost, EvalArgs a, Hw32 hw,
+         const int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
+         const int32_t* __restrict__ choff, const int32_t* __restrict__ total,
+         const int32_t* __restrict__ list) {
+  const int b = blockIdx.x;
+  if (b >= *total) return;
+  int lo = 0, hi = a.n_progs - 1;          // last p with choff[p] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (choff[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const int p = lo;
+  const klr_program P = progs[p];
+  if (!program_desc_ok(P, a)) return;
+  const int n = cnt[p];
+  const int li = (b - choff[p]) * kEvalBlock + (int)threadIdx.x;
+  const bool live = li < n;
+  const int qi = list[off[p] + (live ? li : n - 1)];
+  const float* slot0 = coefs + (int64_t)p * a.max_cfg * kSlotFloats;
+  const CfgRec* rec0 = recs + (int64_t)p * a.max_cfg;
+  const SweepOut o{argmin, best_cost, nullptr};
+  if (P.grid_kind == KLR_GRID_1D)
+    sweep<KLR_GRID_1D>(slot0, rec0, queries, o, hw, P, qi, live);
+  else
+    sweep<KLR_GRID_2D>(slot0, rec0, queries, o, hw, P, qi, live);
 }
 
 }  // namespace
@@ -328,6 +414,51 @@ eval_kernel(const klr_program* __restrict__ progs, const float* __restrict__ coe
 size_t eval_workspace_bytes(int32_t n_progs, int32_t max_cfg) {
   const size_t slots = (size_t)(n_progs > 0 ? n_progs : 0) * (size_t)(max_cfg > 0 ? max_cfg : 0);
   return slots * (kSlotFloats * sizeof(float) + sizeof(CfgRec));
+}
+
+hipError_t launch_collapse_only(const EvalArgs& a) {
+  const int cchunks = a.max_cfg > 0 ? (a.max_cfg + kCollapseBlock - 1) / kCollapseBlock : 1;
+  int t = a.timer ? a.timer->begin(KLR_K_COLLAPSE, a.stream) : -1;
+  hipLaunchKernelGGL(collapse_kernel, dim3((unsigned)a.n_progs * cchunks), dim3(kCollapseBlock), 0,
+                     a.stream, a, cchunks);
+  if (a.timer) a.timer->end(t, a.stream);
+  return hipGetLastError();
+}
+
+size_t fallback_ws_bytes(int32_t n_progs, int64_t q_len) {
+  return ((size_t)3 * (n_progs > 0 ? n_progs : 0) + 64 + (size_t)(q_len > 0 ? q_len : 0)) * sizeof(int32_t);
+}
+
+hipError_t launch_fallback(const EvalArgs& a, const uint8_t* flags, float* best_cost, void* fws) {
+  int32_t* cnt = reinterpret_cast<int32_t*>(fws);
+  int32_t* off = cnt + a.n_progs;
+  int32_t* choff = off + a.n_progs;
+  int32_t* total = choff + a.n_progs;
+  int32_t* list = total + 64;
+  int t = a.timer ? a.timer->begin(KLR_K_FALLBACK, a.stream) : -1;
+  hipLaunchKernelGGL(fb_count, dim3((unsigned)a.n_progs), dim3(kEvalBlock), 0, a.stream, a, flags, cnt);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(fb_scan, dim3(1), dim3(64), 0, a.stream, a.n_progs, cnt, off, choff, total);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(fb_compact, dim3((unsigned)a.n_progs), dim3(kEvalBlock), 0, a.stream, a, flags, off, list);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && a.max_q > 0) {
+    Hw32 hw{a.hw.n_cu, a.hw.wave, a.hw.w_max, a.hw.b_max, a.hw.z_max,
+            a.hw.mem_lat, a.hw.dep_delay, a.hw.issue_cycles, a.hw.bw};
+    const float* coefs = reinterpret_cast<const float*>(a.ws);
+    const CfgRec* recs = reinterpret_cast<const CfgRec*>(
+        reinterpret_cast<const char*>(a.ws) + (int64_t)a.n_progs * a.max_cfg * kSlotFloats * sizeof(float));
+    const unsigned grid = (unsigned)a.n_progs * ((a.max_q + kEvalBlock - 1) / kEvalBlock);
+    hipLaunchKernelGGL(fb_exact, dim3(grid), dim3(kEvalBlock), 0, a.stream, a.progs, coefs, recs, a.queries,
+                       a.argmin, best_cost, a, hw, cnt, off, choff, total, list);
+    e = hipGetLastError();
+  }
+  if (a.timer) a.timer->end(t, a.stream);
+  return e;
 }
 
 hipError_t launch_eval(const EvalArgs& a) {

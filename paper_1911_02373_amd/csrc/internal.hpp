@@ -96,4 +96,83 @@ struct FitArgs {
 size_t fit_workspace_bytes(int32_t n_fits, int64_t f_len, int32_t precision);
 hipError_t launch_fit(const FitArgs& a);
 
+// ---- surrogate network ----------------------------------------------------------------------
+// Parameter vector layout (floats): W2[256][256] | W1[256][4] | b1 | b2 | w3 | b3 | pad | emb.
+constexpr int kO_W2 = 0;
+constexpr int kO_W1 = KLR_MLP_HIDDEN * KLR_MLP_HIDDEN;
+constexpr int kO_B1 = kO_W1 + KLR_MLP_HIDDEN * KLR_MLP_IN;
+constexpr int kO_B2 = kO_B1 + KLR_MLP_HIDDEN;
+constexpr int kO_W3 = kO_B2 + KLR_MLP_HIDDEN;
+constexpr int kO_B3 = kO_W3 + KLR_MLP_HIDDEN;
+constexpr int kO_EMB = kO_B3 + 16;
+constexpr int kLossSlot = kO_B3 - kO_W1 + 1;          // per-tile partial row: small grads, loss
+constexpr int kPartialStride = kO_EMB - kO_W1;
+inline int64_t mlp_np(int32_t nk) { return ((int64_t)kO_EMB + nk + 63) / 64 * 64; }
+inline size_t mlp_param_bytes(int32_t nk) {
+  return (size_t)(16 + 3 * mlp_np(nk)) * sizeof(float) +
+         (size_t)2 * KLR_MLP_HIDDEN * KLR_MLP_HIDDEN * sizeof(uint16_t);
+}
+
+struct Blob {
+  float* hdr;
+  float* P;
+  float* M;
+  float* V;
+  uint16_t* W2b;
+  uint16_t* W2Tb;
+};
+Blob blob_of(void* base, int32_t nk);
+
+struct AdamArgs {
+  float lr, b1, b2, eps, bc1, bc2;   // bc = 1 - beta^step
+};
+
+struct TrainTile {
+  const int32_t* kid;
+  const int32_t* N;
+  const int32_t* L;
+  const float* cost;       // exact costs (ln taken in the kernel), or
+  const float* tstd;       // standardised targets (when non-null)
+  int64_t n;
+  int32_t B;
+  int64_t batch_start;     // position of the batch in the epoch order
+  uint64_t perm_key;
+  int32_t perm_bits;       // 0: no permutation (samples in order)
+  int32_t nk;
+  uint16_t* H1T;           // [256][B] bf16
+  uint16_t* dH2T;          // [256][B] bf16
+  float* partial;          // [B / 64][kPartialStride]
+  unsigned long long* emb_acc;   // [nk] fixed point 2^-44
+};
+size_t mlp_train_ws_bytes(int32_t nk, int32_t B);
+
+struct SelectArgs {
+  const klr_program* progs;
+  int32_t n_progs, max_cfg, max_q, nk;
+  int32_t t_max, wave;
+  const int32_t* cfgs;
+  int64_t cfgs_len;
+  const int32_t* queries;
+  int64_t q_len;
+  float margin;
+  int32_t* argmin;
+  float* pred_cost;
+  uint8_t* fell_back;
+};
+
+hipError_t launch_refresh(const Blob& w, hipStream_t s);
+hipError_t launch_stats(const float* cost, int64_t n, float* hdr, hipStream_t s);
+hipError_t launch_train_step(const TrainTile& t, const Blob& w, const AdamArgs& ad, float* grads,
+                             float* loss_step, float* loss_epoch, float epoch_scale, hipStream_t s);
+hipError_t launch_predict(const int32_t* kid, const int32_t* N, const int32_t* L, int64_t n, int32_t nk,
+                          const Blob& w, float* pred, hipStream_t s);
+hipError_t launch_select(const SelectArgs& a, const Blob& w, hipStream_t s);
+
+// Exact re-evaluation of the queries flagged by the surrogate (compaction by program, then the
+// exact sweep over the compacted list); the collapse workspace must already hold the program
+// coefficients (launch_eval's collapse).  Workspace beyond eval_workspace_bytes:
+size_t fallback_ws_bytes(int32_t n_progs, int64_t q_len);
+hipError_t launch_fallback(const EvalArgs& a, const uint8_t* flags, float* best_cost, void* fws);
+hipError_t launch_collapse_only(const EvalArgs& a);
+
 }  // namespace klr

@@ -35,8 +35,14 @@ PROGRAM = np.dtype([("cfg0", "<i8"), ("q0", "<i8"), ("cost0", "<i8"), ("fit0", "
 
 EXPORTS = ("klr_create", "klr_destroy", "klr_last_error", "klr_fit_workspace", "klr_fit_batched",
            "klr_eval_workspace", "klr_eval_argmin", "klr_abi_layout", "klr_profile_enable",
-           "klr_profile_read")
-K_COLLAPSE, K_EVAL, K_FIT_GRAM, K_FIT_SOLVE, K_MLP = 0, 1, 2, 3, 4
+           "klr_profile_read", "klr_surrogate_param_bytes", "klr_surrogate_layout",
+           "klr_surrogate_train_workspace", "klr_surrogate_train", "klr_surrogate_predict",
+           "klr_surrogate_step", "klr_surrogate_eval_workspace", "klr_surrogate_eval",
+           "klr_surrogate_init")
+K_COLLAPSE, K_EVAL, K_FIT_GRAM, K_FIT_SOLVE, K_MLP, K_SURR, K_FALLBACK = 0, 1, 2, 3, 4, 5, 6
+TRAIN_CFG = np.dtype([("lr", "<f4"), ("beta1", "<f4"), ("beta2", "<f4"), ("eps", "<f4"),
+                      ("batch", "<i4"), ("epochs", "<i4"), ("seed", "<u8")])
+MLP_PARAMS = ("W2", "W1", "b1", "b2", "w3", "b3", "emb")
 
 
 class KlrError(RuntimeError):
@@ -72,7 +78,76 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.klr_profile_enable.restype = I32
     lib.klr_profile_read.argtypes = [P, I32, ctypes.POINTER(D), ctypes.POINTER(I64)]
     lib.klr_profile_read.restype = I32
+    F = ctypes.c_float
+    lib.klr_surrogate_param_bytes.argtypes = [I32]
+    lib.klr_surrogate_param_bytes.restype = SZ
+    lib.klr_surrogate_init.argtypes = [P, P, I32, P]
+    lib.klr_surrogate_init.restype = I32
+    lib.klr_surrogate_layout.argtypes = [I32, ctypes.POINTER(I64), I32]
+    lib.klr_surrogate_layout.restype = I32
+    lib.klr_surrogate_train_workspace.argtypes = [I32, I32]
+    lib.klr_surrogate_train_workspace.restype = SZ
+    lib.klr_surrogate_train.argtypes = [P, P, I32, P, P, P, P, I64, P, P, P, SZ, P]
+    lib.klr_surrogate_train.restype = I32
+    lib.klr_surrogate_predict.argtypes = [P, P, I32, P, P, P, I64, P, P]
+    lib.klr_surrogate_predict.restype = I32
+    lib.klr_surrogate_step.argtypes = [P, P, I32, P, P, P, P, I32, F, I32, F, F, F, P, P, P, SZ, P]
+    lib.klr_surrogate_step.restype = I32
+    lib.klr_surrogate_eval_workspace.argtypes = [I32, I32, I64]
+    lib.klr_surrogate_eval_workspace.restype = SZ
+    lib.klr_surrogate_eval.argtypes = [P, P, I32, P, I32, I32, I32, P, P, I32, P, I32, P, I64, P, I64,
+                                       P, I64, F, P, P, P, P, SZ, P]
+    lib.klr_surrogate_eval.restype = I32
     return lib
+
+
+def surrogate_layout(lib, n_kernels: int) -> dict:
+    buf = (ctypes.c_int64 * 32)()
+    cnt = lib.klr_surrogate_layout(n_kernels, buf, 32)
+    v = [int(buf[i]) for i in range(cnt)]
+    keys = ("np", "P", "M", "V", "W2b", "W2Tb", "bytes", "W2", "W1", "b1", "b2", "w3", "b3", "emb")
+    return dict(zip(keys, v))
+
+
+def pack_params(lib, params: dict, n_kernels: int, mu: float = 0.0, sigma: float = 1.0) -> np.ndarray:
+    """Host blob (uint8) of the surrogate: header (mu, sigma), P from `params`, M = V = 0; the
+    BF16 working copies are written by the library."""
+    lay = surrogate_layout(lib, n_kernels)
+    blob = np.zeros(lay["bytes"], np.uint8)
+    f = blob[: (16 + 3 * lay["np"]) * 4].view(np.float32)
+    f[0], f[1] = mu, sigma
+    P = f[lay["P"]: lay["P"] + lay["np"]]
+    for k in MLP_PARAMS:
+        a = np.asarray(params[k], np.float32).reshape(-1)
+        P[lay[k]: lay[k] + a.size] = a
+    return blob
+
+
+def unpack_params(lib, blob: np.ndarray, n_kernels: int, hidden: int = 256) -> dict:
+    lay = surrogate_layout(lib, n_kernels)
+    f = np.asarray(blob, np.uint8)[: (16 + 3 * lay["np"]) * 4].view(np.float32)
+    out = {"mu": float(f[0]), "sigma": float(f[1])}
+    shapes = {"W2": (hidden, hidden), "W1": (hidden, 4), "b1": (hidden,), "b2": (hidden,),
+              "w3": (hidden,), "b3": (), "emb": (n_kernels,)}
+    for tag in ("P", "M", "V"):
+        base = f[lay[tag]: lay[tag] + lay["np"]]
+        d = {}
+        for k, shp in shapes.items():
+            size = int(np.prod(shp)) if shp else 1
+            d[k] = base[lay[k]: lay[k] + size].reshape(shp).astype(np.float64)
+        out[tag] = d
+    return out
+
+
+def grads_to_dict(lib, g: np.ndarray, n_kernels: int, hidden: int = 256) -> dict:
+    lay = surrogate_layout(lib, n_kernels)
+    shapes = {"W2": (hidden, hidden), "W1": (hidden, 4), "b1": (hidden,), "b2": (hidden,),
+              "w3": (hidden,), "b3": (), "emb": (n_kernels,)}
+    out = {}
+    for k, shp in shapes.items():
+        size = int(np.prod(shp)) if shp else 1
+        out[k] = np.asarray(g[lay[k]: lay[k] + size], np.float64).reshape(shp)
+    return out
 
 
 def abi_layout(lib) -> list:
@@ -165,6 +240,7 @@ class DeviceEval:
     hw: np.ndarray
     costs_len: int
     ws: object
+    sws: object = None
 
     @classmethod
     def from_batch(cls, lib: "Library", pb, with_costs: bool = False, device="cuda", coef=None):
@@ -252,6 +328,90 @@ class Library:
         self._check(st)
         return am, bc, costs, status
 
+    # ---- surrogate ----------------------------------------------------------------------
+    def surrogate_alloc(self, params: dict, n_kernels: int, mu=0.0, sigma=1.0, device="cuda"):
+        """Device parameter blob (256-byte aligned torch uint8 tensor) from host parameters."""
+        torch = _torch()
+        blob = pack_params(self.lib, params, n_kernels, mu, sigma)
+        t = torch.empty(blob.size + 256, dtype=torch.uint8, device=device)
+        off = (-t.data_ptr()) % 256
+        v = t[off: off + blob.size]
+        v.copy_(torch.from_numpy(blob))
+        v._klr_base = t        # keep the allocation alive
+        self._check(self.lib.klr_surrogate_init(self.h, _ptr(v), n_kernels, self._stream(None)))
+        return v
+
+    def surrogate_params(self, blob_t, n_kernels: int) -> dict:
+        return unpack_params(self.lib, blob_t.cpu().numpy(), n_kernels)
+
+    def _aligned(self, nbytes: int, device="cuda"):
+        torch = _torch()
+        t = torch.empty(max(nbytes, 1) + 256, dtype=torch.uint8, device=device)
+        off = (-t.data_ptr()) % 256
+        v = t[off: off + max(nbytes, 1)]
+        v._klr_base = t
+        return v
+
+    def surrogate_train(self, blob_t, n_kernels: int, kid, N, L, cost, lr=1e-3, beta1=0.9,
+                        beta2=0.999, eps=1e-8, batch=4096, epochs=1, seed=0, stream=None):
+        """Returns the per-epoch mean loss (device float32 tensor)."""
+        torch = _torch()
+        cfg = np.zeros(1, TRAIN_CFG)
+        cfg["lr"], cfg["beta1"], cfg["beta2"], cfg["eps"] = lr, beta1, beta2, eps
+        cfg["batch"], cfg["epochs"], cfg["seed"] = batch, epochs, seed
+        ws = self._aligned(int(self.lib.klr_surrogate_train_workspace(n_kernels, batch)), kid.device)
+        loss = torch.zeros(max(epochs, 1), dtype=torch.float32, device=kid.device)
+        st = self.lib.klr_surrogate_train(self.h, _ptr(blob_t), n_kernels, _ptr(kid), _ptr(N), _ptr(L),
+                                          _ptr(cost), int(kid.numel()), cfg.ctypes.data, _ptr(loss),
+                                          _ptr(ws), int(ws.numel()), self._stream(stream))
+        self._check(st)
+        return loss
+
+    def surrogate_predict(self, blob_t, n_kernels: int, kid, N, L, stream=None):
+        torch = _torch()
+        pred = torch.empty(int(kid.numel()), dtype=torch.float32, device=kid.device)
+        st = self.lib.klr_surrogate_predict(self.h, _ptr(blob_t), n_kernels, _ptr(kid), _ptr(N), _ptr(L),
+                                            int(kid.numel()), _ptr(pred), self._stream(stream))
+        self._check(st)
+        return pred
+
+    def surrogate_step(self, blob_t, n_kernels: int, kid, N, L, t_std, lr=0.0, step=1, beta1=0.9,
+                       beta2=0.999, eps=1e-8, stream=None):
+        """One step over the first `batch` = len(kid) samples; returns (grads float32[NP], loss)."""
+        torch = _torch()
+        B = int(kid.numel())
+        lay = surrogate_layout(self.lib, n_kernels)
+        grads = torch.zeros(lay["np"], dtype=torch.float32, device=kid.device)
+        loss = torch.zeros(1, dtype=torch.float32, device=kid.device)
+        ws = self._aligned(int(self.lib.klr_surrogate_train_workspace(n_kernels, B)), kid.device)
+        st = self.lib.klr_surrogate_step(self.h, _ptr(blob_t), n_kernels, _ptr(kid), _ptr(N), _ptr(L),
+                                         _ptr(t_std), B, lr, step, beta1, beta2, eps, _ptr(grads),
+                                         _ptr(loss), _ptr(ws), int(ws.numel()), self._stream(stream))
+        self._check(st)
+        return grads, loss
+
+    def surrogate_eval(self, blob_t, n_kernels: int, de: DeviceEval, margin: float = 0.02, out=None,
+                       stream=None):
+        """Returns (argmin int32, pred_cost float32, fell_back uint8)."""
+        torch = _torch()
+        ql = int(de.queries.numel())
+        if out is None:
+            am = torch.empty(ql, dtype=torch.int32, device=de.queries.device)
+            pc = torch.empty(ql, dtype=torch.float32, device=de.queries.device)
+            fb = torch.empty(ql, dtype=torch.uint8, device=de.queries.device)
+        else:
+            am, pc, fb = out
+        need = int(self.lib.klr_surrogate_eval_workspace(de.n_progs, de.max_cfg, ql))
+        if getattr(de, "sws", None) is None or de.sws.numel() < need:
+            de.sws = self._aligned(need, de.queries.device)
+        st = self.lib.klr_surrogate_eval(
+            self.h, _ptr(blob_t), n_kernels, _ptr(de.progs), de.n_progs, de.max_cfg, de.max_q,
+            de.hw.ctypes.data, _ptr(de.desc), de.n_fits, _ptr(de.exps), de.n_exp_rows, _ptr(de.coef),
+            int(de.coef.numel()), _ptr(de.cfgs), int(de.cfgs.numel()), _ptr(de.queries), ql, margin,
+            _ptr(am), _ptr(pc), _ptr(fb), _ptr(de.sws), int(de.sws.numel()), self._stream(stream))
+        self._check(st)
+        return am, pc, fb
+
     # ---- fit ----------------------------------------------------------------------------
     def fit_workspace(self, n_fits: int, f_len: int, precision: int) -> int:
         return int(self.lib.klr_fit_workspace(n_fits, f_len, precision))
@@ -298,3 +458,20 @@ class DeviceFit:
 def info_records(info_tensor) -> np.ndarray:
     """Device info bytes -> numpy structured array of klr_fit_info."""
     return info_tensor.cpu().numpy().view(FIT_INFO)
+
+
+def grid_samples(pb, de: DeviceEval, costs):
+    """Training samples (kernel id, N, launch pair, exact cost) of a uniform ProgramBatch from
+    its full cost matrix: every (program, query, configuration) point, as device tensors
+    (index bookkeeping only)."""
+    torch = _torch()
+    P, C, Q = pb.n_progs, int(pb.n_cfg[0]), int(pb.n_q[0])
+    if not (np.all(pb.n_cfg == C) and np.all(pb.n_q == Q) and np.all(pb.v_launch == 2)
+            and np.all(pb.cfg0 == pb.cfg0[0])):
+        raise ValueError("grid_samples needs programs of one shape sharing one configuration list")
+    dev = de.queries.device
+    kid = torch.arange(P, dtype=torch.int32, device=dev).view(P, 1, 1).expand(P, C, Q).reshape(-1)
+    N = de.queries.view(P, 1, Q).expand(P, C, Q).reshape(-1)
+    c0 = int(pb.cfg0[0])
+    L = de.cfgs[c0: c0 + 2 * C].view(1, C, 1, 2).expand(P, C, Q, 2).reshape(-1)
+    return kid.contiguous(), N.contiguous(), L.contiguous(), costs[: P * C * Q].contiguous()

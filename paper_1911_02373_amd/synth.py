@@ -365,3 +365,31 @@ def mixed_programs(seed: int, n_progs: int, n_q_range=(1, 700), n_cfg_range=(1, 
         cfg0=np.array(cfg0, np.int64), n_cfg=np.array(n_cfg, np.int32),
         grid_kind=np.array(gk, np.int32), q0=np.array(q0, np.int64), n_q=np.array(n_q, np.int32),
         cfgs=np.concatenate(cfg_parts).astype(np.int32), queries=np.concatenate(q_parts), hw=HW())
+
+
+def mlp_init(seed: int, n_kernels: int, hidden: int = 256):
+    """He-uniform initial weights of the surrogate network (bound sqrt(6 / fan_in)), zero
+    biases, embeddings U(0, 1).  Returns float32 arrays keyed W1 [h][4], b1, W2 [h][h], b2,
+    w3, b3 (shape ()), emb [n_kernels]."""
+    rng = np.random.default_rng(seed)
+    def he(shape, fan_in):
+        b = np.sqrt(6.0 / fan_in)
+        return rng.uniform(-b, b, shape).astype(np.float32)
+    return {"W1": he((hidden, 4), 4), "b1": np.zeros(hidden, np.float32),
+            "W2": he((hidden, hidden), hidden), "b2": np.zeros(hidden, np.float32),
+            "w3": he((hidden,), hidden), "b3": np.zeros((), np.float32),
+            "emb": rng.uniform(0.0, 1.0, n_kernels).astype(np.float32)}
+
+
+def surrogate_training_queries(seed: int, pb: "ProgramBatch", n_q: int = 32,
+                               log2_range=(8.0, 26.0)) -> "ProgramBatch":
+    """The programs of `pb` with fresh training queries: n_q data sizes per program,
+    N = round(2^u), u ~ U(log2_range); every configuration of every query is a training sample
+    (so configurations are uniform over each program's set)."""
+    import copy
+    rng = np.random.default_rng(seed)
+    out = copy.copy(pb)
+    out.queries = np.rint(2.0 ** rng.uniform(log2_range[0], log2_range[1], pb.n_progs * n_q)).astype(np.int32)
+    out.q0 = np.arange(pb.n_progs, dtype=np.int64) * n_q
+    out.n_q = np.full(pb.n_progs, n_q, np.int32)
+    return out

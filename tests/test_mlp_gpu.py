@@ -1,0 +1,177 @@
+"""GPU parity of the surrogate network kernels against the FP64 oracle, and the semantics of
+surrogate selection with exact fallback."""
+import numpy as np
+import pytest
+
+from oracle import mlp as om
+from paper_1911_02373_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t if dtype is None else t.to(dtype)).cuda()
+
+
+def _samples(rng, B, nk):
+    kid = rng.integers(0, nk, B).astype(np.int32)
+    N = np.rint(2.0 ** rng.uniform(8, 26, B)).astype(np.int32)
+    bx = (2 ** rng.integers(0, 11, B)).astype(np.int32)
+    by = rng.integers(1, 65, B).astype(np.int32)
+    return kid, N, bx, by
+
+
+def _f64(p):
+    return {k: np.asarray(v, np.float64) for k, v in p.items()}
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30)
+
+
+def _cos(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+
+
+def test_forward_matches_oracle(klr):
+    import torch
+    rng = np.random.default_rng(0)
+    nk = 16
+    p = synth.mlp_init(1, nk)
+    blob = klr.surrogate_alloc(p, nk)
+    kid, N, bx, by = _samples(rng, 1000, nk)                    # ragged against 64-row tiles
+    L = np.stack([bx, by], 1).reshape(-1)
+    pred = klr.surrogate_predict(blob, nk, _dev(kid), _dev(N), _dev(L))
+    torch.cuda.synchronize()
+    y = pred.cpu().numpy().astype(np.float64)
+    yo, _ = om.forward(_f64(p), kid, N, bx, by)
+    # BF16 h1 and W2 (2^-9 relative rounding) on the 256 x 256 layer, FP32 elsewhere
+    assert _rel(y, yo) < 2e-2 and _cos(y, yo) > 0.999
+    assert np.max(np.abs(y - yo)) < 0.05 * np.sqrt(np.mean(yo ** 2)) + 1e-3
+
+
+def test_gradients_match_oracle(klr):
+    import torch
+    rng = np.random.default_rng(1)
+    nk = 32
+    p = synth.mlp_init(2, nk)
+    blob = klr.surrogate_alloc(p, nk)
+    B = 512
+    kid, N, bx, by = _samples(rng, B, nk)
+    t = rng.normal(size=B).astype(np.float32)
+    grads, loss = klr.surrogate_step(blob, nk, _dev(kid), _dev(N), _dev(np.stack([bx, by], 1).reshape(-1)),
+                                     _dev(t), lr=0.0, step=1)
+    torch.cuda.synchronize()
+    from paper_1911_02373_amd.klr import grads_to_dict
+    g = grads_to_dict(klr.lib, grads.cpu().numpy(), nk)
+    lo, go = om.loss_and_grads(_f64(p), kid, N, bx, by, t.astype(np.float64))
+    assert abs(float(loss.cpu()[0]) - lo) <= 1e-2 * lo
+    for k in om.PARAM_NAMES:
+        if k == "b3":
+            assert abs(float(g[k]) - float(go[k])) <= 2e-2 * abs(float(go[k])) + 1e-4, k
+            continue
+        assert _rel(g[k], go[k]) < 2e-2, (k, _rel(g[k], go[k]))
+        assert _cos(g[k], go[k]) > 0.999, (k, _cos(g[k], go[k]))
+
+
+def test_adam_update_matches_oracle(klr):
+    """Given the gradients the GPU computed, its Adam update equals the oracle's (FP32)."""
+    import torch
+    rng = np.random.default_rng(2)
+    nk = 8
+    p = synth.mlp_init(3, nk)
+    blob = klr.surrogate_alloc(p, nk)
+    B = 256
+    kid, N, bx, by = _samples(rng, B, nk)
+    t = rng.normal(size=B).astype(np.float32)
+    grads, _ = klr.surrogate_step(blob, nk, _dev(kid), _dev(N), _dev(np.stack([bx, by], 1).reshape(-1)),
+                                  _dev(t), lr=1e-3, step=1)
+    torch.cuda.synchronize()
+    from paper_1911_02373_amd.klr import grads_to_dict
+    g = grads_to_dict(klr.lib, grads.cpu().numpy(), nk)
+    got = klr.surrogate_params(blob, nk)
+    # the kernel's hyper-parameters are FP32 values: give the oracle the same numbers
+    b1, b2, eps, lr = (float(np.float32(x)) for x in (0.9, 0.999, 1e-8, 1e-3))
+    p2, m2, v2 = om.adam_step(_f64(p), g, om.zeros_like(_f64(p)), om.zeros_like(_f64(p)), 1, lr=lr,
+                              beta1=b1, beta2=b2, eps=eps)
+    for k in om.PARAM_NAMES:
+        assert np.max(np.abs(got["P"][k] - p2[k])) <= 2e-6, k
+        assert np.allclose(got["M"][k], m2[k], rtol=1e-5, atol=1e-12), k
+        assert np.allclose(got["V"][k], v2[k], rtol=1e-5, atol=1e-15), k
+
+
+def _trained(klr, n_progs=64, epochs=6, seed=4):
+    import torch
+    from paper_1911_02373_amd.klr import DeviceEval, grid_samples
+    pb = synth.config3_programs(seed, n_progs=n_progs, n_q=256)
+    tq = synth.surrogate_training_queries(seed + 1, pb, n_q=32)
+    de = DeviceEval.from_batch(klr, tq, with_costs=True)
+    _, _, costs, _ = klr.eval_argmin(de, want_costs=True)
+    kid, N, L, cost = grid_samples(tq, de, costs)
+    p = synth.mlp_init(seed, n_progs)
+    blob = klr.surrogate_alloc(p, n_progs)
+    loss = klr.surrogate_train(blob, n_progs, kid, N, L, cost, lr=2e-3, batch=1024, epochs=epochs, seed=seed)
+    torch.cuda.synchronize()
+    return pb, blob, loss.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def trained(klr):
+    return _trained(klr)
+
+
+def test_training_reduces_loss(trained):
+    _, _, loss = trained
+    assert np.all(np.isfinite(loss))
+    assert loss[-1] < 0.25 * loss[0], loss
+
+
+def test_selection_fallback_semantics(klr, trained):
+    import torch
+    from paper_1911_02373_amd.klr import DeviceEval
+    pb, blob, _ = trained
+    nk = pb.n_progs
+    de = DeviceEval.from_batch(klr, pb)
+    ea, eb, _, _ = klr.eval_argmin(de)
+    torch.cuda.synchronize()
+    ea, eb = ea.cpu().numpy(), eb.cpu().numpy()
+    # every query falls back: identical to the exact path, bit for bit
+    am, pc, fb = klr.surrogate_eval(blob, nk, de, margin=1e9)
+    torch.cuda.synchronize()
+    assert np.all(fb.cpu().numpy() == 1)
+    assert np.array_equal(am.cpu().numpy(), ea)
+    assert np.array_equal(pc.cpu().numpy().view(np.uint32), eb.view(np.uint32))
+    # the 2 % margin: fallback queries equal the exact path; the others are statically admissible
+    am, pc, fb = klr.surrogate_eval(blob, nk, de, margin=0.02)
+    torch.cuda.synchronize()
+    am, pc, fb = am.cpu().numpy(), pc.cpu().numpy(), fb.cpu().numpy().astype(bool)
+    assert np.array_equal(am[fb], ea[fb])
+    assert np.array_equal(pc[fb].view(np.uint32), eb[fb].view(np.uint32))
+    cfg = synth.config3_launch_configs()
+    picked = cfg[am[~fb]]
+    Nq = pb.queries[~fb]
+    assert np.all(am[~fb] >= 0) and np.all(am[~fb] < 127)
+    assert np.all(picked.max(axis=1) <= Nq) and np.all(np.isfinite(pc[~fb])) and np.all(pc[~fb] > 0)
+    assert 0.0 < fb.mean() < 1.0
+
+
+def test_selection_regret_small(klr, trained):
+    """Regret of the surrogate+fallback picks, judged by the exact rational program."""
+    import torch
+    from paper_1911_02373_amd.klr import DeviceEval
+    pb, blob, _ = trained
+    de = DeviceEval.from_batch(klr, pb, with_costs=True)
+    ea, eb, costs, _ = klr.eval_argmin(de, want_costs=True)
+    am, _, fb = klr.surrogate_eval(blob, pb.n_progs, de, margin=0.02)
+    torch.cuda.synchronize()
+    ea, eb, am = ea.cpu().numpy(), eb.cpu().numpy(), am.cpu().numpy()
+    C = costs.cpu().numpy().reshape(pb.n_progs, 128, -1)
+    nq = int(pb.n_q[0])
+    picked = C[np.repeat(np.arange(pb.n_progs), nq), am, np.tile(np.arange(nq), pb.n_progs)]
+    ok = ea >= 0
+    regret = picked[ok].astype(np.float64) / eb[ok] - 1.0
+    assert np.all(regret >= 0)
+    assert np.median(regret) < 0.01
