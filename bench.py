@@ -60,6 +60,62 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def surrogate_component(lib, klr, synth, pb, de, exact_ms, seed, epochs, regret_programs=64):
+    """Learned surrogate beside the exact path on the same grid: train on 4.2M samples the
+    exact program generates (32 queries x 128 configurations per program), select over the
+    full query grid with the 2 % margin fallback, and judge the picks with the exact costs of
+    `regret_programs` programs."""
+    import numpy as np
+    import torch
+    tq = synth.surrogate_training_queries(seed + 1, pb, n_q=32)
+    de_t = klr.DeviceEval.from_batch(lib, tq, with_costs=True)
+    _, _, costs, _ = lib.eval_argmin(de_t, want_costs=True)
+    kid, N, L, cost = klr.grid_samples(tq, de_t, costs)
+    blob = lib.surrogate_alloc(synth.mlp_init(seed, pb.n_progs), pb.n_progs)
+    torch.cuda.synchronize()
+    lib.profile_enable(True)
+    loss = lib.surrogate_train(blob, pb.n_progs, kid, N, L, cost, lr=2e-3, batch=4096, epochs=epochs,
+                               seed=seed)
+    train_ms, _ = lib.profile_read(klr.K_MLP)
+    lib.profile_enable(False)
+    del de_t, costs, kid, N, L, cost
+    out = lib.surrogate_eval(blob, pb.n_progs, de, margin=0.02)       # warm-up
+    torch.cuda.synchronize()
+    lib.profile_enable(True)
+    am, pc, fb = lib.surrogate_eval(blob, pb.n_progs, de, margin=0.02, out=out)
+    sel_ms, _ = lib.profile_read(klr.K_SURR)
+    fb_ms, _ = lib.profile_read(klr.K_FALLBACK)
+    col_ms, _ = lib.profile_read(klr.K_COLLAPSE)
+    lib.profile_enable(False)
+    fbr = float(fb.float().mean().cpu())
+    sub = regret_programs
+    nq = int(pb.n_q[0])
+    dex = klr.DeviceEval.from_batch(lib, synth.take_programs(pb, sub), with_costs=True)
+    xa, xb, xc, _ = lib.eval_argmin(dex, want_costs=True)
+    C = xc.view(sub, int(pb.n_cfg[0]), nq)
+    ok = xa >= 0
+
+    def regret(a):
+        picked = torch.gather(C, 1, a[: sub * nq].view(sub, 1, nq).long().clamp(min=0)).view(-1).double()
+        return (picked[ok] / xb.double()[ok] - 1.0).cpu().numpy()
+    r = regret(am)
+    am0, _, _ = lib.surrogate_eval(blob, pb.n_progs, dex, margin=0.0)
+    r0 = regret(am0)
+    torch.cuda.synchronize()
+    nonfb = ~fb[: sub * nq][ok].cpu().numpy().astype(bool)
+    total_ms = sel_ms + fb_ms + col_ms
+    return {"train_ms": train_ms, "epochs": epochs, "train_samples": int(tq.n_progs * 32 * 128),
+            "final_loss_std": float(loss[-1].cpu()), "select_ms": sel_ms, "fallback_ms": fb_ms,
+            "collapse_ms": col_ms, "fallback_rate": fbr, "margin": 0.02,
+            "speedup_vs_exact": exact_ms / total_ms,
+            "regret_programs": sub,
+            "regret_with_fallback": {"frac_le_1pct": float(np.mean(r <= 0.01)), "p50": float(np.median(r)),
+                                     "p99": float(np.quantile(r, 0.99)), "max": float(r.max()),
+                                     "nonfallback_frac_le_1pct": float(np.mean(r[nonfb] <= 0.01)) if nonfb.any() else None},
+            "regret_surrogate_alone": {"frac_le_1pct": float(np.mean(r0 <= 0.01)), "p50": float(np.median(r0)),
+                                       "p99": float(np.quantile(r0, 0.99))}}
+
+
 def cpu_baseline(pb, fb, budget_s: float, points: int, n_fits: int):
     """The oracle timed on bounded samples of the same step: FP32 replay + brute-force argmin
     over whole programs' first 16384 queries x all configurations, and pivoted-QR fits over
@@ -100,6 +156,8 @@ def main() -> int:
     ap.add_argument("--cpu-budget-s", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-sweep", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-epochs", type=int, default=20)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -185,6 +243,13 @@ def main() -> int:
                            "err_est_max": float(ir["err_est"].max()),
                            "speedup_vs_fp64": avg[klr.K_FIT_SOLVE] / kavg}
             log(f"{name}: {kavg:.3f} ms, iters mean {ir['iters'].mean():.1f}")
+
+    if not args.no_surrogate:
+        comps["surrogate"] = surrogate_component(lib, klr, synth, pb, de, eval_avg + avg[klr.K_COLLAPSE],
+                                                 args.seed, args.surrogate_epochs)
+        sc = comps["surrogate"]
+        log(f"surrogate: train {sc['train_ms']:.0f} ms, select {sc['select_ms']:.0f} ms, fallback rate "
+            f"{sc['fallback_rate']:.3f}, speedup vs exact {sc['speedup_vs_exact']:.3f}")
 
     res = {
         "metric": METRIC,

@@ -277,6 +277,29 @@ klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernel
                               void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Options of a handle. */
+#define KLR_OPT_FIT_PERSISTENT 0  /* 1 (default): fits run in persistent workgroups popping a    */
+                                  /*   device queue ordered longest first (m n^2); 0: one        */
+                                  /*   workgroup per fit                                         */
+#define KLR_OPT_EVAL_VARIANT 1    /* -1 (default): launch shape of the evaluation sweep chosen by */
+                                  /*   the autotuner; >= 0: a fixed variant index                 */
+#define KLR_OPT_COUNT 8
+klr_status klr_set_option(klr_handle h, int32_t option, int64_t value);
+
+/* ------------------------------------------------------------------------------------------
+ * Graph capture of a sequence of calls (e.g. klr_fit_batched then klr_eval_argmin) issued on a
+ * non-null stream between klr_capture_begin and klr_capture_end; klr_graph_launch replays it
+ * with the same arguments (the same device buffers; their contents may change between
+ * replays).  None of the captured calls allocates, synchronises or records memset nodes; the
+ * evaluation's launch shape inside a capture is the one tuned earlier (or the default), and
+ * kernel timing is off while capturing.  klr_surrogate_train is not capturable. */
+typedef struct klr_graph_s* klr_graph;
+klr_status klr_capture_begin(klr_handle h, void* stream);
+klr_status klr_capture_end(klr_handle h, void* stream, klr_graph* out);
+klr_status klr_graph_launch(klr_handle h, klr_graph g, void* stream);
+void klr_graph_destroy(klr_graph g);
+
+/* ------------------------------------------------------------------------------------------
  * Kernel timing.  When enabled on a handle, every kernel the handle launches is bracketed by a
  * pair of HIP events recorded on the caller's stream (so the elapsed time is the kernel's own,
  * on the stream it runs on).  klr_profile_read synchronises the recorded events, returns the

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -66,7 +67,35 @@ Timer::~Timer() {
   for (hipEvent_t e : pool) hipEventDestroy(e);
 }
 
+void Tuner::record(uint64_t key, int variant, float ms) {
+  entries.emplace_back(key, variant);
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%llu %d %.6f\n", (unsigned long long)key, variant, ms);
+  std::fclose(f);
+}
+
+void Tuner::load() {
+  const char* p = std::getenv("KLR_TUNE_CACHE");
+  if (!p || !*p) return;
+  path = p;
+  FILE* f = std::fopen(p, "r");
+  if (!f) return;
+  unsigned long long k = 0;
+  int v = 0;
+  float ms = 0.0f;
+  while (std::fscanf(f, "%llu %d %f", &k, &v, &ms) == 3)
+    if (v >= 0 && v < eval_num_variants() && find(k) < 0) entries.emplace_back((uint64_t)k, v);
+  std::fclose(f);
+}
+
 namespace {
+
+uint64_t eval_tune_key(int32_t n_progs, int32_t max_cfg, int32_t max_q) {
+  auto lg = [](int64_t x) { int b = 0; while ((int64_t(1) << b) < x && b < 40) ++b; return (uint64_t)b; };
+  return (1ull << 56) | (lg(n_progs) << 32) | (lg(max_cfg) << 16) | lg(max_q);
+}
 
 bool hw_ok(const klr_hw& hw, std::string& why) {
   if (hw.wave != 32 && hw.wave != 64) { why = "hw.wave must be 32 or 64"; return false; }
@@ -98,6 +127,7 @@ klr_status klr_create(klr_handle* out, int device) {
   klr_handle h = new (std::nothrow) klr_handle_s;
   if (!h) return KLR_E_HIP;
   h->device = device;
+  h->tuner.load();
   *out = h;
   return KLR_OK;
 }
@@ -105,6 +135,62 @@ klr_status klr_create(klr_handle* out, int device) {
 void klr_destroy(klr_handle h) { delete h; }
 
 const char* klr_last_error(klr_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+struct klr_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+klr_status klr_capture_begin(klr_handle h, void* stream) {
+  if (!h) return KLR_E_INVALID;
+  h->err.clear();
+  if (!stream) return fail(h, KLR_E_INVALID, "the null stream cannot be captured");
+  if (h->capturing) return fail(h, KLR_E_INVALID, "already capturing");
+  klr_status st = klr::hip_check(h, hipStreamBeginCapture(reinterpret_cast<hipStream_t>(stream),
+                                                          hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+  if (st == KLR_OK) h->capturing = true;
+  return st;
+}
+
+klr_status klr_capture_end(klr_handle h, void* stream, klr_graph* out) {
+  if (!h || !out) return KLR_E_INVALID;
+  *out = nullptr;
+  if (!h->capturing) return fail(h, KLR_E_INVALID, "not capturing");
+  h->capturing = false;
+  hipGraph_t g = nullptr;
+  klr_status st = klr::hip_check(h, hipStreamEndCapture(reinterpret_cast<hipStream_t>(stream), &g),
+                                 "hipStreamEndCapture");
+  if (st != KLR_OK) return st;
+  hipGraphExec_t ex = nullptr;
+  st = klr::hip_check(h, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+  if (st != KLR_OK) { hipGraphDestroy(g); return st; }
+  klr_graph r = new (std::nothrow) klr_graph_s;
+  if (!r) { hipGraphExecDestroy(ex); hipGraphDestroy(g); return fail(h, KLR_E_HIP, "out of host memory"); }
+  r->graph = g;
+  r->exec = ex;
+  *out = r;
+  return KLR_OK;
+}
+
+klr_status klr_graph_launch(klr_handle h, klr_graph g, void* stream) {
+  if (!h || !g) return KLR_E_INVALID;
+  h->err.clear();
+  return klr::hip_check(h, hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream)), "hipGraphLaunch");
+}
+
+void klr_graph_destroy(klr_graph g) {
+  if (!g) return;
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  delete g;
+}
+
+klr_status klr_set_option(klr_handle h, int32_t option, int64_t value) {
+  if (!h) return KLR_E_INVALID;
+  if (option < 0 || option >= KLR_OPT_COUNT) return fail(h, KLR_E_INVALID, "unknown option");
+  h->opt[option] = value;
+  return KLR_OK;
+}
 
 klr_status klr_profile_enable(klr_handle h, int32_t on) {
   if (!h) return KLR_E_INVALID;
@@ -176,7 +262,15 @@ klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_pro
   klr::EvalArgs a{progs, n_progs, max_cfg, max_q, *hw, desc, n_fits, exps, n_exp_rows, coef, coef_len,
                   cfgs, cfgs_len, queries, q_len, argmin, best_cost, all_costs,
                   all_costs ? costs_len : 0, prog_status, ws, ws_bytes,
-                  reinterpret_cast<hipStream_t>(stream), &h->timer};
+                  reinterpret_cast<hipStream_t>(stream), h->capturing ? nullptr : &h->timer, -1, nullptr, 0};
+  a.tune_key = klr::eval_tune_key(n_progs, max_cfg, max_q);
+  if (h->opt[KLR_OPT_EVAL_VARIANT] >= 0) {
+    a.variant = (int)(h->opt[KLR_OPT_EVAL_VARIANT] % klr::eval_num_variants());
+  } else {
+    a.variant = h->tuner.find(a.tune_key);
+    if (a.variant < 0 && !h->capturing) a.tuner = &h->tuner;
+    if (a.variant < 0 && h->capturing) a.variant = 0;
+  }
   return klr::hip_check(h, klr::launch_eval(a), "klr_eval_argmin launch");
 }
 
@@ -207,7 +301,8 @@ klr_status klr_fit_batched(klr_handle h, const klr_fit_desc* desc, int32_t n_fit
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
     return fail(h, KLR_E_INVALID, "workspace must be 256-byte aligned");
   klr::FitArgs a{desc, n_fits, exps, n_exp_rows, X, x_len, f, f_len, precision, max_iter, tol,
-                 coef, coef_len, info, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream), &h->timer};
+                 coef, coef_len, info, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream),
+                 h->capturing ? nullptr : &h->timer, h->opt[KLR_OPT_FIT_PERSISTENT] != 0};
   return klr::hip_check(h, klr::launch_fit(a), "klr_fit_batched launch");
 }
 
@@ -411,14 +506,14 @@ klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernel
   klr::Blob w = klr::blob_of(const_cast<void*>(params), n_kernels);
   klr::SelectArgs sa{progs, n_progs, max_cfg, max_q, n_kernels, hw->t_max, hw->wave, cfgs, cfgs_len,
                      queries, q_len, margin, argmin, pred_cost, fell_back};
-  const int t0 = h->timer.begin(KLR_K_SURR, s);
+  const int t0 = h->capturing ? -1 : h->timer.begin(KLR_K_SURR, s);
   hipError_t e = klr::launch_select(sa, w, s);
-  h->timer.end(t0, s);
+  if (!h->capturing) h->timer.end(t0, s);
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t ews = klr::eval_workspace_bytes(n_progs, max_cfg);
   klr::EvalArgs a{progs, n_progs, max_cfg, max_q, *hw, desc, n_fits, exps, n_exp_rows, coef, coef_len,
                   cfgs, cfgs_len, queries, q_len, argmin, pred_cost, nullptr, 0, nullptr, ws, ews, s,
-                  &h->timer};
+                  h->capturing ? nullptr : &h->timer, 0, nullptr, 0};
   if (e == hipSuccess) e = klr::launch_collapse_only(a);
   if (e == hipSuccess) e = klr::launch_fallback(a, fell_back, pred_cost, reinterpret_cast<char*>(ws) + al(ews));
   return klr::hip_check(h, e, "klr_surrogate_eval");

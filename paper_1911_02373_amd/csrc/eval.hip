@@ -302,26 +302,76 @@ __device__ __forceinline__ void sweep(const float* __restrict__ slot0, const Cfg
   }
 }
 
-__global__ void __launch_bounds__(kEvalBlock)
+// QPL queries per lane, BLOCK lanes per workgroup: each lane carries QPL independent
+// (query, running minimum) chains through the same configuration loop.
+template <int QPL, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
 eval_kernel(const klr_program* __restrict__ progs, const float* __restrict__ coefs,
             const CfgRec* __restrict__ recs, const int32_t* __restrict__ queries,
             int32_t* __restrict__ argmin, float* __restrict__ best_cost,
             float* __restrict__ all_costs, EvalArgs a, Hw32 hw, int chunks) {
   const int p = blockIdx.x / chunks;
-  const int qb = (blockIdx.x % chunks) * kEvalBlock;
+  const int qb = (blockIdx.x % chunks) * BLOCK * QPL;
   if (p >= a.n_progs) return;
   const klr_program P = progs[p];
   if (!program_desc_ok(P, a) || qb >= P.n_q) return;
   const float* slot0 = coefs + (int64_t)p * a.max_cfg * kSlotFloats;
   const CfgRec* rec0 = recs + (int64_t)p * a.max_cfg;
-  const SweepOut o{argmin, best_cost, all_costs};
-  const int qi = qb + (int)threadIdx.x;
-  const bool live = qi < P.n_q;
-  const int qc = live ? qi : P.n_q - 1;
-  if (P.grid_kind == KLR_GRID_1D)
-    sweep<KLR_GRID_1D>(slot0, rec0, queries, o, hw, P, qc, live);
-  else
-    sweep<KLR_GRID_2D>(slot0, rec0, queries, o, hw, P, qc, live);
+  int32_t N[QPL];
+  bool live[QPL];
+  int qi[QPL];
+#pragma unroll
+  for (int u = 0; u < QPL; ++u) {
+    qi[u] = qb + u * BLOCK + (int)threadIdx.x;
+    live[u] = qi[u] < P.n_q;
+    qi[u] = live[u] ? qi[u] : P.n_q - 1;
+    N[u] = queries[P.q0 + qi[u]];
+  }
+  float best[QPL];
+  int32_t bi[QPL];
+#pragma unroll
+  for (int u = 0; u < QPL; ++u) { best[u] = INFINITY; bi[u] = -1; }
+  float* costs = all_costs ? all_costs + P.cost0 : nullptr;
+  for (int c = 0; c < P.n_cfg; ++c) {
+    const CfgRec r = rec0[c];
+    const float* cf = slot0 + (int64_t)c * kSlotFloats;
+#pragma unroll
+    for (int u = 0; u < QPL; ++u) {
+      const float cost = P.grid_kind == KLR_GRID_1D ? point_cost<KLR_GRID_1D>(N[u], cf, r, hw)
+                                                    : point_cost<KLR_GRID_2D>(N[u], cf, r, hw);
+      if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost;
+      if (cost < best[u]) { best[u] = cost; bi[u] = c; }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < QPL; ++u)
+    if (live[u]) {
+      argmin[P.q0 + qi[u]] = bi[u];
+      best_cost[P.q0 + qi[u]] = best[u];
+    }
+}
+
+struct EvalVariant { int qpl, block; };
+constexpr EvalVariant kVariants[] = {{1, 256}, {2, 256}, {1, 128}, {2, 128}, {1, 64}, {4, 64}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+template <int QPL, int BLOCK>
+hipError_t launch_variant(const EvalArgs& a, const Hw32& hw, const float* coefs, const CfgRec* recs) {
+  const int chunks = (a.max_q + BLOCK * QPL - 1) / (BLOCK * QPL);
+  hipLaunchKernelGGL((eval_kernel<QPL, BLOCK>), dim3((unsigned)a.n_progs * chunks), dim3(BLOCK), 0, a.stream,
+                     a.progs, coefs, recs, a.queries, a.argmin, a.best_cost, a.all_costs, a, hw, chunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(int v, const EvalArgs& a, const Hw32& hw, const float* coefs, const CfgRec* recs) {
+  switch (v) {
+    case 1: return launch_variant<2, 256>(a, hw, coefs, recs);
+    case 2: return launch_variant<1, 128>(a, hw, coefs, recs);
+    case 3: return launch_variant<2, 128>(a, hw, coefs, recs);
+    case 4: return launch_variant<1, 64>(a, hw, coefs, recs);
+    case 5: return launch_variant<4, 64>(a, hw, coefs, recs);
+    default: return launch_variant<1, 256>(a, hw, coefs, recs);
+  }
 }
 
 // ---- exact re-evaluation of flagged queries --------------------------------------------------
@@ -461,27 +511,45 @@ hipError_t launch_fallback(const EvalArgs& a, const uint8_t* flags, float* best_
   return e;
 }
 
+int eval_num_variants() { return kNumVariants; }
+
 hipError_t launch_eval(const EvalArgs& a) {
-  const int cchunks = a.max_cfg > 0 ? (a.max_cfg + kCollapseBlock - 1) / kCollapseBlock : 1;
-  int t = a.timer ? a.timer->begin(KLR_K_COLLAPSE, a.stream) : -1;
-  hipLaunchKernelGGL(collapse_kernel, dim3((unsigned)a.n_progs * cchunks), dim3(kCollapseBlock), 0,
-                     a.stream, a, cchunks);
-  if (a.timer) a.timer->end(t, a.stream);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_collapse_only(a);
   if (e != hipSuccess) return e;
   if (a.max_q == 0) return hipSuccess;
   Hw32 hw{a.hw.n_cu, a.hw.wave, a.hw.w_max, a.hw.b_max, a.hw.z_max,
           a.hw.mem_lat, a.hw.dep_delay, a.hw.issue_cycles, a.hw.bw};
-  const int qchunks = (a.max_q + kEvalBlock - 1) / kEvalBlock;
-  const dim3 grid((unsigned)a.n_progs * qchunks);
   const float* coefs = reinterpret_cast<const float*>(a.ws);
   const CfgRec* recs = reinterpret_cast<const CfgRec*>(
       reinterpret_cast<const char*>(a.ws) + (int64_t)a.n_progs * a.max_cfg * kSlotFloats * sizeof(float));
-  t = a.timer ? a.timer->begin(KLR_K_EVAL, a.stream) : -1;
-  hipLaunchKernelGGL(eval_kernel, grid, dim3(kEvalBlock), 0, a.stream, a.progs, coefs, recs, a.queries,
-                     a.argmin, a.best_cost, a.all_costs, a, hw, qchunks);
+  int v = a.variant;
+  if (v < 0 && a.tuner) {
+    // autotune: time every variant once on this problem (all produce identical outputs)
+    float best = 0.0f;
+    int bv = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (int i = 0; i < kNumVariants && e == hipSuccess; ++i) {
+      hipEventRecord(e0, a.stream);
+      e = launch_sweep(i, a, hw, coefs, recs);
+      hipEventRecord(e1, a.stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && (i == 0 || ms < best)) { best = ms; bv = i; }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    a.tuner->record(a.tune_key, bv, best);
+    v = bv;
+  }
+  if (v < 0) v = 0;
+  int t = a.timer ? a.timer->begin(KLR_K_EVAL, a.stream) : -1;
+  e = launch_sweep(v % kNumVariants, a, hw, coefs, recs);
   if (a.timer) a.timer->end(t, a.stream);
-  return hipGetLastError();
+  return e;
 }
 
 }  // namespace klr

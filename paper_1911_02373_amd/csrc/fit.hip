@@ -412,17 +412,22 @@ __device__ int factor(const FitCtx& C, double unit) {
   return rank;
 }
 
+// Size class of a fit: 0 (n <= 32), 1 (<= 64), 2 (<= 128, and every invalid descriptor, which
+// the largest class reports as bad input).
+__device__ __forceinline__ int fit_class(const klr_fit_desc& d) {
+  const int n = d.n_num + d.n_den - 1;
+  const bool shape_ok = d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= KLR_MAX_UNKNOWNS;
+  if (!shape_ok) return 2;
+  return n <= 32 ? 0 : (n <= 64 ? 1 : 2);
+}
+
+// One fit by the whole workgroup (all threads call it with the same fi).
 template <int NM, int PREC>
-__global__ void __launch_bounds__(kFitBlock)
-fit_kernel(FitArgs a, int nm_lo) {
+__device__ void fit_one(const FitArgs& a, int fi, double* smem) {
   using L = Lds<NM>;
-  extern __shared__ double smem[];
-  const int fi = blockIdx.x;
-  if (fi >= a.n_fits) return;
   const klr_fit_desc d = a.desc[fi];
   const int n = d.n_num + d.n_den - 1;
   const bool shape_ok = d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= KLR_MAX_UNKNOWNS;
-  if (shape_ok ? (n > NM || n <= nm_lo) : (NM != 128)) return;
   const int tid = threadIdx.x;
   bool ok = shape_ok && d.v >= 1 && d.v <= KLR_MAX_VARS && d.m >= 1 && d.m <= KLR_MAX_SAMPLES &&
             d.x0 >= 0 && d.x0 + (int64_t)d.m * d.v <= a.x_len && d.f0 >= 0 &&
@@ -562,22 +567,135 @@ fit_kernel(FitArgs a, int nm_lo) {
   }
 }
 
+// Plain schedule: one workgroup per fit and size class (workgroups of other classes leave).
 template <int NM, int PREC>
-hipError_t launch_class(const FitArgs& a, int nm_lo) {
+__global__ void __launch_bounds__(kFitBlock)
+fit_kernel(FitArgs a, int cls) {
+  extern __shared__ double smem[];
+  const int fi = blockIdx.x;
+  if (fi >= a.n_fits || fit_class(a.desc[fi]) != cls) return;
+  fit_one<NM, PREC>(a, fi, smem);
+}
+
+// ---- persistent, longest-first schedule ------------------------------------------------------
+// plan: fits are bucketed by (class, 31 - floor(log2(m n^2 + 1))) so that an ascending scan of
+// the buckets lists each class's fits from the most to the least work; the persistent
+// workgroups of a class then pop positions from that class's queue counter.  A fit's result
+// does not depend on which workgroup computes it, so outputs are deterministic.
+constexpr int kBuckets = 32;
+struct Plan {
+  int32_t counts[3 * kBuckets];
+  int32_t offs[3 * kBuckets];
+  int32_t cursor[3 * kBuckets];
+  int32_t totals[3];
+  int32_t base[3];
+  int32_t queue[3];
+  int32_t pad[7];
+};
+
+__device__ __forceinline__ int cost_bucket(const klr_fit_desc& d) {
+  const int n = d.n_num + d.n_den - 1;
+  const double w = (double)(d.m > 0 ? d.m : 0) * (double)(n > 0 ? n : 0) * (double)(n > 0 ? n : 0) + 1.0;
+  int e = 0;
+  frexp(w, &e);                      // w in [2^(e-1), 2^e)
+  const int lg = e - 1 < kBuckets - 1 ? e - 1 : kBuckets - 1;
+  return kBuckets - 1 - lg;
+}
+
+__global__ void fit_plan_zero(Plan* pl) {
+  const int i = threadIdx.x;
+  if (i < 3 * kBuckets) pl->counts[i] = 0;
+}
+
+__global__ void __launch_bounds__(kFitBlock) fit_plan_count(FitArgs a, Plan* pl) {
+  const int fi = blockIdx.x * kFitBlock + threadIdx.x;
+  if (fi >= a.n_fits) return;
+  const klr_fit_desc d = a.desc[fi];
+  atomicAdd(&pl->counts[fit_class(d) * kBuckets + cost_bucket(d)], 1);
+}
+
+__global__ void fit_plan_scan(Plan* pl) {
+  if (threadIdx.x != 0) return;
+  int32_t base = 0;
+  for (int c = 0; c < 3; ++c) {
+    pl->base[c] = base;
+    int32_t run = 0;
+    for (int b = 0; b < kBuckets; ++b) {
+      pl->offs[c * kBuckets + b] = base + run;
+      pl->cursor[c * kBuckets + b] = 0;
+      run += pl->counts[c * kBuckets + b];
+    }
+    pl->totals[c] = run;
+    pl->queue[c] = 0;
+    base += run;
+  }
+}
+
+__global__ void __launch_bounds__(kFitBlock) fit_plan_scatter(FitArgs a, Plan* pl, int32_t* order) {
+  const int fi = blockIdx.x * kFitBlock + threadIdx.x;
+  if (fi >= a.n_fits) return;
+  const klr_fit_desc d = a.desc[fi];
+  const int k = fit_class(d) * kBuckets + cost_bucket(d);
+  order[pl->offs[k] + atomicAdd(&pl->cursor[k], 1)] = fi;
+}
+
+template <int NM, int PREC>
+__global__ void __launch_bounds__(kFitBlock)
+fit_persistent(FitArgs a, Plan* pl, const int32_t* __restrict__ order, int cls) {
+  extern __shared__ double smem[];
+  __shared__ int next;
+  const int total = pl->totals[cls], base = pl->base[cls];
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(&pl->queue[cls], 1);
+    __syncthreads();
+    const int i = next;
+    __syncthreads();
+    if (i >= total) break;
+    fit_one<NM, PREC>(a, order[base + i], smem);
+  }
+}
+
+size_t plan_offset(int64_t f_len) { return ((size_t)(f_len > 0 ? f_len : 0) * 2 * sizeof(double) + 255) / 256 * 256; }
+
+template <int NM, int PREC>
+hipError_t launch_class(const FitArgs& a, int cls, bool persistent, Plan* pl, const int32_t* order) {
   const size_t lds = (size_t)Lds<NM>::BYTES;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_kernel<NM, PREC>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const void* fn = persistent ? reinterpret_cast<const void*>(&fit_persistent<NM, PREC>)
+                              : reinterpret_cast<const void*>(&fit_kernel<NM, PREC>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((fit_kernel<NM, PREC>), dim3((unsigned)a.n_fits), dim3(kFitBlock), lds, a.stream, a,
-                     nm_lo);
+  if (!persistent) {
+    hipLaunchKernelGGL((fit_kernel<NM, PREC>), dim3((unsigned)a.n_fits), dim3(kFitBlock), lds, a.stream, a, cls);
+    return hipGetLastError();
+  }
+  int dev = 0, ncu = 0, occ = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kFitBlock, lds);
+  if (e != hipSuccess) return e;
+  int64_t g = (int64_t)ncu * (occ > 0 ? occ : 1);
+  if (g > a.n_fits) g = a.n_fits;
+  hipLaunchKernelGGL((fit_persistent<NM, PREC>), dim3((unsigned)g), dim3(kFitBlock), lds, a.stream, a, pl, order,
+                     cls);
   return hipGetLastError();
 }
 
 template <int PREC>
-hipError_t launch_all(const FitArgs& a) {
-  hipError_t e = launch_class<32, PREC>(a, 0);
-  if (e == hipSuccess) e = launch_class<64, PREC>(a, 32);
-  if (e == hipSuccess) e = launch_class<128, PREC>(a, 64);
+hipError_t launch_all(const FitArgs& a, bool persistent) {
+  Plan* pl = reinterpret_cast<Plan*>(reinterpret_cast<char*>(a.ws) + plan_offset(a.f_len));
+  int32_t* order = reinterpret_cast<int32_t*>(pl + 1);
+  hipError_t e = hipSuccess;
+  if (persistent) {
+    const unsigned g = (unsigned)((a.n_fits + kFitBlock - 1) / kFitBlock);
+    hipLaunchKernelGGL(fit_plan_zero, dim3(1), dim3(3 * kBuckets), 0, a.stream, pl);
+    hipLaunchKernelGGL(fit_plan_count, dim3(g), dim3(kFitBlock), 0, a.stream, a, pl);
+    hipLaunchKernelGGL(fit_plan_scan, dim3(1), dim3(64), 0, a.stream, pl);
+    hipLaunchKernelGGL(fit_plan_scatter, dim3(g), dim3(kFitBlock), 0, a.stream, a, pl, order);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = launch_class<32, PREC>(a, 0, persistent, pl, order);
+  if (e == hipSuccess) e = launch_class<64, PREC>(a, 1, persistent, pl, order);
+  if (e == hipSuccess) e = launch_class<128, PREC>(a, 2, persistent, pl, order);
   return e;
 }
 
@@ -585,16 +703,15 @@ hipError_t launch_all(const FitArgs& a) {
 
 size_t fit_workspace_bytes(int32_t n_fits, int64_t f_len, int32_t precision) {
   (void)precision;
-  (void)n_fits;
-  return (size_t)(f_len > 0 ? f_len : 0) * 2 * sizeof(double);
+  return plan_offset(f_len) + sizeof(Plan) + (size_t)(n_fits > 0 ? n_fits : 0) * sizeof(int32_t);
 }
 
 hipError_t launch_fit(const FitArgs& a) {
   const int t = a.timer ? a.timer->begin(KLR_K_FIT_SOLVE, a.stream) : -1;
   hipError_t e;
-  if (a.precision == KLR_FP64) e = launch_all<KLR_FP64>(a);
-  else if (a.precision == KLR_FP32_REFINED) e = launch_all<KLR_FP32_REFINED>(a);
-  else e = launch_all<KLR_BF16_REFINED>(a);
+  if (a.precision == KLR_FP64) e = launch_all<KLR_FP64>(a, a.persistent);
+  else if (a.precision == KLR_FP32_REFINED) e = launch_all<KLR_FP32_REFINED>(a, a.persistent);
+  else e = launch_all<KLR_BF16_REFINED>(a, a.persistent);
   if (a.timer) a.timer->end(t, a.stream);
   return e;
 }

@@ -29,12 +29,29 @@ struct Timer {
   ~Timer();
 };
 
+// Launch-shape autotuner cache: shape key -> chosen variant (kept per handle; optionally
+// persisted in the text file named by KLR_TUNE_CACHE, one "key variant ms" line per entry).
+struct Tuner {
+  std::vector<std::pair<uint64_t, int>> entries;
+  std::string path;
+  int find(uint64_t key) const {
+    for (const auto& e : entries)
+      if (e.first == key) return e.second;
+    return -1;
+  }
+  void record(uint64_t key, int variant, float ms);
+  void load();
+};
+
 }  // namespace klr
 
 struct klr_handle_s {
   int device = 0;
   std::string err;
   klr::Timer timer;
+  klr::Tuner tuner;
+  bool capturing = false;
+  int64_t opt[8] = {1, -1, 0, 0, 0, 0, 0, 0};   // see KLR_OPT_* in klr.h
 };
 
 namespace klr {
@@ -67,10 +84,14 @@ struct EvalArgs {
   size_t ws_bytes;
   hipStream_t stream;
   Timer* timer;
+  int variant;             // launch shape of the sweep; < 0: autotune with `tuner`
+  Tuner* tuner;
+  uint64_t tune_key;
 };
 
 size_t eval_workspace_bytes(int32_t n_progs, int32_t max_cfg);
 hipError_t launch_eval(const EvalArgs& a);
+int eval_num_variants();
 
 // ---- fit ----------------------------------------------------------------------------------
 struct FitArgs {
@@ -91,6 +112,7 @@ struct FitArgs {
   size_t ws_bytes;
   hipStream_t stream;
   Timer* timer;
+  bool persistent;         // longest-first persistent schedule (else one workgroup per fit)
 };
 
 size_t fit_workspace_bytes(int32_t n_fits, int64_t f_len, int32_t precision);

@@ -38,7 +38,9 @@ EXPORTS = ("klr_create", "klr_destroy", "klr_last_error", "klr_fit_workspace", "
            "klr_profile_read", "klr_surrogate_param_bytes", "klr_surrogate_layout",
            "klr_surrogate_train_workspace", "klr_surrogate_train", "klr_surrogate_predict",
            "klr_surrogate_step", "klr_surrogate_eval_workspace", "klr_surrogate_eval",
-           "klr_surrogate_init")
+           "klr_surrogate_init", "klr_set_option", "klr_capture_begin", "klr_capture_end",
+           "klr_graph_launch", "klr_graph_destroy")
+OPT_FIT_PERSISTENT, OPT_EVAL_VARIANT = 0, 1
 K_COLLAPSE, K_EVAL, K_FIT_GRAM, K_FIT_SOLVE, K_MLP, K_SURR, K_FALLBACK = 0, 1, 2, 3, 4, 5, 6
 TRAIN_CFG = np.dtype([("lr", "<f4"), ("beta1", "<f4"), ("beta2", "<f4"), ("eps", "<f4"),
                       ("batch", "<i4"), ("epochs", "<i4"), ("seed", "<u8")])
@@ -81,6 +83,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     F = ctypes.c_float
     lib.klr_surrogate_param_bytes.argtypes = [I32]
     lib.klr_surrogate_param_bytes.restype = SZ
+    lib.klr_capture_begin.argtypes = [P, P]
+    lib.klr_capture_begin.restype = I32
+    lib.klr_capture_end.argtypes = [P, P, ctypes.POINTER(P)]
+    lib.klr_capture_end.restype = I32
+    lib.klr_graph_launch.argtypes = [P, P, P]
+    lib.klr_graph_launch.restype = I32
+    lib.klr_graph_destroy.argtypes = [P]
+    lib.klr_graph_destroy.restype = None
+    lib.klr_set_option.argtypes = [P, I32, I64]
+    lib.klr_set_option.restype = I32
     lib.klr_surrogate_init.argtypes = [P, P, I32, P]
     lib.klr_surrogate_init.restype = I32
     lib.klr_surrogate_layout.argtypes = [I32, ctypes.POINTER(I64), I32]
@@ -290,6 +302,24 @@ class Library:
         torch = _torch()
         s = stream if stream is not None else torch.cuda.current_stream()
         return s.cuda_stream
+
+    # ---- graph capture --------------------------------------------------------------------
+    def capture_begin(self, stream):
+        self._check(self.lib.klr_capture_begin(self.h, stream.cuda_stream))
+
+    def capture_end(self, stream):
+        g = ctypes.c_void_p()
+        self._check(self.lib.klr_capture_end(self.h, stream.cuda_stream, ctypes.byref(g)))
+        return g
+
+    def graph_launch(self, g, stream):
+        self._check(self.lib.klr_graph_launch(self.h, g, stream.cuda_stream))
+
+    def graph_destroy(self, g):
+        self.lib.klr_graph_destroy(g)
+
+    def set_option(self, option: int, value: int):
+        self._check(self.lib.klr_set_option(self.h, option, int(value)))
 
     # ---- kernel timing ------------------------------------------------------------------
     def profile_enable(self, on: bool = True):

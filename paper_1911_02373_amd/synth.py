@@ -393,3 +393,18 @@ def surrogate_training_queries(seed: int, pb: "ProgramBatch", n_q: int = 32,
     out.q0 = np.arange(pb.n_progs, dtype=np.int64) * n_q
     out.n_q = np.full(pb.n_progs, n_q, np.int32)
     return out
+
+
+def take_programs(pb: "ProgramBatch", n: int) -> "ProgramBatch":
+    """The first n programs of a batch (their fits, configurations and queries), re-based."""
+    import copy
+    out = copy.copy(pb)
+    nf = n * N_METRICS
+    out.num0, out.n_num, out.den0, out.n_den = pb.num0[:nf], pb.n_num[:nf], pb.den0[:nf], pb.n_den[:nf]
+    out.coef0, out.scale_exp = pb.coef0[:nf], pb.scale_exp[:nf]
+    out.coef = pb.coef[: int(pb.coef0[nf - 1] + pb.n_num[nf - 1] + pb.n_den[nf - 1] - 1)]
+    out.v_launch, out.fit0, out.cfg0 = pb.v_launch[:n], pb.fit0[:n], pb.cfg0[:n]
+    out.n_cfg, out.grid_kind, out.n_q = pb.n_cfg[:n], pb.grid_kind[:n], pb.n_q[:n]
+    qend = int(pb.q0[n - 1] + pb.n_q[n - 1])
+    out.q0, out.queries = pb.q0[:n], pb.queries[:qend]
+    return out

@@ -191,3 +191,20 @@ def test_deterministic(klr):
     b, ib = _run(klr, fb, prec=1, tol=1e-7)
     assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
     assert np.array_equal(ia.view(np.uint8), ib.view(np.uint8))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_persistent_schedule_matches_plain(klr, prec):
+    """The longest-first persistent schedule computes every fit exactly as the one-workgroup-
+    per-fit launch does (uneven m, all three size classes, invalid descriptors)."""
+    from paper_1911_02373_amd.klr import OPT_FIT_PERSISTENT
+    fb = synth.config2_fits(21, 300, "2b", m_range=(20, 700))
+    try:
+        klr.set_option(OPT_FIT_PERSISTENT, 0)
+        a, ia = _run(klr, fb, prec=prec, tol=1e-9)
+        klr.set_option(OPT_FIT_PERSISTENT, 1)
+        b, ib = _run(klr, fb, prec=prec, tol=1e-9)
+    finally:
+        klr.set_option(OPT_FIT_PERSISTENT, 1)
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    assert np.array_equal(ia.view(np.uint8), ib.view(np.uint8))
