@@ -316,6 +316,11 @@ void klr_graph_destroy(klr_graph g);
 klr_status klr_profile_enable(klr_handle h, int32_t on);   /* on != 0: enable; 0: disable+reset */
 klr_status klr_profile_read(klr_handle h, int32_t kind, double* total_ms, int64_t* launches);
 
+/* [host] Self-test of the invariant-divisor multiplication the evaluation uses for the grid
+ * (floor(n / d) = mulhi(n, m) >> s for 0 <= n < 2^31): checks every divisor 1..d_max on
+ * dividends around its multiples and at the ends of the range; returns the mismatch count. */
+int64_t klr_selftest_divisors(uint32_t d_max);
+
 /* [host] ABI self-description for binding checks: writes up to n entries of
  * {sizeof(klr_fit_desc), sizeof(klr_fit_info), sizeof(klr_hw), sizeof(klr_program), ...}
  * and returns the number of entries available. */

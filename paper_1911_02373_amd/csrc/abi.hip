@@ -102,7 +102,10 @@ bool hw_ok(const klr_hw& hw, std::string& why) {
   if (hw.n_cu < 1 || hw.n_cu > 65536) { why = "hw.n_cu out of [1, 65536]"; return false; }
   if (hw.w_max < 1 || hw.w_max > 1024) { why = "hw.w_max out of [1, 1024]"; return false; }
   if (hw.b_max < 1 || hw.b_max > 1024) { why = "hw.b_max out of [1, 1024]"; return false; }
-  if (hw.r_max < 1 || hw.z_max < 0) { why = "hw.r_max must be >= 1 and hw.z_max >= 0"; return false; }
+  if (hw.r_max < 1 || hw.r_max >= (1 << 20) || hw.z_max < 0 || hw.z_max >= (1 << 20)) {
+    why = "hw.r_max must be in [1, 2^20) and hw.z_max in [0, 2^20)";
+    return false;
+  }
   if (hw.t_max < hw.wave || hw.t_max > 65536) { why = "hw.t_max out of [wave, 65536]"; return false; }
   if (hw.reserved != 0) { why = "hw.reserved must be 0"; return false; }
   const float fl[4] = {hw.mem_lat, hw.dep_delay, hw.issue_cycles, hw.bw};
@@ -206,6 +209,8 @@ klr_status klr_profile_read(klr_handle h, int32_t kind, double* total_ms, int64_
   *launches = h->timer.count[kind];
   return st;
 }
+
+int64_t klr_selftest_divisors(uint32_t d_max) { return klr::selftest_divisors(d_max); }
 
 int32_t klr_abi_layout(int64_t* out, int32_t n) {
   const int64_t v[] = {

@@ -42,9 +42,47 @@ struct CfgRec {          // per (program, configuration) integer terms
   int32_t Lmax;          // largest launch parameter (admissible only if <= N)
   int32_t L0, L1;        // first two launch parameters (two-dimensional grid)
   int32_t ok;            // configuration admissible and the program's fits valid
+  uint32_t magT;         // floor(n / T) = mulhi(n, magT) >> shT for 0 <= n < 2^31
+  int32_t shT;
+  int32_t pad[2];
 };
 
+// Division by an invariant divisor d in [1, 2^31): with l = ceil(log2 d) and
+// m = ceil(2^(31 + l) / d) (fits 32 bits), floor(n / d) = floor(n m / 2^(31 + l)) for every
+// 0 <= n < 2^31, because n (m d - 2^(31 + l)) / (d 2^(31 + l)) < 1/d (round-up method of
+// Granlund and Montgomery).  sh = l - 1; d = 1 is marked by sh = -1.
+__host__ __device__ inline void magic_u31(uint32_t d, uint32_t* m, int32_t* sh) {
+  int l = 0;
+  while (l < 31 && (1u << l) < d) ++l;
+  if (l == 0) { *m = 0u; *sh = -1; return; }
+  const uint64_t p = (uint64_t)1 << (31 + l);
+  *m = (uint32_t)((p + d - 1) / d);
+  *sh = l - 1;
+}
+
+__device__ __forceinline__ uint32_t udiv_magic(uint32_t n, uint32_t m, int32_t sh) {
+  return sh < 0 ? n : (__umulhi(n, m) >> sh);
+}
+
+// Exact floor(a / b) for 0 <= a < 2^20 and 1 <= b <= 2^24: the approximate reciprocal (relative
+// error <= 2^-23) and the rounded product put a b^-1 within a 2^-22 < 1/4 of a / b, so the
+// truncated estimate is off by at most one and one correction step each way makes it exact.
+__device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
+  uint32_t q = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
+  int32_t r = (int32_t)a - (int32_t)__umul24(q, b);
+  if (r < 0) { q -= 1u; r += (int32_t)b; }
+  if (r >= (int32_t)b) q += 1u;
+  return q;
+}
+
 __device__ __forceinline__ float sel_min(float a, float b) { return b < a ? b : a; }
+
+// Per-program highest power of N~, stored after the configuration records.
+__host__ __device__ inline int32_t* prog_degree(const EvalArgs& a) {
+  char* base = reinterpret_cast<char*>(a.ws);
+  const int64_t slots = (int64_t)a.n_progs * a.max_cfg;
+  return reinterpret_cast<int32_t*>(base + slots * (kSlotFloats * (int64_t)sizeof(float) + (int64_t)sizeof(CfgRec)));
+}
 __device__ __forceinline__ float sel_max(float a, float b) { return b > a ? b : a; }
 
 __device__ bool program_desc_ok(const klr_program& P, const EvalArgs& a) {
@@ -114,6 +152,22 @@ collapse_kernel(EvalArgs a, int chunks) {
   }
   if (c == 0 && a.prog_status)
     a.prog_status[p] = (pd_ok ? 0 : KLR_PROG_BAD_DESC) | (pd_ok && !fits_ok ? KLR_PROG_BAD_FIT : 0);
+  if (c == 0) {   // highest power of N~ over the program's metric polynomials (Horner start)
+    int deg = 0;
+    if (fits_ok)
+      for (int j = 0; j < KLR_N_METRICS; ++j) {
+        const klr_fit_desc d = a.desc[P.fit0 + j];
+        for (int t = 0; t < d.n_num; ++t) {
+          const int e = a.exps[(int64_t)(d.num0 + t) * KLR_MAX_VARS];
+          deg = e > deg ? e : deg;
+        }
+        for (int t = 0; t < d.n_den; ++t) {
+          const int e = a.exps[(int64_t)(d.den0 + t) * KLR_MAX_VARS];
+          deg = e > deg ? e : deg;
+        }
+      }
+    prog_degree(a)[p] = deg > kNdeg ? kNdeg : deg;
+  }
   if (!pd_ok || c >= P.n_cfg || c >= a.max_cfg) return;
 
   const int64_t slot = (int64_t)p * a.max_cfg + c;
@@ -141,6 +195,8 @@ collapse_kernel(EvalArgs a, int chunks) {
   r.L0 = L[0] < 1 ? 1 : L[0];
   r.L1 = L[1] < 1 ? 1 : L[1];
   r.ok = (cfg_ok && fits_ok) ? 1 : 0;
+  magic_u31((uint32_t)r.T, &r.magT, &r.shT);
+  r.pad[0] = r.pad[1] = 0;
   *rec = r;
 
   for (int j = 0; j < KLR_N_METRICS; ++j) {
@@ -163,10 +219,20 @@ collapse_kernel(EvalArgs a, int chunks) {
 struct Hw32 {
   int32_t n_cu, wave, w_max, b_max, z_max;
   float lat, dep, iss, bw;
+  uint32_t mag_ncu;
+  int32_t sh_ncu;
 };
 
-// Cost of one (query, configuration) point; +inf where inadmissible.
-template <int GRID>
+Hw32 make_hw32(const klr_hw& h) {
+  Hw32 w{h.n_cu, h.wave, h.w_max, h.b_max, h.z_max, h.mem_lat, h.dep_delay, h.issue_cycles, h.bw, 0u, -1};
+  magic_u31((uint32_t)h.n_cu, &w.mag_ncu, &w.sh_ncu);
+  return w;
+}
+
+// Cost of one (query, configuration) point; +inf where inadmissible.  DEG: the program's highest
+// power of N~ (Horner from there; the normative sequence starts at power 3 with zero
+// coefficients above DEG, which gives bit-identical values because 0 x + a = a exactly).
+template <int GRID, int DEG = kNdeg>
 __device__ __forceinline__ float point_cost(int32_t N, const float* __restrict__ cf, const CfgRec& r,
                                             const Hw32& hw) {
   bool ok = (r.ok != 0) & (N >= r.Lmax);
@@ -176,10 +242,10 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* __restrict__
   for (int j = 0; j < KLR_N_METRICS; ++j) {
     const float* c = cf + j * 2 * (kNdeg + 1);
     const float x = fN * cf[KLR_N_METRICS * 2 * (kNdeg + 1) + j];
-    float p = c[kNdeg];
-    float q = c[2 * kNdeg + 1];
+    float p = c[DEG];
+    float q = c[kNdeg + 1 + DEG];
 #pragma unroll
-    for (int d = kNdeg - 1; d >= 0; --d) {
+    for (int d = DEG - 1; d >= 0; --d) {
       p = p * x;
       p = p + c[d];
       q = q * x;
@@ -201,9 +267,9 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* __restrict__
 
   // occupancy: min(b_max, floor(wave w_max / T), floor(r_max / (R T)), floor(z_max / Z))
   int32_t B = hw.b_max < r.bwarp ? hw.b_max : r.bwarp;
-  const int32_t breg = r.rT / R;
+  const int32_t breg = (int32_t)udiv_small((uint32_t)r.rT, (uint32_t)R);
   B = breg < B ? breg : B;
-  const int32_t blds = Z > 0 ? hw.z_max / Z : hw.b_max;
+  const int32_t blds = Z > 0 ? (int32_t)udiv_small((uint32_t)hw.z_max, (uint32_t)Z) : hw.b_max;
   B = blds < B ? blds : B;
   ok = ok & (B >= 1);
   const int32_t Bs = B >= 1 ? B : 1;
@@ -212,9 +278,11 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* __restrict__
   const int32_t Nc = N >= 1 ? N : 1;
   float repf;
   if (GRID == KLR_GRID_1D) {
-    const uint32_t blocks = (uint32_t)(Nc - 1) / (uint32_t)r.T + 1u;
-    const uint32_t rep = (blocks - 1u) / (uint32_t)(Bs * hw.n_cu) + 1u;
-    repf = (float)rep;
+    // rep = ceil(blocks / (B n_cu)) = ceil(ceil(blocks / n_cu) / B)
+    const uint32_t bm1 = udiv_magic((uint32_t)(Nc - 1), r.magT, r.shT);        // blocks - 1
+    const uint32_t cm1 = udiv_magic(bm1, hw.mag_ncu, hw.sh_ncu);               // ceil(blocks/n_cu) - 1
+    const uint32_t rm1 = cm1 < (1u << 20) ? udiv_small(cm1, (uint32_t)Bs) : cm1 / (uint32_t)Bs;
+    repf = (float)(rm1 + 1u);
   } else {
     const uint64_t blocks = (uint64_t)((uint32_t)(Nc - 1) / (uint32_t)r.L0 + 1u) *
                             (uint64_t)((uint32_t)(Nc - 1) / (uint32_t)r.L1 + 1u);
@@ -302,6 +370,23 @@ __device__ __forceinline__ void sweep(const float* __restrict__ slot0, const Cfg
   }
 }
 
+template <int QPL, int GRID, int DEG>
+__device__ __forceinline__ void sweep_cfgs(const klr_program& P, const float* __restrict__ slot0,
+                                           const CfgRec* __restrict__ rec0, const Hw32& hw,
+                                           const int32_t* N, const bool* live, const int* qi,
+                                           float* costs, float* best, int32_t* bi) {
+  for (int c = 0; c < P.n_cfg; ++c) {
+    const CfgRec r = rec0[c];
+    const float* cf = slot0 + (int64_t)c * kSlotFloats;
+#pragma unroll
+    for (int u = 0; u < QPL; ++u) {
+      const float cost = point_cost<GRID, DEG>(N[u], cf, r, hw);
+      if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost;
+      if (cost < best[u]) { best[u] = cost; bi[u] = c; }
+    }
+  }
+}
+
 // QPL queries per lane, BLOCK lanes per workgroup: each lane carries QPL independent
 // (query, running minimum) chains through the same configuration loop.
 template <int QPL, int BLOCK>
@@ -332,17 +417,13 @@ eval_kernel(const klr_program* __restrict__ progs, const float* __restrict__ coe
 #pragma unroll
   for (int u = 0; u < QPL; ++u) { best[u] = INFINITY; bi[u] = -1; }
   float* costs = all_costs ? all_costs + P.cost0 : nullptr;
-  for (int c = 0; c < P.n_cfg; ++c) {
-    const CfgRec r = rec0[c];
-    const float* cf = slot0 + (int64_t)c * kSlotFloats;
-#pragma unroll
-    for (int u = 0; u < QPL; ++u) {
-      const float cost = P.grid_kind == KLR_GRID_1D ? point_cost<KLR_GRID_1D>(N[u], cf, r, hw)
-                                                    : point_cost<KLR_GRID_2D>(N[u], cf, r, hw);
-      if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost;
-      if (cost < best[u]) { best[u] = cost; bi[u] = c; }
-    }
-  }
+  const int deg = prog_degree(a)[p];
+  if (P.grid_kind == KLR_GRID_1D && deg <= 2)
+    sweep_cfgs<QPL, KLR_GRID_1D, 2>(P, slot0, rec0, hw, N, live, qi, costs, best, bi);
+  else if (P.grid_kind == KLR_GRID_1D)
+    sweep_cfgs<QPL, KLR_GRID_1D, kNdeg>(P, slot0, rec0, hw, N, live, qi, costs, best, bi);
+  else
+    sweep_cfgs<QPL, KLR_GRID_2D, kNdeg>(P, slot0, rec0, hw, N, live, qi, costs, best, bi);
 #pragma unroll
   for (int u = 0; u < QPL; ++u)
     if (live[u]) {
@@ -462,8 +543,9 @@ fb_exact(const klr_program* __restrict__ progs, const float* __restrict__ coefs,
 }  // namespace
 
 size_t eval_workspace_bytes(int32_t n_progs, int32_t max_cfg) {
+  if (n_progs <= 0) return 0;
   const size_t slots = (size_t)(n_progs > 0 ? n_progs : 0) * (size_t)(max_cfg > 0 ? max_cfg : 0);
-  return slots * (kSlotFloats * sizeof(float) + sizeof(CfgRec));
+  return slots * (kSlotFloats * sizeof(float) + sizeof(CfgRec)) + (size_t)(n_progs > 0 ? n_progs : 0) * 4 + 256;
 }
 
 hipError_t launch_collapse_only(const EvalArgs& a) {
@@ -497,8 +579,7 @@ hipError_t launch_fallback(const EvalArgs& a, const uint8_t* flags, float* best_
     e = hipGetLastError();
   }
   if (e == hipSuccess && a.max_q > 0) {
-    Hw32 hw{a.hw.n_cu, a.hw.wave, a.hw.w_max, a.hw.b_max, a.hw.z_max,
-            a.hw.mem_lat, a.hw.dep_delay, a.hw.issue_cycles, a.hw.bw};
+    const Hw32 hw = make_hw32(a.hw);
     const float* coefs = reinterpret_cast<const float*>(a.ws);
     const CfgRec* recs = reinterpret_cast<const CfgRec*>(
         reinterpret_cast<const char*>(a.ws) + (int64_t)a.n_progs * a.max_cfg * kSlotFloats * sizeof(float));
@@ -513,12 +594,36 @@ hipError_t launch_fallback(const EvalArgs& a, const uint8_t* flags, float* best_
 
 int eval_num_variants() { return kNumVariants; }
 
+int64_t selftest_divisors(uint32_t d_max) {
+  // every divisor 1..d_max against dividends at and around its multiples, small values and the
+  // top of the range, with the host form of the same arithmetic (64-bit product, high word)
+  int64_t bad = 0;
+  for (uint32_t d = 1; d <= d_max; ++d) {
+    uint32_t m = 0;
+    int32_t sh = 0;
+    magic_u31(d, &m, &sh);
+    auto chk = [&](uint32_t n) {
+      if (n >= (1u << 31)) return;
+      const uint32_t q = sh < 0 ? n : (uint32_t)(((uint64_t)n * m) >> 32) >> sh;
+      if (q != n / d) ++bad;
+    };
+    for (uint32_t n = 0; n < 4096; ++n) chk(n);
+    const uint32_t top = (1u << 31) - 1u;
+    for (uint32_t k = 0; k < 64; ++k) chk(top - k);
+    for (uint64_t k = d; k < (1ull << 31); k = k * 3 + 7) {
+      chk((uint32_t)(k / d * d));
+      chk((uint32_t)(k / d * d - 1));
+      chk((uint32_t)(k / d * d + d - 1));
+    }
+  }
+  return bad;
+}
+
 hipError_t launch_eval(const EvalArgs& a) {
   hipError_t e = launch_collapse_only(a);
   if (e != hipSuccess) return e;
   if (a.max_q == 0) return hipSuccess;
-  Hw32 hw{a.hw.n_cu, a.hw.wave, a.hw.w_max, a.hw.b_max, a.hw.z_max,
-          a.hw.mem_lat, a.hw.dep_delay, a.hw.issue_cycles, a.hw.bw};
+  const Hw32 hw = make_hw32(a.hw);
   const float* coefs = reinterpret_cast<const float*>(a.ws);
   const CfgRec* recs = reinterpret_cast<const CfgRec*>(
       reinterpret_cast<const char*>(a.ws) + (int64_t)a.n_progs * a.max_cfg * kSlotFloats * sizeof(float));
@@ -531,16 +636,16 @@ hipError_t launch_eval(const EvalArgs& a) {
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     for (int i = 0; i < kNumVariants && e == hipSuccess; ++i) {
-      hipEventRecord(e0, a.stream);
-      e = launch_sweep(i, a, hw, coefs, recs);
-      hipEventRecord(e1, a.stream);
+      e = hipEventRecord(e0, a.stream);
+      if (e == hipSuccess) e = launch_sweep(i, a, hw, coefs, recs);
+      if (e == hipSuccess) e = hipEventRecord(e1, a.stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.0f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (e == hipSuccess && (i == 0 || ms < best)) { best = ms; bv = i; }
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return e;
     a.tuner->record(a.tune_key, bv, best);
     v = bv;

@@ -92,6 +92,7 @@ struct EvalArgs {
 size_t eval_workspace_bytes(int32_t n_progs, int32_t max_cfg);
 hipError_t launch_eval(const EvalArgs& a);
 int eval_num_variants();
+int64_t selftest_divisors(uint32_t d_max);
 
 // ---- fit ----------------------------------------------------------------------------------
 struct FitArgs {

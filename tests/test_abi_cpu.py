@@ -43,3 +43,9 @@ def test_null_handle_rejected_without_launch(lib):
     # host-detectable errors return before touching the device
     assert lib.klr_eval_argmin(None, None, 0, 0, 0, None, None, 0, None, 0, None, 0, None, 0, None,
                                0, None, None, None, 0, None, None, 0, None) == klr.KLR_E_INVALID
+
+
+def test_invariant_divisor_multiplication_exact(lib):
+    """floor(n / d) by multiply-high and shift, for every divisor up to 70000 (block sizes and
+    CU counts) on dividends around its multiples and at the top of [0, 2^31)."""
+    assert lib.klr_selftest_divisors(70000) == 0
