@@ -157,6 +157,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-sweep", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--kernel-only", choices=("eval", "fit", "copy"), default=None,
+                    help="run only this kernel --steps times (for hardware-counter runs); "
+                         "'copy' is a plain 1 GiB device copy used to calibrate byte counters")
     ap.add_argument("--surrogate-epochs", type=int, default=20)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -170,6 +173,16 @@ def main() -> int:
     from paper_1911_02373_amd import klr, synth
 
     lib = klr.Library.get()
+    if args.kernel_only == "copy":
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only": "copy", "bytes_read": x.numel() * 4, "bytes_written": y.numel() * 4,
+                          "launches": args.steps}), flush=True)
+        return 0
     t = time.perf_counter()
     pb = synth.config3_programs(args.seed, n_progs=1024, n_q=65536)
     fb = synth.config2_fits(args.seed, n_fits=4096, domain="2a")
@@ -188,6 +201,19 @@ def main() -> int:
     def step():
         lib.fit_batched(df, klr.KLR_FP64, FIT_MAX_ITER, FIT_TOL[0], out=fit_out)
         lib.eval_argmin(de, out=out)
+
+    if args.kernel_only is not None:
+        lib.eval_argmin(de, out=out)          # tune the sweep's launch shape outside the counted run
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            if args.kernel_only == "eval":
+                lib.eval_argmin(de, out=out)
+            else:
+                lib.fit_batched(df, klr.KLR_FP64, FIT_MAX_ITER, FIT_TOL[0], out=fit_out)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only": args.kernel_only, "launches": args.steps, "points": points,
+                          "fits": int(fb.n_fits), "fit_rows": int(fb.m.sum())}), flush=True)
+        return 0
 
     for _ in range(args.warmup):
         step()

@@ -412,9 +412,11 @@ __device__ int factor(const FitCtx& C, double unit) {
   return rank;
 }
 
-// Size class of a fit: 0 (n <= 32), 1 (<= 64), 2 (<= 128, and every invalid descriptor, which
-// the largest class reports as bad input).
+// Size class of a fit: 3 = one wavefront per fit (fit_wave.hip); otherwise one workgroup per
+// fit with 0 (n <= 32), 1 (<= 64), 2 (<= 128, and every invalid descriptor, which the largest
+// class reports as bad input).
 __device__ __forceinline__ int fit_class(const klr_fit_desc& d) {
+  if (wave_fit_eligible(d)) return 3;
   const int n = d.n_num + d.n_den - 1;
   const bool shape_ok = d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= KLR_MAX_UNKNOWNS;
   if (!shape_ok) return 2;
@@ -583,14 +585,15 @@ fit_kernel(FitArgs a, int cls) {
 // workgroups of a class then pop positions from that class's queue counter.  A fit's result
 // does not depend on which workgroup computes it, so outputs are deterministic.
 constexpr int kBuckets = 32;
+constexpr int kClasses = 4;
 struct Plan {
-  int32_t counts[3 * kBuckets];
-  int32_t offs[3 * kBuckets];
-  int32_t cursor[3 * kBuckets];
-  int32_t totals[3];
-  int32_t base[3];
-  int32_t queue[3];
-  int32_t pad[7];
+  int32_t counts[kClasses * kBuckets];
+  int32_t offs[kClasses * kBuckets];
+  int32_t cursor[kClasses * kBuckets];
+  int32_t totals[kClasses];
+  int32_t base[kClasses];
+  int32_t queue[kClasses];
+  int32_t pad[4];
 };
 
 __device__ __forceinline__ int cost_bucket(const klr_fit_desc& d) {
@@ -604,7 +607,7 @@ __device__ __forceinline__ int cost_bucket(const klr_fit_desc& d) {
 
 __global__ void fit_plan_zero(Plan* pl) {
   const int i = threadIdx.x;
-  if (i < 3 * kBuckets) pl->counts[i] = 0;
+  if (i < kClasses * kBuckets) pl->counts[i] = 0;
 }
 
 __global__ void __launch_bounds__(kFitBlock) fit_plan_count(FitArgs a, Plan* pl) {
@@ -617,7 +620,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_plan_count(FitArgs a, Plan* pl)
 __global__ void fit_plan_scan(Plan* pl) {
   if (threadIdx.x != 0) return;
   int32_t base = 0;
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < kClasses; ++c) {
     pl->base[c] = base;
     int32_t run = 0;
     for (int b = 0; b < kBuckets; ++b) {
@@ -687,11 +690,15 @@ hipError_t launch_all(const FitArgs& a, bool persistent) {
   hipError_t e = hipSuccess;
   if (persistent) {
     const unsigned g = (unsigned)((a.n_fits + kFitBlock - 1) / kFitBlock);
-    hipLaunchKernelGGL(fit_plan_zero, dim3(1), dim3(3 * kBuckets), 0, a.stream, pl);
+    hipLaunchKernelGGL(fit_plan_zero, dim3(1), dim3(kClasses * kBuckets), 0, a.stream, pl);
     hipLaunchKernelGGL(fit_plan_count, dim3(g), dim3(kFitBlock), 0, a.stream, a, pl);
     hipLaunchKernelGGL(fit_plan_scan, dim3(1), dim3(64), 0, a.stream, pl);
     hipLaunchKernelGGL(fit_plan_scatter, dim3(g), dim3(kFitBlock), 0, a.stream, a, pl, order);
     e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    const WavePlanView pv{order, &pl->totals[3], &pl->base[3], &pl->queue[3]};
+    e = launch_fit_wave(a, persistent, pv);
   }
   if (e == hipSuccess) e = launch_class<32, PREC>(a, 0, persistent, pl, order);
   if (e == hipSuccess) e = launch_class<64, PREC>(a, 1, persistent, pl, order);

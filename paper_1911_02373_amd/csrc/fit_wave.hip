@@ -1,0 +1,571 @@
+// Batched rational least-squares fits, one wavefront per fit (small fits), gfx950.
+//
+// Same problem and numerical method as the workgroup kernel in fit.hip (paper: step 2 of the
+// section "An Algorithm to Build and Deploy a Performance-Predicting Rational Program" and
+// section "Building a Driver Program: Rational function estimation"), organised for fits with
+// n <= 48 unknowns, v <= 4 variables and m <= 512 samples:
+//   * lane l owns sample rows l, l + 64, ... (scaled variables, target and residual in VGPRs);
+//   * Gram on MFMA (v_mfma_f64_16x16x4f64 for the FP64 path, v_mfma_f32_16x16x4f32 with FP32
+//     or BF16-rounded design-matrix values for the reduced paths): for each step of 4 rows the
+//     rows are broadcast from their owner lanes and every lane computes exactly the design-
+//     matrix elements of its MFMA operand slots (column l % 16 of each 16-column tile, row
+//     l / 16 of the step), so A is never stored;
+//   * equilibration, shift, diagonally pivoted Cholesky, triangular solves, reductions are
+//     wave-synchronous (no workgroup barriers); four independent fits per workgroup;
+//   * refinement: CGLS on the right-preconditioned problem with one pass over the rows per
+//     iteration: q = A t stays in registers, alpha needs only ||q||^2 (one wave reduction), the
+//     FP64 residual is updated in place and A^T r accumulated in the same pass; stopping by the
+//     delayed Hestenes-Stiefel estimate of ||A(y - y*)||.
+// MFMA layouts (wave64): for both v_mfma_f64_16x16x4f64 and v_mfma_f32_16x16x4f32 lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane l is
+// D[4 r + l / 16][l % 16] for the FP64 instruction and D[4 (l / 16) + r][l % 16] for the FP32 one.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace klr {
+namespace {
+
+constexpr int kNP = 48;            // padded unknowns: three 16-column tiles
+constexpr int kRPL = 8;            // sample rows per lane (m <= 512)
+constexpr int kV = 4;              // variables
+constexpr int kWavesPerGroup = 4;
+constexpr int kSP = kNP * (kNP + 1) / 2;
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct WaveLds {
+  double S[kSP];                   // equilibrated, shifted Gram -> pivoted Cholesky factor
+  double D[kNP];                   // power-of-two column scales
+  double c[kNP];                   // D A^T f
+  double z[kNP];                   // iterate (equilibrated coefficients)
+  double dz[kNP];                  // direction in the equilibrated coefficients
+  double t[kNP];                   // coefficient vector read by the row passes (unscaled)
+  double s[kNP], p[kNP];           // preconditioned normal residual and search direction
+  double g[kNP];                   // D A^T w written by the row passes
+  double piv[kNP];
+  double rd[kNP];                  // 1 / L_kk, pivot-indexed
+  int perm[kNP];
+  int ex[kNP];                     // exponents of column j, one byte per variable
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int symi(int a, int b) {
+  return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a;
+}
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ float round_bf16(float x) {
+  uint32_t b = __float_as_uint(x);
+  b = (b + 0x7FFFu + ((b >> 16) & 1u)) & 0xFFFF0000u;
+  return __uint_as_float(b);
+}
+
+// x~^e for one row (x[0..3]) and a packed exponent word (byte k = exponent of variable k).
+__device__ __forceinline__ double mono(const double* x, int e) {
+  double r = 1.0;
+#pragma unroll
+  for (int k = 0; k < kV; ++k) {
+    const int ek = (e >> (8 * k)) & 0xFF;
+    for (int q = 0; q < ek; ++q) r *= x[k];
+  }
+  return r;
+}
+
+// Design-matrix element of column j for a row with scaled variables x and target f.
+__device__ __forceinline__ double aval(const double* x, double f, int e, int j, int n_num, int n) {
+  if (j >= n) return 0.0;
+  const double m = mono(x, e);
+  return j < n_num ? m : -f * m;
+}
+
+template <int GP>
+struct GramTypes;
+template <>
+struct GramTypes<KLR_FP64> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ double in(double v) { return v; }
+  static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * r + grp; }
+};
+template <>
+struct GramTypes<KLR_FP32_REFINED> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ float in(double v) { return (float)v; }
+  static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * grp + r; }
+};
+template <>
+struct GramTypes<KLR_BF16_REFINED> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);   // products of BF16 values are exact in FP32
+  }
+  static __device__ __forceinline__ float in(double v) { return round_bf16((float)v); }
+  static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * grp + r; }
+};
+
+struct Rows {
+  double x[kRPL][kV];
+  double f[kRPL];
+  double r[kRPL];
+};
+
+// Gram of the equilibrated problem's unscaled matrix: S (packed lower) and c = A^T f.
+template <int GP>
+__device__ void gram(WaveLds& L, const Rows& R, int m, int n, int n_num) {
+  using GT = GramTypes<GP>;
+  typename GT::acc_t acc[6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) acc[t] = (typename GT::acc_t){0, 0, 0, 0};
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
+  int e[3];
+#pragma unroll
+  for (int ct = 0; ct < 3; ++ct) e[ct] = L.ex[ct * 16 + col];
+  double cacc[3] = {0.0, 0.0, 0.0};
+  const int steps = (m + 3) / 4;
+  for (int st = 0; st < steps; ++st) {
+    const int row = 4 * st + grp;             // this lane's row of the step
+    const int src = row & 63, slot = (4 * st) >> 6;
+    double xv[kV], fv = 0.0;
+#pragma unroll
+    for (int s = 0; s < kRPL; ++s) {
+      if (s == slot) {
+#pragma unroll
+        for (int k = 0; k < kV; ++k) xv[k] = __shfl(R.x[s][k], src);
+        fv = __shfl(R.f[s], src);
+      }
+    }
+    const bool live = row < m;
+    double a[3];
+#pragma unroll
+    for (int ct = 0; ct < 3; ++ct) a[ct] = live ? aval(xv, fv, e[ct], ct * 16 + col, n_num, n) : 0.0;
+#pragma unroll
+    for (int ct = 0; ct < 3; ++ct) cacc[ct] += a[ct] * fv;
+    acc[0] = GT::mfma(GT::in(a[0]), GT::in(a[0]), acc[0]);   // tile (0, 0)
+    acc[1] = GT::mfma(GT::in(a[1]), GT::in(a[0]), acc[1]);   // tile (1, 0)
+    acc[2] = GT::mfma(GT::in(a[1]), GT::in(a[1]), acc[2]);   // tile (1, 1)
+    acc[3] = GT::mfma(GT::in(a[2]), GT::in(a[0]), acc[3]);   // tile (2, 0)
+    acc[4] = GT::mfma(GT::in(a[2]), GT::in(a[1]), acc[4]);   // tile (2, 1)
+    acc[5] = GT::mfma(GT::in(a[2]), GT::in(a[2]), acc[5]);   // tile (2, 2)
+  }
+  const int tj[6] = {0, 1, 1, 2, 2, 2}, tk[6] = {0, 0, 1, 0, 1, 2};
+#pragma unroll
+  for (int t = 0; t < 6; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = tj[t] * 16 + GT::out_row(grp, r), k = tk[t] * 16 + col;
+      if (j < n && k < n && k <= j) L.S[symi(j, k)] = (double)acc[t][r];
+    }
+#pragma unroll
+  for (int ct = 0; ct < 3; ++ct) {
+    double v = cacc[ct];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    if (grp == 0 && ct * 16 + col < n) L.c[ct * 16 + col] = v;
+  }
+  wave_sync();
+}
+
+// Equilibrate, shift by mu = 8 u tr / n, diagonally pivoted Cholesky.  Returns the rank.
+__device__ int factor_wave(WaveLds& L, int n, double unit) {
+  const int lane = threadIdx.x & 63;
+  if (lane < n) {
+    const double gjj = L.S[symi(lane, lane)];
+    int e = 0;
+    if (gjj > 0.0 && isfinite(gjj)) frexp(sqrt(gjj), &e);
+    L.D[lane] = ldexp(1.0, -e);
+    L.perm[lane] = lane;
+  }
+  wave_sync();
+  for (int idx = lane; idx < n * (n + 1) / 2; idx += 64) {
+    int j = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+    while (j * (j + 1) / 2 > idx) --j;
+    const int k = idx - j * (j + 1) / 2;
+    L.S[idx] *= L.D[j] * L.D[k];
+  }
+  if (lane < n) L.c[lane] *= L.D[lane];
+  wave_sync();
+  double tr = lane < n ? L.S[symi(lane, lane)] : 0.0;
+  tr = wsum(tr);
+  const double mu = 8.0 * unit * tr / n + 1e-300;
+  if (lane < n) L.S[symi(lane, lane)] += mu;
+  wave_sync();
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = n;
+    if (lane >= k && lane < n) { best = L.S[symi(L.perm[lane], L.perm[lane])]; bi = lane; }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const int pk = L.perm[bi];
+    const int pold = L.perm[k];
+    wave_sync();
+    if (lane == 0) {
+      L.perm[k] = pk;
+      L.perm[bi] = pold;
+      L.piv[k] = best;
+      L.S[symi(pk, pk)] = sqrt(best > 0.0 ? best : mu);
+    }
+    wave_sync();
+    const double lkk = L.S[symi(pk, pk)];
+    if (lane > k && lane < n) L.S[symi(L.perm[lane], pk)] /= lkk;
+    wave_sync();
+    const int w = n - k - 1;
+    for (int e = lane; e < w * w; e += 64) {
+      const int ii = e / w, jj = e - ii * w;
+      if (jj <= ii) {
+        const int ra = L.perm[k + 1 + ii], rb = L.perm[k + 1 + jj];
+        L.S[symi(ra, rb)] -= L.S[symi(ra, pk)] * L.S[symi(rb, pk)];
+      }
+    }
+    wave_sync();
+  }
+  if (lane < n) L.rd[lane] = 1.0 / L.S[symi(L.perm[lane], L.perm[lane])];
+  const unsigned long long full = __ballot(lane < n && L.piv[lane] > 4.0 * mu);
+  wave_sync();
+  return __popcll(full);
+}
+
+// L u = in[perm] (out pivot-indexed).
+__device__ void fwd_wave(const WaveLds& L, int n, const double* in, double* out) {
+  const int lane = threadIdx.x & 63;
+  double b = lane < n ? in[L.perm[lane]] : 0.0;
+  const int pl = lane < n ? L.perm[lane] : 0;
+  for (int k = 0; k < n; ++k) {
+    const int pk = L.perm[k];
+    const double uk = __shfl(b, k) * L.rd[k];
+    if (lane == k) b = uk;
+    if (lane > k && lane < n) b -= L.S[symi(pl, pk)] * uk;
+  }
+  if (lane < n) out[lane] = b;
+  wave_sync();
+}
+
+// L^T v = in (pivot-indexed); out[perm[i]] = v_i.
+__device__ void bwd_wave(const WaveLds& L, int n, const double* in, double* out) {
+  const int lane = threadIdx.x & 63;
+  double b = lane < n ? in[lane] : 0.0;
+  const int pl = lane < n ? L.perm[lane] : 0;
+  for (int k = n - 1; k >= 0; --k) {
+    const int pk = L.perm[k];
+    const double vk = __shfl(b, k) * L.rd[k];
+    if (lane == k) b = vk;
+    if (lane < k) b -= L.S[symi(pk, pl)] * vk;
+  }
+  if (lane < n) out[pl] = b;
+  wave_sync();
+}
+
+__device__ __forceinline__ double dotw(const double* a, const double* b, int n) {
+  const int lane = threadIdx.x & 63;
+  return wsum(lane < n ? a[lane] * b[lane] : 0.0);
+}
+
+// Monomial x~^e of column e (packed exponents, wave-uniform) for each of the lane's rows.
+__device__ __forceinline__ void mono_rows(const Rows& R, int e, double* mo) {
+#pragma unroll
+  for (int s = 0; s < kRPL; ++s) mo[s] = 1.0;
+#pragma unroll
+  for (int k = 0; k < kV; ++k) {
+    const int ek = (e >> (8 * k)) & 0xFF;
+    for (int q = 0; q < ek; ++q)
+#pragma unroll
+      for (int s = 0; s < kRPL; ++s) mo[s] *= R.x[s][k];
+  }
+}
+
+// One pass over the rows with the coefficient vector y held in L.t (D z of the iterate or of the
+// direction): d_i = A_i . y = p_i - f_i s_i with p_i, s_i the numerator and denominator parts.
+//   mode 0: r = f - d, then g = D A^T r;
+//   mode 1: d is the CGLS image q = A D dz: *qq = ||q||^2, alpha = gamma / ||q||^2, the FP64
+//           residual is updated in place (r -= alpha q) and g = D A^T r from the updated residual;
+//   mode 2: returns ||f - d||^2 and counts q(x~_i) = 1 + s_i <= 0 into *qneg.
+// Column exponents are read into scalar registers, so the monomial loops are uniform.
+// Returns alpha in mode 1.
+template <int MODE>
+__device__ double row_pass(WaveLds& L, Rows& R, int m, int n, int n_num, double gamma, double* qq, int* qneg) {
+  const int lane = threadIdx.x & 63;
+  double pn[kRPL], pd[kRPL], mo[kRPL];
+#pragma unroll
+  for (int s = 0; s < kRPL; ++s) pn[s] = pd[s] = 0.0;
+  for (int j = 0; j < n_num; ++j) {
+    mono_rows(R, __builtin_amdgcn_readfirstlane(L.ex[j]), mo);
+    const double tj = L.t[j];
+#pragma unroll
+    for (int s = 0; s < kRPL; ++s) pn[s] += mo[s] * tj;
+  }
+  for (int j = n_num; j < n; ++j) {
+    mono_rows(R, __builtin_amdgcn_readfirstlane(L.ex[j]), mo);
+    const double tj = L.t[j];
+#pragma unroll
+    for (int s = 0; s < kRPL; ++s) pd[s] += mo[s] * tj;
+  }
+  double sq = 0.0;
+  int qn = 0;
+  double d[kRPL];
+#pragma unroll
+  for (int s = 0; s < kRPL; ++s) {
+    const bool live = lane + 64 * s < m;
+    d[s] = live ? pn[s] - R.f[s] * pd[s] : 0.0;
+    if (MODE == 0 && live) R.r[s] = R.f[s] - d[s];
+    if (MODE == 1) sq += d[s] * d[s];
+    if (MODE == 2 && live) {
+      const double res = R.f[s] - d[s];
+      sq += res * res;
+      if (!(1.0 + pd[s] > 0.0)) ++qn;
+    }
+  }
+  if (MODE == 2) {
+    int q = qn;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) q += __shfl_xor(q, off);
+    *qneg = q;
+    return wsum(sq);
+  }
+  double alpha = 0.0;
+  if (MODE == 1) {
+    const double qn2 = wsum(sq);
+    *qq = qn2;
+    alpha = qn2 > 0.0 ? gamma / qn2 : 0.0;
+#pragma unroll
+    for (int s = 0; s < kRPL; ++s) R.r[s] -= alpha * d[s];
+  }
+  // g_j = D_j sum_i A_ij r_i: numerator columns weigh r_i, denominator columns -f_i r_i
+  double wf[kRPL];
+#pragma unroll
+  for (int s = 0; s < kRPL; ++s) wf[s] = -R.f[s] * R.r[s];
+  for (int j = 0; j < n; ++j) {
+    mono_rows(R, __builtin_amdgcn_readfirstlane(L.ex[j]), mo);
+    double v = 0.0;
+    if (j < n_num) {
+#pragma unroll
+      for (int s = 0; s < kRPL; ++s) v += mo[s] * R.r[s];
+    } else {
+#pragma unroll
+      for (int s = 0; s < kRPL; ++s) v += mo[s] * wf[s];
+    }
+    v = wsum(v);
+    if (lane == 0) L.g[j] = v * L.D[j];
+  }
+  wave_sync();
+  return alpha;
+}
+
+template <int PREC>
+__device__ void fit_wave_one(const FitArgs& a, int fi, WaveLds& L) {
+  const int lane = threadIdx.x & 63;
+  const klr_fit_desc d = a.desc[fi];
+  const int n = d.n_num + d.n_den - 1;
+  const bool coef_ok = d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= kNP && d.coef0 >= 0 &&
+                       d.coef0 + (int64_t)n <= a.coef_len;
+  bool ok = coef_ok && d.v >= 1 && d.v <= kV && d.m >= 1 && d.m <= kRPL * 64 && d.x0 >= 0 &&
+            d.x0 + (int64_t)d.m * d.v <= a.x_len && d.f0 >= 0 && d.f0 + (int64_t)d.m <= a.f_len &&
+            d.num0 >= 0 && (int64_t)d.num0 + d.n_num <= a.n_exp_rows && d.den0 >= 0 &&
+            (int64_t)d.den0 + d.n_den <= a.n_exp_rows;
+  if (ok)
+#pragma unroll
+    for (int k = 0; k < kV; ++k)
+      if (k < d.v) {
+        if (d.scale_exp[k] < -100 || d.scale_exp[k] > 100) ok = false;
+        if (a.exps[(int64_t)d.den0 * KLR_MAX_VARS + k] != 0) ok = false;
+      }
+  klr_fit_info info{};
+  Rows R;
+#pragma unroll
+  for (int s = 0; s < kRPL; ++s) {
+#pragma unroll
+    for (int k = 0; k < kV; ++k) R.x[s][k] = 0.0;
+    R.f[s] = 0.0;
+    R.r[s] = 0.0;
+  }
+  bool bad = !ok;
+  if (ok) {
+    if (lane < kNP) {
+      int w = 0;
+      if (lane < n) {
+        const int row = lane < d.n_num ? d.num0 + lane : d.den0 + (lane - d.n_num + 1);
+        for (int k = 0; k < d.v; ++k) w |= (int)a.exps[(int64_t)row * KLR_MAX_VARS + k] << (8 * k);
+      }
+      L.ex[lane] = w;
+    }
+    bool nonfinite = false;
+#pragma unroll
+    for (int s = 0; s < kRPL; ++s) {
+      const int i = lane + 64 * s;
+      if (i < d.m) {
+#pragma unroll
+        for (int k = 0; k < kV; ++k)
+          if (k < d.v) R.x[s][k] = ldexp((double)a.X[d.x0 + (int64_t)i * d.v + k], -(int)d.scale_exp[k]);
+        R.f[s] = a.f[d.f0 + i];
+        nonfinite |= !isfinite(R.f[s]);
+      }
+    }
+    bad = __any(nonfinite);
+    wave_sync();
+  }
+  if (bad) {
+    if (coef_ok)
+      for (int j = lane; j < n; j += 64) a.coef[d.coef0 + j] = 0.0;
+    if (lane == 0) {
+      info.status = KLR_FIT_BAD_INPUT;
+      info.resid_norm = NAN;
+      info.err_est = NAN;
+      a.info[fi] = info;
+    }
+    return;
+  }
+  double fn2 = 0.0;
+#pragma unroll
+  for (int s = 0; s < kRPL; ++s) fn2 += R.f[s] * R.f[s];
+  const double fnorm = sqrt(wsum(fn2));
+
+  int prec = PREC, iters = 0, rank = 0;
+  bool converged = false;
+  double err = 0.0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    double unit;
+    if (prec == KLR_FP64) { gram<KLR_FP64>(L, R, d.m, n, d.n_num); unit = 0x1p-53; }
+    else if (prec == KLR_FP32_REFINED) { gram<KLR_FP32_REFINED>(L, R, d.m, n, d.n_num); unit = 0x1p-24; }
+    else { gram<KLR_BF16_REFINED>(L, R, d.m, n, d.n_num); unit = 0x1p-8; }
+    rank = factor_wave(L, n, unit);
+    fwd_wave(L, n, L.c, L.s);                          // z0 = (G~ + mu I)^-1 D A^T f
+    bwd_wave(L, n, L.s, L.z);
+    if (lane < n) L.t[lane] = L.D[lane] * L.z[lane];
+    wave_sync();
+    row_pass<0>(L, R, d.m, n, d.n_num, 0.0, nullptr, nullptr);   // r0 = f - A y0, g = D A^T r0
+    fwd_wave(L, n, L.g, L.s);                          // s0 = R^-T Pi^T g
+    if (lane < n) L.p[lane] = L.s[lane];
+    wave_sync();
+    double gamma = dotw(L.s, L.s, n);
+    iters = 0;
+    converged = a.max_iter == 0 || gamma == 0.0;
+    err = 0.0;
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0;   // the last three alpha gamma terms
+    const int need = a.max_iter < 3 ? a.max_iter : 3;
+    for (int it = 0; it < a.max_iter && !converged; ++it) {
+      bwd_wave(L, n, L.p, L.dz);                       // dz = Pi R^-1 p
+      if (lane < n) L.t[lane] = L.D[lane] * L.dz[lane];
+      wave_sync();
+      double qq = 0.0;   // ||A D dz||^2; r -= alpha A D dz; g = D A^T r
+      const double alpha = row_pass<1>(L, R, d.m, n, d.n_num, gamma, &qq, nullptr);
+      if (lane < n) L.z[lane] += alpha * L.dz[lane];
+      wave_sync();
+      h0 = h1;
+      h1 = h2;
+      h2 = alpha * gamma;
+      ++iters;
+      if (it + 1 >= need) {
+        const double est = sqrt(h0 + h1 + h2);
+        err = fnorm > 0.0 ? est / fnorm : 0.0;
+        if (est <= a.tol * fnorm) { converged = true; break; }
+      }
+      if (qq == 0.0) { converged = true; break; }
+      fwd_wave(L, n, L.g, L.s);                        // s = B^T r from the updated residual
+      const double gnew = dotw(L.s, L.s, n);
+      const double beta = gamma > 0.0 ? gnew / gamma : 0.0;
+      if (lane < n) L.p[lane] = L.s[lane] + beta * L.p[lane];
+      wave_sync();
+      gamma = gnew;
+      if (gamma == 0.0) { converged = true; break; }
+    }
+    if (converged || prec == KLR_FP64) break;
+    info.status |= KLR_FIT_FELL_BACK_FP64;
+    prec = KLR_FP64;
+  }
+  if (lane < n) L.t[lane] = L.D[lane] * L.z[lane];
+  wave_sync();
+  int qneg = 0;
+  const double rr = row_pass<2>(L, R, d.m, n, d.n_num, 0.0, nullptr, &qneg);
+  if (lane < n) a.coef[d.coef0 + lane] = L.t[lane];
+  if (lane == 0) {
+    if (rank < n) info.status |= KLR_FIT_RANK_DEFICIENT;
+    if (d.m < n) info.status |= KLR_FIT_UNDERDETERMINED;
+    if (!converged) info.status |= KLR_FIT_NOT_CONVERGED;
+    if (qneg > 0) info.status |= KLR_FIT_Q_NONPOS;
+    info.rank = rank;
+    info.iters = iters;
+    info.q_nonpos = qneg;
+    info.resid_norm = sqrt(rr);
+    info.err_est = err;
+    a.info[fi] = info;
+  }
+  wave_sync();
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(2)))
+fit_wave_persistent(FitArgs a, WavePlanView pv) {
+  __shared__ WaveLds lds[kWavesPerGroup];
+  WaveLds& L = lds[threadIdx.x >> 6];
+  const int total = *pv.total, base = *pv.base;
+  for (;;) {
+    int i = 0;
+    if ((threadIdx.x & 63) == 0) i = atomicAdd(pv.queue, 1);
+    i = __shfl(i, 0);
+    if (i >= total) break;
+    fit_wave_one<PREC>(a, pv.order[base + i], L);
+  }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(2))) fit_wave_plain(FitArgs a) {
+  __shared__ WaveLds lds[kWavesPerGroup];
+  const int fi = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+  if (fi >= a.n_fits || !wave_fit_eligible(a.desc[fi])) return;
+  fit_wave_one<PREC>(a, fi, lds[threadIdx.x >> 6]);
+}
+
+template <int PREC>
+hipError_t launch_wave_t(const FitArgs& a, bool persistent, const WavePlanView& pv) {
+  const int block = 64 * kWavesPerGroup;
+  if (!persistent) {
+    hipLaunchKernelGGL(fit_wave_plain<PREC>, dim3((unsigned)((a.n_fits + kWavesPerGroup - 1) / kWavesPerGroup)),
+                       dim3(block), 0, a.stream, a);
+    return hipGetLastError();
+  }
+  int dev = 0, ncu = 0, occ = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&fit_wave_persistent<PREC>),
+                                                     block, 0);
+  if (e != hipSuccess) return e;
+  int64_t g = (int64_t)ncu * (occ > 0 ? occ : 1);
+  const int64_t need = (a.n_fits + kWavesPerGroup - 1) / kWavesPerGroup;
+  if (g > need) g = need;
+  hipLaunchKernelGGL(fit_wave_persistent<PREC>, dim3((unsigned)g), dim3(block), 0, a.stream, a, pv);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fit_wave(const FitArgs& a, bool persistent, const WavePlanView& pv) {
+  if (a.precision == KLR_FP64) return launch_wave_t<KLR_FP64>(a, persistent, pv);
+  if (a.precision == KLR_FP32_REFINED) return launch_wave_t<KLR_FP32_REFINED>(a, persistent, pv);
+  return launch_wave_t<KLR_BF16_REFINED>(a, persistent, pv);
+}
+
+}  // namespace klr

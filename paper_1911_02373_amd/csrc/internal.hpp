@@ -119,6 +119,19 @@ struct FitArgs {
 size_t fit_workspace_bytes(int32_t n_fits, int64_t f_len, int32_t precision);
 hipError_t launch_fit(const FitArgs& a);
 
+// Fits small enough for one wavefront: n <= 48 unknowns, v <= 4 variables, m <= 512 samples.
+__host__ __device__ inline bool wave_fit_eligible(const klr_fit_desc& d) {
+  const int n = d.n_num + d.n_den - 1;
+  return d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= 48 && d.v >= 1 && d.v <= 4 && d.m >= 1 && d.m <= 512;
+}
+struct WavePlanView {        // the wave-fit queue of the persistent schedule
+  const int32_t* order;
+  const int32_t* total;
+  const int32_t* base;
+  int32_t* queue;
+};
+hipError_t launch_fit_wave(const FitArgs& a, bool persistent, const WavePlanView& pv);
+
 // ---- surrogate network ----------------------------------------------------------------------
 // Parameter vector layout (floats): W2[256][256] | W1[256][4] | b1 | b2 | w3 | b3 | pad | emb.
 constexpr int kO_W2 = 0;
