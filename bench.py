@@ -41,12 +41,14 @@ FIT_MAX_ITER = 256
 
 def eval_ops_per_point(degree: int) -> int:
     """Operations of the normative FP32 sequence per (query, configuration) point, each IEEE
-    add / mul / div / compare / select / conversion and each integer op counted once.
+    add / mul / fused multiply-add / div / compare / select / conversion and each integer op
+    counted once (each is at least one lane-instruction).
 
-    per metric (8): scale 1, Horner 4*degree, q > 0 1, divide 1, finiteness 1, clean 1, and 1
-    clamps 14, occupancy 13, grid and repetitions 14, cycle estimate 49, argmin update 3,
+    per metric (8): scale 1, Horner 2*degree (one fused multiply-add per power, p and q),
+    q > 0 1, divide 1, finiteness 1, clean 1, and 1; clamps 14, occupancy 13, grid and
+    repetitions 14, cycle estimate 43 (six of its a*b + c terms fused), argmin update 3,
     data-size conversion 1."""
-    return 8 * (6 + 4 * degree) + 14 + 13 + 14 + 49 + 3 + 1
+    return 8 * (6 + 2 * degree) + 14 + 13 + 14 + 43 + 3 + 1
 
 
 def fit_flops(m, n, iters):
@@ -58,6 +60,38 @@ def fit_flops(m, n, iters):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "eval_kernel_hbm_traffic.md")
+EVAL_SOURCE = os.path.join(ROOT, "paper_1911_02373_amd", "csrc", "eval.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the evaluation kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each divided by what the same counter reads
+    for a plain device copy of known size), or None when the kernel source changed since the
+    counters were taken or no summary exists."""
+    import hashlib
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            lines = f.read().splitlines()
+        with open(EVAL_SOURCE, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        if ln.startswith("- ") and ": " in ln:
+            k, v = ln[2:].split(": ", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    try:
+        if kv.get("eval.hip sha256") != digest:
+            return None
+        fetch = float(kv["FETCH_SIZE KiB per launch"]) / float(kv["FETCH_SIZE copy factor"])
+        write = float(kv["WRITE_SIZE KiB per launch"]) / float(kv["WRITE_SIZE copy factor"])
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+    return (fetch + write) * 1024.0
 
 
 def surrogate_component(lib, klr, synth, pb, de, exact_ms, seed, epochs, regret_programs=64):
@@ -295,7 +329,7 @@ def main() -> int:
         "components": comps,
         "roofline": {"bound": "alu", "kernel": "eval_kernel", "achieved": achieved,
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "ops_per_point": ops, "traffic": None},
+                     "ops_per_point": ops, "traffic": measured_traffic()},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(pb, fb, args.cpu_budget_s, points, fb.n_fits)

@@ -25,9 +25,17 @@ Two precisions:
   truth  - FP64: each metric is the full multivariate p/q evaluated directly at (N~, L~).
   replay - FP32: the normative FP32 operation sequence: per (program, config) the metric
            polynomials are collapsed to polynomials in N~ (FP64, monomial order, then rounded to
-           FP32); per point Horner with separately rounded multiply and add, correctly rounded
-           division, explicit compare-select min/max, exact integer parts.  The argmin is
-           decided in this precision on both sides.
+           FP32); per point Horner by fused multiply-add (one rounding per step), the a*b + c
+           terms of the cycle estimate fused the same way, every other operation rounded on its
+           own, correctly rounded division, explicit compare-select min/max, exact integer
+           parts.  The argmin is decided in this precision on both sides.
+
+Fused multiply-add in FP32 (fma32): a*b is exact in FP64 (two 24-bit significands); the FP64 sum
+with a*b is rounded to odd (the exact error of the FP64 addition, from the two-sum, decides
+whether the result moves to its odd neighbour), and rounding that to FP32 by round-to-nearest-even
+gives the correctly rounded a*b + c, since FP64 carries more than FP32's precision plus two bits
+(Boldo and Melquiond, "Emulation of FMA and correctly rounded sums: proved algorithms using
+rounding to odd", IEEE Trans. Computers 57(4), 2008).
 
 Metric order: I_comp, I_mc, I_mu, U, I_sync, R, Z, B_w.
 """
@@ -122,12 +130,35 @@ def collapse(coef, E_num, E_den, s, L):
     return np.array(a, np.float32), np.array(b, np.float32)
 
 
+def fma32(a, b, c):
+    """Correctly rounded FP32 a*b + c (one rounding), elementwise, by rounding to odd in FP64."""
+    a, b, c = np.broadcast_arrays(np.asarray(a, np.float32), np.asarray(b, np.float32),
+                                  np.asarray(c, np.float32))
+    with np.errstate(all="ignore"):
+        p = a.astype(np.float64) * b.astype(np.float64)          # exact
+        c64 = c.astype(np.float64)
+        s = p + c64
+        bv = s - p                                                # two-sum: s + e = p + c exactly
+        e = (p - (s - bv)) + (c64 - bv)
+        even = (s.view(np.int64) & 1) == 0
+        move = np.isfinite(s) & np.isfinite(e) & (e != 0) & even
+        toward = np.where(e > 0, np.inf, -np.inf)
+        s = np.where(move, np.nextafter(s, toward), s)
+        return s.astype(np.float32)
+
+
+def _fma(a, b, c, dt):
+    """a*b + c with one rounding in the replay (FP32); plain FP64 arithmetic for the truth."""
+    if dt == np.float32:
+        return fma32(a, b, c)
+    return np.asarray(a, dt) * np.asarray(b, dt) + np.asarray(c, dt)
+
+
 def horner32(c, x):
-    """FP32 Horner over powers MAX_NDEG..0, multiply and add rounded separately."""
+    """FP32 Horner over powers MAX_NDEG..0 by fused multiply-add (zero padding at the top is exact)."""
     acc = np.full(x.shape, c[MAX_NDEG], np.float32)
     for d in range(MAX_NDEG - 1, -1, -1):
-        acc = acc * x
-        acc = acc + c[d]
+        acc = fma32(acc, x, c[d])
     return acc
 
 
@@ -183,18 +214,13 @@ def cycles_from_metrics(g, N, L, grid_kind, hw, dt):
         iss, bw = F(hw.issue_cycles), F(hw.bw)
 
         Im = Imc + Imu
-        Lu = U - F(1)
-        Lu = Lu * dep
-        Lu = Lu + lat
-        mem = lat * Imc
-        t = Lu * Imu
-        mem = mem + t
+        Lu = _fma(U - F(1), dep, lat, dt)            # (U - 1) dep + lat
+        mem = _fma(Lu, Imu, lat * Imc, dt)           # lat I_mc + L_u I_mu
         comp = Icomp + Im
         comp = iss * comp
 
         # memory-bound branch quantities (computed everywhere, selected where Im > 0)
-        d1 = U * Imu
-        d1 = Imc + d1
+        d1 = _fma(U, Imu, Imc, dt)                   # I_mc + U I_mu
         d1 = dep * d1
         mwp_lat = mem / d1
         n2 = bw * mem
@@ -207,14 +233,12 @@ def cycles_from_metrics(g, N, L, grid_kind, hw, dt):
         cwp_full = tot >= Nwf * comp
         cwp_ge_mwp = tot >= mwp * comp
         cpm = comp / Im
-        ovl = mwp - F(1)
-        ovl = cpm * ovl
-        e1 = tot + ovl
+        m1 = mwp - F(1)
+        e1 = _fma(cpm, m1, tot, dt)                  # tot + cpm (MWP - 1)
         t2 = mem * Nwf
         t2 = t2 / mwp
-        e2 = t2 + ovl
-        t3 = comp * Nwf
-        e3 = lat + t3
+        e2 = _fma(cpm, m1, t2, dt)                   # mem N_w / MWP + cpm (MWP - 1)
+        e3 = _fma(comp, Nwf, lat, dt)                # lat + comp N_w
         case1 = (mwp >= Nwf) & cwp_full
         case2 = cwp_ge_mwp | (comp > mem)
         ex_mem = np.where(case1, e1, np.where(case2, e2, e3))
@@ -223,13 +247,12 @@ def cycles_from_metrics(g, N, L, grid_kind, hw, dt):
         mwp = np.where(pure, F(1), mwp)
         ex = np.where(pure, comp * Nwf, ex_mem)
 
-        cost = ex * repf
         sy = mwp - F(1)
         sy = dep * sy
         sy = sy * Isync
         sy = sy * Bf
         sy = sy * repf
-        cost = cost + sy
+        cost = _fma(ex, repf, sy, dt)                # exec rep + sync
         ok &= np.isfinite(cost)
     return np.where(ok, cost, dt(np.inf)).astype(dt)
 

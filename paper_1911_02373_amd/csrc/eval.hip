@@ -16,7 +16,9 @@
 //               the configuration's coefficients are wave-uniform (scalar loads), so each lane
 //               keeps its own running (cost, index) minimum with a strict "<" and no cross-lane
 //               reduction is needed.  All decisions are taken in FP32 with the exact operation
-//               order (no contraction: this file is compiled with -ffp-contract=off), correctly
+//               order: fused multiply-adds exactly where written (the Horner steps and the
+//               a b + c terms of the cycle estimate), every other operation rounded on its own
+//               (no contraction: this file is compiled with -ffp-contract=off), correctly
 //               rounded division and compare-select min/max, so a CPU replay reproduces every
 //               cost and index bit for bit.
 #include <hip/hip_runtime.h>
@@ -231,7 +233,8 @@ Hw32 make_hw32(const klr_hw& h) {
 
 // Cost of one (query, configuration) point; +inf where inadmissible.  DEG: the program's highest
 // power of N~ (Horner from there; the normative sequence starts at power 3 with zero
-// coefficients above DEG, which gives bit-identical values because 0 x + a = a exactly).
+// coefficients above DEG, which gives bit-identical values because fma(0, x, a) = a exactly for
+// finite x and a != -0, and collapsed coefficients are sums that start from +0).
 template <int GRID, int DEG = kNdeg>
 __device__ __forceinline__ float point_cost(int32_t N, const float* __restrict__ cf, const CfgRec& r,
                                             const Hw32& hw) {
@@ -246,10 +249,8 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* __restrict__
     float q = c[kNdeg + 1 + DEG];
 #pragma unroll
     for (int d = DEG - 1; d >= 0; --d) {
-      p = p * x;
-      p = p + c[d];
-      q = q * x;
-      q = q + c[kNdeg + 1 + d];
+      p = __builtin_fmaf(p, x, c[d]);
+      q = __builtin_fmaf(q, x, c[kNdeg + 1 + d]);
     }
     const float v = p / q;
     const bool good = (q > 0.0f) & (fabsf(v) <= 3.402823466e38f);
@@ -293,17 +294,12 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* __restrict__
   const float Bf = (float)Bs;
 
   const float Im = Imc + Imu;
-  float Lu = U - 1.0f;
-  Lu = Lu * hw.dep;
-  Lu = Lu + hw.lat;
-  float mem = hw.lat * Imc;
-  const float tu = Lu * Imu;
-  mem = mem + tu;
+  const float Lu = __builtin_fmaf(U - 1.0f, hw.dep, hw.lat);      // (U - 1) dep + lat
+  const float mem = __builtin_fmaf(Lu, Imu, hw.lat * Imc);         // lat I_mc + L_u I_mu
   float comp = Icomp + Im;
   comp = hw.iss * comp;
 
-  float d1 = U * Imu;
-  d1 = Imc + d1;
+  float d1 = __builtin_fmaf(U, Imu, Imc);                          // I_mc + U I_mu
   d1 = hw.dep * d1;
   const float mwp_lat = mem / d1;
   const float n2 = hw.bw * mem;
@@ -316,14 +312,12 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* __restrict__
   const bool cwp_full = tot >= Nwf * comp;
   const bool cwp_ge_mwp = tot >= mwp * comp;
   const float cpm = comp / Im;
-  float ovl = mwp - 1.0f;
-  ovl = cpm * ovl;
-  const float e1 = tot + ovl;
+  const float m1 = mwp - 1.0f;
+  const float e1 = __builtin_fmaf(cpm, m1, tot);                   // tot + cpm (MWP - 1)
   float t2 = mem * Nwf;
   t2 = t2 / mwp;
-  const float e2 = t2 + ovl;
-  const float t3 = comp * Nwf;
-  const float e3 = hw.lat + t3;
+  const float e2 = __builtin_fmaf(cpm, m1, t2);                    // mem N_w / MWP + cpm (MWP - 1)
+  const float e3 = __builtin_fmaf(comp, Nwf, hw.lat);              // lat + comp N_w
   const bool case1 = (mwp >= Nwf) & cwp_full;
   const bool case2 = cwp_ge_mwp | (comp > mem);
   float ex = case1 ? e1 : (case2 ? e2 : e3);
@@ -331,13 +325,12 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* __restrict__
   mwp = pure ? 1.0f : mwp;
   ex = pure ? comp * Nwf : ex;
 
-  float cost = ex * repf;
   float sy = mwp - 1.0f;
   sy = hw.dep * sy;
   sy = sy * Isync;
   sy = sy * Bf;
   sy = sy * repf;
-  cost = cost + sy;
+  const float cost = __builtin_fmaf(ex, repf, sy);                 // exec rep + sync
   ok = ok & (fabsf(cost) <= 3.402823466e38f);
   return ok ? cost : INFINITY;
 }

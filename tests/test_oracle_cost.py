@@ -138,3 +138,72 @@ def test_config3_launch_configs():
     # the pad is never admissible
     pb = synth.config3_programs(1, n_progs=1, n_q=100)
     assert np.all(np.isinf(oc.program_costs(pb, 0)[127]))
+
+
+# ---------------------------------------------------------------------------------------------
+# FP32 fused multiply-add of the replay, against exact rational arithmetic
+
+def _round_f32_exact(x):
+    """Correctly rounded (nearest, ties to even) FP32 of an exact Fraction, by comparing the
+    FP32 neighbours of a nearby candidate exactly."""
+    from fractions import Fraction
+    f = np.float32(float(x))
+    cands = [np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))]
+    best = None
+    for c in cands:
+        if not np.isfinite(c):
+            continue
+        d = abs(Fraction(float(c)) - x)
+        if best is None or d < best[0] or (d == best[0] and (int(np.float32(c).view(np.int32)) & 1) == 0):
+            best = (d, c)
+    return np.float32(best[1])
+
+
+def _fma_exact(a, b, c):
+    from fractions import Fraction
+    return _round_f32_exact(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
+
+
+def test_fma32_matches_exact_rounding_on_random_inputs():
+    rng = np.random.default_rng(7)
+    n = 3000
+    a = (rng.standard_normal(n) * 2.0 ** rng.integers(-20, 20, n)).astype(np.float32)
+    b = (rng.standard_normal(n) * 2.0 ** rng.integers(-20, 20, n)).astype(np.float32)
+    c = (rng.standard_normal(n) * 2.0 ** rng.integers(-30, 30, n)).astype(np.float32)
+    c[: n // 3] = -(a[: n // 3] * b[: n // 3])                # near cancellation
+    got = oc.fma32(a, b, c)
+    want = np.array([_fma_exact(x, y, z) for x, y, z in zip(a, b, c)], np.float32)
+    assert np.array_equal(got.view(np.int32), want.view(np.int32))
+
+
+def test_fma32_single_rounding_where_double_rounding_fails():
+    """a b + c lands a hair off an FP32 halfway point, inside FP64's last place: rounding to FP64
+    first produces an exact tie that ties-to-even resolves the wrong way; one rounding does not."""
+    cases = []
+    for i in (1, 3, 77, 300):
+        for c in (np.float32(1 + 2.0 ** -23), np.float32(3.0 + 2.0 ** -22), np.float32(-(1 + 2.0 ** -23))):
+            ulp = float(np.spacing(np.float32(abs(c))))
+            a = np.float32(1 + i * 2.0 ** -23)
+            b = np.float32((1 - i * 2.0 ** -23) * ulp / 2)     # a b = ulp/2 (1 - i^2 2^-46)
+            cases.append((a, b, c))
+            cases.append((a, np.float32(-b), c))
+    naive_wrong = 0
+    for a, b, c in cases:
+        want = _fma_exact(a, b, c)
+        got = oc.fma32(np.float32(a), np.float32(b), np.float32(c))
+        assert got.view(np.int32) == want.view(np.int32), (a, b, c, got, want)
+        naive = np.float32(float(a) * float(b) + float(c))
+        naive_wrong += int(naive != want)
+    assert naive_wrong >= len(cases) // 2      # the cases do separate one rounding from two
+
+
+def test_fma32_special_values():
+    inf, nan = np.float32(np.inf), np.float32(np.nan)
+    assert oc.fma32(np.float32(2), np.float32(3), np.float32(1)) == np.float32(7)
+    assert oc.fma32(np.float32(0), np.float32(5), np.float32(-0.0)).view(np.int32) == 0   # +0
+    assert oc.fma32(inf, np.float32(1), np.float32(1)) == inf
+    assert np.isnan(oc.fma32(inf, np.float32(0), np.float32(1)))
+    assert np.isnan(oc.fma32(inf, np.float32(1), -inf))
+    assert np.isnan(oc.fma32(nan, np.float32(1), np.float32(1)))
+    big = np.float32(3e38)
+    assert oc.fma32(big, np.float32(2), np.float32(0)) == inf
