@@ -150,6 +150,55 @@ def surrogate_component(lib, klr, synth, pb, de, exact_ms, seed, epochs, regret_
                                        "p99": float(np.quantile(r0, 0.99))}}
 
 
+def large_batch_component(lib, klr, synth, seed, replays=3):
+    """The large persistent batch beside the step: 16384 programs with uneven launch grids
+    (32..512 configurations of 2-4 launch parameters), all 131072 metric fits (degree <= 3,
+    64..1024 samples, FP64 to tol 1e-5) and the evaluation/argmin of 4096 queries per program
+    with the fitted coefficients, captured once in a graph and replayed; per-kernel HIP-event
+    times from a timed eager pass."""
+    import numpy as np
+    import torch
+    t = time.perf_counter()
+    fb, pb = synth.config5_batch(seed)
+    gen_s = time.perf_counter() - t
+    df = klr.DeviceFit.from_batch(fb)
+    s = torch.cuda.Stream()
+    fit_out = (torch.empty(df.n_coef, dtype=torch.float64, device="cuda"),
+               torch.empty(df.n_fits * klr.FIT_INFO.itemsize, dtype=torch.uint8, device="cuda"))
+    de = klr.DeviceEval.from_batch(lib, pb, coef=fit_out[0])
+    nq = de.queries.numel()
+    ev_out = (torch.empty(nq, dtype=torch.int32, device="cuda"), torch.empty(nq, dtype=torch.float32, device="cuda"),
+              None, torch.empty(de.n_progs, dtype=torch.int32, device="cuda"))
+    points = int((pb.n_cfg.astype(np.int64) * pb.n_q).sum())
+    with torch.cuda.stream(s):
+        lib.profile_enable(True)
+        lib.fit_batched(df, klr.KLR_FP64, FIT_MAX_ITER, 1e-5, out=fit_out, stream=s)
+        lib.eval_argmin(de, out=ev_out, stream=s)
+        s.synchronize()
+        fit_ms, _ = lib.profile_read(klr.K_FIT_SOLVE)
+        ev_ms, _ = lib.profile_read(klr.K_EVAL)
+        col_ms, _ = lib.profile_read(klr.K_COLLAPSE)
+        lib.profile_enable(False)
+    lib.capture_begin(s)
+    lib.fit_batched(df, klr.KLR_FP64, FIT_MAX_ITER, 1e-5, out=fit_out, stream=s)
+    lib.eval_argmin(de, out=ev_out, stream=s)
+    g = lib.capture_end(s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(replays):
+        lib.graph_launch(g, s)
+    e1.record(s)
+    s.synchronize()
+    lib.graph_destroy(g)
+    ms = e0.elapsed_time(e1) / replays
+    ir = klr.info_records(fit_out[1])
+    return {"programs": int(pb.n_progs), "fits": int(fb.n_fits), "fit_rows": int(fb.m.sum()),
+            "points": points, "generate_s": gen_s, "graph_ms": ms,
+            "fit_ms": fit_ms, "eval_ms": ev_ms, "collapse_ms": col_ms,
+            "fits_per_s": fb.n_fits / (fit_ms / 1e3), "evals_per_s": points / (ev_ms / 1e3),
+            "iters_mean": float(ir["iters"].mean()), "not_converged": float(np.mean((ir["status"] & 4) > 0))}
+
+
 def cpu_baseline(pb, fb, budget_s: float, points: int, n_fits: int):
     """The oracle timed on bounded samples of the same step: FP32 replay + brute-force argmin
     over whole programs' first 16384 queries x all configurations, and pivoted-QR fits over
@@ -191,6 +240,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-sweep", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-large-batch", action="store_true")
     ap.add_argument("--kernel-only", choices=("eval", "fit", "copy"), default=None,
                     help="run only this kernel --steps times (for hardware-counter runs); "
                          "'copy' is a plain 1 GiB device copy used to calibrate byte counters")
@@ -310,6 +360,13 @@ def main() -> int:
         sc = comps["surrogate"]
         log(f"surrogate: train {sc['train_ms']:.0f} ms, select {sc['select_ms']:.0f} ms, fallback rate "
             f"{sc['fallback_rate']:.3f}, speedup vs exact {sc['speedup_vs_exact']:.3f}")
+
+    if not args.no_large_batch:
+        del de, df
+        torch.cuda.empty_cache()
+        comps["large_batch"] = lb = large_batch_component(lib, klr, synth, args.seed)
+        log(f"large batch: {lb['fits']} fits + {lb['points']:.3e} points, graph {lb['graph_ms']:.1f} ms "
+            f"(fit {lb['fit_ms']:.1f}, eval {lb['eval_ms']:.1f}); generated in {lb['generate_s']:.0f} s")
 
     res = {
         "metric": METRIC,

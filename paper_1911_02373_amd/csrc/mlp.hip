@@ -465,115 +465,204 @@ mlp_predict(const int32_t* __restrict__ kid, const int32_t* __restrict__ Nq, con
   }
 }
 
-// Surrogate selection: one workgroup = one program x kSelQ queries; each query's configurations
-// are processed in 64-row tiles; the running best / second-best predictions live in LDS.
-constexpr int kSelQ = 8;
+// Surrogate selection.  Persistent workgroups of 8 waves; each holds W2 in LDS (BF16, in
+// MFMA fragment order) and loops over work items of (program, 64 queries).  A wave takes one
+// query at a time through the whole network for 64 configurations at once, with no LDS round
+// trip of the activations:
+//   layer 1: H1^T = W1 X^T + b1 on v_mfma_f32_32x32x2f32 (A = W1 rows from registers, B = the
+//            features of 32 configurations, C = b1), relu, v_cvt_pk_bf16_f32;
+//   layer 2: D2^T = W2 H1^T + b2 on v_mfma_f32_32x32x16_bf16 (A = W2 fragments from LDS,
+//            B = the layer-1 registers: k-block kb holds hidden units 16 kb .. 16 kb + 15, lane
+//            group g the units 16 kb + 8 (e / 4) + 4 g + e % 4, which is exactly where the
+//            32 x 32 FP32 output of layer 1 keeps them, so H1 never leaves registers);
+//   layer 3: y = w3 . relu(D2^T) + b3 summed over the lane's 16 output registers, then the two
+//            lane groups in a fixed order.
+// Each lane keeps the running (best, index, second best) of its configurations; one wave
+// reduction per query gives the pick and the margin.
 constexpr int kSelMaxCfg = 1024;
+constexpr int kSelWaves = 8;
+constexpr int kSelQ = 64;            // queries per work item
 
-__global__ void __launch_bounds__(kBlock)
-mlp_select(SelectArgs a, Blob w, int chunks) {
-  __shared__ __attribute__((aligned(16))) uint16_t H1s[TS * HP];
-  __shared__ float xs[TS][4];
-  __shared__ float part[4][TS];
-  __shared__ float cfx[kSelMaxCfg][2];
-  __shared__ int cT[kSelMaxCfg], cL[kSelMaxCfg];
-  __shared__ float best_v, second_v;
-  __shared__ int best_i;
-  const int tid = threadIdx.x;
-  const int p = blockIdx.x / chunks;
-  const int qb = (blockIdx.x % chunks) * kSelQ;
-  if (p >= a.n_progs) return;
-  const klr_program P = a.progs[p];
-  const bool range_ok = P.reserved == 0 && P.n_q >= 0 && P.n_q <= a.max_q && P.q0 >= 0 &&
-                        P.q0 + (int64_t)P.n_q <= a.q_len;
-  if (!range_ok || qb >= P.n_q) return;
-  const bool sel_ok = P.v_launch == 2 && P.n_cfg >= 0 && P.n_cfg <= a.max_cfg && P.n_cfg <= kSelMaxCfg &&
-                      P.cfg0 >= 0 && P.cfg0 + 2 * (int64_t)P.n_cfg <= a.cfgs_len;
-  if (!sel_ok) {   // not representable by the network: leave the whole query to the exact path
-    if (tid < kSelQ && qb + tid < P.n_q) {
-      const int64_t o = P.q0 + qb + tid;
-      a.argmin[o] = -1;
-      a.pred_cost[o] = INFINITY;
-      a.fell_back[o] = 1;
-    }
-    return;
+struct SelLds {
+  uint4 w2f[8 * 16 * 64];            // [h2 tile][k block][lane] -> 8 BF16 of W2
+  float b1f[8][2][16];               // b1, b2, w3 in the 32 x 32 output layout: [tile][group][reg]
+  float b2f[8][2][16];
+  float w3f[8][2][16];
+  float2 cfx[kSelMaxCfg];            // (log2 bx / 10, log2 by / 10)
+  int32_t cL[kSelMaxCfg];            // max(bx, by); INT_MAX if not statically admissible
+};
+
+__device__ __forceinline__ int out_hidden(int tile, int g, int r) {   // 32 x 32 output row index
+  return 32 * tile + 8 * (r >> 2) + 4 * g + (r & 3);
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  bf16x2 v;
+  v[0] = (__bf16)a;
+  v[1] = (__bf16)b;
+  return *reinterpret_cast<uint32_t*>(&v);
+}
+
+__global__ void __launch_bounds__(64 * kSelWaves)
+mlp_select(SelectArgs a, Blob w, int chunks, int64_t n_items) {
+  extern __shared__ __attribute__((aligned(16))) char sel_raw[];
+  SelLds& S = *reinterpret_cast<SelLds*>(sel_raw);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 5;
+  for (int i = tid; i < 8 * 16 * 64; i += 64 * kSelWaves) {
+    const int t2 = i >> 10, kb = (i >> 6) & 15, ln = i & 63;
+    const uint16_t* src = w.W2b + (int64_t)(32 * t2 + (ln & 31)) * H + 16 * kb + 4 * (ln >> 5);
+    const uint2 lo = *reinterpret_cast<const uint2*>(src);
+    const uint2 hi = *reinterpret_cast<const uint2*>(src + 8);
+    S.w2f[i] = make_uint4(lo.x, lo.y, hi.x, hi.y);
   }
-  const float emb = p < a.nk ? w.P[kO_EMB + p] : 0.0f;
-  for (int c = tid; c < P.n_cfg; c += kBlock) {
-    const int32_t bx = a.cfgs[P.cfg0 + 2 * c], by = a.cfgs[P.cfg0 + 2 * c + 1];
-    const bool pos = bx >= 1 && by >= 1;
-    const int64_t T = pos ? (int64_t)bx * by : 0;
-    const bool ok = pos && T <= a.t_max && (T % a.wave) == 0;
-    cfx[c][0] = log2f((float)(bx >= 1 ? bx : 1)) * 0.1f;
-    cfx[c][1] = log2f((float)(by >= 1 ? by : 1)) * 0.1f;
-    cT[c] = ok ? 1 : 0;
-    cL[c] = bx > by ? bx : by;
+  for (int i = tid; i < 8 * 2 * 16; i += 64 * kSelWaves) {
+    const int t = i >> 5, gg = (i >> 4) & 1, r = i & 15;
+    const int h = out_hidden(t, gg, r);
+    S.b1f[t][gg][r] = w.P[kO_B1 + h];
+    S.b2f[t][gg][r] = w.P[kO_B2 + h];
+    S.w3f[t][gg][r] = w.P[kO_W3 + h];
   }
-  __syncthreads();
-  const float mu = w.hdr[0], sig = w.hdr[1];
+  float w1r[8][2];                   // A operand of layer 1: W1[32 t + lane % 32][2 s + lane / 32]
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int st = 0; st < 2; ++st) w1r[t][st] = w.P[kO_W1 + 4 * (32 * t + (lane & 31)) + 2 * st + g];
+  const float mu = w.hdr[0], sig = w.hdr[1], b3 = w.P[kO_B3];
   const float lnm = logf(1.0f + a.margin);
-  const float b3 = w.P[kO_B3];
-  for (int qi = qb; qi < qb + kSelQ && qi < P.n_q; ++qi) {
-    const int32_t N = a.queries[P.q0 + qi];
-    const float fN = log2f((float)(N >= 1 ? N : 1)) * (1.0f / 26.0f);
-    if (tid == 0) { best_v = INFINITY; second_v = INFINITY; best_i = -1; }
-    for (int c0 = 0; c0 < P.n_cfg; c0 += TS) {
-      if (tid < TS) {
-        const int c = c0 + tid < P.n_cfg ? c0 + tid : P.n_cfg - 1;
-        xs[tid][0] = fN;
-        xs[tid][1] = cfx[c][0];
-        xs[tid][2] = cfx[c][1];
-        xs[tid][3] = emb;
+  int loaded = -1;
+  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int p = (int)(item / chunks);
+    const int qb = (int)(item % chunks) * kSelQ;
+    const klr_program P = a.progs[p];
+    const bool range_ok = P.reserved == 0 && P.n_q >= 0 && P.n_q <= a.max_q && P.q0 >= 0 &&
+                          P.q0 + (int64_t)P.n_q <= a.q_len;
+    if (!range_ok || qb >= P.n_q) continue;
+    const bool sel_ok = P.v_launch == 2 && P.n_cfg >= 0 && P.n_cfg <= a.max_cfg && P.n_cfg <= kSelMaxCfg &&
+                        P.cfg0 >= 0 && P.cfg0 + 2 * (int64_t)P.n_cfg <= a.cfgs_len;
+    const int qe = qb + kSelQ < P.n_q ? qb + kSelQ : P.n_q;
+    if (!sel_ok) {   // not representable by the network: the exact path answers these queries
+      for (int qi = qb + tid; qi < qe; qi += 64 * kSelWaves) {
+        const int64_t o = P.q0 + qi;
+        a.argmin[o] = -1;
+        a.pred_cost[o] = INFINITY;
+        a.fell_back[o] = 1;
+      }
+      continue;
+    }
+    if (p != loaded) {
+      __syncthreads();               // every wave is done with the previous program's tables
+      for (int c = tid; c < P.n_cfg; c += 64 * kSelWaves) {
+        const int32_t bx = a.cfgs[P.cfg0 + 2 * c], by = a.cfgs[P.cfg0 + 2 * c + 1];
+        const bool pos = bx >= 1 && by >= 1;
+        const int64_t T = pos ? (int64_t)bx * by : 0;
+        const bool ok = pos && T <= a.t_max && (T % a.wave) == 0;
+        S.cfx[c] = make_float2(log2f((float)(bx >= 1 ? bx : 1)) * 0.1f, log2f((float)(by >= 1 ? by : 1)) * 0.1f);
+        S.cL[c] = ok ? (bx > by ? bx : by) : 0x7fffffff;
       }
       __syncthreads();
-      layer1(w, xs, H1s, nullptr, 0, 0);
-      __syncthreads();
-      f32x16 acc[2][2];
-      gemm_tile(H1s, w.W2b, acc);
-      layer3_partial(w, acc, part);
-      __syncthreads();
-      if (tid < 64) {
-        // (best, index, second) over the tile: lexicographic (value, index) minimum; the
-        // second best collects the loser of every comparison, so equal values give margin 0
-        const int c = c0 + tid;
-        float b = INFINITY, sec = INFINITY;
-        int bi = 0x7fffffff;
-        if (c < P.n_cfg && cT[c] && cL[c] <= N) {
-          const float y = ((part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid])) + b3;
-          b = mu + sig * y;
-          bi = c;
+      loaded = p;
+    }
+    const float emb = p < a.nk ? w.P[kO_EMB + p] : 0.0f;
+    for (int qi = qb + wv; qi < qe; qi += kSelWaves) {
+      const int32_t N = a.queries[P.q0 + qi];
+      const float fN = log2f((float)(N >= 1 ? N : 1)) * (1.0f / 26.0f);
+      float best = INFINITY, sec = INFINITY;
+      int bi = 0x7fffffff;
+      for (int c0 = 0; c0 < P.n_cfg; c0 += 64) {
+        // layer 1 for two tiles of 32 configurations
+        bf16x8 h1[2][16];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+          int c = c0 + 32 * rt + (lane & 31);
+          c = c < P.n_cfg ? c : P.n_cfg - 1;
+          const float2 cx = S.cfx[c];
+          const float xb0 = g == 0 ? fN : cx.x;       // features 0, 1 (k-step 0)
+          const float xb1 = g == 0 ? cx.y : emb;      // features 2, 3 (k-step 1)
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            f32x16 acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = S.b1f[t][g][r];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w1r[t][0], xb0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w1r[t][1], xb1, acc, 0, 0, 0);
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+              uint4 u;
+              u.x = pack_bf16(fmaxf(acc[8 * half + 0], 0.0f), fmaxf(acc[8 * half + 1], 0.0f));
+              u.y = pack_bf16(fmaxf(acc[8 * half + 2], 0.0f), fmaxf(acc[8 * half + 3], 0.0f));
+              u.z = pack_bf16(fmaxf(acc[8 * half + 4], 0.0f), fmaxf(acc[8 * half + 5], 0.0f));
+              u.w = pack_bf16(fmaxf(acc[8 * half + 6], 0.0f), fmaxf(acc[8 * half + 7], 0.0f));
+              h1[rt][2 * t + half] = *reinterpret_cast<bf16x8*>(&u);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        // layers 2 and 3
+        float yp[2] = {0.0f, 0.0f};
+        for (int t2 = 0; t2 < 8; ++t2) {
+          f32x16 acc0, acc1;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = S.b2f[t2][g][r];
+          // W2 fragments are loaded one k-block ahead; the scheduling barriers keep the compiler
+          // from hoisting all sixteen loads (64 registers) next to the 128 registers of H1
+          uint4 wa = S.w2f[(t2 * 16) * 64 + lane];
+#pragma unroll
+          for (int kb = 0; kb < 16; ++kb) {
+            uint4 wn = wa;
+            if (kb + 1 < 16) wn = S.w2f[(t2 * 16 + kb + 1) * 64 + lane];
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(&wa);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, h1[0][kb], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, h1[1][kb], acc1, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            wa = wn;
+          }
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const float w3 = S.w3f[t2][g][r];
+            yp[0] += w3 * fmaxf(acc0[r], 0.0f);
+            yp[1] += w3 * fmaxf(acc1[r], 0.0f);
+          }
         }
 #pragma unroll
-        for (int off = 1; off <= 32; off <<= 1) {
-          const float ob = __shfl_xor(b, off), os = __shfl_xor(sec, off);
-          const int oi = __shfl_xor(bi, off);
-          if (ob < b || (ob == b && oi < bi)) {
-            sec = fminf(b, os);
-            b = ob;
-            bi = oi;
-          } else {
-            sec = fminf(sec, ob);
-          }
-        }
-        if (tid == 0) {     // the running result holds lower indices: it wins ties
-          if (b < best_v) {
-            second_v = fminf(best_v, sec);
-            best_v = b;
-            best_i = bi;
-          } else {
-            second_v = fminf(second_v, b);
+        for (int rt = 0; rt < 2; ++rt) {
+          const float other = __shfl_xor(yp[rt], 32);
+          const float y = (g == 0 ? yp[rt] + other : other + yp[rt]) + b3;   // same order in both groups
+          const int c = c0 + 32 * rt + (lane & 31);
+          if (c < P.n_cfg && S.cL[c] <= N) {
+            const float v = mu + sig * y;
+            if (v < best) {       // configurations arrive in increasing index order per lane
+              sec = fminf(sec, best);
+              best = v;
+              bi = c;
+            } else {
+              sec = fminf(sec, v);
+            }
           }
         }
       }
-      __syncthreads();
+      // (best, index) lexicographic minimum over the 32 configuration lanes; the second best
+      // collects the loser of every comparison, so equal values give a zero margin
+#pragma unroll
+      for (int off = 1; off <= 16; off <<= 1) {
+        const float ob = __shfl_xor(best, off), os = __shfl_xor(sec, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob < best || (ob == best && oi < bi)) {
+          sec = fminf(best, os);
+          best = ob;
+          bi = oi;
+        } else {
+          sec = fminf(sec, ob);
+        }
+      }
+      if (lane == 0) {
+        const int64_t o = P.q0 + qi;
+        const bool found = bi != 0x7fffffff;
+        a.argmin[o] = found ? bi : -1;
+        a.pred_cost[o] = found ? expf(best) : INFINITY;
+        a.fell_back[o] = (!found || !(sec - best >= lnm)) ? 1 : 0;
+      }
     }
-    if (tid == 0) {
-      const int64_t o = P.q0 + qi;
-      a.argmin[o] = best_i;
-      a.pred_cost[o] = best_i >= 0 ? expf(best_v) : INFINITY;
-      a.fell_back[o] = (best_i < 0 || !(second_v - best_v >= lnm)) ? 1 : 0;
-    }
-    __syncthreads();
   }
 }
 
@@ -625,9 +714,18 @@ hipError_t launch_predict(const int32_t* kid, const int32_t* N, const int32_t* L
 }
 
 hipError_t launch_select(const SelectArgs& a, const Blob& w, hipStream_t s) {
+  if (a.max_q <= 0 || a.n_progs <= 0) return hipSuccess;
   const int chunks = (a.max_q + kSelQ - 1) / kSelQ;
-  if (a.max_q == 0) return hipSuccess;
-  hipLaunchKernelGGL(mlp_select, dim3((unsigned)a.n_progs * chunks), dim3(kBlock), 0, s, a, w, chunks);
+  const int64_t n_items = (int64_t)a.n_progs * chunks;
+  const size_t lds = sizeof(SelLds);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_select),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int dev = 0, ncu = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const int64_t grid = n_items < ncu ? n_items : ncu;     // one persistent workgroup per CU
+  hipLaunchKernelGGL(mlp_select, dim3((unsigned)grid), dim3(64 * kSelWaves), lds, s, a, w, chunks, n_items);
   return hipGetLastError();
 }
 

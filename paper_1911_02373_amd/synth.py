@@ -24,6 +24,8 @@ Layouts (structure of arrays, all numpy):
 from __future__ import annotations
 
 import itertools
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -365,6 +367,138 @@ def mixed_programs(seed: int, n_progs: int, n_q_range=(1, 700), n_cfg_range=(1, 
         cfg0=np.array(cfg0, np.int64), n_cfg=np.array(n_cfg, np.int32),
         grid_kind=np.array(gk, np.int32), q0=np.array(q0, np.int64), n_q=np.array(n_q, np.int32),
         cfgs=np.concatenate(cfg_parts).astype(np.int32), queries=np.concatenate(q_parts), hw=HW())
+
+
+def config5_batch(seed: int, n_progs: int = 16384, n_q: int = 4096, m_range=(64, 1024),
+                  n_cfg_range=(32, 512), v_launch_choices=(2, 3, 4), degree: int = 3,
+                  noise: float = 0.01, log2_range=(8.0, 26.0), chunk_rows: int = 1 << 18):
+    """Large persistent batch: programs with uneven launch grids whose 8 metrics are FITTED.
+
+    Program p: v_launch ~ U(v_launch_choices); n_cfg ~ U{n_cfg_range} configurations drawn
+    without replacement from the power-of-two tuples with product in 64..1024 (the 127 config-3
+    tuples when v_launch = 2, all of them when fewer exist); n_q data sizes N = round(2^u),
+    u ~ U(log2_range).  Its metric j has the ground truth lo_j + s_j p/q of total degree
+    <= `degree` in (N/2^26, L_k/2^10) (coefficients U(0.1, 2), q's constant 1, s_j = (hi_j -
+    lo_j) / (2 #monomials)).  Fit (p, j) has m ~ U{m_range} samples at (N, L) with N drawn like
+    the queries and L one of the program's configurations, target truth * exp(noise z).
+
+    Returns (fits, programs): the FitBatch of all 8 n_progs fits and the ProgramBatch whose
+    fit descriptors are the same (its coef holds the ground truth; the workload replaces it by
+    the fitted coefficients).  Rows are generated per v_launch class in chunks."""
+    rng = np.random.default_rng(seed)
+    vls = rng.choice(np.asarray(v_launch_choices), n_progs).astype(np.int32)
+    E_of, r0_of, blocks, row = {}, {}, [], 0
+    for vl in sorted(set(int(x) for x in vls)):
+        E = monomials(1 + vl, degree)
+        E_of[vl], r0_of[vl] = E, row
+        blocks.append(E)
+        row += E.shape[0]
+    exps = np.concatenate(blocks)
+    n_fits = n_progs * N_METRICS
+    nm_p = np.array([E_of[int(v)].shape[0] for v in vls], np.int64)
+    nm_f = np.repeat(nm_p, N_METRICS)
+    v_f = np.repeat(vls + 1, N_METRICS).astype(np.int32)
+    # ground-truth coefficients, fits' layout (numerator lo q + s p, denominator q without q0)
+    ncoef = 2 * nm_f - 1
+    coef0 = np.zeros(n_fits, np.int64)
+    coef0[1:] = np.cumsum(ncoef[:-1])
+    coef = np.empty(int(ncoef.sum()))
+    cnum, cden = {}, {}           # per v_launch class: [fits of the class][nm]
+    fit_ids = {}
+    for vl in E_of:
+        nm = E_of[vl].shape[0]
+        ids = np.nonzero(v_f == vl + 1)[0]
+        lo = np.array([METRIC_RANGES[j][0] for j in range(N_METRICS)])[ids % N_METRICS]
+        hi = np.array([METRIC_RANGES[j][1] for j in range(N_METRICS)])[ids % N_METRICS]
+        sj = (hi - lo) / (2.0 * nm)
+        pc = rng.uniform(0.1, 2.0, (ids.size, nm))
+        qc = np.concatenate([np.ones((ids.size, 1)), rng.uniform(0.1, 2.0, (ids.size, nm - 1))], axis=1)
+        cn = lo[:, None] * qc + sj[:, None] * pc
+        cnum[vl], cden[vl], fit_ids[vl] = cn, qc, ids
+        for t, i in enumerate(ids):
+            coef[coef0[i]: coef0[i] + 2 * nm - 1] = np.concatenate([cn[t], qc[t, 1:]])
+    # launch configurations
+    n_cfg = rng.integers(n_cfg_range[0], n_cfg_range[1] + 1, n_progs).astype(np.int32)
+    base_of = {vl: (config3_launch_configs()[:127] if vl == 2 else pow2_launch_tuples(vl)) for vl in E_of}
+    cfg_parts, cfg0, off = [], np.zeros(n_progs, np.int64), 0
+    for p in range(n_progs):
+        base = base_of[int(vls[p])]
+        k = min(int(n_cfg[p]), base.shape[0])
+        n_cfg[p] = k
+        pick = base[np.sort(rng.choice(base.shape[0], k, replace=False))]
+        cfg_parts.append(pick.reshape(-1))
+        cfg0[p] = off
+        off += pick.size
+    cfgs = np.concatenate(cfg_parts).astype(np.int32)
+    queries = np.rint(2.0 ** rng.uniform(log2_range[0], log2_range[1], n_progs * n_q)).astype(np.int32)
+    # samples
+    m = rng.integers(m_range[0], m_range[1] + 1, n_fits).astype(np.int32)
+    f0 = np.zeros(n_fits, np.int64)
+    f0[1:] = np.cumsum(m.astype(np.int64)[:-1])
+    x0 = np.zeros(n_fits, np.int64)
+    x0[1:] = np.cumsum((m.astype(np.int64) * v_f)[:-1])
+    X = np.empty(int((m.astype(np.int64) * v_f).sum()), np.int32)
+    f = np.empty(int(m.sum()))
+    for vl in E_of:
+        E = E_of[vl][:, :1 + vl].astype(np.int64)
+        ids = fit_ids[vl]
+        pos = np.empty(n_fits, np.int64)
+        pos[ids] = np.arange(ids.size)
+        rows_fit = np.repeat(ids, m[ids])                         # fit of every row of the class
+        R = rows_fit.size
+        Nv = np.rint(2.0 ** rng.uniform(log2_range[0], log2_range[1], R)).astype(np.int64)
+        prog = rows_fit // N_METRICS
+        pick = (rng.random(R) * n_cfg[prog]).astype(np.int64)
+        Lv = cfgs[(cfg0[prog] + pick * vl)[:, None] + np.arange(vl)[None, :]].astype(np.int64)
+        Xc = np.concatenate([Nv[:, None], Lv], axis=1)          # [R][1 + vl]
+        z = rng.normal(0.0, 1.0, R)
+        start = np.repeat(f0[ids], m[ids])
+        within = np.arange(R) - np.repeat(np.cumsum(np.concatenate([[0], m[ids][:-1].astype(np.int64)])), m[ids])
+        frow = start + within
+        xrow = np.repeat(x0[ids], m[ids]) + within * (1 + vl)
+        X[xrow[:, None] + np.arange(1 + vl)[None, :]] = Xc.astype(np.int32)
+        sdiv = 2.0 ** -np.array([26.0] + [10.0] * vl)
+
+        def chunk(c0, vl=vl, E=E, R=R, Xc=Xc, sdiv=sdiv, pos=pos, rows_fit=rows_fit, frow=frow, z=z):
+            c1 = min(R, c0 + chunk_rows)
+            xt = Xc[c0:c1].astype(np.float64) * sdiv
+            powk = [[np.ones(c1 - c0)] for _ in range(1 + vl)]
+            for k in range(1 + vl):
+                for d in range(1, degree + 1):
+                    powk[k].append(powk[k][-1] * xt[:, k])
+            mono = np.empty((c1 - c0, E.shape[0]))
+            for t in range(E.shape[0]):
+                col = powk[0][E[t, 0]]
+                for k in range(1, 1 + vl):
+                    if E[t, k]:
+                        col = col * powk[k][E[t, k]]
+                mono[:, t] = col
+            fr = pos[rows_fit[c0:c1]]
+            pv = np.einsum("ij,ij->i", mono, cnum[vl][fr])
+            qv = np.einsum("ij,ij->i", mono, cden[vl][fr])
+            f[frow[c0:c1]] = pv / qv * np.exp(noise * z[c0:c1])
+
+        # chunks write disjoint rows and every random draw is made above, so the thread pool
+        # changes nothing but the wall time
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            list(ex.map(chunk, range(0, R, chunk_rows)))
+    scale = np.zeros((n_fits, MAX_VARS), np.int8)
+    scale[:, 0] = 26
+    for k in range(1, 5):
+        scale[v_f > k, k] = 10
+    num0 = np.array([r0_of[int(v) - 1] for v in v_f], np.int32)
+    fits = FitBatch(X=X, f=f, exps=exps, x0=x0, f0=f0, m=m, v=v_f, num0=num0,
+                    n_num=nm_f.astype(np.int32), den0=num0.copy(), n_den=nm_f.astype(np.int32),
+                    coef0=coef0, scale_exp=scale, n_coef=int(ncoef.sum()), truth_coef=coef.copy(),
+                    meta={"noise": noise})
+    progs = ProgramBatch(
+        fits=fits, coef=coef, exps=exps, num0=fits.num0, n_num=fits.n_num, den0=fits.den0,
+        n_den=fits.n_den, coef0=coef0, scale_exp=scale, v_launch=vls,
+        fit0=np.arange(n_progs, dtype=np.int32) * N_METRICS, cfg0=cfg0, n_cfg=n_cfg,
+        grid_kind=np.zeros(n_progs, np.int32),
+        q0=np.arange(n_progs, dtype=np.int64) * n_q, n_q=np.full(n_progs, n_q, np.int32),
+        cfgs=cfgs, queries=queries, hw=HW())
+    return fits, progs
 
 
 def mlp_init(seed: int, n_kernels: int, hidden: int = 256):

@@ -175,3 +175,37 @@ def test_selection_regret_small(klr, trained):
     regret = picked[ok].astype(np.float64) / eb[ok] - 1.0
     assert np.all(regret >= 0)
     assert np.median(regret) < 0.01
+
+
+def test_training_gain_over_untrained_network(klr, trained):
+    """What learning buys: with the same network, kernels and 2 % fallback rule, the trained
+    weights settle far more queries without the exact program, and their own picks (no
+    fallback) are far closer to the exact optimum than those of the initial weights."""
+    import torch
+    from paper_1911_02373_amd.klr import DeviceEval
+    pb, blob, _ = trained
+    nk = pb.n_progs
+    blob0 = klr.surrogate_alloc(synth.mlp_init(4, nk), nk)       # the trained net's initial weights
+    de = DeviceEval.from_batch(klr, pb, with_costs=True)
+    ea, eb, costs, _ = klr.eval_argmin(de, want_costs=True)
+    torch.cuda.synchronize()
+    C = costs.cpu().numpy().reshape(nk, 128, -1)
+    nq = int(pb.n_q[0])
+    ea, eb = ea.cpu().numpy(), eb.cpu().numpy()
+    ok = ea >= 0
+
+    def judge(b):
+        alone, _, _ = klr.surrogate_eval(b, nk, de, margin=0.0)
+        _, _, fb = klr.surrogate_eval(b, nk, de, margin=0.02)
+        torch.cuda.synchronize()
+        a = alone.cpu().numpy()
+        picked = C[np.repeat(np.arange(nk), nq), np.maximum(a, 0), np.tile(np.arange(nq), nk)]
+        regret = picked[ok].astype(np.float64) / eb[ok] - 1.0
+        return np.mean(regret <= 0.01), 1.0 - fb.cpu().numpy().astype(bool).mean()
+
+    within_t, settled_t = judge(blob)
+    within_0, settled_0 = judge(blob0)
+    print(f"picks within 1 %: trained {within_t:.3f}, untrained {within_0:.3f}; settled without the "
+          f"exact program: trained {settled_t:.3f}, untrained {settled_0:.3f}")
+    assert within_t >= 0.5 and within_t >= within_0 + 0.25, (within_t, within_0)
+    assert settled_t >= 0.2, settled_t
