@@ -370,11 +370,14 @@ __device__ int factor(const FitCtx& C, double unit) {
   __syncthreads();
   for (int k = 0; k < n; ++k) {
     if (tid < 64) {
-      double best = -1.0;
+      // largest remaining diagonal, lowest index on ties; NaN ranks below every number, so the
+      // pick is always one of the remaining indices k..n-1
+      double best = -INFINITY;
       int bi = n;
       for (int i = k + tid; i < n; i += 64) {
         const double vv = C.S[symi(C.perm[i], C.perm[i])];
-        if (vv > best || (vv == best && i < bi)) { best = vv; bi = i; }
+        const double key = vv == vv ? vv : -INFINITY;
+        if (key > best || (key == best && i < bi)) { best = key; bi = i; }
       }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
@@ -383,16 +386,32 @@ __device__ int factor(const FitCtx& C, double unit) {
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
       if (tid == 0) {
-        const int pt = C.perm[k];
-        C.perm[k] = C.perm[bi];
-        C.perm[bi] = pt;
-        double dk = C.S[symi(C.perm[k], C.perm[k])];
-        C.piv[k] = dk;
-        if (!(dk > 0.0)) dk = mu;
-        C.S[symi(C.perm[k], C.perm[k])] = sqrt(dk);
+        C.red[kFitBlock - 3] = best;
+        if (best > 4.0 * mu) {
+          const int pt = C.perm[k];
+          C.perm[k] = C.perm[bi];
+          C.perm[bi] = pt;
+          C.piv[k] = best;
+          C.S[symi(C.perm[k], C.perm[k])] = sqrt(best);
+        }
       }
     }
     __syncthreads();
+    if (!(C.red[kFitBlock - 3] > 4.0 * mu)) {
+      // numerical rank reached: every remaining diagonal is at most 4 mu, i.e. the remaining
+      // Schur complement is rounding noise; the rest of the factor becomes sqrt(mu) I (the
+      // shift alone), so the noise is never divided by a tiny pivot
+      for (int i = k + tid; i < n; i += kFitBlock) C.piv[i] = C.S[symi(C.perm[i], C.perm[i])];
+      __syncthreads();
+      const double smu = sqrt(mu);
+      const int w = n - k;
+      for (int e = tid; e < w * w; e += kFitBlock) {
+        const int ii = e / w, jj = e - ii * w;
+        if (jj <= ii) C.S[symi(C.perm[k + ii], C.perm[k + jj])] = ii == jj ? smu : 0.0;
+      }
+      __syncthreads();
+      break;
+    }
     const int pk = C.perm[k];
     const double lkk = C.S[symi(pk, pk)];
     for (int i = k + 1 + tid; i < n; i += kFitBlock) C.S[symi(C.perm[i], pk)] /= lkk;

@@ -211,14 +211,35 @@ __device__ int factor_wave(WaveLds& L, int n, double unit) {
   if (lane < n) L.S[symi(lane, lane)] += mu;
   wave_sync();
   for (int k = 0; k < n; ++k) {
-    double best = -1.0;
+    // largest remaining diagonal, lowest index on ties; NaN ranks below every number and lanes
+    // without a candidate hold (-inf, n), so the pick is always one of k..n-1; the butterfly
+    // leaves the same (best, bi) in every lane
+    double best = -INFINITY;
     int bi = n;
-    if (lane >= k && lane < n) { best = L.S[symi(L.perm[lane], L.perm[lane])]; bi = lane; }
+    if (lane >= k && lane < n) {
+      const double vv = L.S[symi(L.perm[lane], L.perm[lane])];
+      best = vv == vv ? vv : -INFINITY;
+      bi = lane;
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       const double ob = __shfl_xor(best, off);
       const int oi = __shfl_xor(bi, off);
       if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (!(best > 4.0 * mu)) {
+      // numerical rank reached: the remaining Schur complement is rounding noise; the rest of
+      // the factor becomes sqrt(mu) I (the shift alone)
+      if (lane >= k && lane < n) L.piv[lane] = L.S[symi(L.perm[lane], L.perm[lane])];
+      wave_sync();
+      const double smu = sqrt(mu);
+      const int w = n - k;
+      for (int e = lane; e < w * w; e += 64) {
+        const int ii = e / w, jj = e - ii * w;
+        if (jj <= ii) L.S[symi(L.perm[k + ii], L.perm[k + jj])] = ii == jj ? smu : 0.0;
+      }
+      wave_sync();
+      break;
     }
     const int pk = L.perm[bi];
     const int pold = L.perm[k];
@@ -227,7 +248,7 @@ __device__ int factor_wave(WaveLds& L, int n, double unit) {
       L.perm[k] = pk;
       L.perm[bi] = pold;
       L.piv[k] = best;
-      L.S[symi(pk, pk)] = sqrt(best > 0.0 ? best : mu);
+      L.S[symi(pk, pk)] = sqrt(best);
     }
     wave_sync();
     const double lkk = L.S[symi(pk, pk)];

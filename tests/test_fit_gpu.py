@@ -208,3 +208,40 @@ def test_persistent_schedule_matches_plain(klr, prec):
         klr.set_option(OPT_FIT_PERSISTENT, 1)
     assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
     assert np.array_equal(ia.view(np.uint8), ib.view(np.uint8))
+
+
+@pytest.mark.parametrize("kind", ["workgroup_n111", "wave_n39"])
+def test_underdetermined_deterministic_whatever_the_workspace(klr, kind):
+    """m < n: the pivoted Cholesky reaches the numerical rank early and the rest of its factor
+    is the shift alone.  Results must not depend on the workspace's previous contents or on the
+    schedule, and the fitted values must interpolate like the oracle's minimum-norm solution."""
+    import torch
+    from paper_1911_02373_amd.klr import OPT_FIT_PERSISTENT, DeviceFit, info_records
+    if kind == "workgroup_n111":
+        fb, _ = synth.config5_batch(21, n_progs=24, n_q=1, m_range=(64, 78), v_launch_choices=(4,))
+    else:
+        fb = synth.config2_fits(22, 96, "2a", m_range=(20, 38))
+    df = DeviceFit.from_batch(fb)
+    klr.fit_batched(df, 0, 256, 1e-10)                       # allocates the workspace
+    runs = []
+    try:
+        for fill, pers in ((float("nan"), 1), (0.0, 1), (1e300, 0)):
+            klr.set_option(OPT_FIT_PERSISTENT, pers)
+            df.ws[: df.ws.numel() // 8 * 8].view(torch.float64).fill_(fill)
+            c, i = klr.fit_batched(df, 0, 256, 1e-10)
+            torch.cuda.synchronize()
+            runs.append((c.cpu().numpy(), info_records(i)))
+    finally:
+        klr.set_option(OPT_FIT_PERSISTENT, 1)
+    for c, i in runs[1:]:
+        assert np.array_equal(c.view(np.uint64), runs[0][0].view(np.uint64))
+        assert np.array_equal(i.view(np.uint8), runs[0][1].view(np.uint8))
+    coef, info = runs[0]
+    assert np.all(np.isfinite(coef)) and not np.any(info["status"] & 16)
+    assert np.all(info["status"] & 2)                          # underdetermined
+    ora, _ = of.fit_batch(fb, indices=range(0, fb.n_fits, 7))
+    for f in range(0, fb.n_fits, 7):
+        Xi, fi, En, Ed, s = fb.fit_arrays(f)
+        A, b = of.design_matrix(Xi, fi, En, Ed, s)
+        y, yo = _coefs(fb, coef, f), _coefs(fb, ora, f)
+        assert np.linalg.norm(A @ y - A @ yo) <= 1e-6 * np.linalg.norm(b), f
