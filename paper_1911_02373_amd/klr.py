@@ -487,9 +487,10 @@ class DeviceFit:
                    n_coef=int(fb.n_coef))
 
 
-def info_records(info_tensor) -> np.ndarray:
-    """Device info bytes -> numpy structured array of klr_fit_info."""
-    return info_tensor.cpu().numpy().view(FIT_INFO)
+def info_records(info) -> np.ndarray:
+    """Info bytes (device tensor or host array) -> numpy structured array of klr_fit_info."""
+    arr = info.cpu().numpy() if hasattr(info, "cpu") else np.asarray(info)
+    return arr.view(np.uint8).view(FIT_INFO)
 
 
 def grid_samples(pb, de: DeviceEval, costs):
