@@ -244,7 +244,7 @@ def main() -> int:
     ap.add_argument("--kernel-only", choices=("eval", "fit", "copy"), default=None,
                     help="run only this kernel --steps times (for hardware-counter runs); "
                          "'copy' is a plain 1 GiB device copy used to calibrate byte counters")
-    ap.add_argument("--surrogate-epochs", type=int, default=20)
+    ap.add_argument("--surrogate-epochs", type=int, default=60)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -278,9 +278,11 @@ klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernel
 
 /* ------------------------------------------------------------------------------------------
  * Options of a handle. */
-#define KLR_OPT_FIT_PERSISTENT 0  /* 1 (default): fits run in persistent workgroups popping a    */
-                                  /*   device queue ordered longest first (m n^2); 0: one        */
-                                  /*   workgroup per fit                                         */
+#define KLR_OPT_FIT_PERSISTENT 0  /* 1 (default): fits are ordered longest first (m n^2) on the */
+                                  /*   device; small fits (one wavefront each) are started in   */
+                                  /*   that order and larger ones run in persistent workgroups  */
+                                  /*   popping a device queue; 0: fits in descriptor order, one */
+                                  /*   wavefront or workgroup each.  Results are identical.     */
 #define KLR_OPT_EVAL_VARIANT 1    /* -1 (default): launch shape of the evaluation sweep chosen by */
                                   /*   the autotuner; >= 0: a fixed variant index                 */
 #define KLR_OPT_COUNT 8

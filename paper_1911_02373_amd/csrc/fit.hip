@@ -434,8 +434,8 @@ __device__ int factor(const FitCtx& C, double unit) {
 // Size class of a fit: 3 = one wavefront per fit (fit_wave.hip); otherwise one workgroup per
 // fit with 0 (n <= 32), 1 (<= 64), 2 (<= 128, and every invalid descriptor, which the largest
 // class reports as bad input).
-__device__ __forceinline__ int fit_class(const klr_fit_desc& d) {
-  if (wave_fit_eligible(d)) return 3;
+__device__ __forceinline__ int fit_class(const FitArgs& a, const klr_fit_desc& d) {
+  if (wave_fit_eligible(a, d)) return 3;
   const int n = d.n_num + d.n_den - 1;
   const bool shape_ok = d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= KLR_MAX_UNKNOWNS;
   if (!shape_ok) return 2;
@@ -594,15 +594,16 @@ __global__ void __launch_bounds__(kFitBlock)
 fit_kernel(FitArgs a, int cls) {
   extern __shared__ double smem[];
   const int fi = blockIdx.x;
-  if (fi >= a.n_fits || fit_class(a.desc[fi]) != cls) return;
+  if (fi >= a.n_fits || fit_class(a, a.desc[fi]) != cls) return;
   fit_one<NM, PREC>(a, fi, smem);
 }
 
 // ---- persistent, longest-first schedule ------------------------------------------------------
 // plan: fits are bucketed by (class, 31 - floor(log2(m n^2 + 1))) so that an ascending scan of
 // the buckets lists each class's fits from the most to the least work; the persistent
-// workgroups of a class then pop positions from that class's queue counter.  A fit's result
-// does not depend on which workgroup computes it, so outputs are deterministic.
+// workgroups of a workgroup class then pop positions from that class's queue counter, and the
+// wave class (one wavefront per fit) is launched as a grid that takes positions in order.  A
+// fit's result does not depend on which workgroup computes it, so outputs are deterministic.
 constexpr int kBuckets = 32;
 constexpr int kClasses = 4;
 struct Plan {
@@ -633,7 +634,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_plan_count(FitArgs a, Plan* pl)
   const int fi = blockIdx.x * kFitBlock + threadIdx.x;
   if (fi >= a.n_fits) return;
   const klr_fit_desc d = a.desc[fi];
-  atomicAdd(&pl->counts[fit_class(d) * kBuckets + cost_bucket(d)], 1);
+  atomicAdd(&pl->counts[fit_class(a, d) * kBuckets + cost_bucket(d)], 1);
 }
 
 __global__ void fit_plan_scan(Plan* pl) {
@@ -657,7 +658,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_plan_scatter(FitArgs a, Plan* p
   const int fi = blockIdx.x * kFitBlock + threadIdx.x;
   if (fi >= a.n_fits) return;
   const klr_fit_desc d = a.desc[fi];
-  const int k = fit_class(d) * kBuckets + cost_bucket(d);
+  const int k = fit_class(a, d) * kBuckets + cost_bucket(d);
   order[pl->offs[k] + atomicAdd(&pl->cursor[k], 1)] = fi;
 }
 
@@ -716,7 +717,7 @@ hipError_t launch_all(const FitArgs& a, bool persistent) {
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    const WavePlanView pv{order, &pl->totals[3], &pl->base[3], &pl->queue[3]};
+    const WavePlanView pv{order, &pl->totals[3], &pl->base[3]};
     e = launch_fit_wave(a, persistent, pv);
   }
   if (e == hipSuccess) e = launch_class<32, PREC>(a, 0, persistent, pl, order);

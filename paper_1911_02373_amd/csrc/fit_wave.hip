@@ -3,19 +3,22 @@
 // Same problem and numerical method as the workgroup kernel in fit.hip (paper: step 2 of the
 // section "An Algorithm to Build and Deploy a Performance-Predicting Rational Program" and
 // section "Building a Driver Program: Rational function estimation"), organised for fits with
-// n <= 48 unknowns, v <= 4 variables and m <= 512 samples:
+// n <= 48 unknowns, v <= 4 variables, m <= 512 samples and exponents <= 3:
 //   * lane l owns sample rows l, l + 64, ... (scaled variables, target and residual in VGPRs);
 //   * Gram on MFMA (v_mfma_f64_16x16x4f64 for the FP64 path, v_mfma_f32_16x16x4f32 with FP32
 //     or BF16-rounded design-matrix values for the reduced paths): for each step of 4 rows the
-//     rows are broadcast from their owner lanes and every lane computes exactly the design-
-//     matrix elements of its MFMA operand slots (column l % 16 of each 16-column tile, row
-//     l / 16 of the step), so A is never stored;
-//   * equilibration, shift, diagonally pivoted Cholesky, triangular solves, reductions are
-//     wave-synchronous (no workgroup barriers); four independent fits per workgroup;
+//     lanes build a table of x_k^p (p <= 3) of the step's rows in LDS, one entry per lane, and
+//     every lane forms exactly the design-matrix elements of its MFMA operand slots (column
+//     l % 16 of each 16-column tile, row l / 16 of the step) from four table entries, so A is
+//     never stored;
+//   * equilibration, shift, diagonally pivoted Cholesky kept in pivot order (rows and columns
+//     swapped in place), triangular solves and reductions are wave-synchronous (no workgroup
+//     barriers); four independent fits per workgroup;
 //   * refinement: CGLS on the right-preconditioned problem with one pass over the rows per
 //     iteration: q = A t stays in registers, alpha needs only ||q||^2 (one wave reduction), the
-//     FP64 residual is updated in place and A^T r accumulated in the same pass; stopping by the
-//     delayed Hestenes-Stiefel estimate of ||A(y - y*)||.
+//     FP64 residual is updated in place and A^T r accumulated in the same pass; column
+//     exponents are read into scalar registers so the monomial loops are uniform; stopping by
+//     the delayed Hestenes-Stiefel estimate of ||A(y - y*)||.
 // MFMA layouts (wave64): for both v_mfma_f64_16x16x4f64 and v_mfma_f32_16x16x4f32 lane l
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane l is
 // D[4 r + l / 16][l % 16] for the FP64 instruction and D[4 (l / 16) + r][l % 16] for the FP32 one.
@@ -51,11 +54,23 @@ struct WaveLds {
   double rd[kNP];                  // 1 / L_kk, pivot-indexed
   int perm[kNP];
   int ex[kNP];                     // exponents of column j, one byte per variable
+  double T[64];                    // per Gram step: x_k^p of the step's 4 rows, [row][k][p]
 };
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+// Row base of the packed lower triangle: element (i, j), j <= i, is at rbase(i) + j.
+__device__ __forceinline__ int rbase(int i) { return i * (i + 1) / 2; }
+
+// Lane l's value of v, broadcast through scalar registers (l wave-uniform).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, l);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 __device__ __forceinline__ int symi(int a, int b) {
@@ -72,24 +87,6 @@ __device__ __forceinline__ float round_bf16(float x) {
   uint32_t b = __float_as_uint(x);
   b = (b + 0x7FFFu + ((b >> 16) & 1u)) & 0xFFFF0000u;
   return __uint_as_float(b);
-}
-
-// x~^e for one row (x[0..3]) and a packed exponent word (byte k = exponent of variable k).
-__device__ __forceinline__ double mono(const double* x, int e) {
-  double r = 1.0;
-#pragma unroll
-  for (int k = 0; k < kV; ++k) {
-    const int ek = (e >> (8 * k)) & 0xFF;
-    for (int q = 0; q < ek; ++q) r *= x[k];
-  }
-  return r;
-}
-
-// Design-matrix element of column j for a row with scaled variables x and target f.
-__device__ __forceinline__ double aval(const double* x, double f, int e, int j, int n_num, int n) {
-  if (j >= n) return 0.0;
-  const double m = mono(x, e);
-  return j < n_num ? m : -f * m;
 }
 
 template <int GP>
@@ -137,9 +134,26 @@ __device__ void gram(WaveLds& L, const Rows& R, int m, int n, int n_num) {
   for (int t = 0; t < 6; ++t) acc[t] = (typename GT::acc_t){0, 0, 0, 0};
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, grp = lane >> 4;
-  int e[3];
+  // table position of x_k^(e_k) for each of the lane's three columns, as byte offsets packed
+  // two per word: entry (row g, variable k, power p) is T[16 g + 4 k + p]
+  unsigned offs[3][2];
+  bool numc[3], inr[3];
 #pragma unroll
-  for (int ct = 0; ct < 3; ++ct) e[ct] = L.ex[ct * 16 + col];
+  for (int ct = 0; ct < 3; ++ct) {
+    const int j = ct * 16 + col, ew = L.ex[j];
+    unsigned o[4];
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
+      const int ek = (ew >> (8 * k)) & 0xFF;
+      o[k] = 8u * (unsigned)(16 * grp + 4 * k + ek);
+    }
+    offs[ct][0] = o[0] | (o[1] << 16);
+    offs[ct][1] = o[2] | (o[3] << 16);
+    numc[ct] = j < n_num;
+    inr[ct] = j < n;
+  }
+  const int tk_var = (lane >> 2) & 3, tk_pow = lane & 3;   // the table entry this lane writes
+  const char* Tb = reinterpret_cast<const char*>(L.T);
   double cacc[3] = {0.0, 0.0, 0.0};
   const int steps = (m + 3) / 4;
   for (int st = 0; st < steps; ++st) {
@@ -156,8 +170,22 @@ __device__ void gram(WaveLds& L, const Rows& R, int m, int n, int n_num) {
     }
     const bool live = row < m;
     double a[3];
+    {
+      const double xk = tk_var == 0 ? xv[0] : (tk_var == 1 ? xv[1] : (tk_var == 2 ? xv[2] : xv[3]));
+      const double x2 = xk * xk;
+      L.T[lane] = tk_pow == 0 ? 1.0 : (tk_pow == 1 ? xk : (tk_pow == 2 ? x2 : x2 * xk));
+      wave_sync();
 #pragma unroll
-    for (int ct = 0; ct < 3; ++ct) a[ct] = live ? aval(xv, fv, e[ct], ct * 16 + col, n_num, n) : 0.0;
+      for (int ct = 0; ct < 3; ++ct) {
+        const double m0 = *reinterpret_cast<const double*>(Tb + (offs[ct][0] & 0xFFFFu));
+        const double m1 = *reinterpret_cast<const double*>(Tb + (offs[ct][0] >> 16));
+        const double m2 = *reinterpret_cast<const double*>(Tb + (offs[ct][1] & 0xFFFFu));
+        const double m3 = *reinterpret_cast<const double*>(Tb + (offs[ct][1] >> 16));
+        const double mo = (m0 * m1) * (m2 * m3);
+        a[ct] = (live && inr[ct]) ? (numc[ct] ? mo : -fv * mo) : 0.0;
+      }
+      wave_sync();                           // the table is rewritten by the next step
+    }
 #pragma unroll
     for (int ct = 0; ct < 3; ++ct) cacc[ct] += a[ct] * fv;
     acc[0] = GT::mfma(GT::in(a[0]), GT::in(a[0]), acc[0]);   // tile (0, 0)
@@ -173,7 +201,7 @@ __device__ void gram(WaveLds& L, const Rows& R, int m, int n, int n_num) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int j = tj[t] * 16 + GT::out_row(grp, r), k = tk[t] * 16 + col;
-      if (j < n && k < n && k <= j) L.S[symi(j, k)] = (double)acc[t][r];
+      if (j < n && k < n && k <= j) L.S[rbase(j) + k] = (double)acc[t][r];
     }
 #pragma unroll
   for (int ct = 0; ct < 3; ++ct) {
@@ -186,38 +214,36 @@ __device__ void gram(WaveLds& L, const Rows& R, int m, int n, int n_num) {
 }
 
 // Equilibrate, shift by mu = 8 u tr / n, diagonally pivoted Cholesky.  Returns the rank.
+// The factor is kept in pivot order: at step k the rows and columns k and bi are swapped in
+// place (the computed part of L and the Schur complement alike), so element (i, j) of L is at
+// rbase(i) + j and perm maps a pivot position to the original column.
 __device__ int factor_wave(WaveLds& L, int n, double unit) {
   const int lane = threadIdx.x & 63;
+  const int myb = rbase(lane);
   if (lane < n) {
-    const double gjj = L.S[symi(lane, lane)];
+    const double gjj = L.S[myb + lane];
     int e = 0;
     if (gjj > 0.0 && isfinite(gjj)) frexp(sqrt(gjj), &e);
     L.D[lane] = ldexp(1.0, -e);
     L.perm[lane] = lane;
   }
   wave_sync();
-  for (int idx = lane; idx < n * (n + 1) / 2; idx += 64) {
-    int j = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-    while ((j + 1) * (j + 2) / 2 <= idx) ++j;
-    while (j * (j + 1) / 2 > idx) --j;
-    const int k = idx - j * (j + 1) / 2;
-    L.S[idx] *= L.D[j] * L.D[k];
+  if (lane < n) {                       // row `lane` of the lower triangle
+    const double dl = L.D[lane];
+    for (int j = 0; j <= lane; ++j) L.S[myb + j] *= dl * L.D[j];
+    L.c[lane] *= dl;
   }
-  if (lane < n) L.c[lane] *= L.D[lane];
   wave_sync();
-  double tr = lane < n ? L.S[symi(lane, lane)] : 0.0;
+  double tr = lane < n ? L.S[myb + lane] : 0.0;
   tr = wsum(tr);
   const double mu = 8.0 * unit * tr / n + 1e-300;
-  if (lane < n) L.S[symi(lane, lane)] += mu;
+  if (lane < n) L.S[myb + lane] += mu;
   wave_sync();
   for (int k = 0; k < n; ++k) {
-    // largest remaining diagonal, lowest index on ties; NaN ranks below every number and lanes
-    // without a candidate hold (-inf, n), so the pick is always one of k..n-1; the butterfly
-    // leaves the same (best, bi) in every lane
     double best = -INFINITY;
     int bi = n;
     if (lane >= k && lane < n) {
-      const double vv = L.S[symi(L.perm[lane], L.perm[lane])];
+      const double vv = L.S[myb + lane];
       best = vv == vv ? vv : -INFINITY;
       bi = lane;
     }
@@ -228,43 +254,50 @@ __device__ int factor_wave(WaveLds& L, int n, double unit) {
       if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
     if (!(best > 4.0 * mu)) {
-      // numerical rank reached: the remaining Schur complement is rounding noise; the rest of
-      // the factor becomes sqrt(mu) I (the shift alone)
-      if (lane >= k && lane < n) L.piv[lane] = L.S[symi(L.perm[lane], L.perm[lane])];
-      wave_sync();
       const double smu = sqrt(mu);
-      const int w = n - k;
-      for (int e = lane; e < w * w; e += 64) {
-        const int ii = e / w, jj = e - ii * w;
-        if (jj <= ii) L.S[symi(L.perm[k + ii], L.perm[k + jj])] = ii == jj ? smu : 0.0;
+      if (lane >= k && lane < n) {
+        L.piv[lane] = L.S[myb + lane];
+        for (int j = k; j < lane; ++j) L.S[myb + j] = 0.0;
+        L.S[myb + lane] = smu;
       }
       wave_sync();
       break;
     }
-    const int pk = L.perm[bi];
-    const int pold = L.perm[k];
-    wave_sync();
-    if (lane == 0) {
-      L.perm[k] = pk;
-      L.perm[bi] = pold;
-      L.piv[k] = best;
-      L.S[symi(pk, pk)] = sqrt(best);
-    }
-    wave_sync();
-    const double lkk = L.S[symi(pk, pk)];
-    if (lane > k && lane < n) L.S[symi(L.perm[lane], pk)] /= lkk;
-    wave_sync();
-    const int w = n - k - 1;
-    for (int e = lane; e < w * w; e += 64) {
-      const int ii = e / w, jj = e - ii * w;
-      if (jj <= ii) {
-        const int ra = L.perm[k + 1 + ii], rb = L.perm[k + 1 + jj];
-        L.S[symi(ra, rb)] -= L.S[symi(ra, pk)] * L.S[symi(rb, pk)];
+    if (bi != k) {                      // symmetric swap of positions k < bi
+      const int ba = rbase(k), bb = rbase(bi);
+      int p0 = -1, p1 = -1;
+      if (lane < k) { p0 = ba + lane; p1 = bb + lane; }
+      else if (lane == k) { p0 = ba + k; p1 = bb + bi; }
+      else if (lane < bi) { p0 = myb + k; p1 = bb + lane; }
+      else if (lane > bi && lane < n) { p0 = myb + k; p1 = myb + bi; }
+      if (p0 >= 0) {
+        const double t0 = L.S[p0], t1 = L.S[p1];
+        L.S[p0] = t1;
+        L.S[p1] = t0;
       }
+      if (lane == 0) {
+        const int t = L.perm[k];
+        L.perm[k] = L.perm[bi];
+        L.perm[bi] = t;
+      }
+      wave_sync();
+    }
+    const double lkk = sqrt(best);
+    double lik = 0.0;
+    if (lane == k) {
+      L.piv[k] = best;
+      L.S[myb + k] = lkk;
+    } else if (lane > k && lane < n) {
+      lik = L.S[myb + k] / lkk;
+      L.S[myb + k] = lik;
+    }
+    for (int j = k + 1; j < n; ++j) {   // S(i, j) -= L(i, k) L(j, k) for k < j <= i
+      const double ljk = readlane_d(lik, j);
+      if (lane >= j && lane < n) L.S[myb + j] -= lik * ljk;
     }
     wave_sync();
   }
-  if (lane < n) L.rd[lane] = 1.0 / L.S[symi(L.perm[lane], L.perm[lane])];
+  if (lane < n) L.rd[lane] = 1.0 / L.S[myb + lane];
   const unsigned long long full = __ballot(lane < n && L.piv[lane] > 4.0 * mu);
   wave_sync();
   return __popcll(full);
@@ -273,13 +306,12 @@ __device__ int factor_wave(WaveLds& L, int n, double unit) {
 // L u = in[perm] (out pivot-indexed).
 __device__ void fwd_wave(const WaveLds& L, int n, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
+  const int myb = rbase(lane);
   double b = lane < n ? in[L.perm[lane]] : 0.0;
-  const int pl = lane < n ? L.perm[lane] : 0;
   for (int k = 0; k < n; ++k) {
-    const int pk = L.perm[k];
-    const double uk = __shfl(b, k) * L.rd[k];
+    const double uk = readlane_d(b, k) * L.rd[k];
     if (lane == k) b = uk;
-    if (lane > k && lane < n) b -= L.S[symi(pl, pk)] * uk;
+    if (lane > k && lane < n) b -= L.S[myb + k] * uk;
   }
   if (lane < n) out[lane] = b;
   wave_sync();
@@ -289,14 +321,12 @@ __device__ void fwd_wave(const WaveLds& L, int n, const double* in, double* out)
 __device__ void bwd_wave(const WaveLds& L, int n, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
   double b = lane < n ? in[lane] : 0.0;
-  const int pl = lane < n ? L.perm[lane] : 0;
   for (int k = n - 1; k >= 0; --k) {
-    const int pk = L.perm[k];
-    const double vk = __shfl(b, k) * L.rd[k];
+    const double vk = readlane_d(b, k) * L.rd[k];
     if (lane == k) b = vk;
-    if (lane < k) b -= L.S[symi(pk, pl)] * vk;
+    if (lane < k) b -= L.S[rbase(k) + lane] * vk;
   }
-  if (lane < n) out[pl] = b;
+  if (lane < n) out[L.perm[lane]] = b;
   wave_sync();
 }
 
@@ -536,57 +566,42 @@ __device__ void fit_wave_one(const FitArgs& a, int fi, WaveLds& L) {
   wave_sync();
 }
 
+// Longest-first schedule: wave w of workgroup b takes position 4 b + w of the wave-fit part of
+// the plan's order (the dispatcher starts workgroups in index order, so the longest fits start
+// first); positions past the wave-fit count leave at once.
 template <int PREC>
 __global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(2)))
-fit_wave_persistent(FitArgs a, WavePlanView pv) {
+fit_wave_ordered(FitArgs a, WavePlanView pv) {
   __shared__ WaveLds lds[kWavesPerGroup];
-  WaveLds& L = lds[threadIdx.x >> 6];
-  const int total = *pv.total, base = *pv.base;
-  for (;;) {
-    int i = 0;
-    if ((threadIdx.x & 63) == 0) i = atomicAdd(pv.queue, 1);
-    i = __shfl(i, 0);
-    if (i >= total) break;
-    fit_wave_one<PREC>(a, pv.order[base + i], L);
-  }
+  const int i = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+  if (i >= *pv.total) return;
+  fit_wave_one<PREC>(a, pv.order[*pv.base + i], lds[threadIdx.x >> 6]);
 }
 
+// One wave per fit in descriptor order; waves whose fit is not a wave fit leave at once.
 template <int PREC>
-__global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(2))) fit_wave_plain(FitArgs a) {
+__global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(2)))
+fit_wave_plain(FitArgs a) {
   __shared__ WaveLds lds[kWavesPerGroup];
   const int fi = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
-  if (fi >= a.n_fits || !wave_fit_eligible(a.desc[fi])) return;
+  if (fi >= a.n_fits || !wave_fit_eligible(a, a.desc[fi])) return;
   fit_wave_one<PREC>(a, fi, lds[threadIdx.x >> 6]);
 }
 
 template <int PREC>
-hipError_t launch_wave_t(const FitArgs& a, bool persistent, const WavePlanView& pv) {
-  const int block = 64 * kWavesPerGroup;
-  if (!persistent) {
-    hipLaunchKernelGGL(fit_wave_plain<PREC>, dim3((unsigned)((a.n_fits + kWavesPerGroup - 1) / kWavesPerGroup)),
-                       dim3(block), 0, a.stream, a);
-    return hipGetLastError();
-  }
-  int dev = 0, ncu = 0, occ = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&fit_wave_persistent<PREC>),
-                                                     block, 0);
-  if (e != hipSuccess) return e;
-  int64_t g = (int64_t)ncu * (occ > 0 ? occ : 1);
-  const int64_t need = (a.n_fits + kWavesPerGroup - 1) / kWavesPerGroup;
-  if (g > need) g = need;
-  hipLaunchKernelGGL(fit_wave_persistent<PREC>, dim3((unsigned)g), dim3(block), 0, a.stream, a, pv);
+hipError_t launch_wave_t(const FitArgs& a, bool ordered, const WavePlanView& pv) {
+  const dim3 grid((unsigned)((a.n_fits + kWavesPerGroup - 1) / kWavesPerGroup)), block(64 * kWavesPerGroup);
+  if (ordered) hipLaunchKernelGGL(fit_wave_ordered<PREC>, grid, block, 0, a.stream, a, pv);
+  else hipLaunchKernelGGL(fit_wave_plain<PREC>, grid, block, 0, a.stream, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_fit_wave(const FitArgs& a, bool persistent, const WavePlanView& pv) {
-  if (a.precision == KLR_FP64) return launch_wave_t<KLR_FP64>(a, persistent, pv);
-  if (a.precision == KLR_FP32_REFINED) return launch_wave_t<KLR_FP32_REFINED>(a, persistent, pv);
-  return launch_wave_t<KLR_BF16_REFINED>(a, persistent, pv);
+hipError_t launch_fit_wave(const FitArgs& a, bool ordered, const WavePlanView& pv) {
+  if (a.precision == KLR_FP64) return launch_wave_t<KLR_FP64>(a, ordered, pv);
+  if (a.precision == KLR_FP32_REFINED) return launch_wave_t<KLR_FP32_REFINED>(a, ordered, pv);
+  return launch_wave_t<KLR_BF16_REFINED>(a, ordered, pv);
 }
 
 }  // namespace klr

@@ -119,18 +119,28 @@ struct FitArgs {
 size_t fit_workspace_bytes(int32_t n_fits, int64_t f_len, int32_t precision);
 hipError_t launch_fit(const FitArgs& a);
 
-// Fits small enough for one wavefront: n <= 48 unknowns, v <= 4 variables, m <= 512 samples.
-__host__ __device__ inline bool wave_fit_eligible(const klr_fit_desc& d) {
+// Fits for one wavefront: n <= 48 unknowns, v <= 4 variables, 1 <= m <= 512 samples, valid
+// exponent rows with every exponent <= 3 (the Gram's power table holds x^0 .. x^3).
+__device__ inline bool wave_fit_eligible(const FitArgs& a, const klr_fit_desc& d) {
   const int n = d.n_num + d.n_den - 1;
-  return d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= 48 && d.v >= 1 && d.v <= 4 && d.m >= 1 && d.m <= 512;
+  if (!(d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= 48 && d.v >= 1 && d.v <= 4 && d.m >= 1 && d.m <= 512))
+    return false;
+  if (d.num0 < 0 || (int64_t)d.num0 + d.n_num > a.n_exp_rows || d.den0 < 0 ||
+      (int64_t)d.den0 + d.n_den > a.n_exp_rows)
+    return false;
+  for (int r = 0; r < d.n_num + d.n_den; ++r) {
+    const int64_t row = r < d.n_num ? (int64_t)d.num0 + r : (int64_t)d.den0 + (r - d.n_num);
+    for (int k = 0; k < d.v; ++k)
+      if (a.exps[row * KLR_MAX_VARS + k] > 3) return false;
+  }
+  return true;
 }
-struct WavePlanView {        // the wave-fit queue of the persistent schedule
+struct WavePlanView {        // the wave-fit part of the longest-first order
   const int32_t* order;
   const int32_t* total;
   const int32_t* base;
-  int32_t* queue;
 };
-hipError_t launch_fit_wave(const FitArgs& a, bool persistent, const WavePlanView& pv);
+hipError_t launch_fit_wave(const FitArgs& a, bool ordered, const WavePlanView& pv);
 
 // ---- surrogate network ----------------------------------------------------------------------
 // Parameter vector layout (floats): W2[256][256] | W1[256][4] | b1 | b2 | w3 | b3 | pad | emb.

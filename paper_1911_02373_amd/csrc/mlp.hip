@@ -411,6 +411,8 @@ mlp_small_adam(const float* __restrict__ partial, int32_t ntiles, unsigned long 
   int idx = -1;
   float g = 0.0f;
   if (i < nsmall) {
+    // fixed summation order over the tiles; unrolled so that the loads are in flight together
+#pragma unroll 16
     for (int t = 0; t < ntiles; ++t) g += partial[(int64_t)t * kPartialStride + i];
     idx = kO_W1 + i;
   } else if (i - nsmall < nk) {
@@ -429,6 +431,7 @@ mlp_small_adam(const float* __restrict__ partial, int32_t ntiles, unsigned long 
   }
   if (i == 0) {
     float L = 0.0f;
+#pragma unroll 16
     for (int t = 0; t < ntiles; ++t) L += partial[(int64_t)t * kPartialStride + kLossSlot];
     L /= (float)B;
     if (loss_step) *loss_step = L;
