@@ -45,13 +45,13 @@ struct Lds {
   static constexpr int CH = Chunk<NM>::CH;
   static constexpr int S = 0;                         // packed symmetric NM x NM (doubles)
   static constexpr int A = S + NM * (NM + 1) / 2;     // design-matrix chunk CH x NM
-  static constexpr int XT = A + CH * NM;              // scaled variables CH x 8
-  static constexpr int F = XT + CH * 8;               // targets of the chunk
+  static constexpr int PT = A + CH * NM;              // powers x~_k^p of the chunk, CH x 8 x 4
+  static constexpr int F = PT + CH * 32;              // targets of the chunk
   static constexpr int R = F + CH;                    // residuals of the chunk
   static constexpr int V = R + CH;                    // 9 vectors of NM
   static constexpr int RED = V + 9 * NM;              // reduction scratch
   static constexpr int NDOUBLE = RED + kFitBlock;
-  static constexpr int BYTES = NDOUBLE * 8 + NM * 8 + NM * 4 + 64;
+  static constexpr int BYTES = NDOUBLE * 8 + NM * 8 + NM * 4 + 64 + NM * 4;
 };
 
 __device__ __forceinline__ int symi(int a, int b) {
@@ -84,12 +84,14 @@ __device__ __forceinline__ float round_bf16(float x) {
 struct FitCtx {
   int n, n_num, n_den, m, v;
   int64_t x0, f0;
-  double* S; double* A; double* xt; double* fch; double* rch;
+  double* S; double* A; double* pt; double* fch; double* rch;
   double *D, *c, *z, *t, *s, *p, *g, *tp, *piv;
   double* red;
-  int8_t* ex;
+  uint8_t* ex;
   int* perm;
   int* flags;
+  uint32_t* ep;    // exponents of column j, two bits per variable (when every exponent <= 3)
+  bool pow3;       // every exponent of the fit is <= 3: monomials are products of table entries
 };
 
 // Stage rows [i0, i0 + rows) of the fit: scaled variables and targets.  Returns false if a
@@ -101,7 +103,15 @@ __device__ bool stage_rows(const FitArgs& a, const FitCtx& C, const int8_t* sc, 
   const int t = threadIdx.x;
   if (t < rows) {
     const int32_t* xr = a.X + C.x0 + (int64_t)(i0 + t) * C.v;
-    for (int k = 0; k < C.v; ++k) C.xt[t * 8 + k] = ldexp((double)xr[k], -(int)sc[k]);
+    for (int k = 0; k < C.v; ++k) {
+      const double x = ldexp((double)xr[k], -(int)sc[k]);
+      double* pw = C.pt + t * 32 + k * 4;
+      const double x2 = x * x;
+      pw[0] = 1.0;
+      pw[1] = x;
+      pw[2] = x2;
+      pw[3] = x2 * x;
+    }
     const double fv = a.f[C.f0 + i0 + t];
     C.fch[t] = fv;
     bad = !isfinite(fv);
@@ -110,10 +120,19 @@ __device__ bool stage_rows(const FitArgs& a, const FitCtx& C, const int8_t* sc, 
   return bad;
 }
 
-__device__ __forceinline__ double monomial(const double* xr, const int8_t* e, int v) {
+// Monomial of column j at staged row i: a product of table entries x~_k^(e_k) when every
+// exponent is <= 3, otherwise repeated multiplication by x~_k = pt[i][k][1].
+__device__ __forceinline__ double monomial(const FitCtx& C, int i, int j) {
+  const double* pw = C.pt + i * 32;
   double mono = 1.0;
-  for (int k = 0; k < v; ++k)
-    for (int r = 0; r < e[k]; ++r) mono *= xr[k];
+  if (C.pow3) {
+    const uint32_t w = C.ep[j];
+    for (int k = 0; k < C.v; ++k) mono *= pw[k * 4 + ((w >> (2 * k)) & 3u)];
+  } else {
+    const uint8_t* e = C.ex + j * 8;
+    for (int k = 0; k < C.v; ++k)
+      for (int r = 0; r < e[k]; ++r) mono *= pw[k * 4 + 1];
+  }
   return mono;
 }
 
@@ -125,7 +144,7 @@ __device__ void build_chunk(const FitCtx& C, int rows) {
     const int i = e / nb4, j = e - i * nb4;
     double val = 0.0;
     if (j < C.n) {
-      const double mono = monomial(C.xt + i * 8, C.ex + j * 8, C.v);
+      const double mono = monomial(C, i, j);
       val = j < C.n_num ? mono : -C.fch[i] * mono;
     }
     C.A[i * NM + j] = val;
@@ -292,7 +311,7 @@ __device__ double row_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, 
         const double res = C.fch[i] - dsum;
         acc += res * res;
         double qv = 1.0;
-        for (int j = C.n_num; j < C.n; ++j) qv += C.tp[j] * monomial(C.xt + i * 8, C.ex + j * 8, C.v);
+        for (int j = C.n_num; j < C.n; ++j) qv += C.tp[j] * monomial(C, i, j);
         if (!(qv > 0.0)) ++qneg;
       }
     }
@@ -465,23 +484,34 @@ __device__ void fit_one(const FitArgs& a, int fi, double* smem) {
 
   FitCtx C;
   C.n = n; C.n_num = d.n_num; C.n_den = d.n_den; C.m = d.m; C.v = d.v; C.x0 = d.x0; C.f0 = d.f0;
-  C.S = smem + L::S; C.A = smem + L::A; C.xt = smem + L::XT; C.fch = smem + L::F; C.rch = smem + L::R;
+  C.S = smem + L::S; C.A = smem + L::A; C.pt = smem + L::PT; C.fch = smem + L::F; C.rch = smem + L::R;
   double* V = smem + L::V;
   C.D = V; C.c = V + NM; C.z = V + 2 * NM; C.t = V + 3 * NM; C.s = V + 4 * NM; C.p = V + 5 * NM;
   C.g = V + 6 * NM; C.tp = V + 7 * NM; C.piv = V + 8 * NM;
   C.red = smem + L::RED;
-  C.ex = reinterpret_cast<int8_t*>(smem + L::NDOUBLE);
+  C.ex = reinterpret_cast<uint8_t*>(smem + L::NDOUBLE);
   C.perm = reinterpret_cast<int*>(C.ex + NM * 8);
   C.flags = C.perm + NM;
+  C.ep = reinterpret_cast<uint32_t*>(C.flags + 16);
 
   klr_fit_info info{};
-  if (tid == 0) C.flags[0] = 0;
+  if (tid == 0) { C.flags[0] = 0; C.flags[1] = 0; }
+  __syncthreads();
   if (ok && tid < n) {
     const int row = tid < d.n_num ? d.num0 + tid : d.den0 + (tid - d.n_num + 1);
-    for (int k = 0; k < KLR_MAX_VARS; ++k)
-      C.ex[tid * 8 + k] = k < d.v ? (int8_t)a.exps[(int64_t)row * KLR_MAX_VARS + k] : 0;
+    uint32_t w = 0;
+    bool big = false;
+    for (int k = 0; k < KLR_MAX_VARS; ++k) {
+      const int e = k < d.v ? (int)a.exps[(int64_t)row * KLR_MAX_VARS + k] : 0;
+      C.ex[tid * 8 + k] = (uint8_t)e;
+      w |= (uint32_t)(e & 3) << (2 * k);
+      big |= e > 3;
+    }
+    C.ep[tid] = w;
+    if (big) atomicOr(&C.flags[1], 1);
   }
   __syncthreads();
+  C.pow3 = C.flags[1] == 0;
   int8_t sc[KLR_MAX_VARS];
   for (int k = 0; k < KLR_MAX_VARS; ++k) sc[k] = d.scale_exp[k];
   double* wsr = reinterpret_cast<double*>(a.ws);
