@@ -136,18 +136,37 @@ __device__ __forceinline__ double monomial(const FitCtx& C, int i, int j) {
   return mono;
 }
 
-// Design-matrix chunk: A[i][j] for j < n, zero up to the 4-padded width.
+// Design-matrix chunk: A[i][j] for j < n, zero up to the 4-padded width.  Each thread owns one
+// column (its exponents are read once) and the rows i = g, g + G, ... of its row group g.
 template <int NM>
 __device__ void build_chunk(const FitCtx& C, int rows) {
+  constexpr int G = kFitBlock / NM;
+  const int j = threadIdx.x % NM, g = threadIdx.x / NM;
   const int nb4 = ((C.n + 3) / 4) * 4;
-  for (int e = threadIdx.x; e < rows * nb4; e += kFitBlock) {
-    const int i = e / nb4, j = e - i * nb4;
-    double val = 0.0;
-    if (j < C.n) {
-      const double mono = monomial(C, i, j);
-      val = j < C.n_num ? mono : -C.fch[i] * mono;
+  if (j >= nb4) return;
+  if (j >= C.n) {
+    for (int i = g; i < rows; i += G) C.A[i * NM + j] = 0.0;
+    return;
+  }
+  const bool num = j < C.n_num;
+  if (C.pow3) {
+    const uint32_t w = C.ep[j];
+    int off[KLR_MAX_VARS];
+#pragma unroll
+    for (int k = 0; k < KLR_MAX_VARS; ++k) off[k] = k * 4 + (int)((w >> (2 * k)) & 3u);
+    for (int i = g; i < rows; i += G) {
+      const double* pw = C.pt + i * 32;
+      double mono = 1.0;
+#pragma unroll
+      for (int k = 0; k < KLR_MAX_VARS; ++k)
+        if (k < C.v) mono *= pw[off[k]];
+      C.A[i * NM + j] = num ? mono : -C.fch[i] * mono;
     }
-    C.A[i * NM + j] = val;
+  } else {
+    for (int i = g; i < rows; i += G) {
+      const double mono = monomial(C, i, j);
+      C.A[i * NM + j] = num ? mono : -C.fch[i] * mono;
+    }
   }
 }
 
@@ -233,37 +252,41 @@ __device__ bool gram_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, d
   return C.flags[0] != 0;
 }
 
-// Forward solve L u = in[perm[.]] (pivoted order), by wave 0.  out is pivot-indexed.
+// Row base of the packed lower triangle: element (i, j), j <= i, is at rbase(i) + j.
+__device__ __forceinline__ int rbase(int i) { return i * (i + 1) / 2; }
+
+// Forward solve L u = in[perm[.]] by wave 0 (L in pivot order, see factor).  out is
+// pivot-indexed.
 __device__ void solve_fwd(const FitCtx& C, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
   const int n = C.n;
+  const int b0r = rbase(lane), b1r = rbase(lane + 64);
   double b0 = lane < n ? in[C.perm[lane]] : 0.0;
   double b1 = lane + 64 < n ? in[C.perm[lane + 64]] : 0.0;
   for (int k = 0; k < n; ++k) {
-    const int pk = C.perm[k];
     const double bk = __shfl(k < 64 ? b0 : b1, k & 63);
-    const double uk = bk / C.S[symi(pk, pk)];
+    const double uk = bk / C.S[rbase(k) + k];
     if (lane == (k & 63)) { if (k < 64) b0 = uk; else b1 = uk; }
-    if (lane > k && lane < n) b0 -= C.S[symi(C.perm[lane], pk)] * uk;
-    if (lane + 64 > k && lane + 64 < n) b1 -= C.S[symi(C.perm[lane + 64], pk)] * uk;
+    if (lane > k && lane < n) b0 -= C.S[b0r + k] * uk;
+    if (lane + 64 > k && lane + 64 < n) b1 -= C.S[b1r + k] * uk;
   }
   if (lane < n) out[lane] = b0;
   if (lane + 64 < n) out[lane + 64] = b1;
 }
 
-// Backward solve L^T v = in (pivot-indexed), by wave 0; out[perm[i]] = v_i.
+// Backward solve L^T v = in (pivot-indexed) by wave 0; out[perm[i]] = v_i.
 __device__ void solve_bwd(const FitCtx& C, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
   const int n = C.n;
   double b0 = lane < n ? in[lane] : 0.0;
   double b1 = lane + 64 < n ? in[lane + 64] : 0.0;
   for (int k = n - 1; k >= 0; --k) {
-    const int pk = C.perm[k];
+    const int bk_row = rbase(k);
     const double bk = __shfl(k < 64 ? b0 : b1, k & 63);
-    const double vk = bk / C.S[symi(pk, pk)];
+    const double vk = bk / C.S[bk_row + k];
     if (lane == (k & 63)) { if (k < 64) b0 = vk; else b1 = vk; }
-    if (lane < k) b0 -= C.S[symi(pk, C.perm[lane])] * vk;
-    if (lane + 64 < k) b1 -= C.S[symi(pk, C.perm[lane + 64])] * vk;
+    if (lane < k) b0 -= C.S[bk_row + lane] * vk;
+    if (lane + 64 < k) b1 -= C.S[bk_row + lane + 64] * vk;
   }
   if (lane < n) out[C.perm[lane]] = b0;
   if (lane + 64 < n) out[C.perm[lane + 64]] = b1;
@@ -359,42 +382,46 @@ __device__ void atr_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, do
   __syncthreads();
 }
 
-// Equilibrate, shift and factor S.  Returns the numerical rank.
+// Equilibrate, shift and factor S.  Returns the numerical rank.  The factor is kept in pivot
+// order: at step k the rows and columns k and bi are swapped in place (the computed part of L
+// and the Schur complement alike), so element (i, j) of L is at rbase(i) + j and perm maps a
+// pivot position to the original column.
 __device__ int factor(const FitCtx& C, double unit) {
   const int n = C.n;
   const int tid = threadIdx.x;
   if (tid < n) {
-    const double gjj = C.S[symi(tid, tid)];
+    const double gjj = C.S[rbase(tid) + tid];
     int e = 0;
     if (gjj > 0.0 && isfinite(gjj)) frexp(sqrt(gjj), &e);
     C.D[tid] = ldexp(1.0, -e);
     C.perm[tid] = tid;
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += kFitBlock) {
-    const int j = e / n, k = e - j * n;
-    if (k <= j) C.S[symi(j, k)] *= C.D[j] * C.D[k];
+  if (tid < n) {                       // row tid of the lower triangle
+    const double dj = C.D[tid];
+    const int rb = rbase(tid);
+    for (int k = 0; k <= tid; ++k) C.S[rb + k] *= dj * C.D[k];
+    C.c[tid] *= dj;
   }
-  if (tid < n) C.c[tid] *= C.D[tid];
   __syncthreads();
   if (tid < 64) {
     double tr = 0.0;
-    for (int j = tid; j < n; j += 64) tr += C.S[symi(j, j)];
+    for (int j = tid; j < n; j += 64) tr += C.S[rbase(j) + j];
     tr = wave_sum(tr);
     if (tid == 0) C.red[kFitBlock - 1] = 8.0 * unit * tr / n + 1e-300;
   }
   __syncthreads();
   const double mu = C.red[kFitBlock - 1];
-  if (tid < n) C.S[symi(tid, tid)] += mu;
+  if (tid < n) C.S[rbase(tid) + tid] += mu;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
     if (tid < 64) {
       // largest remaining diagonal, lowest index on ties; NaN ranks below every number, so the
-      // pick is always one of the remaining indices k..n-1
+      // pick is always one of the remaining positions k..n-1
       double best = -INFINITY;
       int bi = n;
       for (int i = k + tid; i < n; i += 64) {
-        const double vv = C.S[symi(C.perm[i], C.perm[i])];
+        const double vv = C.S[rbase(i) + i];
         const double key = vv == vv ? vv : -INFINITY;
         if (key > best || (key == best && i < bi)) { best = key; bi = i; }
       }
@@ -406,41 +433,66 @@ __device__ int factor(const FitCtx& C, double unit) {
       }
       if (tid == 0) {
         C.red[kFitBlock - 3] = best;
-        if (best > 4.0 * mu) {
-          const int pt = C.perm[k];
-          C.perm[k] = C.perm[bi];
-          C.perm[bi] = pt;
-          C.piv[k] = best;
-          C.S[symi(C.perm[k], C.perm[k])] = sqrt(best);
-        }
+        C.flags[2] = bi;
       }
     }
     __syncthreads();
-    if (!(C.red[kFitBlock - 3] > 4.0 * mu)) {
+    const double best = C.red[kFitBlock - 3];
+    const int bi = C.flags[2];
+    if (!(best > 4.0 * mu)) {
       // numerical rank reached: every remaining diagonal is at most 4 mu, i.e. the remaining
       // Schur complement is rounding noise; the rest of the factor becomes sqrt(mu) I (the
       // shift alone), so the noise is never divided by a tiny pivot
-      for (int i = k + tid; i < n; i += kFitBlock) C.piv[i] = C.S[symi(C.perm[i], C.perm[i])];
-      __syncthreads();
       const double smu = sqrt(mu);
-      const int w = n - k;
-      for (int e = tid; e < w * w; e += kFitBlock) {
-        const int ii = e / w, jj = e - ii * w;
-        if (jj <= ii) C.S[symi(C.perm[k + ii], C.perm[k + jj])] = ii == jj ? smu : 0.0;
+      const int i = k + tid;
+      if (i < n) {
+        const int rb = rbase(i);
+        C.piv[i] = C.S[rb + i];
+        for (int j = k; j < i; ++j) C.S[rb + j] = 0.0;
+        C.S[rb + i] = smu;
       }
       __syncthreads();
       break;
     }
-    const int pk = C.perm[k];
-    const double lkk = C.S[symi(pk, pk)];
-    for (int i = k + 1 + tid; i < n; i += kFitBlock) C.S[symi(C.perm[i], pk)] /= lkk;
+    if (bi != k) {                     // symmetric swap of positions k < bi
+      const int ba = rbase(k), bb = rbase(bi);
+      const int i = tid;
+      int p0 = -1, p1 = -1;
+      if (i < k) { p0 = ba + i; p1 = bb + i; }
+      else if (i == k) { p0 = ba + k; p1 = bb + bi; }
+      else if (i < bi) { p0 = rbase(i) + k; p1 = bb + i; }
+      else if (i > bi && i < n) { p0 = rbase(i) + k; p1 = rbase(i) + bi; }
+      if (p0 >= 0) {
+        const double t0 = C.S[p0], t1 = C.S[p1];
+        C.S[p0] = t1;
+        C.S[p1] = t0;
+      }
+      if (tid == 0) {
+        const int t = C.perm[k];
+        C.perm[k] = C.perm[bi];
+        C.perm[bi] = t;
+      }
+      __syncthreads();
+    }
+    const double lkk = sqrt(best);
+    if (tid == 0) {
+      C.piv[k] = best;
+      C.S[rbase(k) + k] = lkk;
+    }
+    {
+      const int i = k + 1 + tid;
+      if (i < n) C.S[rbase(i) + k] /= lkk;
+    }
     __syncthreads();
-    const int w = n - k - 1;
-    for (int e = tid; e < w * w; e += kFitBlock) {
-      const int ii = e / w, jj = e - ii * w;
-      if (jj <= ii) {
-        const int ra = C.perm[k + 1 + ii], rb = C.perm[k + 1 + jj];
-        C.S[symi(ra, rb)] -= C.S[symi(ra, pk)] * C.S[symi(rb, pk)];
+    // trailing update S(i, j) -= L(i, k) L(j, k), k < j <= i: two threads per row, alternate
+    // columns (rows beyond 128 cannot occur: n <= 128)
+    {
+      const int r = tid & 127, h = tid >> 7;
+      const int i = k + 1 + r;
+      if (i < n) {
+        const int rb = rbase(i);
+        const double lik = C.S[rb + k];
+        for (int j = k + 1 + h; j <= i; j += 2) C.S[rb + j] -= lik * C.S[rbase(j) + k];
       }
     }
     __syncthreads();
