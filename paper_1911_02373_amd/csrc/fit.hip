@@ -48,8 +48,9 @@ struct Lds {
   static constexpr int PT = A + CH * NM;              // powers x~_k^p of the chunk, CH x 8 x 4
   static constexpr int F = PT + CH * 32;              // targets of the chunk
   static constexpr int R = F + CH;                    // residuals of the chunk
-  static constexpr int V = R + CH;                    // 9 vectors of NM
-  static constexpr int RED = V + 9 * NM;              // reduction scratch
+  static constexpr int Q = R + CH;                    // A t of the chunk
+  static constexpr int V = Q + CH;                    // 10 vectors of NM
+  static constexpr int RED = V + 10 * NM;             // reduction scratch
   static constexpr int NDOUBLE = RED + kFitBlock;
   static constexpr int BYTES = NDOUBLE * 8 + NM * 8 + NM * 4 + 64 + NM * 4;
 };
@@ -84,8 +85,8 @@ __device__ __forceinline__ float round_bf16(float x) {
 struct FitCtx {
   int n, n_num, n_den, m, v;
   int64_t x0, f0;
-  double* S; double* A; double* pt; double* fch; double* rch;
-  double *D, *c, *z, *t, *s, *p, *g, *tp, *piv;
+  double* S; double* A; double* pt; double* fch; double* rch; double* qch;
+  double *D, *c, *z, *t, *s, *p, *g, *gq, *tp, *piv;
   double* red;
   uint8_t* ex;
   int* perm;
@@ -300,13 +301,10 @@ __device__ double dot_w0(const double* x, const double* y, int n) {
   return wave_sum(v);
 }
 
-enum RowMode { kR0 = 0, kQ = 1, kFinal = 2 };
-
-// Row pass: d_i = sum_j A_ij tp_j.  kR0: r_i = f_i - d_i.  kQ: q_i = d_i, returns sum q_i^2.
-// kFinal: returns sum (f_i - d_i)^2 and counts samples with q(x~_i) <= 0 (tp holds y).
-template <int NM, int MODE>
-__device__ double row_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, double* wsr,
-                           double* wsq, int* qneg_out) {
+// Final pass: returns sum (f_i - d_i)^2 with d = A tp (tp holds y) and counts the samples with
+// q(x~_i) <= 0 into *qneg_out.
+template <int NM>
+__device__ double final_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, int* qneg_out) {
   constexpr int CH = Chunk<NM>::CH;
   constexpr int TPR = kFitBlock / CH;
   const int i = threadIdx.x / TPR, sub = threadIdx.x % TPR;
@@ -324,62 +322,95 @@ __device__ double row_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, 
 #pragma unroll
     for (int off = TPR / 2; off >= 1; off >>= 1) dsum += __shfl_xor(dsum, off);
     if (i < rows && sub == 0) {
-      const int64_t row = C.f0 + i0 + i;
-      if (MODE == kR0) {
-        wsr[row] = C.fch[i] - dsum;
-      } else if (MODE == kQ) {
-        wsq[row] = dsum;
-        acc += dsum * dsum;
-      } else {
-        const double res = C.fch[i] - dsum;
-        acc += res * res;
-        double qv = 1.0;
-        for (int j = C.n_num; j < C.n; ++j) qv += C.tp[j] * monomial(C, i, j);
-        if (!(qv > 0.0)) ++qneg;
-      }
+      const double res = C.fch[i] - dsum;
+      acc += res * res;
+      double qv = 1.0;
+      for (int j = C.n_num; j < C.n; ++j) qv += C.tp[j] * monomial(C, i, j);
+      if (!(qv > 0.0)) ++qneg;
     }
     __syncthreads();
   }
-  if (MODE == kFinal) {
-    const double qn = block_sum((double)qneg, C.red);
-    *qneg_out = (int)qn;
-  }
+  const double qn = block_sum((double)qneg, C.red);
+  *qneg_out = (int)qn;
   return block_sum(acc, C.red);
 }
 
-// g = D A^T r, with r updated first (r -= alpha q) when `update`.
-template <int NM>
-__device__ void atr_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, double* wsr,
-                         const double* wsq, bool update, double alpha) {
+enum CgMode { kR0 = 0, kQ = 1 };
+
+// One sweep over the fit's rows for the refinement, each chunk of A built once:
+//   kR0: r = f - A tp (stored), C.g = A^T r;
+//   kQ : when `upd`, r = r - alpha_prev q_prev (the residual update of the previous iteration,
+//        applied to the stored rows first); q = A tp (stored), C.g = A^T r, C.gq = A^T q;
+//        returns ||q||^2.
+// The caller forms D A^T r_next = D (C.g - alpha C.gq) once alpha is known, so every iteration
+// reads the FP64 residual of the samples and builds each chunk once.
+template <int NM, int MODE>
+__device__ double cg_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, double* wsr, double* wsq,
+                          bool upd, double alpha_prev) {
   constexpr int CH = Chunk<NM>::CH;
+  constexpr int TPR = kFitBlock / CH;
   constexpr int TPC = kFitBlock / NM;
-  const int j = threadIdx.x % NM, sub = threadIdx.x / NM;
-  double acc = 0.0;
+  const int ri = threadIdx.x / TPR, rsub = threadIdx.x % TPR;
+  const int cj = threadIdx.x % NM, csub = threadIdx.x / NM;
+  double accr = 0.0, accq = 0.0, qq = 0.0;
   for (int i0 = 0; i0 < C.m; i0 += CH) {
     const int rows = C.m - i0 < CH ? C.m - i0 : CH;
     stage_rows<NM>(a, C, sc, i0, rows);
-    const int t = threadIdx.x;
-    if (t < rows) {
-      const int64_t row = C.f0 + i0 + t;
-      double r = wsr[row];
-      if (update) { r -= alpha * wsq[row]; wsr[row] = r; }
-      C.rch[t] = r;
-    }
     __syncthreads();
     build_chunk<NM>(C, rows);
     __syncthreads();
-    if (j < C.n)
-      for (int i = sub; i < rows; i += TPC) acc += C.A[i * NM + j] * C.rch[i];
+    double dsum = 0.0;
+    if (ri < rows)
+      for (int j = rsub; j < C.n; j += TPR) dsum += C.A[ri * NM + j] * C.tp[j];
+#pragma unroll
+    for (int off = TPR / 2; off >= 1; off >>= 1) dsum += __shfl_xor(dsum, off);
+    if (ri < rows && rsub == 0) {
+      const int64_t row = C.f0 + i0 + ri;
+      if (MODE == kR0) {
+        const double r = C.fch[ri] - dsum;
+        wsr[row] = r;
+        C.rch[ri] = r;
+      } else {
+        double r = wsr[row];
+        if (upd) {
+          r -= alpha_prev * wsq[row];
+          wsr[row] = r;
+        }
+        C.rch[ri] = r;
+        C.qch[ri] = dsum;
+        wsq[row] = dsum;
+        qq += dsum * dsum;
+      }
+    }
+    __syncthreads();
+    if (cj < C.n)
+      for (int i = csub; i < rows; i += TPC) {
+        const double av = C.A[i * NM + cj];
+        accr += av * C.rch[i];
+        if (MODE == kQ) accq += av * C.qch[i];
+      }
     __syncthreads();
   }
-  C.red[threadIdx.x] = acc;
+  C.red[threadIdx.x] = accr;
   __syncthreads();
   if ((int)threadIdx.x < C.n) {
-    double gsum = 0.0;
-    for (int s = 0; s < TPC; ++s) gsum += C.red[threadIdx.x + s * NM];
-    C.g[threadIdx.x] = gsum * C.D[threadIdx.x];
+    double v = 0.0;
+    for (int s2 = 0; s2 < TPC; ++s2) v += C.red[threadIdx.x + s2 * NM];
+    C.g[threadIdx.x] = v;
   }
   __syncthreads();
+  if (MODE == kQ) {
+    C.red[threadIdx.x] = accq;
+    __syncthreads();
+    if ((int)threadIdx.x < C.n) {
+      double v = 0.0;
+      for (int s2 = 0; s2 < TPC; ++s2) v += C.red[threadIdx.x + s2 * NM];
+      C.gq[threadIdx.x] = v;
+    }
+    __syncthreads();
+    return block_sum(qq, C.red);
+  }
+  return 0.0;
 }
 
 // Equilibrate, shift and factor S.  Returns the numerical rank.  The factor is kept in pivot
@@ -537,9 +568,10 @@ __device__ void fit_one(const FitArgs& a, int fi, double* smem) {
   FitCtx C;
   C.n = n; C.n_num = d.n_num; C.n_den = d.n_den; C.m = d.m; C.v = d.v; C.x0 = d.x0; C.f0 = d.f0;
   C.S = smem + L::S; C.A = smem + L::A; C.pt = smem + L::PT; C.fch = smem + L::F; C.rch = smem + L::R;
+  C.qch = smem + L::Q;
   double* V = smem + L::V;
   C.D = V; C.c = V + NM; C.z = V + 2 * NM; C.t = V + 3 * NM; C.s = V + 4 * NM; C.p = V + 5 * NM;
-  C.g = V + 6 * NM; C.tp = V + 7 * NM; C.piv = V + 8 * NM;
+  C.g = V + 6 * NM; C.tp = V + 7 * NM; C.piv = V + 8 * NM; C.gq = V + 9 * NM;
   C.red = smem + L::RED;
   C.ex = reinterpret_cast<uint8_t*>(smem + L::NDOUBLE);
   C.perm = reinterpret_cast<int*>(C.ex + NM * 8);
@@ -590,8 +622,9 @@ __device__ void fit_one(const FitArgs& a, int fi, double* smem) {
     __syncthreads();
     if (tid < n) C.tp[tid] = C.D[tid] * C.z[tid];
     __syncthreads();
-    row_pass<NM, kR0>(a, C, sc, wsr, wsq, nullptr);
-    atr_pass<NM>(a, C, sc, wsr, wsq, false, 0.0);
+    cg_pass<NM, kR0>(a, C, sc, wsr, wsq, false, 0.0);
+    if (tid < n) C.g[tid] *= C.D[tid];
+    __syncthreads();
     if (tid < 64) solve_fwd(C, C.g, C.s);
     __syncthreads();
     if (tid < n) C.p[tid] = C.s[tid];
@@ -604,26 +637,31 @@ __device__ void fit_one(const FitArgs& a, int fi, double* smem) {
     // CGLS increments are B^T B-orthogonal, so sum_{j >= k} alpha_j gamma_j = ||A (y* - y_k)||^2:
     // the last kDelay terms estimate the error of the fitted values (Hestenes-Stiefel).
     constexpr int kDelay = 3;
-    double hist[kDelay] = {0.0, 0.0, 0.0};
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0;     // the last kDelay alpha gamma terms
     const int need = a.max_iter < kDelay ? a.max_iter : kDelay;
+    double alpha_prev = 0.0;
     for (int it = 0; it < a.max_iter && !converged; ++it) {
       if (tid < 64) solve_bwd(C, C.p, C.t);
       __syncthreads();
       if (tid < n) C.tp[tid] = C.D[tid] * C.t[tid];
       __syncthreads();
-      const double qq = row_pass<NM, kQ>(a, C, sc, wsr, wsq, nullptr);
+      const double qq = cg_pass<NM, kQ>(a, C, sc, wsr, wsq, it > 0, alpha_prev);
       const double alpha = qq > 0.0 ? gamma / qq : 0.0;
       if (tid < n) C.z[tid] += alpha * C.t[tid];
       __syncthreads();
-      hist[it % kDelay] = alpha * gamma;
+      h0 = h1;
+      h1 = h2;
+      h2 = alpha * gamma;
       ++iters;
       if (it + 1 >= need) {
-        const double est = sqrt(hist[0] + hist[1] + hist[2]);
+        const double est = sqrt(h0 + h1 + h2);
         err = fnorm > 0.0 ? est / fnorm : 0.0;
         if (est <= a.tol * fnorm) { converged = true; break; }
       }
       if (qq == 0.0) { converged = true; break; }
-      atr_pass<NM>(a, C, sc, wsr, wsq, true, alpha);
+      if (tid < n) C.g[tid] = C.D[tid] * (C.g[tid] - alpha * C.gq[tid]);   // D A^T (r - alpha q)
+      __syncthreads();
+      alpha_prev = alpha;
       if (tid < 64) solve_fwd(C, C.g, C.s);
       __syncthreads();
       if (tid < 64) { const double gg = dot_w0(C.s, C.s, n); if (tid == 0) C.red[kFitBlock - 2] = gg; }
@@ -654,7 +692,7 @@ __device__ void fit_one(const FitArgs& a, int fi, double* smem) {
   if (tid < n) C.tp[tid] = C.D[tid] * C.z[tid];
   __syncthreads();
   int qneg = 0;
-  const double rr = row_pass<NM, kFinal>(a, C, sc, wsr, wsq, &qneg);
+  const double rr = final_pass<NM>(a, C, sc, &qneg);
   if (tid < n) a.coef[d.coef0 + tid] = C.tp[tid];
   if (tid == 0) {
     if (rank < n) info.status |= KLR_FIT_RANK_DEFICIENT;

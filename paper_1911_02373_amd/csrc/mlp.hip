@@ -361,11 +361,17 @@ __global__ void __launch_bounds__(kBlock) mlp_fwd_bwd(TrainTile a, Blob w) {
     const long long q = __double2ll_rn((double)de * 0x1p44);
     atomicAdd(a.emb_acc + ks[tid], (unsigned long long)q);
   }
-  if (tid == 0) {
-    float sdy = 0.0f, sl = 0.0f;
-    for (int s = 0; s < TS; ++s) { sdy += dys[s]; sl += lss[s]; }
-    prt[kO_B3 - kO_W1] = sdy;
-    prt[kLossSlot] = sl;
+  if (tid < TS) {               // wave 0: butterfly sums over the tile (fixed pattern, deterministic)
+    float sdy = dys[tid], sl = lss[tid];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      sdy += __shfl_xor(sdy, off);
+      sl += __shfl_xor(sl, off);
+    }
+    if (tid == 0) {
+      prt[kO_B3 - kO_W1] = sdy;
+      prt[kLossSlot] = sl;
+    }
   }
 }
 
