@@ -76,12 +76,6 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-__device__ __forceinline__ float round_bf16(float x) {
-  uint32_t b = __float_as_uint(x);
-  b = (b + 0x7FFFu + ((b >> 16) & 1u)) & 0xFFFF0000u;   // round to nearest even, finite inputs
-  return __uint_as_float(b);
-}
-
 struct FitCtx {
   int n, n_num, n_den, m, v;
   int64_t x0, f0;
@@ -98,14 +92,14 @@ struct FitCtx {
 // Stage rows [i0, i0 + rows) of the fit: scaled variables and targets.  Returns false if a
 // target is not finite.
 template <int NM>
-__device__ bool stage_rows(const FitArgs& a, const FitCtx& C, const int8_t* sc, int i0, int rows,
+__device__ bool stage_rows(const FitArgs& a, const FitCtx& C, uint64_t sc, int i0, int rows,
                            double* ff = nullptr) {
   bool bad = false;
   const int t = threadIdx.x;
   if (t < rows) {
     const int32_t* xr = a.X + C.x0 + (int64_t)(i0 + t) * C.v;
     for (int k = 0; k < C.v; ++k) {
-      const double x = ldexp((double)xr[k], -(int)sc[k]);
+      const double x = ldexp((double)xr[k], -(int)(int8_t)(uint8_t)(sc >> (8 * k)));
       double* pw = C.pt + t * 32 + k * 4;
       const double x2 = x * x;
       pw[0] = 1.0;
@@ -171,90 +165,83 @@ __device__ void build_chunk(const FitCtx& C, int rows) {
   }
 }
 
+// Row base of the packed lower triangle: element (i, j), j <= i, is at rbase(i) + j.
+__device__ __forceinline__ int rbase(int i) { return i * (i + 1) / 2; }
+
 // Gram pass: S (packed lower, unscaled), c = A^T f and ||f||^2 (into *fnorm2).
 // GP: Gram precision.  Returns true if a target is not finite.
+// S is formed on the matrix cores: the 16-column tiles of A give nt (nt + 1) / 2 lower tile
+// pairs, dealt round-robin to the waves; at every step of 4 chunk rows the wave issues one MFMA
+// per pair it owns, each lane reading its operand slots (row l / 16, column l % 16 of the two
+// tiles) from LDS.  c = A^T f stays in FP64 on the vector units.
 template <int NM, int GP>
-__device__ bool gram_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, double* fnorm2) {
+__device__ bool gram_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double* fnorm2) {
+  using GT = GramTypes<GP>;
+  using acc_t = typename GT::acc_t;
   constexpr int CH = Chunk<NM>::CH;
-  constexpr int NBMAX = NM / 4;
-  constexpr int BPT = (NBMAX * (NBMAX + 1) / 2 + kFitBlock - 1) / kFitBlock;
-  using acc_t = typename std::conditional<GP == KLR_FP64, double, float>::type;
-  const int nb = (C.n + 3) / 4;
-  const int nbl = nb * (nb + 1) / 2;
-  int bj[BPT], bk[BPT];
-  acc_t acc[BPT][16];
+  constexpr int NT = NM / 16;                       // column tiles
+  constexpr int W = kFitBlock / 64;                 // waves
+  constexpr int PPW = (NT * (NT + 1) / 2 + W - 1) / W;
+  constexpr int TPC = kFitBlock / NM;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int grp = lane >> 4, col = lane & 15;
+  const int nt = (C.n + 15) / 16;
+  const int npair = nt * (nt + 1) / 2;
+  int tj[PPW], tk[PPW];
+  acc_t acc[PPW];
 #pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    const int blk = threadIdx.x + b * kFitBlock;
-    int r = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
-    while ((r + 1) * (r + 2) / 2 <= blk) ++r;
-    while (r * (r + 1) / 2 > blk) --r;
-    bj[b] = r;
-    bk[b] = blk - r * (r + 1) / 2;
+  for (int q = 0; q < PPW; ++q) {
+    const int p = wv + W * q;
+    int r = 0;
+    while ((r + 1) * (r + 2) / 2 <= p) ++r;
+    tj[q] = r;
+    tk[q] = p - r * (r + 1) / 2;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[b][u] = 0;
+    for (int u = 0; u < 4; ++u) acc[q][u] = 0;
   }
+  const int cj = threadIdx.x % NM, csub = threadIdx.x / NM;
   double cacc = 0.0, ff = 0.0;
   bool bad = false;
   for (int i0 = 0; i0 < C.m; i0 += CH) {
     const int rows = C.m - i0 < CH ? C.m - i0 : CH;
+    const int rows4 = (rows + 3) & ~3;
     bad |= stage_rows<NM>(a, C, sc, i0, rows, &ff);
     __syncthreads();
     build_chunk<NM>(C, rows);
+    for (int e = threadIdx.x; e < (rows4 - rows) * NM; e += kFitBlock) C.A[rows * NM + e] = 0.0;
     __syncthreads();
+    for (int i = 0; i < rows4; i += 4) {
+      const double* ar = C.A + (i + grp) * NM + col;
 #pragma unroll
-    for (int b = 0; b < BPT; ++b) {
-      const int blk = threadIdx.x + b * kFitBlock;
-      if (blk < nbl) {
-        const double* pa = C.A + 4 * bj[b];
-        const double* pb = C.A + 4 * bk[b];
-        for (int i = 0; i < rows; ++i) {
-          acc_t x[4], y[4];
+      for (int q = 0; q < PPW; ++q)
+        if (wv + W * q < npair)
+          acc[q] = GT::mfma(GT::in(ar[16 * tj[q]]), GT::in(ar[16 * tk[q]]), acc[q]);
+    }
+    if (cj < C.n)
+      for (int i = csub; i < rows; i += TPC) cacc += C.A[i * NM + cj] * C.fch[i];
+    __syncthreads();
+  }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if (GP == KLR_FP64) {
-              x[u] = (acc_t)pa[i * NM + u];
-              y[u] = (acc_t)pb[i * NM + u];
-            } else if (GP == KLR_FP32_REFINED) {
-              x[u] = (acc_t)(float)pa[i * NM + u];
-              y[u] = (acc_t)(float)pb[i * NM + u];
-            } else {
-              x[u] = (acc_t)round_bf16((float)pa[i * NM + u]);
-              y[u] = (acc_t)round_bf16((float)pb[i * NM + u]);
-            }
-          }
+  for (int q = 0; q < PPW; ++q) {
+    if (wv + W * q < npair) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int w = 0; w < 4; ++w) acc[b][u * 4 + w] += x[u] * y[w];
-        }
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * tj[q] + GT::out_row(grp, r), k = 16 * tk[q] + col;
+        if (j < C.n && k <= j) C.S[rbase(j) + k] = (double)acc[q][r];
       }
     }
-    if ((int)threadIdx.x < C.n)
-      for (int i = 0; i < rows; ++i) cacc += C.A[i * NM + threadIdx.x] * C.fch[i];
-    __syncthreads();
   }
-#pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    const int blk = threadIdx.x + b * kFitBlock;
-    if (blk < nbl) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          const int j = 4 * bj[b] + u, k = 4 * bk[b] + w;
-          if (j < C.n && k < C.n && k <= j) C.S[symi(j, k)] = (double)acc[b][u * 4 + w];
-        }
-    }
+  C.red[threadIdx.x] = cacc;
+  __syncthreads();
+  if ((int)threadIdx.x < C.n) {
+    double v = 0.0;
+    for (int s2 = 0; s2 < TPC; ++s2) v += C.red[threadIdx.x + s2 * NM];
+    C.c[threadIdx.x] = v;
   }
-  if ((int)threadIdx.x < C.n) C.c[threadIdx.x] = cacc;
   if (bad) C.flags[0] = 1;
   *fnorm2 = block_sum(ff, C.red);
   return C.flags[0] != 0;
 }
-
-// Row base of the packed lower triangle: element (i, j), j <= i, is at rbase(i) + j.
-__device__ __forceinline__ int rbase(int i) { return i * (i + 1) / 2; }
 
 // Forward solve L u = in[perm[.]] by wave 0 (L in pivot order, see factor).  out is
 // pivot-indexed.
@@ -304,7 +291,7 @@ __device__ double dot_w0(const double* x, const double* y, int n) {
 // Final pass: returns sum (f_i - d_i)^2 with d = A tp (tp holds y) and counts the samples with
 // q(x~_i) <= 0 into *qneg_out.
 template <int NM>
-__device__ double final_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, int* qneg_out) {
+__device__ double final_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, int* qneg_out) {
   constexpr int CH = Chunk<NM>::CH;
   constexpr int TPR = kFitBlock / CH;
   const int i = threadIdx.x / TPR, sub = threadIdx.x % TPR;
@@ -345,7 +332,7 @@ enum CgMode { kR0 = 0, kQ = 1 };
 // The caller forms D A^T r_next = D (C.g - alpha C.gq) once alpha is known, so every iteration
 // reads the FP64 residual of the samples and builds each chunk once.
 template <int NM, int MODE>
-__device__ double cg_pass(const FitArgs& a, const FitCtx& C, const int8_t* sc, double* wsr, double* wsq,
+__device__ double cg_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double* wsr, double* wsq,
                           bool upd, double alpha_prev) {
   constexpr int CH = Chunk<NM>::CH;
   constexpr int TPR = kFitBlock / CH;
@@ -445,6 +432,11 @@ __device__ int factor(const FitCtx& C, double unit) {
   const double mu = C.red[kFitBlock - 1];
   if (tid < n) C.S[rbase(tid) + tid] += mu;
   __syncthreads();
+  // Step k: (A) wave 0 picks the pivot while waves 1-3 divide column k-1 by its pivot's root;
+  // (B) symmetric swap; (C) trailing update from the unscaled column k, rows and columns dealt
+  // cyclically over a 16 x 16 thread grid so every thread has the same share of the triangle.
+  double lprev = 1.0;                  // root of the previous pivot
+  const int ty = tid >> 4, tx = tid & 15;
   for (int k = 0; k < n; ++k) {
     if (tid < 64) {
       // largest remaining diagonal, lowest index on ties; NaN ranks below every number, so the
@@ -466,6 +458,9 @@ __device__ int factor(const FitCtx& C, double unit) {
         C.red[kFitBlock - 3] = best;
         C.flags[2] = bi;
       }
+    } else if (k > 0) {
+      const int i = k + tid - 64;      // rows k.. of column k-1
+      if (i < n) C.S[rbase(i) + k - 1] /= lprev;
     }
     __syncthreads();
     const double best = C.red[kFitBlock - 3];
@@ -506,26 +501,28 @@ __device__ int factor(const FitCtx& C, double unit) {
       __syncthreads();
     }
     const double lkk = sqrt(best);
-    if (tid == 0) {
+    const double rinv = 1.0 / best;
+    if (tid == 0) {                    // nothing reads (k, k) during the update
       C.piv[k] = best;
       C.S[rbase(k) + k] = lkk;
     }
-    {
-      const int i = k + 1 + tid;
-      if (i < n) C.S[rbase(i) + k] /= lkk;
+    // S(i, j) -= S(i, k) S(j, k) / best for k < j <= i (n <= 128: at most 8 columns per thread)
+    double lj[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int j = k + 1 + tx + 16 * b;
+      lj[b] = j < n ? C.S[rbase(j) + k] : 0.0;
     }
-    __syncthreads();
-    // trailing update S(i, j) -= L(i, k) L(j, k), k < j <= i: two threads per row, alternate
-    // columns (rows beyond 128 cannot occur: n <= 128)
-    {
-      const int r = tid & 127, h = tid >> 7;
-      const int i = k + 1 + r;
-      if (i < n) {
-        const int rb = rbase(i);
-        const double lik = C.S[rb + k];
-        for (int j = k + 1 + h; j <= i; j += 2) C.S[rb + j] -= lik * C.S[rbase(j) + k];
+    for (int i = k + 1 + ty; i < n; i += 16) {
+      const int rb = rbase(i);
+      const double lik = C.S[rb + k] * rinv;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int j = k + 1 + tx + 16 * b;
+        if (j <= i) C.S[rb + j] -= lik * lj[b];
       }
     }
+    lprev = lkk;
     __syncthreads();
   }
   int rank = 0;
@@ -596,8 +593,9 @@ __device__ void fit_one(const FitArgs& a, int fi, double* smem) {
   }
   __syncthreads();
   C.pow3 = C.flags[1] == 0;
-  int8_t sc[KLR_MAX_VARS];
-  for (int k = 0; k < KLR_MAX_VARS; ++k) sc[k] = d.scale_exp[k];
+  uint64_t sc = 0;                     // scale exponents s_k, one byte each
+#pragma unroll
+  for (int k = 0; k < KLR_MAX_VARS; ++k) sc |= (uint64_t)(uint8_t)d.scale_exp[k] << (8 * k);
   double* wsr = reinterpret_cast<double*>(a.ws);
   double* wsq = wsr + a.f_len;
 

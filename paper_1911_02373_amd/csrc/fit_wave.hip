@@ -38,8 +38,6 @@ constexpr int kV = 4;              // variables
 constexpr int kWavesPerGroup = 4;
 constexpr int kSP = kNP * (kNP + 1) / 2;
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct WaveLds {
   double S[kSP];                   // equilibrated, shifted Gram -> pivoted Cholesky factor
@@ -82,42 +80,6 @@ __device__ __forceinline__ double wsum(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
   return v;
 }
-
-__device__ __forceinline__ float round_bf16(float x) {
-  uint32_t b = __float_as_uint(x);
-  b = (b + 0x7FFFu + ((b >> 16) & 1u)) & 0xFFFF0000u;
-  return __uint_as_float(b);
-}
-
-template <int GP>
-struct GramTypes;
-template <>
-struct GramTypes<KLR_FP64> {
-  typedef f64x4 acc_t;
-  static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ double in(double v) { return v; }
-  static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * r + grp; }
-};
-template <>
-struct GramTypes<KLR_FP32_REFINED> {
-  typedef f32x4 acc_t;
-  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ float in(double v) { return (float)v; }
-  static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * grp + r; }
-};
-template <>
-struct GramTypes<KLR_BF16_REFINED> {
-  typedef f32x4 acc_t;
-  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);   // products of BF16 values are exact in FP32
-  }
-  static __device__ __forceinline__ float in(double v) { return round_bf16((float)v); }
-  static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * grp + r; }
-};
 
 struct Rows {
   double x[kRPL][kV];

@@ -135,6 +135,51 @@ __device__ inline bool wave_fit_eligible(const FitArgs& a, const klr_fit_desc& d
   }
   return true;
 }
+// Rounds an FP32 value to the nearest BF16 value (ties to even), kept in FP32.
+__device__ __forceinline__ float round_bf16(float x) {
+  uint32_t b = __float_as_uint(x);
+  b = (b + 0x7FFFu + ((b >> 16) & 1u)) & 0xFFFF0000u;
+  return __uint_as_float(b);
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Gram products on the matrix cores, per Gram precision.  For v_mfma_f64_16x16x4f64 and
+// v_mfma_f32_16x16x4f32 alike, lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result
+// register r of lane l is D[out_row(l / 16, r)][l % 16]: row 4 r + l / 16 for the FP64
+// instruction, 4 (l / 16) + r for the FP32 one.  The reduced paths round the design-matrix
+// values to FP32 or BF16 and accumulate in FP32 (products of BF16 values are exact in FP32).
+template <int GP>
+struct GramTypes;
+template <>
+struct GramTypes<KLR_FP64> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ double in(double v) { return v; }
+  static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * r + grp; }
+};
+template <>
+struct GramTypes<KLR_FP32_REFINED> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ float in(double v) { return (float)v; }
+  static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * grp + r; }
+};
+template <>
+struct GramTypes<KLR_BF16_REFINED> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ float in(double v) { return round_bf16((float)v); }
+  static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * grp + r; }
+};
+
 struct WavePlanView {        // the wave-fit part of the longest-first order
   const int32_t* order;
   const int32_t* total;
