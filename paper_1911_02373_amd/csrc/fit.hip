@@ -35,8 +35,14 @@ namespace {
 
 constexpr int kFitBlock = 256;
 
+// Rows per chunk.  The 96- and 112-column classes are sized so that two workgroups share a CU
+// (at most 80 KB of LDS each).
 template <int NM>
 struct Chunk { static constexpr int CH = 64; };
+template <>
+struct Chunk<96> { static constexpr int CH = 32; };
+template <>
+struct Chunk<112> { static constexpr int CH = 16; };
 template <>
 struct Chunk<128> { static constexpr int CH = 32; };
 
@@ -50,9 +56,12 @@ struct Lds {
   static constexpr int R = F + CH;                    // residuals of the chunk
   static constexpr int Q = R + CH;                    // A t of the chunk
   static constexpr int V = Q + CH;                    // 10 vectors of NM
-  static constexpr int RED = V + 10 * NM;             // reduction scratch
-  static constexpr int NDOUBLE = RED + kFitBlock;
+  static constexpr int NDOUBLE = V + 10 * NM;
   static constexpr int BYTES = NDOUBLE * 8 + NM * 8 + NM * 4 + 64 + NM * 4;
+  // reduction scratch (kFitBlock doubles) shares the power table: no reduction value is kept
+  // across a pass over the rows
+  static_assert(CH * 32 >= kFitBlock, "reduction scratch must fit in the power table");
+  static_assert(CH % 4 == 0 && kFitBlock % CH == 0 && NM % 16 == 0, "chunk and tile shapes");
 };
 
 __device__ __forceinline__ int symi(int a, int b) {
@@ -66,7 +75,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Deterministic sum over the workgroup (result valid in every thread).
-__device__ double block_sum(double v, double* red) {
+__device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
@@ -89,28 +98,49 @@ struct FitCtx {
   bool pow3;       // every exponent of the fit is <= 3: monomials are products of table entries
 };
 
-// Stage rows [i0, i0 + rows) of the fit: scaled variables and targets.  Returns false if a
-// target is not finite.
-template <int NM>
-__device__ bool stage_rows(const FitArgs& a, const FitCtx& C, uint64_t sc, int i0, int rows,
-                           double* ff = nullptr) {
-  bool bad = false;
+// Samples of one chunk held in registers (thread t < rows holds row i0 + t), so that the loads
+// of the next chunk are in flight while the current one is processed.
+struct RowLoad {
+  int32_t x[KLR_MAX_VARS];
+  double f;
+};
+
+__device__ __forceinline__ void load_rows(const FitArgs& a, const FitCtx& C, int i0, int rows, RowLoad& L) {
   const int t = threadIdx.x;
   if (t < rows) {
     const int32_t* xr = a.X + C.x0 + (int64_t)(i0 + t) * C.v;
-    for (int k = 0; k < C.v; ++k) {
-      const double x = ldexp((double)xr[k], -(int)(int8_t)(uint8_t)(sc >> (8 * k)));
-      double* pw = C.pt + t * 32 + k * 4;
-      const double x2 = x * x;
-      pw[0] = 1.0;
-      pw[1] = x;
-      pw[2] = x2;
-      pw[3] = x2 * x;
+#pragma unroll
+    for (int k = 0; k < KLR_MAX_VARS; ++k) L.x[k] = k < C.v ? xr[k] : 0;
+    L.f = a.f[C.f0 + i0 + t];
+  }
+}
+
+__device__ __forceinline__ int chunk_rows(const FitCtx& C, int i0, int ch) {
+  return C.m - i0 < ch ? C.m - i0 : ch;
+}
+
+// Stage the loaded rows: scaled variables x~_k and their powers 0..3, and targets.  Returns
+// true if a target is not finite; adds the squared targets to *ff when given.
+__device__ __forceinline__ bool put_rows(const FitCtx& C, uint64_t sc, int rows, const RowLoad& L,
+                                         double* ff = nullptr) {
+  bool bad = false;
+  const int t = threadIdx.x;
+  if (t < rows) {
+#pragma unroll
+    for (int k = 0; k < KLR_MAX_VARS; ++k) {
+      if (k < C.v) {
+        const double x = ldexp((double)L.x[k], -(int)(int8_t)(uint8_t)(sc >> (8 * k)));
+        double* pw = C.pt + t * 32 + k * 4;
+        const double x2 = x * x;
+        pw[0] = 1.0;
+        pw[1] = x;
+        pw[2] = x2;
+        pw[3] = x2 * x;
+      }
     }
-    const double fv = a.f[C.f0 + i0 + t];
-    C.fch[t] = fv;
-    bad = !isfinite(fv);
-    if (ff) *ff += fv * fv;
+    C.fch[t] = L.f;
+    bad = !isfinite(L.f);
+    if (ff) *ff += L.f * L.f;
   }
   return bad;
 }
@@ -134,11 +164,11 @@ __device__ __forceinline__ double monomial(const FitCtx& C, int i, int j) {
 // Design-matrix chunk: A[i][j] for j < n, zero up to the 4-padded width.  Each thread owns one
 // column (its exponents are read once) and the rows i = g, g + G, ... of its row group g.
 template <int NM>
-__device__ void build_chunk(const FitCtx& C, int rows) {
+__device__ __forceinline__ void build_chunk(const FitCtx& C, int rows) {
   constexpr int G = kFitBlock / NM;
   const int j = threadIdx.x % NM, g = threadIdx.x / NM;
   const int nb4 = ((C.n + 3) / 4) * 4;
-  if (j >= nb4) return;
+  if (j >= nb4 || g >= G) return;
   if (j >= C.n) {
     for (int i = g; i < rows; i += G) C.A[i * NM + j] = 0.0;
     return;
@@ -175,7 +205,7 @@ __device__ __forceinline__ int rbase(int i) { return i * (i + 1) / 2; }
 // per pair it owns, each lane reading its operand slots (row l / 16, column l % 16 of the two
 // tiles) from LDS.  c = A^T f stays in FP64 on the vector units.
 template <int NM, int GP>
-__device__ bool gram_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double* fnorm2) {
+__device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double* fnorm2) {
   using GT = GramTypes<GP>;
   using acc_t = typename GT::acc_t;
   constexpr int CH = Chunk<NM>::CH;
@@ -202,10 +232,13 @@ __device__ bool gram_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double
   const int cj = threadIdx.x % NM, csub = threadIdx.x / NM;
   double cacc = 0.0, ff = 0.0;
   bool bad = false;
+  RowLoad rl;
+  load_rows(a, C, 0, chunk_rows(C, 0, CH), rl);
   for (int i0 = 0; i0 < C.m; i0 += CH) {
-    const int rows = C.m - i0 < CH ? C.m - i0 : CH;
+    const int rows = chunk_rows(C, i0, CH);
     const int rows4 = (rows + 3) & ~3;
-    bad |= stage_rows<NM>(a, C, sc, i0, rows, &ff);
+    bad |= put_rows(C, sc, rows, rl, &ff);
+    if (i0 + CH < C.m) load_rows(a, C, i0 + CH, chunk_rows(C, i0 + CH, CH), rl);
     __syncthreads();
     build_chunk<NM>(C, rows);
     for (int e = threadIdx.x; e < (rows4 - rows) * NM; e += kFitBlock) C.A[rows * NM + e] = 0.0;
@@ -217,7 +250,7 @@ __device__ bool gram_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double
         if (wv + W * q < npair)
           acc[q] = GT::mfma(GT::in(ar[16 * tj[q]]), GT::in(ar[16 * tk[q]]), acc[q]);
     }
-    if (cj < C.n)
+    if (cj < C.n && csub < TPC)
       for (int i = csub; i < rows; i += TPC) cacc += C.A[i * NM + cj] * C.fch[i];
     __syncthreads();
   }
@@ -245,7 +278,7 @@ __device__ bool gram_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double
 
 // Forward solve L u = in[perm[.]] by wave 0 (L in pivot order, see factor).  out is
 // pivot-indexed.
-__device__ void solve_fwd(const FitCtx& C, const double* in, double* out) {
+__device__ __forceinline__ void solve_fwd(const FitCtx& C, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
   const int n = C.n;
   const int b0r = rbase(lane), b1r = rbase(lane + 64);
@@ -263,7 +296,7 @@ __device__ void solve_fwd(const FitCtx& C, const double* in, double* out) {
 }
 
 // Backward solve L^T v = in (pivot-indexed) by wave 0; out[perm[i]] = v_i.
-__device__ void solve_bwd(const FitCtx& C, const double* in, double* out) {
+__device__ __forceinline__ void solve_bwd(const FitCtx& C, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
   const int n = C.n;
   double b0 = lane < n ? in[lane] : 0.0;
@@ -281,7 +314,7 @@ __device__ void solve_bwd(const FitCtx& C, const double* in, double* out) {
 }
 
 // sum_j x_j y_j over n entries, by wave 0 (valid in wave 0).
-__device__ double dot_w0(const double* x, const double* y, int n) {
+__device__ __forceinline__ double dot_w0(const double* x, const double* y, int n) {
   const int lane = threadIdx.x & 63;
   double v = 0.0;
   for (int j = lane; j < n; j += 64) v += x[j] * y[j];
@@ -291,15 +324,18 @@ __device__ double dot_w0(const double* x, const double* y, int n) {
 // Final pass: returns sum (f_i - d_i)^2 with d = A tp (tp holds y) and counts the samples with
 // q(x~_i) <= 0 into *qneg_out.
 template <int NM>
-__device__ double final_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, int* qneg_out) {
+__device__ __forceinline__ double final_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, int* qneg_out) {
   constexpr int CH = Chunk<NM>::CH;
   constexpr int TPR = kFitBlock / CH;
   const int i = threadIdx.x / TPR, sub = threadIdx.x % TPR;
   double acc = 0.0;
   int qneg = 0;
+  RowLoad rl;
+  load_rows(a, C, 0, chunk_rows(C, 0, CH), rl);
   for (int i0 = 0; i0 < C.m; i0 += CH) {
-    const int rows = C.m - i0 < CH ? C.m - i0 : CH;
-    stage_rows<NM>(a, C, sc, i0, rows);
+    const int rows = chunk_rows(C, i0, CH);
+    put_rows(C, sc, rows, rl);
+    if (i0 + CH < C.m) load_rows(a, C, i0 + CH, chunk_rows(C, i0 + CH, CH), rl);
     __syncthreads();
     build_chunk<NM>(C, rows);
     __syncthreads();
@@ -332,7 +368,7 @@ enum CgMode { kR0 = 0, kQ = 1 };
 // The caller forms D A^T r_next = D (C.g - alpha C.gq) once alpha is known, so every iteration
 // reads the FP64 residual of the samples and builds each chunk once.
 template <int NM, int MODE>
-__device__ double cg_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double* wsr, double* wsq,
+__device__ __forceinline__ double cg_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double* wsr, double* wsq,
                           bool upd, double alpha_prev) {
   constexpr int CH = Chunk<NM>::CH;
   constexpr int TPR = kFitBlock / CH;
@@ -340,9 +376,12 @@ __device__ double cg_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double
   const int ri = threadIdx.x / TPR, rsub = threadIdx.x % TPR;
   const int cj = threadIdx.x % NM, csub = threadIdx.x / NM;
   double accr = 0.0, accq = 0.0, qq = 0.0;
+  RowLoad rl;
+  load_rows(a, C, 0, chunk_rows(C, 0, CH), rl);
   for (int i0 = 0; i0 < C.m; i0 += CH) {
-    const int rows = C.m - i0 < CH ? C.m - i0 : CH;
-    stage_rows<NM>(a, C, sc, i0, rows);
+    const int rows = chunk_rows(C, i0, CH);
+    put_rows(C, sc, rows, rl);
+    if (i0 + CH < C.m) load_rows(a, C, i0 + CH, chunk_rows(C, i0 + CH, CH), rl);
     __syncthreads();
     build_chunk<NM>(C, rows);
     __syncthreads();
@@ -370,7 +409,7 @@ __device__ double cg_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double
       }
     }
     __syncthreads();
-    if (cj < C.n)
+    if (cj < C.n && csub < TPC)
       for (int i = csub; i < rows; i += TPC) {
         const double av = C.A[i * NM + cj];
         accr += av * C.rch[i];
@@ -404,7 +443,7 @@ __device__ double cg_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double
 // order: at step k the rows and columns k and bi are swapped in place (the computed part of L
 // and the Schur complement alike), so element (i, j) of L is at rbase(i) + j and perm maps a
 // pivot position to the original column.
-__device__ int factor(const FitCtx& C, double unit) {
+__device__ __forceinline__ int factor(const FitCtx& C, double unit) {
   const int n = C.n;
   const int tid = threadIdx.x;
   if (tid < n) {
@@ -530,20 +569,21 @@ __device__ int factor(const FitCtx& C, double unit) {
   return rank;
 }
 
-// Size class of a fit: 3 = one wavefront per fit (fit_wave.hip); otherwise one workgroup per
-// fit with 0 (n <= 32), 1 (<= 64), 2 (<= 128, and every invalid descriptor, which the largest
-// class reports as bad input).
+// Size class of a fit: kWaveClass = one wavefront per fit (fit_wave.hip); otherwise one
+// workgroup per fit with padded width 32 (class 0), 64 (1), 96 (2), 112 (3) or 128 (4, which also
+// takes every invalid descriptor and reports it as bad input).
+constexpr int kWaveClass = 5;
 __device__ __forceinline__ int fit_class(const FitArgs& a, const klr_fit_desc& d) {
-  if (wave_fit_eligible(a, d)) return 3;
+  if (wave_fit_eligible(a, d)) return kWaveClass;
   const int n = d.n_num + d.n_den - 1;
   const bool shape_ok = d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= KLR_MAX_UNKNOWNS;
-  if (!shape_ok) return 2;
-  return n <= 32 ? 0 : (n <= 64 ? 1 : 2);
+  if (!shape_ok) return 4;
+  return n <= 32 ? 0 : (n <= 64 ? 1 : (n <= 96 ? 2 : (n <= 112 ? 3 : 4)));
 }
 
 // One fit by the whole workgroup (all threads call it with the same fi).
 template <int NM, int PREC>
-__device__ void fit_one(const FitArgs& a, int fi, double* smem) {
+__device__ __forceinline__ void fit_one(const FitArgs& a, int fi, double* smem) {
   using L = Lds<NM>;
   const klr_fit_desc d = a.desc[fi];
   const int n = d.n_num + d.n_den - 1;
@@ -569,7 +609,7 @@ __device__ void fit_one(const FitArgs& a, int fi, double* smem) {
   double* V = smem + L::V;
   C.D = V; C.c = V + NM; C.z = V + 2 * NM; C.t = V + 3 * NM; C.s = V + 4 * NM; C.p = V + 5 * NM;
   C.g = V + 6 * NM; C.tp = V + 7 * NM; C.piv = V + 8 * NM; C.gq = V + 9 * NM;
-  C.red = smem + L::RED;
+  C.red = smem + L::PT;
   C.ex = reinterpret_cast<uint8_t*>(smem + L::NDOUBLE);
   C.perm = reinterpret_cast<int*>(C.ex + NM * 8);
   C.flags = C.perm + NM;
@@ -707,13 +747,25 @@ __device__ void fit_one(const FitArgs& a, int fi, double* smem) {
 }
 
 // Plain schedule: one workgroup per fit and size class (workgroups of other classes leave).
+// The classes whose LDS allows two workgroups per CU are compiled for two waves per SIMD.
 template <int NM, int PREC>
-__global__ void __launch_bounds__(kFitBlock)
-fit_kernel(FitArgs a, int cls) {
-  extern __shared__ double smem[];
+__device__ __forceinline__ void fit_plain_body(const FitArgs& a, int cls, double* smem) {
   const int fi = blockIdx.x;
   if (fi >= a.n_fits || fit_class(a, a.desc[fi]) != cls) return;
   fit_one<NM, PREC>(a, fi, smem);
+}
+
+template <int NM, int PREC>
+__global__ void __launch_bounds__(kFitBlock) fit_kernel(FitArgs a, int cls) {
+  extern __shared__ double smem[];
+  fit_plain_body<NM, PREC>(a, cls, smem);
+}
+
+template <int NM, int PREC>
+__global__ void __launch_bounds__(kFitBlock) __attribute__((amdgpu_waves_per_eu(2)))
+fit_kernel2(FitArgs a, int cls) {
+  extern __shared__ double smem[];
+  fit_plain_body<NM, PREC>(a, cls, smem);
 }
 
 // ---- persistent, longest-first schedule ------------------------------------------------------
@@ -723,7 +775,7 @@ fit_kernel(FitArgs a, int cls) {
 // wave class (one wavefront per fit) is launched as a grid that takes positions in order.  A
 // fit's result does not depend on which workgroup computes it, so outputs are deterministic.
 constexpr int kBuckets = 32;
-constexpr int kClasses = 4;
+constexpr int kClasses = 6;
 struct Plan {
   int32_t counts[kClasses * kBuckets];
   int32_t offs[kClasses * kBuckets];
@@ -781,32 +833,59 @@ __global__ void __launch_bounds__(kFitBlock) fit_plan_scatter(FitArgs a, Plan* p
 }
 
 template <int NM, int PREC>
-__global__ void __launch_bounds__(kFitBlock)
-fit_persistent(FitArgs a, Plan* pl, const int32_t* __restrict__ order, int cls) {
-  extern __shared__ double smem[];
-  __shared__ int next;
+__device__ __forceinline__ void fit_persistent_body(const FitArgs& a, Plan* pl, const int32_t* order, int cls,
+                                                    double* smem, int* next) {
   const int total = pl->totals[cls], base = pl->base[cls];
   for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(&pl->queue[cls], 1);
+    if (threadIdx.x == 0) *next = atomicAdd(&pl->queue[cls], 1);
     __syncthreads();
-    const int i = next;
+    const int i = *next;
     __syncthreads();
     if (i >= total) break;
     fit_one<NM, PREC>(a, order[base + i], smem);
   }
 }
 
+template <int NM, int PREC>
+__global__ void __launch_bounds__(kFitBlock)
+fit_persistent(FitArgs a, Plan* pl, const int32_t* __restrict__ order, int cls) {
+  extern __shared__ double smem[];
+  __shared__ int next;
+  fit_persistent_body<NM, PREC>(a, pl, order, cls, smem, &next);
+}
+
+template <int NM, int PREC>
+__global__ void __launch_bounds__(kFitBlock) __attribute__((amdgpu_waves_per_eu(2)))
+fit_persistent2(FitArgs a, Plan* pl, const int32_t* __restrict__ order, int cls) {
+  extern __shared__ double smem[];
+  __shared__ int next;
+  fit_persistent_body<NM, PREC>(a, pl, order, cls, smem, &next);
+}
+
 size_t plan_offset(int64_t f_len) { return ((size_t)(f_len > 0 ? f_len : 0) * 2 * sizeof(double) + 255) / 256 * 256; }
+
+// Two workgroups per CU when the dynamic LDS of a class leaves room for a second one (160 KB
+// per CU, with a margin for the static queue slot and allocation granularity).
+template <int NM>
+constexpr bool two_per_cu() { return Lds<NM>::BYTES <= 80 * 1024 - 512; }
 
 template <int NM, int PREC>
 hipError_t launch_class(const FitArgs& a, int cls, bool persistent, Plan* pl, const int32_t* order) {
   const size_t lds = (size_t)Lds<NM>::BYTES;
-  const void* fn = persistent ? reinterpret_cast<const void*>(&fit_persistent<NM, PREC>)
-                              : reinterpret_cast<const void*>(&fit_kernel<NM, PREC>);
+  const void* fn;
+  if constexpr (two_per_cu<NM>())
+    fn = persistent ? reinterpret_cast<const void*>(&fit_persistent2<NM, PREC>)
+                    : reinterpret_cast<const void*>(&fit_kernel2<NM, PREC>);
+  else
+    fn = persistent ? reinterpret_cast<const void*>(&fit_persistent<NM, PREC>)
+                    : reinterpret_cast<const void*>(&fit_kernel<NM, PREC>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (!persistent) {
-    hipLaunchKernelGGL((fit_kernel<NM, PREC>), dim3((unsigned)a.n_fits), dim3(kFitBlock), lds, a.stream, a, cls);
+    if constexpr (two_per_cu<NM>())
+      hipLaunchKernelGGL((fit_kernel2<NM, PREC>), dim3((unsigned)a.n_fits), dim3(kFitBlock), lds, a.stream, a, cls);
+    else
+      hipLaunchKernelGGL((fit_kernel<NM, PREC>), dim3((unsigned)a.n_fits), dim3(kFitBlock), lds, a.stream, a, cls);
     return hipGetLastError();
   }
   int dev = 0, ncu = 0, occ = 0;
@@ -816,8 +895,12 @@ hipError_t launch_class(const FitArgs& a, int cls, bool persistent, Plan* pl, co
   if (e != hipSuccess) return e;
   int64_t g = (int64_t)ncu * (occ > 0 ? occ : 1);
   if (g > a.n_fits) g = a.n_fits;
-  hipLaunchKernelGGL((fit_persistent<NM, PREC>), dim3((unsigned)g), dim3(kFitBlock), lds, a.stream, a, pl, order,
-                     cls);
+  if constexpr (two_per_cu<NM>())
+    hipLaunchKernelGGL((fit_persistent2<NM, PREC>), dim3((unsigned)g), dim3(kFitBlock), lds, a.stream, a, pl,
+                       order, cls);
+  else
+    hipLaunchKernelGGL((fit_persistent<NM, PREC>), dim3((unsigned)g), dim3(kFitBlock), lds, a.stream, a, pl,
+                       order, cls);
   return hipGetLastError();
 }
 
@@ -835,12 +918,14 @@ hipError_t launch_all(const FitArgs& a, bool persistent) {
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    const WavePlanView pv{order, &pl->totals[3], &pl->base[3]};
+    const WavePlanView pv{order, &pl->totals[kWaveClass], &pl->base[kWaveClass]};
     e = launch_fit_wave(a, persistent, pv);
   }
   if (e == hipSuccess) e = launch_class<32, PREC>(a, 0, persistent, pl, order);
   if (e == hipSuccess) e = launch_class<64, PREC>(a, 1, persistent, pl, order);
-  if (e == hipSuccess) e = launch_class<128, PREC>(a, 2, persistent, pl, order);
+  if (e == hipSuccess) e = launch_class<96, PREC>(a, 2, persistent, pl, order);
+  if (e == hipSuccess) e = launch_class<112, PREC>(a, 3, persistent, pl, order);
+  if (e == hipSuccess) e = launch_class<128, PREC>(a, 4, persistent, pl, order);
   return e;
 }
 

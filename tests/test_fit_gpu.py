@@ -131,23 +131,27 @@ def test_refined_reduced_precision_within_1e5(klr, prec):
 
 
 def test_size_classes_and_variables(klr):
-    """n in each launch class (<= 32, <= 64, <= 128), v = 1..5, ragged chunks."""
+    """n in each launch class (padded widths 32, 64, 96, 112, 128 and the one-wavefront class),
+    v = 1..5, ragged chunks; the n = 119 case has denominator exponents up to 4."""
     rng = np.random.default_rng(3)
     samples, exps_rows, num0, nn, den0, nd, scales = [], [], [], [], [], [], []
     row = 0
-    cases = [(1, 3), (2, 2), (3, 2), (3, 3), (4, 3), (5, 3), (2, 4)]
-    for v, deg in cases:
-        E = synth.monomials(v, deg)
-        m = int(rng.integers(E.shape[0] * 2 + 1, 700))
+    # (v, numerator degree, denominator degree, denominator monomials kept; None = all)
+    cases = [(1, 3, 3, None), (2, 2, 2, None), (3, 2, 2, None), (3, 3, 3, None), (4, 3, 3, None),
+             (5, 3, 3, None), (2, 4, 4, None), (5, 3, 4, 64)]
+    for v, dn, dd, keep in cases:
+        En = synth.monomials(v, dn)
+        Ed = synth.monomials(v, dd)[:keep]
+        m = int(rng.integers((En.shape[0] + Ed.shape[0]) * 2 + 1, 700))
         X = rng.integers(1, 1 << 12, (m, v)).astype(np.int32)
         xt = X / 4096.0
         p = 1.0 + xt.sum(1)
         q = 1.0 + 0.5 * xt[:, 0]
         f = p / q * np.exp(0.01 * rng.normal(size=m))
         samples.append((X, f))
-        exps_rows.append(E)
-        num0.append(row); nn.append(E.shape[0]); den0.append(row); nd.append(E.shape[0])
-        row += E.shape[0]
+        exps_rows += [En, Ed]
+        num0.append(row); nn.append(En.shape[0]); den0.append(row + En.shape[0]); nd.append(Ed.shape[0])
+        row += En.shape[0] + Ed.shape[0]
         sc = np.zeros(8, np.int8); sc[:v] = 12
         scales.append(sc)
     fb = synth._pack_fits(samples, np.concatenate(exps_rows), num0, nn, den0, nd, np.array(scales))
