@@ -213,15 +213,17 @@ __device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uin
   constexpr int W = kFitBlock / 64;                 // waves
   constexpr int PPW = (NT * (NT + 1) / 2 + W - 1) / W;
   constexpr int TPC = kFitBlock / NM;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int grp = lane >> 4, col = lane & 15;
   const int nt = (C.n + 15) / 16;
   const int npair = nt * (nt + 1) / 2;
+  const int mine = npair > wv ? (npair - wv + W - 1) / W : 0;   // pairs of this wave
   int tj[PPW], tk[PPW];
   acc_t acc[PPW];
 #pragma unroll
   for (int q = 0; q < PPW; ++q) {
-    const int p = wv + W * q;
+    const int p = q < mine ? wv + W * q : 0;
     int r = 0;
     while ((r + 1) * (r + 2) / 2 <= p) ++r;
     tj[q] = r;
@@ -245,10 +247,15 @@ __device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uin
     __syncthreads();
     for (int i = 0; i < rows4; i += 4) {
       const double* ar = C.A + (i + grp) * NM + col;
+      double xa[PPW], xb[PPW];
+#pragma unroll
+      for (int q = 0; q < PPW; ++q) {
+        xa[q] = ar[16 * tj[q]];
+        xb[q] = ar[16 * tk[q]];
+      }
 #pragma unroll
       for (int q = 0; q < PPW; ++q)
-        if (wv + W * q < npair)
-          acc[q] = GT::mfma(GT::in(ar[16 * tj[q]]), GT::in(ar[16 * tk[q]]), acc[q]);
+        if (q < mine) acc[q] = GT::mfma(GT::in(xa[q]), GT::in(xb[q]), acc[q]);
     }
     if (cj < C.n && csub < TPC)
       for (int i = csub; i < rows; i += TPC) cacc += C.A[i * NM + cj] * C.fch[i];
@@ -256,7 +263,7 @@ __device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uin
   }
 #pragma unroll
   for (int q = 0; q < PPW; ++q) {
-    if (wv + W * q < npair) {
+    if (q < mine) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int j = 16 * tj[q] + GT::out_row(grp, r), k = 16 * tk[q] + col;
@@ -339,16 +346,21 @@ __device__ __forceinline__ double final_pass(const FitArgs& a, const FitCtx& C, 
     __syncthreads();
     build_chunk<NM>(C, rows);
     __syncthreads();
-    double dsum = 0.0;
-    if (i < rows)
+    // d_i = A_i tp and q(x~_i) - 1, each split over the TPR threads of row i
+    double dsum = 0.0, qs = 0.0;
+    if (i < rows) {
       for (int j = sub; j < C.n; j += TPR) dsum += C.A[i * NM + j] * C.tp[j];
+      for (int j = C.n_num + sub; j < C.n; j += TPR) qs += C.tp[j] * monomial(C, i, j);
+    }
 #pragma unroll
-    for (int off = TPR / 2; off >= 1; off >>= 1) dsum += __shfl_xor(dsum, off);
+    for (int off = TPR / 2; off >= 1; off >>= 1) {
+      dsum += __shfl_xor(dsum, off);
+      qs += __shfl_xor(qs, off);
+    }
     if (i < rows && sub == 0) {
       const double res = C.fch[i] - dsum;
       acc += res * res;
-      double qv = 1.0;
-      for (int j = C.n_num; j < C.n; ++j) qv += C.tp[j] * monomial(C, i, j);
+      const double qv = 1.0 + qs;
       if (!(qv > 0.0)) ++qneg;
     }
     __syncthreads();
