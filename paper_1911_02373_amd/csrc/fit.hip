@@ -89,7 +89,8 @@ struct FitCtx {
   int n, n_num, n_den, m, v;
   int64_t x0, f0;
   double* S; double* A; double* pt; double* fch; double* rch; double* qch;
-  double *D, *c, *z, *t, *s, *p, *g, *gq, *tp, *piv;
+  double *D, *c, *z, *t, *s, *p, *g, *gq, *tp;
+  double* piv;     // pivots during the factorization, then 1 / L(k, k)
   double* red;
   uint8_t* ex;
   int* perm;
@@ -119,8 +120,10 @@ __device__ __forceinline__ int chunk_rows(const FitCtx& C, int i0, int ch) {
   return C.m - i0 < ch ? C.m - i0 : ch;
 }
 
-// Stage the loaded rows: scaled variables x~_k and their powers 0..3, and targets.  Returns
-// true if a target is not finite; adds the squared targets to *ff when given.
+// Stage the loaded rows: scaled variables x~_k and their powers 0..3, and targets.  The
+// 0-th power entry of the unused variables k >= v is 1 as well, so a monomial is the product
+// of all KLR_MAX_VARS table entries and needs no branch on v.  Returns true if a target is not
+// finite; adds the squared targets to *ff when given.
 __device__ __forceinline__ bool put_rows(const FitCtx& C, uint64_t sc, int rows, const RowLoad& L,
                                          double* ff = nullptr) {
   bool bad = false;
@@ -128,11 +131,11 @@ __device__ __forceinline__ bool put_rows(const FitCtx& C, uint64_t sc, int rows,
   if (t < rows) {
 #pragma unroll
     for (int k = 0; k < KLR_MAX_VARS; ++k) {
+      double* pw = C.pt + t * 32 + k * 4;
+      pw[0] = 1.0;
       if (k < C.v) {
         const double x = ldexp((double)L.x[k], -(int)(int8_t)(uint8_t)(sc >> (8 * k)));
-        double* pw = C.pt + t * 32 + k * 4;
         const double x2 = x * x;
-        pw[0] = 1.0;
         pw[1] = x;
         pw[2] = x2;
         pw[3] = x2 * x;
@@ -150,9 +153,12 @@ __device__ __forceinline__ bool put_rows(const FitCtx& C, uint64_t sc, int rows,
 __device__ __forceinline__ double monomial(const FitCtx& C, int i, int j) {
   const double* pw = C.pt + i * 32;
   double mono = 1.0;
-  if (C.pow3) {
+  if (C.pow3) {                         // same product order as build_chunk
     const uint32_t w = C.ep[j];
-    for (int k = 0; k < C.v; ++k) mono *= pw[k * 4 + ((w >> (2 * k)) & 3u)];
+    double pv[KLR_MAX_VARS];
+#pragma unroll
+    for (int k = 0; k < KLR_MAX_VARS; ++k) pv[k] = pw[k * 4 + ((w >> (2 * k)) & 3u)];
+    mono = ((pv[0] * pv[1]) * (pv[2] * pv[3])) * ((pv[4] * pv[5]) * (pv[6] * pv[7]));
   } else {
     const uint8_t* e = C.ex + j * 8;
     for (int k = 0; k < C.v; ++k)
@@ -179,13 +185,23 @@ __device__ __forceinline__ void build_chunk(const FitCtx& C, int rows) {
     int off[KLR_MAX_VARS];
 #pragma unroll
     for (int k = 0; k < KLR_MAX_VARS; ++k) off[k] = k * 4 + (int)((w >> (2 * k)) & 3u);
-    for (int i = g; i < rows; i += G) {
+    constexpr int CH = Chunk<NM>::CH;
+    // all table loads of a row are issued before its products; full chunks skip the row guard
+    auto row = [&](int i) {
       const double* pw = C.pt + i * 32;
-      double mono = 1.0;
+      double pv[KLR_MAX_VARS];
 #pragma unroll
-      for (int k = 0; k < KLR_MAX_VARS; ++k)
-        if (k < C.v) mono *= pw[off[k]];
-      C.A[i * NM + j] = num ? mono : -C.fch[i] * mono;
+      for (int k = 0; k < KLR_MAX_VARS; ++k) pv[k] = pw[off[k]];
+      const double fi = C.fch[i];
+      static_assert(KLR_MAX_VARS == 8, "product tree over 8 table entries");
+      const double mono = ((pv[0] * pv[1]) * (pv[2] * pv[3])) * ((pv[4] * pv[5]) * (pv[6] * pv[7]));
+      C.A[i * NM + j] = num ? mono : -fi * mono;
+    };
+    if (rows == CH) {
+#pragma unroll 2
+      for (int u = 0; u < CH / G; ++u) row(g + u * G);
+    } else {
+      for (int i = g; i < rows; i += G) row(i);
     }
   } else {
     for (int i = g; i < rows; i += G) {
@@ -257,8 +273,13 @@ __device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uin
       for (int q = 0; q < PPW; ++q)
         if (q < mine) acc[q] = GT::mfma(GT::in(xa[q]), GT::in(xb[q]), acc[q]);
     }
-    if (cj < C.n && csub < TPC)
-      for (int i = csub; i < rows; i += TPC) cacc += C.A[i * NM + cj] * C.fch[i];
+    if (cj < C.n && csub < TPC) {
+#pragma unroll 4
+      for (int u = 0; u < CH / TPC; ++u) {
+        const int i = csub + u * TPC;
+        if (i < rows) cacc += C.A[i * NM + cj] * C.fch[i];
+      }
+    }
     __syncthreads();
   }
 #pragma unroll
@@ -292,8 +313,7 @@ __device__ __forceinline__ void solve_fwd(const FitCtx& C, const double* in, dou
   double b0 = lane < n ? in[C.perm[lane]] : 0.0;
   double b1 = lane + 64 < n ? in[C.perm[lane + 64]] : 0.0;
   for (int k = 0; k < n; ++k) {
-    const double bk = __shfl(k < 64 ? b0 : b1, k & 63);
-    const double uk = bk / C.S[rbase(k) + k];
+    const double uk = readlane_d(k < 64 ? b0 : b1, k & 63) * C.piv[k];
     if (lane == (k & 63)) { if (k < 64) b0 = uk; else b1 = uk; }
     if (lane > k && lane < n) b0 -= C.S[b0r + k] * uk;
     if (lane + 64 > k && lane + 64 < n) b1 -= C.S[b1r + k] * uk;
@@ -310,8 +330,7 @@ __device__ __forceinline__ void solve_bwd(const FitCtx& C, const double* in, dou
   double b1 = lane + 64 < n ? in[lane + 64] : 0.0;
   for (int k = n - 1; k >= 0; --k) {
     const int bk_row = rbase(k);
-    const double bk = __shfl(k < 64 ? b0 : b1, k & 63);
-    const double vk = bk / C.S[bk_row + k];
+    const double vk = readlane_d(k < 64 ? b0 : b1, k & 63) * C.piv[k];
     if (lane == (k & 63)) { if (k < 64) b0 = vk; else b1 = vk; }
     if (lane < k) b0 -= C.S[bk_row + lane] * vk;
     if (lane + 64 < k) b1 -= C.S[bk_row + lane + 64] * vk;
@@ -349,14 +368,15 @@ __device__ __forceinline__ double final_pass(const FitArgs& a, const FitCtx& C, 
     // d_i = A_i tp and q(x~_i) - 1, each split over the TPR threads of row i
     double dsum = 0.0, qs = 0.0;
     if (i < rows) {
-      for (int j = sub; j < C.n; j += TPR) dsum += C.A[i * NM + j] * C.tp[j];
+#pragma unroll 4
+      for (int u = 0; u < NM / TPR; ++u) {
+        const int j = sub + u * TPR;
+        if (j < C.n) dsum += C.A[i * NM + j] * C.tp[j];
+      }
       for (int j = C.n_num + sub; j < C.n; j += TPR) qs += C.tp[j] * monomial(C, i, j);
     }
-#pragma unroll
-    for (int off = TPR / 2; off >= 1; off >>= 1) {
-      dsum += __shfl_xor(dsum, off);
-      qs += __shfl_xor(qs, off);
-    }
+    dsum = group_sum<TPR>(dsum);
+    qs = group_sum<TPR>(qs);
     if (i < rows && sub == 0) {
       const double res = C.fch[i] - dsum;
       acc += res * res;
@@ -390,18 +410,38 @@ __device__ __forceinline__ double cg_pass(const FitArgs& a, const FitCtx& C, uin
   double accr = 0.0, accq = 0.0, qq = 0.0;
   RowLoad rl;
   load_rows(a, C, 0, chunk_rows(C, 0, CH), rl);
+  // kQ: the stored residual and previous image of the row are read one chunk ahead by the
+  // thread that owns the row (the one that wrote them)
+  const bool owner = rsub == 0;
+  double rn = 0.0, qn = 0.0;
+  if (MODE == kQ && owner && ri < chunk_rows(C, 0, CH)) {
+    rn = wsr[C.f0 + ri];
+    if (upd) qn = wsq[C.f0 + ri];
+  }
   for (int i0 = 0; i0 < C.m; i0 += CH) {
     const int rows = chunk_rows(C, i0, CH);
     put_rows(C, sc, rows, rl);
-    if (i0 + CH < C.m) load_rows(a, C, i0 + CH, chunk_rows(C, i0 + CH, CH), rl);
+    double rn2 = 0.0, qn2 = 0.0;
+    if (i0 + CH < C.m) {
+      const int rows2 = chunk_rows(C, i0 + CH, CH);
+      load_rows(a, C, i0 + CH, rows2, rl);
+      if (MODE == kQ && owner && ri < rows2) {
+        rn2 = wsr[C.f0 + i0 + CH + ri];
+        if (upd) qn2 = wsq[C.f0 + i0 + CH + ri];
+      }
+    }
     __syncthreads();
     build_chunk<NM>(C, rows);
     __syncthreads();
     double dsum = 0.0;
-    if (ri < rows)
-      for (int j = rsub; j < C.n; j += TPR) dsum += C.A[ri * NM + j] * C.tp[j];
-#pragma unroll
-    for (int off = TPR / 2; off >= 1; off >>= 1) dsum += __shfl_xor(dsum, off);
+    if (ri < rows) {
+#pragma unroll 4
+      for (int u = 0; u < NM / TPR; ++u) {
+        const int j = rsub + u * TPR;
+        if (j < C.n) dsum += C.A[ri * NM + j] * C.tp[j];
+      }
+    }
+    dsum = group_sum<TPR>(dsum);
     if (ri < rows && rsub == 0) {
       const int64_t row = C.f0 + i0 + ri;
       if (MODE == kR0) {
@@ -409,9 +449,9 @@ __device__ __forceinline__ double cg_pass(const FitArgs& a, const FitCtx& C, uin
         wsr[row] = r;
         C.rch[ri] = r;
       } else {
-        double r = wsr[row];
+        double r = rn;
         if (upd) {
-          r -= alpha_prev * wsq[row];
+          r -= alpha_prev * qn;
           wsr[row] = r;
         }
         C.rch[ri] = r;
@@ -421,13 +461,20 @@ __device__ __forceinline__ double cg_pass(const FitArgs& a, const FitCtx& C, uin
       }
     }
     __syncthreads();
-    if (cj < C.n && csub < TPC)
-      for (int i = csub; i < rows; i += TPC) {
-        const double av = C.A[i * NM + cj];
-        accr += av * C.rch[i];
-        if (MODE == kQ) accq += av * C.qch[i];
+    if (cj < C.n && csub < TPC) {
+#pragma unroll 4
+      for (int u = 0; u < CH / TPC; ++u) {
+        const int i = csub + u * TPC;
+        if (i < rows) {
+          const double av = C.A[i * NM + cj];
+          accr += av * C.rch[i];
+          if (MODE == kQ) accq += av * C.qch[i];
+        }
       }
+    }
     __syncthreads();
+    rn = rn2;
+    qn = qn2;
   }
   C.red[threadIdx.x] = accr;
   __syncthreads();
@@ -578,6 +625,9 @@ __device__ __forceinline__ int factor(const FitCtx& C, double unit) {
   }
   int rank = 0;
   for (int k = 0; k < n; ++k) rank += C.piv[k] > 4.0 * mu ? 1 : 0;
+  __syncthreads();
+  if (tid < n) C.piv[tid] = 1.0 / C.S[rbase(tid) + tid];   // the solves multiply by 1 / L(k, k)
+  __syncthreads();
   return rank;
 }
 

@@ -63,14 +63,6 @@ __device__ __forceinline__ void wave_sync() {
 // Row base of the packed lower triangle: element (i, j), j <= i, is at rbase(i) + j.
 __device__ __forceinline__ int rbase(int i) { return i * (i + 1) / 2; }
 
-// Lane l's value of v, broadcast through scalar registers (l wave-uniform).
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, l);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 __device__ __forceinline__ int symi(int a, int b) {
   return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a;
 }

@@ -135,6 +135,46 @@ __device__ inline bool wave_fit_eligible(const FitArgs& a, const klr_fit_desc& d
   }
   return true;
 }
+// ---- cross-lane moves on the VALU (no LDS round trip) ----------------------------------------
+// Lane l's value of v, broadcast through scalar registers (l wave-uniform).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, l);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// DPP move of a double within rows of 16 lanes (CTRL: quad_perm, row_mirror, ...).  Every lane
+// of the wavefront must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141; // lane i <- 7 - i within each 8 lanes
+constexpr int kDppMirror = 0x140;     // lane i <- 15 - i within each 16 lanes
+
+// Sum over aligned groups of G lanes (G = 4, 8 or 16); every lane of a group receives the same
+// value (each step adds a value from the other half of the group, and addition commutes).
+// Every lane of the wavefront must be active.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(G == 4 || G == 8 || G == 16, "group of 4, 8 or 16 lanes");
+  v += dpp_d<kDppXor1>(v);
+  v += dpp_d<kDppXor2>(v);
+  if (G >= 8) v += dpp_d<kDppHalfMirror>(v);
+  if (G >= 16) v += dpp_d<kDppMirror>(v);
+  return v;
+}
+
 // Rounds an FP32 value to the nearest BF16 value (ties to even), kept in FP32.
 __device__ __forceinline__ float round_bf16(float x) {
   uint32_t b = __float_as_uint(x);
