@@ -68,11 +68,7 @@ __device__ __forceinline__ int symi(int a, int b) {
   return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_d(v); }
 
 // Deterministic sum over the workgroup (result valid in every thread).
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -546,12 +542,7 @@ __device__ __forceinline__ int factor(const FitCtx& C, double unit) {
         const double key = vv == vv ? vv : -INFINITY;
         if (key > best || (key == best && i < bi)) { best = key; bi = i; }
       }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
+      wave_argmax(best, bi);
       if (tid == 0) {
         C.red[kFitBlock - 3] = best;
         C.flags[2] = bi;

@@ -67,11 +67,7 @@ __device__ __forceinline__ int symi(int a, int b) {
   return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a;
 }
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
+__device__ __forceinline__ double wsum(double v) { return wave_sum_d(v); }
 
 struct Rows {
   double x[kRPL][kV];
@@ -159,9 +155,7 @@ __device__ void gram(WaveLds& L, const Rows& R, int m, int n, int n_num) {
     }
 #pragma unroll
   for (int ct = 0; ct < 3; ++ct) {
-    double v = cacc[ct];
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
+    const double v = pair_sum32(pair_sum16(cacc[ct]));
     if (grp == 0 && ct * 16 + col < n) L.c[ct * 16 + col] = v;
   }
   wave_sync();
@@ -201,12 +195,7 @@ __device__ int factor_wave(WaveLds& L, int n, double unit) {
       best = vv == vv ? vv : -INFINITY;
       bi = lane;
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
+    wave_argmax(best, bi);
     if (!(best > 4.0 * mu)) {
       const double smu = sqrt(mu);
       if (lane >= k && lane < n) {
@@ -344,10 +333,7 @@ __device__ double row_pass(WaveLds& L, Rows& R, int m, int n, int n_num, double 
     }
   }
   if (MODE == 2) {
-    int q = qn;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) q += __shfl_xor(q, off);
-    *qneg = q;
+    *qneg = (int)wsum((double)qn);     // a count: exact in FP64
     return wsum(sq);
   }
   double alpha = 0.0;

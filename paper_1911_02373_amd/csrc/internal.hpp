@@ -175,6 +175,66 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// Sum of lane l and lane l ^ 16 (resp. l ^ 32) through the gfx950 lane-swap instructions:
+// swapping a register with itself leaves the value of one half of each lane pair in each of the
+// two results, so their sum is the pair sum, in the same order in every lane.
+__device__ __forceinline__ double pair_sum16(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+  const double a = __longlong_as_double((long long)(((unsigned long long)(unsigned)hi[0] << 32) | (unsigned)lo[0]));
+  const double b = __longlong_as_double((long long)(((unsigned long long)(unsigned)hi[1] << 32) | (unsigned)lo[1]));
+  return a + b;
+}
+__device__ __forceinline__ double pair_sum32(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+  const double a = __longlong_as_double((long long)(((unsigned long long)(unsigned)hi[0] << 32) | (unsigned)lo[0]));
+  const double b = __longlong_as_double((long long)(((unsigned long long)(unsigned)hi[1] << 32) | (unsigned)lo[1]));
+  return a + b;
+}
+
+// Sum over the 64 lanes of the wavefront, the same value in every lane (all lanes active).
+__device__ __forceinline__ double wave_sum_d(double v) {
+  return pair_sum32(pair_sum16(group_sum<16>(v)));
+}
+
+// Largest key over the 64 lanes, lowest index among equal keys (keys are never NaN); every
+// lane receives the same (key, index).  All lanes active.
+__device__ __forceinline__ void argmax_take(double& best, int& bi, double ob, int oi) {
+  if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double& best, int& bi) {
+  const double ob = dpp_d<CTRL>(best);
+  const int oi = dpp_i<CTRL>(bi);
+  argmax_take(best, bi, ob, oi);
+}
+template <bool K32>
+__device__ __forceinline__ void argmax_swap(double& best, int& bi) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(best);
+  const unsigned ulo = (unsigned)u, uhi = (unsigned)(u >> 32), ui = (unsigned)bi;
+  const auto lo = K32 ? __builtin_amdgcn_permlane32_swap(ulo, ulo, false, false)
+                      : __builtin_amdgcn_permlane16_swap(ulo, ulo, false, false);
+  const auto hi = K32 ? __builtin_amdgcn_permlane32_swap(uhi, uhi, false, false)
+                      : __builtin_amdgcn_permlane16_swap(uhi, uhi, false, false);
+  const auto ix = K32 ? __builtin_amdgcn_permlane32_swap(ui, ui, false, false)
+                      : __builtin_amdgcn_permlane16_swap(ui, ui, false, false);
+  best = __longlong_as_double((long long)(((unsigned long long)(unsigned)hi[0] << 32) | (unsigned)lo[0]));
+  bi = (int)ix[0];
+  const double ob = __longlong_as_double((long long)(((unsigned long long)(unsigned)hi[1] << 32) | (unsigned)lo[1]));
+  argmax_take(best, bi, ob, (int)ix[1]);
+}
+__device__ __forceinline__ void wave_argmax(double& best, int& bi) {
+  argmax_dpp<kDppXor1>(best, bi);
+  argmax_dpp<kDppXor2>(best, bi);
+  argmax_dpp<kDppHalfMirror>(best, bi);
+  argmax_dpp<kDppMirror>(best, bi);
+  argmax_swap<false>(best, bi);
+  argmax_swap<true>(best, bi);
+}
+
 // Rounds an FP32 value to the nearest BF16 value (ties to even), kept in FP32.
 __device__ __forceinline__ float round_bf16(float x) {
   uint32_t b = __float_as_uint(x);
