@@ -853,11 +853,20 @@ __global__ void fit_plan_zero(Plan* pl) {
   if (i < kClasses * kBuckets) pl->counts[i] = 0;
 }
 
+// Per-workgroup histograms in LDS, then one global atomic per non-empty bin and workgroup (a
+// single bucket can hold every fit of the batch).
 __global__ void __launch_bounds__(kFitBlock) fit_plan_count(FitArgs a, Plan* pl) {
+  __shared__ int32_t hist[kClasses * kBuckets];
+  for (int b = threadIdx.x; b < kClasses * kBuckets; b += kFitBlock) hist[b] = 0;
+  __syncthreads();
   const int fi = blockIdx.x * kFitBlock + threadIdx.x;
-  if (fi >= a.n_fits) return;
-  const klr_fit_desc d = a.desc[fi];
-  atomicAdd(&pl->counts[fit_class(a, d) * kBuckets + cost_bucket(d)], 1);
+  if (fi < a.n_fits) {
+    const klr_fit_desc d = a.desc[fi];
+    atomicAdd(&hist[fit_class(a, d) * kBuckets + cost_bucket(d)], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kClasses * kBuckets; b += kFitBlock)
+    if (hist[b] > 0) atomicAdd(&pl->counts[b], hist[b]);
 }
 
 __global__ void fit_plan_scan(Plan* pl) {
@@ -877,12 +886,25 @@ __global__ void fit_plan_scan(Plan* pl) {
   }
 }
 
+// Each workgroup reserves one range per bin with a global atomic and places its fits in it by
+// their LDS rank (the order inside a bucket is arbitrary; a fit's result does not depend on it).
 __global__ void __launch_bounds__(kFitBlock) fit_plan_scatter(FitArgs a, Plan* pl, int32_t* order) {
+  __shared__ int32_t hist[kClasses * kBuckets];
+  __shared__ int32_t start[kClasses * kBuckets];
+  for (int b = threadIdx.x; b < kClasses * kBuckets; b += kFitBlock) hist[b] = 0;
+  __syncthreads();
   const int fi = blockIdx.x * kFitBlock + threadIdx.x;
-  if (fi >= a.n_fits) return;
-  const klr_fit_desc d = a.desc[fi];
-  const int k = fit_class(a, d) * kBuckets + cost_bucket(d);
-  order[pl->offs[k] + atomicAdd(&pl->cursor[k], 1)] = fi;
+  int key = -1, rank = 0;
+  if (fi < a.n_fits) {
+    const klr_fit_desc d = a.desc[fi];
+    key = fit_class(a, d) * kBuckets + cost_bucket(d);
+    rank = atomicAdd(&hist[key], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kClasses * kBuckets; b += kFitBlock)
+    start[b] = hist[b] > 0 ? pl->offs[b] + atomicAdd(&pl->cursor[b], hist[b]) : 0;
+  __syncthreads();
+  if (key >= 0) order[start[key] + rank] = fi;
 }
 
 template <int NM, int PREC>

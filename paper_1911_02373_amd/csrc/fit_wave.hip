@@ -33,6 +33,7 @@ namespace klr {
 namespace {
 
 constexpr int kNP = 48;            // padded unknowns: three 16-column tiles
+static_assert(kNP <= 48, "the 8 x 8 update grid of the factorization covers 48 rows");
 constexpr int kRPL = 8;            // sample rows per lane (m <= 512)
 constexpr int kV = 4;              // variables
 constexpr int kWavesPerGroup = 4;
@@ -178,6 +179,7 @@ __device__ int factor_wave(WaveLds& L, int n, double unit) {
   wave_sync();
   if (lane < n) {                       // row `lane` of the lower triangle
     const double dl = L.D[lane];
+#pragma unroll 8
     for (int j = 0; j <= lane; ++j) L.S[myb + j] *= dl * L.D[j];
     L.c[lane] *= dl;
   }
@@ -226,17 +228,37 @@ __device__ int factor_wave(WaveLds& L, int n, double unit) {
       wave_sync();
     }
     const double lkk = sqrt(best);
-    double lik = 0.0;
     if (lane == k) {
       L.piv[k] = best;
       L.S[myb + k] = lkk;
     } else if (lane > k && lane < n) {
-      lik = L.S[myb + k] / lkk;
-      L.S[myb + k] = lik;
+      L.S[myb + k] = L.S[myb + k] / lkk;
     }
-    for (int j = k + 1; j < n; ++j) {   // S(i, j) -= L(i, k) L(j, k) for k < j <= i
-      const double ljk = readlane_d(lik, j);
-      if (lane >= j && lane < n) L.S[myb + j] -= lik * ljk;
+    wave_sync();
+    // S(i, j) -= L(i, k) L(j, k) for k < j <= i: lane (ty, tx) of an 8 x 8 grid takes rows
+    // k + 1 + ty + 8 a and columns k + 1 + tx + 8 b (n <= 48: a, b < 6), so the entries of
+    // the trailing triangle are spread evenly and the loads of a row are independent
+    {
+      const int ty = lane >> 3, tx = lane & 7;
+      double lj[6];
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        const int j = k + 1 + tx + 8 * b;
+        lj[b] = j < n ? L.S[rbase(j) + k] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const int i = k + 1 + ty + 8 * a;
+        if (i < n) {
+          const int rb = rbase(i);
+          const double li = L.S[rb + k];
+#pragma unroll
+          for (int b = 0; b < 6; ++b) {
+            const int j = k + 1 + tx + 8 * b;
+            if (j <= i) L.S[rb + j] -= li * lj[b];
+          }
+        }
+      }
     }
     wave_sync();
   }
