@@ -241,7 +241,7 @@ def main() -> int:
     ap.add_argument("--no-precision-sweep", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-large-batch", action="store_true")
-    ap.add_argument("--kernel-only", choices=("eval", "fit", "copy"), default=None,
+    ap.add_argument("--kernel-only", choices=("eval", "fit", "copy", "large"), default=None,
                     help="run only this kernel --steps times (for hardware-counter runs); "
                          "'copy' is a plain 1 GiB device copy used to calibrate byte counters")
     ap.add_argument("--surrogate-epochs", type=int, default=60)
@@ -266,6 +266,26 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"kernel_only": "copy", "bytes_read": x.numel() * 4, "bytes_written": y.numel() * 4,
                           "launches": args.steps}), flush=True)
+        return 0
+    if args.kernel_only == "large":
+        # the large persistent batch alone (fits, then collapse + evaluation), eagerly
+        fb5, pb5 = synth.config5_batch(args.seed)
+        df5 = klr.DeviceFit.from_batch(fb5)
+        fo = (torch.empty(df5.n_coef, dtype=torch.float64, device="cuda"),
+              torch.empty(df5.n_fits * klr.FIT_INFO.itemsize, dtype=torch.uint8, device="cuda"))
+        de5 = klr.DeviceEval.from_batch(lib, pb5, coef=fo[0])
+        nq5 = de5.queries.numel()
+        eo = (torch.empty(nq5, dtype=torch.int32, device="cuda"), torch.empty(nq5, dtype=torch.float32, device="cuda"),
+              None, torch.empty(de5.n_progs, dtype=torch.int32, device="cuda"))
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            lib.fit_batched(df5, klr.KLR_FP64, FIT_MAX_ITER, 1e-5, out=fo)
+            lib.eval_argmin(de5, out=eo)
+            torch.cuda.synchronize()
+            log("large batch pass done")
+        print(json.dumps({"kernel_only": "large", "launches": args.steps, "fits": int(fb5.n_fits),
+                          "fit_rows": int(fb5.m.sum()),
+                          "points": int((pb5.n_cfg.astype(np.int64) * pb5.n_q).sum())}), flush=True)
         return 0
     t = time.perf_counter()
     pb = synth.config3_programs(args.seed, n_progs=1024, n_q=65536)

@@ -105,7 +105,8 @@ typedef struct {
 typedef enum { KLR_FP64 = 0, KLR_FP32_REFINED = 1, KLR_BF16_REFINED = 2 } klr_precision;
 
 /* Workspace bytes klr_fit_batched needs for n_fits fits whose targets span f[0, f_len)
- * (two FP64 values per sample row for the refinement residuals). */
+ * (two FP64 values per sample row for the refinement residuals, then the schedule: a small
+ * plan record and two int32 per fit for the longest-first order and the fits' buckets). */
 size_t klr_fit_workspace(int32_t n_fits, int64_t f_len, int32_t precision);
 
 /* Fit n_fits independent rational functions (uneven m and monomial sets in one launch).

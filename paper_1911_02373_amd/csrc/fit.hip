@@ -308,11 +308,26 @@ __device__ __forceinline__ void solve_fwd(const FitCtx& C, const double* in, dou
   const int b0r = rbase(lane), b1r = rbase(lane + 64);
   double b0 = lane < n ? in[C.perm[lane]] : 0.0;
   double b1 = lane + 64 < n ? in[C.perm[lane + 64]] : 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double uk = readlane_d(k < 64 ? b0 : b1, k & 63) * C.piv[k];
-    if (lane == (k & 63)) { if (k < 64) b0 = uk; else b1 = uk; }
-    if (lane > k && lane < n) b0 -= C.S[b0r + k] * uk;
-    if (lane + 64 > k && lane + 64 < n) b1 -= C.S[b1r + k] * uk;
+  // steps in groups of 4: the factor entries of a group are loaded before its dependent chain
+  for (int k0 = 0; k0 < n; k0 += 4) {
+    double rp[4], s0[4], s1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u;
+      rp[u] = k < n ? C.piv[k] : 0.0;
+      s0[u] = (k < n && lane > k && lane < n) ? C.S[b0r + k] : 0.0;
+      s1[u] = (k < n && lane + 64 > k && lane + 64 < n) ? C.S[b1r + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u;
+      if (k < n) {
+        const double uk = readlane_d(k < 64 ? b0 : b1, k & 63) * rp[u];
+        if (lane == (k & 63)) { if (k < 64) b0 = uk; else b1 = uk; }
+        if (lane > k && lane < n) b0 -= s0[u] * uk;
+        if (lane + 64 > k && lane + 64 < n) b1 -= s1[u] * uk;
+      }
+    }
   }
   if (lane < n) out[lane] = b0;
   if (lane + 64 < n) out[lane + 64] = b1;
@@ -324,12 +339,26 @@ __device__ __forceinline__ void solve_bwd(const FitCtx& C, const double* in, dou
   const int n = C.n;
   double b0 = lane < n ? in[lane] : 0.0;
   double b1 = lane + 64 < n ? in[lane + 64] : 0.0;
-  for (int k = n - 1; k >= 0; --k) {
-    const int bk_row = rbase(k);
-    const double vk = readlane_d(k < 64 ? b0 : b1, k & 63) * C.piv[k];
-    if (lane == (k & 63)) { if (k < 64) b0 = vk; else b1 = vk; }
-    if (lane < k) b0 -= C.S[bk_row + lane] * vk;
-    if (lane + 64 < k) b1 -= C.S[bk_row + lane + 64] * vk;
+  for (int k0 = n - 1; k0 >= 0; k0 -= 4) {
+    double rp[4], s0[4], s1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 - u;
+      const int bk_row = k >= 0 ? rbase(k) : 0;
+      rp[u] = k >= 0 ? C.piv[k] : 0.0;
+      s0[u] = (k >= 0 && lane < k) ? C.S[bk_row + lane] : 0.0;
+      s1[u] = (k >= 0 && lane + 64 < k) ? C.S[bk_row + lane + 64] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 - u;
+      if (k >= 0) {
+        const double vk = readlane_d(k < 64 ? b0 : b1, k & 63) * rp[u];
+        if (lane == (k & 63)) { if (k < 64) b0 = vk; else b1 = vk; }
+        if (lane < k) b0 -= s0[u] * vk;
+        if (lane + 64 < k) b1 -= s1[u] * vk;
+      }
+    }
   }
   if (lane < n) out[C.perm[lane]] = b0;
   if (lane + 64 < n) out[C.perm[lane + 64]] = b1;
@@ -855,14 +884,17 @@ __global__ void fit_plan_zero(Plan* pl) {
 
 // Per-workgroup histograms in LDS, then one global atomic per non-empty bin and workgroup (a
 // single bucket can hold every fit of the batch).
-__global__ void __launch_bounds__(kFitBlock) fit_plan_count(FitArgs a, Plan* pl) {
+// The bin of each fit is kept in `keys` for the scatter.
+__global__ void __launch_bounds__(kFitBlock) fit_plan_count(FitArgs a, Plan* pl, int32_t* keys) {
   __shared__ int32_t hist[kClasses * kBuckets];
   for (int b = threadIdx.x; b < kClasses * kBuckets; b += kFitBlock) hist[b] = 0;
   __syncthreads();
   const int fi = blockIdx.x * kFitBlock + threadIdx.x;
   if (fi < a.n_fits) {
     const klr_fit_desc d = a.desc[fi];
-    atomicAdd(&hist[fit_class(a, d) * kBuckets + cost_bucket(d)], 1);
+    const int key = fit_class(a, d) * kBuckets + cost_bucket(d);
+    keys[fi] = key;
+    atomicAdd(&hist[key], 1);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < kClasses * kBuckets; b += kFitBlock)
@@ -888,7 +920,8 @@ __global__ void fit_plan_scan(Plan* pl) {
 
 // Each workgroup reserves one range per bin with a global atomic and places its fits in it by
 // their LDS rank (the order inside a bucket is arbitrary; a fit's result does not depend on it).
-__global__ void __launch_bounds__(kFitBlock) fit_plan_scatter(FitArgs a, Plan* pl, int32_t* order) {
+__global__ void __launch_bounds__(kFitBlock) fit_plan_scatter(FitArgs a, Plan* pl, const int32_t* keys,
+                                                               int32_t* order) {
   __shared__ int32_t hist[kClasses * kBuckets];
   __shared__ int32_t start[kClasses * kBuckets];
   for (int b = threadIdx.x; b < kClasses * kBuckets; b += kFitBlock) hist[b] = 0;
@@ -896,8 +929,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_plan_scatter(FitArgs a, Plan* p
   const int fi = blockIdx.x * kFitBlock + threadIdx.x;
   int key = -1, rank = 0;
   if (fi < a.n_fits) {
-    const klr_fit_desc d = a.desc[fi];
-    key = fit_class(a, d) * kBuckets + cost_bucket(d);
+    key = keys[fi];
     rank = atomicAdd(&hist[key], 1);
   }
   __syncthreads();
@@ -983,13 +1015,14 @@ template <int PREC>
 hipError_t launch_all(const FitArgs& a, bool persistent) {
   Plan* pl = reinterpret_cast<Plan*>(reinterpret_cast<char*>(a.ws) + plan_offset(a.f_len));
   int32_t* order = reinterpret_cast<int32_t*>(pl + 1);
+  int32_t* keys = order + (a.n_fits > 0 ? a.n_fits : 0);
   hipError_t e = hipSuccess;
   if (persistent) {
     const unsigned g = (unsigned)((a.n_fits + kFitBlock - 1) / kFitBlock);
     hipLaunchKernelGGL(fit_plan_zero, dim3(1), dim3(kClasses * kBuckets), 0, a.stream, pl);
-    hipLaunchKernelGGL(fit_plan_count, dim3(g), dim3(kFitBlock), 0, a.stream, a, pl);
+    hipLaunchKernelGGL(fit_plan_count, dim3(g), dim3(kFitBlock), 0, a.stream, a, pl, keys);
     hipLaunchKernelGGL(fit_plan_scan, dim3(1), dim3(64), 0, a.stream, pl);
-    hipLaunchKernelGGL(fit_plan_scatter, dim3(g), dim3(kFitBlock), 0, a.stream, a, pl, order);
+    hipLaunchKernelGGL(fit_plan_scatter, dim3(g), dim3(kFitBlock), 0, a.stream, a, pl, keys, order);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
@@ -1008,7 +1041,7 @@ hipError_t launch_all(const FitArgs& a, bool persistent) {
 
 size_t fit_workspace_bytes(int32_t n_fits, int64_t f_len, int32_t precision) {
   (void)precision;
-  return plan_offset(f_len) + sizeof(Plan) + (size_t)(n_fits > 0 ? n_fits : 0) * sizeof(int32_t);
+  return plan_offset(f_len) + sizeof(Plan) + (size_t)(n_fits > 0 ? n_fits : 0) * 2 * sizeof(int32_t);
 }
 
 hipError_t launch_fit(const FitArgs& a) {

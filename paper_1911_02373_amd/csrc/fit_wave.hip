@@ -273,23 +273,48 @@ __device__ void fwd_wave(const WaveLds& L, int n, const double* in, double* out)
   const int lane = threadIdx.x & 63;
   const int myb = rbase(lane);
   double b = lane < n ? in[L.perm[lane]] : 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double uk = readlane_d(b, k) * L.rd[k];
-    if (lane == k) b = uk;
-    if (lane > k && lane < n) b -= L.S[myb + k] * uk;
+  // steps in groups of 4: the factor entries of a group are loaded before its dependent chain
+  for (int k0 = 0; k0 < n; k0 += 4) {
+    double rp[4], sv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u;
+      rp[u] = k < n ? L.rd[k] : 0.0;
+      sv[u] = (k < n && lane > k && lane < n) ? L.S[myb + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u;
+      if (k < n) {
+        const double uk = readlane_d(b, k) * rp[u];
+        if (lane == k) b = uk;
+        if (lane > k && lane < n) b -= sv[u] * uk;
+      }
+    }
   }
   if (lane < n) out[lane] = b;
   wave_sync();
 }
-
-// L^T v = in (pivot-indexed); out[perm[i]] = v_i.
 __device__ void bwd_wave(const WaveLds& L, int n, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
   double b = lane < n ? in[lane] : 0.0;
-  for (int k = n - 1; k >= 0; --k) {
-    const double vk = readlane_d(b, k) * L.rd[k];
-    if (lane == k) b = vk;
-    if (lane < k) b -= L.S[rbase(k) + lane] * vk;
+  for (int k0 = n - 1; k0 >= 0; k0 -= 4) {
+    double rp[4], sv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 - u;
+      rp[u] = k >= 0 ? L.rd[k] : 0.0;
+      sv[u] = (k >= 0 && lane < k) ? L.S[rbase(k) + lane] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 - u;
+      if (k >= 0) {
+        const double vk = readlane_d(b, k) * rp[u];
+        if (lane == k) b = vk;
+        if (lane < k) b -= sv[u] * vk;
+      }
+    }
   }
   if (lane < n) out[L.perm[lane]] = b;
   wave_sync();
