@@ -651,12 +651,16 @@ __device__ __forceinline__ int factor(const FitCtx& C, double unit) {
   return rank;
 }
 
-// Size class of a fit: kWaveClass = one wavefront per fit (fit_wave.hip); otherwise one
-// workgroup per fit with padded width 32 (class 0), 64 (1), 96 (2), 112 (3) or 128 (4, which also
-// takes every invalid descriptor and reports it as bad input).
+// Size class of a fit: kWaveClass (8 rows per lane) and kWaveClass16 (16) = one wavefront per
+// fit (fit_wave.hip); otherwise one workgroup per fit with padded width 32 (class 0), 64 (1),
+// 96 (2), 112 (3) or 128 (4, which also takes every invalid descriptor and reports it as bad
+// input).
 constexpr int kWaveClass = 5;
+constexpr int kWaveClass16 = 6;
 __device__ __forceinline__ int fit_class(const FitArgs& a, const klr_fit_desc& d) {
-  if (wave_fit_eligible(a, d)) return kWaveClass;
+  const int rpl = wave_fit_rows(a, d);
+  if (rpl == 8) return kWaveClass;
+  if (rpl == 16) return kWaveClass16;
   const int n = d.n_num + d.n_den - 1;
   const bool shape_ok = d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= KLR_MAX_UNKNOWNS;
   if (!shape_ok) return 4;
@@ -857,7 +861,7 @@ fit_kernel2(FitArgs a, int cls) {
 // wave class (one wavefront per fit) is launched as a grid that takes positions in order.  A
 // fit's result does not depend on which workgroup computes it, so outputs are deterministic.
 constexpr int kBuckets = 32;
-constexpr int kClasses = 6;
+constexpr int kClasses = 7;
 struct Plan {
   int32_t counts[kClasses * kBuckets];
   int32_t offs[kClasses * kBuckets];
@@ -1026,8 +1030,9 @@ hipError_t launch_all(const FitArgs& a, bool persistent) {
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    const WavePlanView pv{order, &pl->totals[kWaveClass], &pl->base[kWaveClass]};
-    e = launch_fit_wave(a, persistent, pv);
+    const WavePlanView pv8{order, &pl->totals[kWaveClass], &pl->base[kWaveClass]};
+    const WavePlanView pv16{order, &pl->totals[kWaveClass16], &pl->base[kWaveClass16]};
+    e = launch_fit_wave(a, persistent, pv8, pv16);
   }
   if (e == hipSuccess) e = launch_class<32, PREC>(a, 0, persistent, pl, order);
   if (e == hipSuccess) e = launch_class<64, PREC>(a, 1, persistent, pl, order);

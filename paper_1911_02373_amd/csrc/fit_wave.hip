@@ -3,8 +3,9 @@
 // Same problem and numerical method as the workgroup kernel in fit.hip (paper: step 2 of the
 // section "An Algorithm to Build and Deploy a Performance-Predicting Rational Program" and
 // section "Building a Driver Program: Rational function estimation"), organised for fits with
-// n <= 48 unknowns, v <= 4 variables, m <= 512 samples and exponents <= 3:
-//   * lane l owns sample rows l, l + 64, ... (scaled variables, target and residual in VGPRs);
+// n <= 48 unknowns, v <= 4 variables, m <= 1024 samples and exponents <= 3:
+//   * lane l owns sample rows l, l + 64, ... (scaled variables, target and residual in VGPRs;
+//     8 rows per lane for m <= 512 at two waves per SIMD, 16 for m <= 1024 at one);
 //   * Gram on MFMA (v_mfma_f64_16x16x4f64 for the FP64 path, v_mfma_f32_16x16x4f32 with FP32
 //     or BF16-rounded design-matrix values for the reduced paths): for each step of 4 rows the
 //     lanes build a table of x_k^p (p <= 3) of the step's rows in LDS, one entry per lane, and
@@ -34,7 +35,6 @@ namespace {
 
 constexpr int kNP = 48;            // padded unknowns: three 16-column tiles
 static_assert(kNP <= 48, "the 8 x 8 update grid of the factorization covers 48 rows");
-constexpr int kRPL = 8;            // sample rows per lane (m <= 512)
 constexpr int kV = 4;              // variables
 constexpr int kWavesPerGroup = 4;
 constexpr int kSP = kNP * (kNP + 1) / 2;
@@ -70,15 +70,18 @@ __device__ __forceinline__ int symi(int a, int b) {
 
 __device__ __forceinline__ double wsum(double v) { return wave_sum_d(v); }
 
+// Sample rows of one fit held in registers: lane l owns rows l, l + 64, ..., RPL rows per lane
+// (RPL = 8 for m <= 512, 16 for m <= 1024).
+template <int RPL>
 struct Rows {
-  double x[kRPL][kV];
-  double f[kRPL];
-  double r[kRPL];
+  double x[RPL][kV];
+  double f[RPL];
+  double r[RPL];
 };
 
 // Gram of the equilibrated problem's unscaled matrix: S (packed lower) and c = A^T f.
-template <int GP>
-__device__ void gram(WaveLds& L, const Rows& R, int m, int n, int n_num) {
+template <int GP, int RPL>
+__device__ void gram(WaveLds& L, const Rows<RPL>& R, int m, int n, int n_num) {
   using GT = GramTypes<GP>;
   typename GT::acc_t acc[6];
 #pragma unroll
@@ -112,7 +115,7 @@ __device__ void gram(WaveLds& L, const Rows& R, int m, int n, int n_num) {
     const int src = row & 63, slot = (4 * st) >> 6;
     double xv[kV], fv = 0.0;
 #pragma unroll
-    for (int s = 0; s < kRPL; ++s) {
+    for (int s = 0; s < RPL; ++s) {
       if (s == slot) {
 #pragma unroll
         for (int k = 0; k < kV; ++k) xv[k] = __shfl(R.x[s][k], src);
@@ -326,15 +329,16 @@ __device__ __forceinline__ double dotw(const double* a, const double* b, int n) 
 }
 
 // Monomial x~^e of column e (packed exponents, wave-uniform) for each of the lane's rows.
-__device__ __forceinline__ void mono_rows(const Rows& R, int e, double* mo) {
+template <int RPL>
+__device__ __forceinline__ void mono_rows(const Rows<RPL>& R, int e, double* mo) {
 #pragma unroll
-  for (int s = 0; s < kRPL; ++s) mo[s] = 1.0;
+  for (int s = 0; s < RPL; ++s) mo[s] = 1.0;
 #pragma unroll
   for (int k = 0; k < kV; ++k) {
     const int ek = (e >> (8 * k)) & 0xFF;
     for (int q = 0; q < ek; ++q)
 #pragma unroll
-      for (int s = 0; s < kRPL; ++s) mo[s] *= R.x[s][k];
+      for (int s = 0; s < RPL; ++s) mo[s] *= R.x[s][k];
   }
 }
 
@@ -346,29 +350,29 @@ __device__ __forceinline__ void mono_rows(const Rows& R, int e, double* mo) {
 //   mode 2: returns ||f - d||^2 and counts q(x~_i) = 1 + s_i <= 0 into *qneg.
 // Column exponents are read into scalar registers, so the monomial loops are uniform.
 // Returns alpha in mode 1.
-template <int MODE>
-__device__ double row_pass(WaveLds& L, Rows& R, int m, int n, int n_num, double gamma, double* qq, int* qneg) {
+template <int MODE, int RPL>
+__device__ double row_pass(WaveLds& L, Rows<RPL>& R, int m, int n, int n_num, double gamma, double* qq, int* qneg) {
   const int lane = threadIdx.x & 63;
-  double pn[kRPL], pd[kRPL], mo[kRPL];
+  double pn[RPL], pd[RPL], mo[RPL];
 #pragma unroll
-  for (int s = 0; s < kRPL; ++s) pn[s] = pd[s] = 0.0;
+  for (int s = 0; s < RPL; ++s) pn[s] = pd[s] = 0.0;
   for (int j = 0; j < n_num; ++j) {
     mono_rows(R, __builtin_amdgcn_readfirstlane(L.ex[j]), mo);
     const double tj = L.t[j];
 #pragma unroll
-    for (int s = 0; s < kRPL; ++s) pn[s] += mo[s] * tj;
+    for (int s = 0; s < RPL; ++s) pn[s] += mo[s] * tj;
   }
   for (int j = n_num; j < n; ++j) {
     mono_rows(R, __builtin_amdgcn_readfirstlane(L.ex[j]), mo);
     const double tj = L.t[j];
 #pragma unroll
-    for (int s = 0; s < kRPL; ++s) pd[s] += mo[s] * tj;
+    for (int s = 0; s < RPL; ++s) pd[s] += mo[s] * tj;
   }
   double sq = 0.0;
   int qn = 0;
-  double d[kRPL];
+  double d[RPL];
 #pragma unroll
-  for (int s = 0; s < kRPL; ++s) {
+  for (int s = 0; s < RPL; ++s) {
     const bool live = lane + 64 * s < m;
     d[s] = live ? pn[s] - R.f[s] * pd[s] : 0.0;
     if (MODE == 0 && live) R.r[s] = R.f[s] - d[s];
@@ -389,21 +393,21 @@ __device__ double row_pass(WaveLds& L, Rows& R, int m, int n, int n_num, double 
     *qq = qn2;
     alpha = qn2 > 0.0 ? gamma / qn2 : 0.0;
 #pragma unroll
-    for (int s = 0; s < kRPL; ++s) R.r[s] -= alpha * d[s];
+    for (int s = 0; s < RPL; ++s) R.r[s] -= alpha * d[s];
   }
   // g_j = D_j sum_i A_ij r_i: numerator columns weigh r_i, denominator columns -f_i r_i
-  double wf[kRPL];
+  double wf[RPL];
 #pragma unroll
-  for (int s = 0; s < kRPL; ++s) wf[s] = -R.f[s] * R.r[s];
+  for (int s = 0; s < RPL; ++s) wf[s] = -R.f[s] * R.r[s];
   for (int j = 0; j < n; ++j) {
     mono_rows(R, __builtin_amdgcn_readfirstlane(L.ex[j]), mo);
     double v = 0.0;
     if (j < n_num) {
 #pragma unroll
-      for (int s = 0; s < kRPL; ++s) v += mo[s] * R.r[s];
+      for (int s = 0; s < RPL; ++s) v += mo[s] * R.r[s];
     } else {
 #pragma unroll
-      for (int s = 0; s < kRPL; ++s) v += mo[s] * wf[s];
+      for (int s = 0; s < RPL; ++s) v += mo[s] * wf[s];
     }
     v = wsum(v);
     if (lane == 0) L.g[j] = v * L.D[j];
@@ -412,14 +416,14 @@ __device__ double row_pass(WaveLds& L, Rows& R, int m, int n, int n_num, double 
   return alpha;
 }
 
-template <int PREC>
+template <int PREC, int RPL>
 __device__ void fit_wave_one(const FitArgs& a, int fi, WaveLds& L) {
   const int lane = threadIdx.x & 63;
   const klr_fit_desc d = a.desc[fi];
   const int n = d.n_num + d.n_den - 1;
   const bool coef_ok = d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= kNP && d.coef0 >= 0 &&
                        d.coef0 + (int64_t)n <= a.coef_len;
-  bool ok = coef_ok && d.v >= 1 && d.v <= kV && d.m >= 1 && d.m <= kRPL * 64 && d.x0 >= 0 &&
+  bool ok = coef_ok && d.v >= 1 && d.v <= kV && d.m >= 1 && d.m <= RPL * 64 && d.x0 >= 0 &&
             d.x0 + (int64_t)d.m * d.v <= a.x_len && d.f0 >= 0 && d.f0 + (int64_t)d.m <= a.f_len &&
             d.num0 >= 0 && (int64_t)d.num0 + d.n_num <= a.n_exp_rows && d.den0 >= 0 &&
             (int64_t)d.den0 + d.n_den <= a.n_exp_rows;
@@ -431,9 +435,9 @@ __device__ void fit_wave_one(const FitArgs& a, int fi, WaveLds& L) {
         if (a.exps[(int64_t)d.den0 * KLR_MAX_VARS + k] != 0) ok = false;
       }
   klr_fit_info info{};
-  Rows R;
+  Rows<RPL> R;
 #pragma unroll
-  for (int s = 0; s < kRPL; ++s) {
+  for (int s = 0; s < RPL; ++s) {
 #pragma unroll
     for (int k = 0; k < kV; ++k) R.x[s][k] = 0.0;
     R.f[s] = 0.0;
@@ -451,7 +455,7 @@ __device__ void fit_wave_one(const FitArgs& a, int fi, WaveLds& L) {
     }
     bool nonfinite = false;
 #pragma unroll
-    for (int s = 0; s < kRPL; ++s) {
+    for (int s = 0; s < RPL; ++s) {
       const int i = lane + 64 * s;
       if (i < d.m) {
 #pragma unroll
@@ -477,7 +481,7 @@ __device__ void fit_wave_one(const FitArgs& a, int fi, WaveLds& L) {
   }
   double fn2 = 0.0;
 #pragma unroll
-  for (int s = 0; s < kRPL; ++s) fn2 += R.f[s] * R.f[s];
+  for (int s = 0; s < RPL; ++s) fn2 += R.f[s] * R.f[s];
   const double fnorm = sqrt(wsum(fn2));
 
   int prec = PREC, iters = 0, rank = 0;
@@ -485,15 +489,15 @@ __device__ void fit_wave_one(const FitArgs& a, int fi, WaveLds& L) {
   double err = 0.0;
   for (int attempt = 0; attempt < 2; ++attempt) {
     double unit;
-    if (prec == KLR_FP64) { gram<KLR_FP64>(L, R, d.m, n, d.n_num); unit = 0x1p-53; }
-    else if (prec == KLR_FP32_REFINED) { gram<KLR_FP32_REFINED>(L, R, d.m, n, d.n_num); unit = 0x1p-24; }
-    else { gram<KLR_BF16_REFINED>(L, R, d.m, n, d.n_num); unit = 0x1p-8; }
+    if (prec == KLR_FP64) { gram<KLR_FP64, RPL>(L, R, d.m, n, d.n_num); unit = 0x1p-53; }
+    else if (prec == KLR_FP32_REFINED) { gram<KLR_FP32_REFINED, RPL>(L, R, d.m, n, d.n_num); unit = 0x1p-24; }
+    else { gram<KLR_BF16_REFINED, RPL>(L, R, d.m, n, d.n_num); unit = 0x1p-8; }
     rank = factor_wave(L, n, unit);
     fwd_wave(L, n, L.c, L.s);                          // z0 = (G~ + mu I)^-1 D A^T f
     bwd_wave(L, n, L.s, L.z);
     if (lane < n) L.t[lane] = L.D[lane] * L.z[lane];
     wave_sync();
-    row_pass<0>(L, R, d.m, n, d.n_num, 0.0, nullptr, nullptr);   // r0 = f - A y0, g = D A^T r0
+    row_pass<0, RPL>(L, R, d.m, n, d.n_num, 0.0, nullptr, nullptr);   // r0 = f - A y0, g = D A^T r0
     fwd_wave(L, n, L.g, L.s);                          // s0 = R^-T Pi^T g
     if (lane < n) L.p[lane] = L.s[lane];
     wave_sync();
@@ -508,7 +512,7 @@ __device__ void fit_wave_one(const FitArgs& a, int fi, WaveLds& L) {
       if (lane < n) L.t[lane] = L.D[lane] * L.dz[lane];
       wave_sync();
       double qq = 0.0;   // ||A D dz||^2; r -= alpha A D dz; g = D A^T r
-      const double alpha = row_pass<1>(L, R, d.m, n, d.n_num, gamma, &qq, nullptr);
+      const double alpha = row_pass<1, RPL>(L, R, d.m, n, d.n_num, gamma, &qq, nullptr);
       if (lane < n) L.z[lane] += alpha * L.dz[lane];
       wave_sync();
       h0 = h1;
@@ -536,7 +540,7 @@ __device__ void fit_wave_one(const FitArgs& a, int fi, WaveLds& L) {
   if (lane < n) L.t[lane] = L.D[lane] * L.z[lane];
   wave_sync();
   int qneg = 0;
-  const double rr = row_pass<2>(L, R, d.m, n, d.n_num, 0.0, nullptr, &qneg);
+  const double rr = row_pass<2, RPL>(L, R, d.m, n, d.n_num, 0.0, nullptr, &qneg);
   if (lane < n) a.coef[d.coef0 + lane] = L.t[lane];
   if (lane == 0) {
     if (rank < n) info.status |= KLR_FIT_RANK_DEFICIENT;
@@ -553,42 +557,69 @@ __device__ void fit_wave_one(const FitArgs& a, int fi, WaveLds& L) {
   wave_sync();
 }
 
-// Longest-first schedule: wave w of workgroup b takes position 4 b + w of the wave-fit part of
-// the plan's order (the dispatcher starts workgroups in index order, so the longest fits start
-// first); positions past the wave-fit count leave at once.
+// Longest-first schedule: wave w of workgroup b takes position 4 b + w of its row class's part
+// of the plan's order (the dispatcher starts workgroups in index order, so the longest fits
+// start first); positions past the class's count leave at once.  Fits with 8 rows per lane run
+// two waves per SIMD; those with 16 rows per lane need the whole register file of one.
+template <int PREC, int RPL>
+__device__ __forceinline__ void ordered_body(const FitArgs& a, const WavePlanView& pv, WaveLds* lds) {
+  const int i = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+  if (i >= *pv.total) return;
+  fit_wave_one<PREC, RPL>(a, pv.order[*pv.base + i], lds[threadIdx.x >> 6]);
+}
+template <int PREC, int RPL>
+__device__ __forceinline__ void plain_body(const FitArgs& a, WaveLds* lds) {
+  const int fi = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+  if (fi >= a.n_fits || wave_fit_rows(a, a.desc[fi]) != RPL) return;
+  fit_wave_one<PREC, RPL>(a, fi, lds[threadIdx.x >> 6]);
+}
+
 template <int PREC>
 __global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(2)))
 fit_wave_ordered(FitArgs a, WavePlanView pv) {
   __shared__ WaveLds lds[kWavesPerGroup];
-  const int i = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
-  if (i >= *pv.total) return;
-  fit_wave_one<PREC>(a, pv.order[*pv.base + i], lds[threadIdx.x >> 6]);
+  ordered_body<PREC, 8>(a, pv, lds);
+}
+template <int PREC>
+__global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(1)))
+fit_wave_ordered16(FitArgs a, WavePlanView pv) {
+  __shared__ WaveLds lds[kWavesPerGroup];
+  ordered_body<PREC, 16>(a, pv, lds);
 }
 
-// One wave per fit in descriptor order; waves whose fit is not a wave fit leave at once.
+// One wave per fit in descriptor order; waves whose fit is not of the kernel's row class leave.
 template <int PREC>
 __global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(2)))
 fit_wave_plain(FitArgs a) {
   __shared__ WaveLds lds[kWavesPerGroup];
-  const int fi = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
-  if (fi >= a.n_fits || !wave_fit_eligible(a, a.desc[fi])) return;
-  fit_wave_one<PREC>(a, fi, lds[threadIdx.x >> 6]);
+  plain_body<PREC, 8>(a, lds);
+}
+template <int PREC>
+__global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(1)))
+fit_wave_plain16(FitArgs a) {
+  __shared__ WaveLds lds[kWavesPerGroup];
+  plain_body<PREC, 16>(a, lds);
 }
 
 template <int PREC>
-hipError_t launch_wave_t(const FitArgs& a, bool ordered, const WavePlanView& pv) {
+hipError_t launch_wave_t(const FitArgs& a, bool ordered, const WavePlanView& pv8, const WavePlanView& pv16) {
   const dim3 grid((unsigned)((a.n_fits + kWavesPerGroup - 1) / kWavesPerGroup)), block(64 * kWavesPerGroup);
-  if (ordered) hipLaunchKernelGGL(fit_wave_ordered<PREC>, grid, block, 0, a.stream, a, pv);
-  else hipLaunchKernelGGL(fit_wave_plain<PREC>, grid, block, 0, a.stream, a);
+  if (ordered) {
+    hipLaunchKernelGGL(fit_wave_ordered16<PREC>, grid, block, 0, a.stream, a, pv16);
+    hipLaunchKernelGGL(fit_wave_ordered<PREC>, grid, block, 0, a.stream, a, pv8);
+  } else {
+    hipLaunchKernelGGL(fit_wave_plain16<PREC>, grid, block, 0, a.stream, a);
+    hipLaunchKernelGGL(fit_wave_plain<PREC>, grid, block, 0, a.stream, a);
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_fit_wave(const FitArgs& a, bool ordered, const WavePlanView& pv) {
-  if (a.precision == KLR_FP64) return launch_wave_t<KLR_FP64>(a, ordered, pv);
-  if (a.precision == KLR_FP32_REFINED) return launch_wave_t<KLR_FP32_REFINED>(a, ordered, pv);
-  return launch_wave_t<KLR_BF16_REFINED>(a, ordered, pv);
+hipError_t launch_fit_wave(const FitArgs& a, bool ordered, const WavePlanView& pv8, const WavePlanView& pv16) {
+  if (a.precision == KLR_FP64) return launch_wave_t<KLR_FP64>(a, ordered, pv8, pv16);
+  if (a.precision == KLR_FP32_REFINED) return launch_wave_t<KLR_FP32_REFINED>(a, ordered, pv8, pv16);
+  return launch_wave_t<KLR_BF16_REFINED>(a, ordered, pv8, pv16);
 }
 
 }  // namespace klr

@@ -121,19 +121,21 @@ hipError_t launch_fit(const FitArgs& a);
 
 // Fits for one wavefront: n <= 48 unknowns, v <= 4 variables, 1 <= m <= 512 samples, valid
 // exponent rows with every exponent <= 3 (the Gram's power table holds x^0 .. x^3).
-__device__ inline bool wave_fit_eligible(const FitArgs& a, const klr_fit_desc& d) {
+// Rows per lane of the one-wavefront fit kernel for this fit: 8 (m <= 512) or 16 (m <= 1024)
+// when n <= 48, v <= 4 and every exponent is <= 3; 0 when the fit takes the workgroup kernel.
+__device__ inline int wave_fit_rows(const FitArgs& a, const klr_fit_desc& d) {
   const int n = d.n_num + d.n_den - 1;
-  if (!(d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= 48 && d.v >= 1 && d.v <= 4 && d.m >= 1 && d.m <= 512))
-    return false;
+  if (!(d.n_num >= 0 && d.n_den >= 1 && n >= 1 && n <= 48 && d.v >= 1 && d.v <= 4 && d.m >= 1 && d.m <= 1024))
+    return 0;
   if (d.num0 < 0 || (int64_t)d.num0 + d.n_num > a.n_exp_rows || d.den0 < 0 ||
       (int64_t)d.den0 + d.n_den > a.n_exp_rows)
-    return false;
+    return 0;
   for (int r = 0; r < d.n_num + d.n_den; ++r) {
     const int64_t row = r < d.n_num ? (int64_t)d.num0 + r : (int64_t)d.den0 + (r - d.n_num);
     for (int k = 0; k < d.v; ++k)
-      if (a.exps[row * KLR_MAX_VARS + k] > 3) return false;
+      if (a.exps[row * KLR_MAX_VARS + k] > 3) return 0;
   }
-  return true;
+  return d.m <= 512 ? 8 : 16;
 }
 // ---- cross-lane moves on the VALU (no LDS round trip) ----------------------------------------
 // Lane l's value of v, broadcast through scalar registers (l wave-uniform).
@@ -285,7 +287,7 @@ struct WavePlanView {        // the wave-fit part of the longest-first order
   const int32_t* total;
   const int32_t* base;
 };
-hipError_t launch_fit_wave(const FitArgs& a, bool ordered, const WavePlanView& pv);
+hipError_t launch_fit_wave(const FitArgs& a, bool ordered, const WavePlanView& pv8, const WavePlanView& pv16);
 
 // ---- surrogate network ----------------------------------------------------------------------
 // Parameter vector layout (floats): W2[256][256] | W1[256][4] | b1 | b2 | w3 | b3 | pad | emb.

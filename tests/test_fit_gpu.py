@@ -131,18 +131,22 @@ def test_refined_reduced_precision_within_1e5(klr, prec):
 
 
 def test_size_classes_and_variables(klr):
-    """n in each launch class (padded widths 32, 64, 96, 112, 128 and the one-wavefront class),
-    v = 1..5, ragged chunks; the n = 119 case has denominator exponents up to 4."""
+    """n in each launch class (padded widths 32, 64, 96, 112, 128 and the one-wavefront classes
+    with 8 and 16 rows per lane), v = 1..5, ragged chunks; the n = 119 case has denominator
+    exponents up to 4."""
     rng = np.random.default_rng(3)
     samples, exps_rows, num0, nn, den0, nd, scales = [], [], [], [], [], [], []
     row = 0
-    # (v, numerator degree, denominator degree, denominator monomials kept; None = all)
-    cases = [(1, 3, 3, None), (2, 2, 2, None), (3, 2, 2, None), (3, 3, 3, None), (4, 3, 3, None),
-             (5, 3, 3, None), (2, 4, 4, None), (5, 3, 4, 64)]
-    for v, dn, dd, keep in cases:
+    # (v, numerator degree, denominator degree, denominator monomials kept (None = all), m range
+    # (None = up to 700)); the last two take the one-wavefront kernel with 16 rows per lane
+    cases = [(1, 3, 3, None, None), (2, 2, 2, None, None), (3, 2, 2, None, None), (3, 3, 3, None, None),
+             (4, 3, 3, None, None), (5, 3, 3, None, None), (2, 4, 4, None, None), (5, 3, 4, 64, None),
+             (3, 3, 3, None, (513, 1025)), (1, 3, 3, None, (900, 1025))]
+    for v, dn, dd, keep, mr in cases:
         En = synth.monomials(v, dn)
         Ed = synth.monomials(v, dd)[:keep]
-        m = int(rng.integers((En.shape[0] + Ed.shape[0]) * 2 + 1, 700))
+        lo, hi = mr if mr else ((En.shape[0] + Ed.shape[0]) * 2 + 1, 700)
+        m = int(rng.integers(lo, hi))
         X = rng.integers(1, 1 << 12, (m, v)).astype(np.int32)
         xt = X / 4096.0
         p = 1.0 + xt.sum(1)
