@@ -115,59 +115,109 @@ __device__ bool fit_desc_ok(const klr_fit_desc& d, int v_expected, const EvalArg
 }
 
 // Polynomial in N~ of one metric polynomial at fixed launch parameters.  FP64, monomials in set
-// order, each monomial value by repeated multiplication in variable order.
-__device__ bool collapse_poly(const uint8_t* exps, int row0, int nrows, int v, const int8_t* s,
-                              const double* coef, bool den, const int32_t* L, double out[kNdeg + 1]) {
-  double Lt[KLR_MAX_LAUNCH];
-  for (int k = 1; k < v; ++k) Lt[k - 1] = ldexp((double)L[k - 1], -(int)s[k]);
-  for (int d = 0; d <= kNdeg; ++d) out[d] = 0.0;
-  for (int t = 0; t < nrows; ++t) {
-    const uint8_t* e = exps + (int64_t)(row0 + t) * KLR_MAX_VARS;
-    if (e[0] > kNdeg) return false;
-    double mono = 1.0;
-    for (int k = 1; k < v; ++k)
-      for (int r = 0; r < e[k]; ++r) mono = mono * Lt[k - 1];
-    double c = den ? (t == 0 ? 1.0 : coef[t - 1]) : coef[t];
-    out[e[0]] = out[e[0]] + c * mono;
-  }
-  return true;
+// order, each monomial value by repeated multiplication in variable order.  `rows` points at
+// the polynomial's exponent rows (8 bytes each), `coef` at its coefficients (the denominator's
+// constant 1 is implicit).  Every exponent of N~ has been checked to be <= kNdeg.
+__device__ __forceinline__ uint64_t exp_row(const uint8_t* exps, int64_t row) {
+  const uint8_t* e = exps + row * KLR_MAX_VARS;
+  if ((reinterpret_cast<uintptr_t>(e) & 7u) == 0) return *reinterpret_cast<const uint64_t*>(e);
+  uint64_t w = 0;
+  for (int k = 0; k < KLR_MAX_VARS; ++k) w |= (uint64_t)e[k] << (8 * k);
+  return w;
 }
 
+template <bool STAGED>
+__device__ __forceinline__ void collapse_poly(const uint64_t* srows, const uint8_t* exps, int64_t row0, int nrows,
+                                              int v, const double* Lt, const double* coef, bool den,
+                                              double out[kNdeg + 1]) {
+  double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;
+  static_assert(kNdeg == 3, "four powers of N~");
+  for (int t = 0; t < nrows; ++t) {
+    // the same row for every thread: its exponents go to scalar registers
+    const uint64_t w = STAGED ? srows[t] : exp_row(exps, row0 + t);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)w);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(w >> 32));
+    double mono = 1.0;
+    for (int k = 1; k < v; ++k) {
+      const int ek = (int)(((k < 4 ? lo >> (8 * k) : hi >> (8 * (k - 4)))) & 0xFFu);
+      for (int r = 0; r < ek; ++r) mono = mono * Lt[k - 1];
+    }
+    const double c = den ? (t == 0 ? 1.0 : coef[t - 1]) : coef[t];
+    const double term = c * mono;
+    switch (lo & 0xFFu) {
+      case 0: o0 = o0 + term; break;
+      case 1: o1 = o1 + term; break;
+      case 2: o2 = o2 + term; break;
+      default: o3 = o3 + term; break;
+    }
+  }
+  out[0] = o0; out[1] = o1; out[2] = o2; out[3] = o3;
+}
+
+// One workgroup per (program, block of configurations).  The program's eight fit descriptors
+// are validated once per workgroup, and their exponent rows and coefficients are staged in LDS
+// when they fit (every thread then reads the same LDS rows); one thread per configuration
+// computes its record and the collapsed coefficients of the eight metrics.
+constexpr int kCollapseCapRows = KLR_N_METRICS * (KLR_MAX_UNKNOWNS + 1);
 __global__ void __launch_bounds__(kCollapseBlock)
 collapse_kernel(EvalArgs a, int chunks) {
+  __shared__ uint64_t s_rows[kCollapseCapRows];       // exponent rows, numerator then denominator
+  __shared__ double s_coef[kCollapseCapRows];
+  __shared__ klr_fit_desc s_desc[KLR_N_METRICS];
+  __shared__ int s_off[KLR_N_METRICS + 1];
+  __shared__ int s_bad, s_deg, s_staged;
   const int p = blockIdx.x / chunks;
   const int c = (blockIdx.x % chunks) * kCollapseBlock + threadIdx.x;
   if (p >= a.n_progs) return;
   const klr_program P = a.progs[p];
   const bool pd_ok = program_desc_ok(P, a);
-  bool fits_ok = pd_ok;
   const int v = 1 + (pd_ok ? P.v_launch : 0);
-  if (pd_ok) {
+  if (threadIdx.x == 0) { s_bad = 0; s_deg = 0; }
+  __syncthreads();
+  if (pd_ok && threadIdx.x < KLR_N_METRICS) {
+    const klr_fit_desc d = a.desc[P.fit0 + threadIdx.x];
+    s_desc[threadIdx.x] = d;
+    if (!fit_desc_ok(d, v, a)) atomicOr(&s_bad, 1);
+  }
+  __syncthreads();
+  bool fits_ok = pd_ok && s_bad == 0;
+  if (threadIdx.x == 0 && fits_ok) {
+    int off = 0;
     for (int j = 0; j < KLR_N_METRICS; ++j) {
-      const klr_fit_desc d = a.desc[P.fit0 + j];
-      if (!fit_desc_ok(d, v, a)) { fits_ok = false; break; }
-      for (int t = 0; t < d.n_num && fits_ok; ++t)
-        if (a.exps[(int64_t)(d.num0 + t) * KLR_MAX_VARS] > kNdeg) fits_ok = false;
-      for (int t = 0; t < d.n_den && fits_ok; ++t)
-        if (a.exps[(int64_t)(d.den0 + t) * KLR_MAX_VARS] > kNdeg) fits_ok = false;
+      s_off[j] = off;
+      off += s_desc[j].n_num + s_desc[j].n_den;
+    }
+    s_off[KLR_N_METRICS] = off;
+    s_staged = off <= kCollapseCapRows;
+  }
+  __syncthreads();
+  // one pass over the exponent rows: powers of N~ checked, the highest one found, rows and
+  // coefficients staged in LDS when they fit
+  const bool stage = fits_ok && s_staged;
+  if (fits_ok) {
+    for (int j = 0; j < KLR_N_METRICS; ++j) {
+      const klr_fit_desc& d = s_desc[j];
+      const int nr = d.n_num + d.n_den;
+      for (int t = threadIdx.x; t < nr; t += kCollapseBlock) {
+        const int64_t row = t < d.n_num ? (int64_t)d.num0 + t : (int64_t)d.den0 + (t - d.n_num);
+        const uint64_t w = exp_row(a.exps, row);
+        const int e0 = (int)(w & 0xFFu);
+        if (e0 > kNdeg) atomicOr(&s_bad, 1);
+        atomicMax(&s_deg, e0);
+        if (stage) {
+          s_rows[s_off[j] + t] = w;
+          if (t < nr - 1) s_coef[s_off[j] + t] = a.coef[d.coef0 + t];
+        }
+      }
     }
   }
+  __syncthreads();
+  fits_ok = fits_ok && s_bad == 0;
+  const bool staged = fits_ok && stage;
   if (c == 0 && a.prog_status)
     a.prog_status[p] = (pd_ok ? 0 : KLR_PROG_BAD_DESC) | (pd_ok && !fits_ok ? KLR_PROG_BAD_FIT : 0);
   if (c == 0) {   // highest power of N~ over the program's metric polynomials (Horner start)
-    int deg = 0;
-    if (fits_ok)
-      for (int j = 0; j < KLR_N_METRICS; ++j) {
-        const klr_fit_desc d = a.desc[P.fit0 + j];
-        for (int t = 0; t < d.n_num; ++t) {
-          const int e = a.exps[(int64_t)(d.num0 + t) * KLR_MAX_VARS];
-          deg = e > deg ? e : deg;
-        }
-        for (int t = 0; t < d.n_den; ++t) {
-          const int e = a.exps[(int64_t)(d.den0 + t) * KLR_MAX_VARS];
-          deg = e > deg ? e : deg;
-        }
-      }
+    const int deg = fits_ok ? s_deg : 0;
     prog_degree(a)[p] = deg > kNdeg ? kNdeg : deg;
   }
   if (!pd_ok || c >= P.n_cfg || c >= a.max_cfg) return;
@@ -205,9 +255,19 @@ collapse_kernel(EvalArgs a, int chunks) {
     double num[kNdeg + 1] = {0, 0, 0, 0}, den[kNdeg + 1] = {1, 0, 0, 0};
     float sc = 1.0f;
     if (fits_ok) {
-      const klr_fit_desc d = a.desc[P.fit0 + j];
-      collapse_poly(a.exps, d.num0, d.n_num, v, d.scale_exp, a.coef + d.coef0, false, L, num);
-      collapse_poly(a.exps, d.den0, d.n_den, v, d.scale_exp, a.coef + d.coef0 + d.n_num, true, L, den);
+      const klr_fit_desc& d = s_desc[j];
+      double Lt[KLR_MAX_LAUNCH];
+#pragma unroll
+      for (int k = 1; k <= KLR_MAX_LAUNCH; ++k)
+        Lt[k - 1] = k < v ? ldexp((double)L[k - 1], -(int)d.scale_exp[k]) : 1.0;
+      if (staged) {
+        const uint64_t* rows = s_rows + s_off[j];
+        collapse_poly<true>(rows, nullptr, 0, d.n_num, v, Lt, s_coef + s_off[j], false, num);
+        collapse_poly<true>(rows + d.n_num, nullptr, 0, d.n_den, v, Lt, s_coef + s_off[j] + d.n_num, true, den);
+      } else {
+        collapse_poly<false>(nullptr, a.exps, d.num0, d.n_num, v, Lt, a.coef + d.coef0, false, num);
+        collapse_poly<false>(nullptr, a.exps, d.den0, d.n_den, v, Lt, a.coef + d.coef0 + d.n_num, true, den);
+      }
       sc = ldexpf(1.0f, -(int)d.scale_exp[0]);
     }
     for (int e = 0; e <= kNdeg; ++e) {
