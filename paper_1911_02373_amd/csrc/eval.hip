@@ -130,28 +130,43 @@ template <bool STAGED>
 __device__ __forceinline__ void collapse_poly(const uint64_t* srows, const uint8_t* exps, int64_t row0, int nrows,
                                               int v, const double* Lt, const double* coef, bool den,
                                               double out[kNdeg + 1]) {
-  double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;
+  double o[kNdeg + 1] = {0.0, 0.0, 0.0, 0.0};
   static_assert(kNdeg == 3, "four powers of N~");
-  for (int t = 0; t < nrows; ++t) {
-    // the same row for every thread: its exponents go to scalar registers
-    const uint64_t w = STAGED ? srows[t] : exp_row(exps, row0 + t);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)w);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(w >> 32));
-    double mono = 1.0;
-    for (int k = 1; k < v; ++k) {
-      const int ek = (int)(((k < 4 ? lo >> (8 * k) : hi >> (8 * (k - 4)))) & 0xFFu);
-      for (int r = 0; r < ek; ++r) mono = mono * Lt[k - 1];
+  // rows in groups of 4: the group's exponent words and coefficients are loaded first; each row
+  // is the same for every thread, so its exponents go to scalar registers
+  for (int t0 = 0; t0 < nrows; t0 += 4) {
+    uint64_t w[4];
+    double cf[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u < nrows ? t0 + u : nrows - 1;
+      w[u] = STAGED ? srows[t] : exp_row(exps, row0 + t);
+      cf[u] = den ? (t == 0 ? 1.0 : coef[t > 0 ? t - 1 : 0]) : coef[t];
     }
-    const double c = den ? (t == 0 ? 1.0 : coef[t - 1]) : coef[t];
-    const double term = c * mono;
-    switch (lo & 0xFFu) {
-      case 0: o0 = o0 + term; break;
-      case 1: o1 = o1 + term; break;
-      case 2: o2 = o2 + term; break;
-      default: o3 = o3 + term; break;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (t0 + u < nrows) {
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)w[u]);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(w[u] >> 32));
+        double mono = 1.0;
+#pragma unroll
+        for (int k = 1; k <= KLR_MAX_LAUNCH; ++k) {
+          if (k < v) {
+            const int ek = (int)(((k < 4 ? lo >> (8 * k) : hi >> (8 * (k - 4)))) & 0xFFu);
+            for (int r = 0; r < ek; ++r) mono = mono * Lt[k - 1];
+          }
+        }
+        const double term = cf[u] * mono;
+        switch (lo & 0xFFu) {
+          case 0: o[0] = o[0] + term; break;
+          case 1: o[1] = o[1] + term; break;
+          case 2: o[2] = o[2] + term; break;
+          default: o[3] = o[3] + term; break;
+        }
+      }
     }
   }
-  out[0] = o0; out[1] = o1; out[2] = o2; out[3] = o3;
+  for (int e = 0; e <= kNdeg; ++e) out[e] = o[e];
 }
 
 // One workgroup per (program, block of configurations).  The program's eight fit descriptors
@@ -195,6 +210,7 @@ collapse_kernel(EvalArgs a, int chunks) {
   // coefficients staged in LDS when they fit
   const bool stage = fits_ok && s_staged;
   if (fits_ok) {
+    int emax = 0;
     for (int j = 0; j < KLR_N_METRICS; ++j) {
       const klr_fit_desc& d = s_desc[j];
       const int nr = d.n_num + d.n_den;
@@ -202,14 +218,15 @@ collapse_kernel(EvalArgs a, int chunks) {
         const int64_t row = t < d.n_num ? (int64_t)d.num0 + t : (int64_t)d.den0 + (t - d.n_num);
         const uint64_t w = exp_row(a.exps, row);
         const int e0 = (int)(w & 0xFFu);
-        if (e0 > kNdeg) atomicOr(&s_bad, 1);
-        atomicMax(&s_deg, e0);
+        emax = e0 > emax ? e0 : emax;
         if (stage) {
           s_rows[s_off[j] + t] = w;
           if (t < nr - 1) s_coef[s_off[j] + t] = a.coef[d.coef0 + t];
         }
       }
     }
+    if (emax > kNdeg) atomicOr(&s_bad, 1);
+    if (emax > 0) atomicMax(&s_deg, emax);
   }
   __syncthreads();
   fits_ok = fits_ok && s_bad == 0;
@@ -231,11 +248,14 @@ collapse_kernel(EvalArgs a, int chunks) {
   bool cfg_ok = true;
   int64_t T = 1;
   int32_t Lmax = 1;
-  for (int k = 0; k < P.v_launch; ++k) {
-    L[k] = a.cfgs[P.cfg0 + (int64_t)c * P.v_launch + k];
-    if (L[k] < 1) cfg_ok = false;
-    if (L[k] > Lmax) Lmax = L[k];
-    if (cfg_ok) { T *= L[k]; if (T > (int64_t)a.hw.t_max) cfg_ok = false; }
+#pragma unroll
+  for (int k = 0; k < KLR_MAX_LAUNCH; ++k) {
+    if (k < P.v_launch) {
+      L[k] = a.cfgs[P.cfg0 + (int64_t)c * P.v_launch + k];
+      if (L[k] < 1) cfg_ok = false;
+      if (L[k] > Lmax) Lmax = L[k];
+      if (cfg_ok) { T *= L[k]; if (T > (int64_t)a.hw.t_max) cfg_ok = false; }
+    }
   }
   if (cfg_ok && (T % a.hw.wave) != 0) cfg_ok = false;
   CfgRec r;
