@@ -303,19 +303,26 @@ def pow2_launch_tuples(v_launch: int, t_min: int = 64, t_max: int = 1024) -> np.
 
 def mixed_programs(seed: int, n_progs: int, n_q_range=(1, 700), n_cfg_range=(1, 160),
                    degree: int = 3, log2_range=(4.0, 26.0), v_launch_choices=(1, 2, 3, 4),
-                   p_2d: float = 0.3, p_bad_cfg: float = 0.05) -> ProgramBatch:
+                   p_2d: float = 0.3, p_bad_cfg: float = 0.05,
+                   launch_degree: int | None = None) -> ProgramBatch:
     """Uneven programs: v_launch from `v_launch_choices`, n_cfg and n_q uniform in the given
     ranges, metrics of total degree <= `degree` in (N/2^26, L_k/2^10) with the same lo + s*p/q
-    construction as config3_programs (s = (hi - lo) / (2 * #monomials)).  Configurations are
-    power-of-two tuples with product 64..1024 (the 2-parameter case uses the 127 config-3
-    tuples), plus a few random tuples that may be inadmissible.  Two-dimensional grids are
-    drawn with probability p_2d when v_launch >= 2."""
+    construction as config3_programs (s = (hi - lo) / (2 * #monomials)).  With
+    `launch_degree`, the monomials are instead N^a L^b with a <= `degree` and total launch degree
+    <= `launch_degree` (large monomial sets).  Configurations are power-of-two tuples with
+    product 64..1024 (the 2-parameter case uses the 127 config-3 tuples), plus a few random
+    tuples that may be inadmissible.  Two-dimensional grids are drawn with probability p_2d when
+    v_launch >= 2."""
     rng = np.random.default_rng(seed)
     vls = rng.choice(np.asarray(v_launch_choices), n_progs)
     exps_blocks, exps_index = [], {}
     row = 0
     for vl in sorted(set(int(x) for x in vls)):
-        E = monomials(1 + vl, degree)
+        if launch_degree is None:
+            E = monomials(1 + vl, degree)
+        else:
+            E = monomials(1 + vl, degree + launch_degree)
+            E = E[(E[:, 0] <= degree) & (E[:, 1:].sum(1) <= launch_degree)]
         exps_index[vl] = (row, E.shape[0])
         exps_blocks.append(E)
         row += E.shape[0]

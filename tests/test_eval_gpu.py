@@ -68,6 +68,21 @@ def test_mixed_uneven_programs_bit_exact(klr):
         off += int(pb.n_cfg[p]) * int(pb.n_q[p])
 
 
+def test_large_monomial_sets_bit_exact(klr):
+    """Metrics with 280 numerator and 280 denominator monomials (N^a L^b, a <= 3, launch degree
+    <= 4 over 4 launch parameters): more exponent rows than the collapse stages in LDS, so the
+    collapse reads them from device memory."""
+    pb = synth.mixed_programs(203, 4, n_q_range=(1, 200), n_cfg_range=(1, 48), v_launch_choices=(4,),
+                              launch_degree=4)
+    assert int(pb.n_num[0]) == 280
+    am, bc, costs, st = _run(klr, pb)
+    assert np.all(st == 0)
+    off = 0
+    for p in range(pb.n_progs):
+        _check_program_exact(pb, p, am, bc, costs, off)
+        off += int(pb.n_cfg[p]) * int(pb.n_q[p])
+
+
 def test_config3_full_size_sampled(klr):
     """1024 programs x 65536 queries x 128 configurations as timed; argmin and best cost of
     sampled queries against the oracle's replay."""
