@@ -94,6 +94,12 @@ def measured_traffic():
     return (fetch + write) * 1024.0
 
 
+# Surrogate training: 16384 samples per Adam step (one 64-sample tile per CU), peak learning rate
+# 6e-3 with the cosine schedule; 150 epochs over the 4.2 M samples.
+SURR_BATCH = 16384
+SURR_LR = 6e-3
+
+
 def surrogate_component(lib, klr, synth, pb, de, exact_ms, seed, epochs, regret_programs=64):
     """Learned surrogate beside the exact path on the same grid: train on 4.2M samples the
     exact program generates (32 queries x 128 configurations per program), select over the
@@ -108,7 +114,7 @@ def surrogate_component(lib, klr, synth, pb, de, exact_ms, seed, epochs, regret_
     blob = lib.surrogate_alloc(synth.mlp_init(seed, pb.n_progs), pb.n_progs)
     torch.cuda.synchronize()
     lib.profile_enable(True)
-    loss = lib.surrogate_train(blob, pb.n_progs, kid, N, L, cost, lr=2e-3, batch=4096, epochs=epochs,
+    loss = lib.surrogate_train(blob, pb.n_progs, kid, N, L, cost, lr=SURR_LR, batch=SURR_BATCH, epochs=epochs,
                                seed=seed)
     train_ms, _ = lib.profile_read(klr.K_MLP)
     lib.profile_enable(False)
@@ -138,7 +144,8 @@ def surrogate_component(lib, klr, synth, pb, de, exact_ms, seed, epochs, regret_
     torch.cuda.synchronize()
     nonfb = ~fb[: sub * nq][ok].cpu().numpy().astype(bool)
     total_ms = sel_ms + fb_ms + col_ms
-    return {"train_ms": train_ms, "epochs": epochs, "train_samples": int(tq.n_progs * 32 * 128),
+    return {"train_ms": train_ms, "epochs": epochs, "batch": SURR_BATCH, "lr": SURR_LR,
+            "train_samples": int(tq.n_progs * 32 * 128),
             "final_loss_std": float(loss[-1].cpu()), "select_ms": sel_ms, "fallback_ms": fb_ms,
             "collapse_ms": col_ms, "fallback_rate": fbr, "margin": 0.02,
             "speedup_vs_exact": exact_ms / total_ms,
@@ -244,7 +251,7 @@ def main() -> int:
     ap.add_argument("--kernel-only", choices=("eval", "fit", "copy", "large"), default=None,
                     help="run only this kernel --steps times (for hardware-counter runs); "
                          "'copy' is a plain 1 GiB device copy used to calibrate byte counters")
-    ap.add_argument("--surrogate-epochs", type=int, default=60)
+    ap.add_argument("--surrogate-epochs", type=int, default=150)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
