@@ -353,18 +353,22 @@ __device__ __forceinline__ void mono_rows(const Rows<RPL>& R, int e, double* mo)
 template <int MODE, int RPL>
 __device__ double row_pass(WaveLds& L, Rows<RPL>& R, int m, int n, int n_num, double gamma, double* qq, int* qneg) {
   const int lane = threadIdx.x & 63;
+  // lane j holds column j's exponents and coefficient; the column loops broadcast them by
+  // readlane instead of an LDS round trip per column
+  const int exv = lane < kNP ? L.ex[lane] : 0;
+  const double tv = lane < kNP ? L.t[lane] : 0.0;
   double pn[RPL], pd[RPL], mo[RPL];
 #pragma unroll
   for (int s = 0; s < RPL; ++s) pn[s] = pd[s] = 0.0;
   for (int j = 0; j < n_num; ++j) {
-    mono_rows(R, __builtin_amdgcn_readfirstlane(L.ex[j]), mo);
-    const double tj = L.t[j];
+    mono_rows(R, __builtin_amdgcn_readlane(exv, j), mo);
+    const double tj = readlane_d(tv, j);
 #pragma unroll
     for (int s = 0; s < RPL; ++s) pn[s] += mo[s] * tj;
   }
   for (int j = n_num; j < n; ++j) {
-    mono_rows(R, __builtin_amdgcn_readfirstlane(L.ex[j]), mo);
-    const double tj = L.t[j];
+    mono_rows(R, __builtin_amdgcn_readlane(exv, j), mo);
+    const double tj = readlane_d(tv, j);
 #pragma unroll
     for (int s = 0; s < RPL; ++s) pd[s] += mo[s] * tj;
   }
@@ -399,19 +403,30 @@ __device__ double row_pass(WaveLds& L, Rows<RPL>& R, int m, int n, int n_num, do
   double wf[RPL];
 #pragma unroll
   for (int s = 0; s < RPL; ++s) wf[s] = -R.f[s] * R.r[s];
-  for (int j = 0; j < n; ++j) {
-    mono_rows(R, __builtin_amdgcn_readfirstlane(L.ex[j]), mo);
-    double v = 0.0;
-    if (j < n_num) {
+  // column sums collected in lane j of gv (one wavefront sum per column, two columns per step
+  // so that their reductions overlap)
+  double gv = 0.0;
+  for (int j0 = 0; j0 < n; j0 += 2) {
+    double v2[2];
 #pragma unroll
-      for (int s = 0; s < RPL; ++s) v += mo[s] * R.r[s];
-    } else {
+    for (int u = 0; u < 2; ++u) {
+      const int j = j0 + u < n ? j0 + u : j0;
+      mono_rows(R, __builtin_amdgcn_readlane(exv, j), mo);
+      double v = 0.0;
+      if (j < n_num) {
 #pragma unroll
-      for (int s = 0; s < RPL; ++s) v += mo[s] * wf[s];
+        for (int s = 0; s < RPL; ++s) v += mo[s] * R.r[s];
+      } else {
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) v += mo[s] * wf[s];
+      }
+      v2[u] = v;
     }
-    v = wsum(v);
-    if (lane == 0) L.g[j] = v * L.D[j];
+    const double s0 = wsum(v2[0]), s1 = wsum(v2[1]);
+    if (lane == j0) gv = s0;
+    if (lane == j0 + 1) gv = s1;
   }
+  if (lane < n) L.g[lane] = gv * L.D[lane];
   wave_sync();
   return alpha;
 }
