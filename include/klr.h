@@ -112,8 +112,10 @@ size_t klr_fit_workspace(int32_t n_fits, int64_t f_len, int32_t precision);
 /* Fit n_fits independent rational functions (uneven m and monomial sets in one launch).
  *   desc[n_fits], exps[n_exp_rows][8] (uint8 exponent tuples), X[x_len] int32,
  *   f[f_len] float64, coef[coef_len] float64 (out), info[n_fits] (out).
- * Method (one workgroup per fit): the design matrix is built in LDS-staged row chunks from X
- * and f; the Gram matrix A^T A and A^T f are formed; columns are equilibrated by powers of two;
+ * Method (one wavefront per fit when n <= 48, v <= 4, m <= 1024 and every exponent <= 3, else
+ * one workgroup per fit): the design matrix is built from X and f (in registers or LDS-staged
+ * row chunks, never stored in device memory); the Gram matrix A^T A is formed on the matrix
+ * cores and A^T f in FP64; columns are equilibrated by powers of two;
  * the equilibrated Gram matrix, shifted by mu = 8 u tr/n (u = unit roundoff of the Gram
  * precision), is factored by diagonally pivoted Cholesky in FP64 (the numerical rank is the
  * count of pivots above 4 mu); the normal-equations solution is then refined by conjugate

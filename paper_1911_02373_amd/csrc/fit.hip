@@ -6,20 +6,23 @@
 // function p/q over given monomial sets, as a linear least-squares problem on a Vandermonde-like
 // design matrix (ill-conditioned, possibly rank deficient).
 //
-// One workgroup (4 waves) per fit, one launch per size class of the unknown count n (<= 32,
-// <= 64, <= 128); every workgroup of a launch reads its fit's descriptor and leaves at once when
-// the fit belongs to another class.  Per fit:
+// One workgroup (4 waves) per fit, one launch per size class of padded width 32, 64, 96, 112 or
+// 128 columns (the 96- and 112-column classes at two workgroups per CU); fits small enough for
+// one wavefront go to fit_wave.hip.  Persistent workgroups pop fits of their class from a
+// longest-first order; the plain schedule launches one workgroup per fit, and workgroups whose
+// fit belongs to another class leave at once.  Per fit:
 //   1. the design matrix is built in LDS in chunks of CH rows from the staged samples
-//      (x~ = x 2^-s exact in FP64; A_ij = x~^e_j, or -f_i x~^e_j for denominator columns);
-//   2. Gram G = A^T A (4x4 register blocks per thread; FP64, or FP32 / BF16-rounded inputs with
-//      FP32 accumulation) and c = A^T f in FP64;
+//      (x~ = x 2^-s exact in FP64; A_ij = x~^e_j, or -f_i x~^e_j for denominator columns), the
+//      next chunk's samples being loaded into registers meanwhile;
+//   2. Gram G = A^T A on MFMA (16-column tiles dealt to the waves as lower tile pairs; FP64, or
+//      FP32 / BF16-rounded inputs with FP32 accumulation) and c = A^T f in FP64;
 //   3. power-of-two column equilibration (exact), diagonal shift mu = 8 u tr/n;
-//   4. diagonally pivoted Cholesky in FP64 in LDS (packed symmetric storage addressed through the
-//      pivot permutation); rank = pivots above 4 mu;
+//   4. diagonally pivoted Cholesky in FP64 in LDS, kept in pivot order (rows and columns swapped
+//      in place); rank = pivots above 4 mu, the rest of the factor sqrt(mu) I;
 //   5. z0 = normal-equations solution, then CGLS on min || A D Pi R^-1 w - f ||, i.e. right-
-//      preconditioned by the factor, with the residual f - A D z recomputed and updated in FP64
-//      from the samples every iteration; stop when the delayed Hestenes-Stiefel estimate of
-//      ||A (y - y*)|| (error of the fitted linearised values) is <= tol ||f||;
+//      preconditioned by the factor, one sweep over the rows per iteration with the FP64
+//      residual of the samples kept in the workspace; stop when the delayed Hestenes-Stiefel
+//      estimate of ||A (y - y*)|| (error of the fitted linearised values) is <= tol ||f||;
 //   6. reduced-precision Gram paths that do not converge are redone with the FP64 Gram;
 //   7. epilogue: y = D z, ||f - A y||, count of samples with q(x~_i) <= 0, status.
 #include <hip/hip_runtime.h>

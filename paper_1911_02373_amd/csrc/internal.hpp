@@ -119,8 +119,6 @@ struct FitArgs {
 size_t fit_workspace_bytes(int32_t n_fits, int64_t f_len, int32_t precision);
 hipError_t launch_fit(const FitArgs& a);
 
-// Fits for one wavefront: n <= 48 unknowns, v <= 4 variables, 1 <= m <= 512 samples, valid
-// exponent rows with every exponent <= 3 (the Gram's power table holds x^0 .. x^3).
 // Rows per lane of the one-wavefront fit kernel for this fit: 8 (m <= 512) or 16 (m <= 1024)
 // when n <= 48, v <= 4 and every exponent is <= 3; 0 when the fit takes the workgroup kernel.
 __device__ inline int wave_fit_rows(const FitArgs& a, const klr_fit_desc& d) {
