@@ -95,7 +95,7 @@ def measured_traffic():
 
 
 # Surrogate training: 16384 samples per Adam step (one 64-sample tile per CU), peak learning rate
-# 6e-3 with the cosine schedule; 150 epochs over the 4.2 M samples.
+# 6e-3 with the cosine schedule; 300 epochs over the 4.2 M samples.
 SURR_BATCH = 16384
 SURR_LR = 6e-3
 
@@ -251,7 +251,7 @@ def main() -> int:
     ap.add_argument("--kernel-only", choices=("eval", "fit", "copy", "large"), default=None,
                     help="run only this kernel --steps times (for hardware-counter runs); "
                          "'copy' is a plain 1 GiB device copy used to calibrate byte counters")
-    ap.add_argument("--surrogate-epochs", type=int, default=150)
+    ap.add_argument("--surrogate-epochs", type=int, default=300)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

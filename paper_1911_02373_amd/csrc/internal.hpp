@@ -200,6 +200,28 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return pair_sum32(pair_sum16(group_sum<16>(v)));
 }
 
+// FP32 versions: sum over aligned groups of 16 lanes by DPP, and the pair sum of lanes l and
+// l ^ 16 by the lane-swap instruction (all lanes active).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float group16_sum_f(float v) {
+  v += dpp_f<kDppXor1>(v);
+  v += dpp_f<kDppXor2>(v);
+  v += dpp_f<kDppHalfMirror>(v);
+  v += dpp_f<kDppMirror>(v);
+  return v;
+}
+__device__ __forceinline__ float pair_sum16_f(float v) {
+  const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float((unsigned)s[0]) + __uint_as_float((unsigned)s[1]);
+}
+__device__ __forceinline__ float pair_sum32_f(float v) {
+  const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float((unsigned)s[0]) + __uint_as_float((unsigned)s[1]);
+}
+
 // Largest key over the 64 lanes, lowest index among equal keys (keys are never NaN); every
 // lane receives the same (key, index).  All lanes active.
 __device__ __forceinline__ void argmax_take(double& best, int& bi, double ob, int oi) {

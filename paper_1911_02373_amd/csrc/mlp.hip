@@ -15,10 +15,10 @@
 //                   gradients accumulated in 2^-44 fixed point with integer atomics (exact and
 //                   order independent, so results are deterministic)
 //   mlp_dw2_adam    dW2 = dA2^T h1 over the batch on v_mfma_f32_16x16x32_bf16 (one 16 x 16
-//                   output tile per workgroup, the batch split over its 4 waves and summed in a
+//                   output tile per workgroup, the batch split over its 16 waves and summed in a
 //                   fixed order), Adam on W2, refresh of W2b / W2Tb
-//   mlp_small_adam  fixed-order sum of the per-tile partials, Adam on W1, b1, b2, w3, b3 and
-//                   the embeddings, batch loss
+//   mlp_small_adam  fixed-order sum of the per-tile partials (8 lanes per parameter), Adam on
+//                   W1, b1, b2, w3, b3 and the embeddings, batch loss
 //   mlp_predict     forward pass for arbitrary samples
 //   mlp_select      surrogate selection over the (query x configuration) grid of a program
 //
@@ -143,11 +143,9 @@ __device__ __forceinline__ int acc_row(int rt, int r, int lane) {
   return rt * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
 }
 
-__device__ __forceinline__ float sum32(float v) {
-#pragma unroll
-  for (int off = 16; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
+// Sum over the 32 lanes of each half-wavefront (all lanes active): DPP within rows of 16, then
+// the lane-swap pair sum of rows 0 and 1 (2 and 3).
+__device__ __forceinline__ float sum32(float v) { return pair_sum16_f(group16_sum_f(v)); }
 
 // y[row] partial of this wave: sum over its columns of w3[j] relu(acc + b2[j]); written to
 // part[wave][row].
@@ -296,8 +294,8 @@ __global__ void __launch_bounds__(kBlock) mlp_fwd_bwd(TrainTile a, Blob w) {
       }
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
-      gw3[ct] += __shfl_xor(gw3[ct], 32);
-      gb2[ct] += __shfl_xor(gb2[ct], 32);
+      gw3[ct] = pair_sum32_f(gw3[ct]);
+      gb2[ct] = pair_sum32_f(gb2[ct]);
       if (lane < 32) {
         prt[kO_W3 - kO_W1 + jc[ct]] = gw3[ct];
         prt[kO_B2 - kO_W1 + jc[ct]] = gb2[ct];
@@ -346,8 +344,8 @@ __global__ void __launch_bounds__(kBlock) mlp_fwd_bwd(TrainTile a, Blob w) {
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) gw1[ct][f] += __shfl_xor(gw1[ct][f], 32);
-      gb1[ct] += __shfl_xor(gb1[ct], 32);
+      for (int f = 0; f < 4; ++f) gw1[ct][f] = pair_sum32_f(gw1[ct][f]);
+      gb1[ct] = pair_sum32_f(gb1[ct]);
       if (lane < 32) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) prt[4 * kc[ct] + f] = gw1[ct][f];
@@ -375,25 +373,47 @@ __global__ void __launch_bounds__(kBlock) mlp_fwd_bwd(TrainTile a, Blob w) {
   }
 }
 
-__global__ void __launch_bounds__(kBlock)
+// dW2 tile (16 x 16 outputs per workgroup) over the batch: the 32-sample chunks are dealt
+// round-robin to 16 waves (four chunks per round, loads issued before the products), then the
+// waves' partial tiles are summed in a fixed order and Adam is applied.
+constexpr int kDw2Waves = 16;
+__global__ void __launch_bounds__(64 * kDw2Waves)
 mlp_dw2_adam(const uint16_t* __restrict__ dH2T, const uint16_t* __restrict__ H1T, int32_t B, Blob w,
              AdamArgs ad, float* grads) {
-  __shared__ float red[4][16][16];
+  __shared__ float red[kDw2Waves][16][16];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int tj = blockIdx.x / (H / 16), tk = blockIdx.x % (H / 16);
-  const int per = B / 4;
-  const int sbeg = wv * per, send = sbeg + per;
   f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
   const int row = lane & 15, kh = 8 * (lane >> 4);
   const uint16_t* pa = dH2T + (int64_t)(16 * tj + row) * B + kh;
   const uint16_t* pb = H1T + (int64_t)(16 * tk + row) * B + kh;
-  for (int s = sbeg; s < send; s += 32)
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(pa + s), ld8(pb + s), acc, 0, 0, 0);
+  const int nch = B / 32;
+  int c = wv;
+  for (; c + 3 * kDw2Waves < nch; c += 4 * kDw2Waves) {
+    bf16x8 av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = ld8(pa + (int64_t)(c + u * kDw2Waves) * 32);
+      bv[u] = ld8(pb + (int64_t)(c + u * kDw2Waves) * 32);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[u], bv[u], acc, 0, 0, 0);
+  }
+  for (; c < nch; c += kDw2Waves)
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(pa + (int64_t)c * 32), ld8(pb + (int64_t)c * 32), acc, 0, 0, 0);
 #pragma unroll
   for (int r = 0; r < 4; ++r) red[wv][4 * (lane >> 4) + r][lane & 15] = acc[r];
   __syncthreads();
+  if (threadIdx.x >= 256) return;
   const int rr = threadIdx.x / 16, cc = threadIdx.x % 16;
-  const float g = (red[0][rr][cc] + red[1][rr][cc]) + (red[2][rr][cc] + red[3][rr][cc]);
+  float q[kDw2Waves / 2];
+#pragma unroll
+  for (int i = 0; i < kDw2Waves / 2; ++i) q[i] = red[2 * i][rr][cc] + red[2 * i + 1][rr][cc];
+#pragma unroll
+  for (int h = kDw2Waves / 4; h >= 1; h >>= 1)
+#pragma unroll
+    for (int i = 0; i < h; ++i) q[i] = q[2 * i] + q[2 * i + 1];
+  const float g = q[0];
   const int j = 16 * tj + rr, k = 16 * tk + cc;
   const int idx = kO_W2 + j * H + k;
   if (grads) grads[idx] = g;
@@ -408,21 +428,40 @@ mlp_dw2_adam(const uint16_t* __restrict__ dH2T, const uint16_t* __restrict__ H1T
   w.W2Tb[k * H + j] = u;
 }
 
+// Small parameters: eight consecutive lanes per parameter sum interleaved tiles (lane s takes
+// tiles s, s + 8, ...), then the eight partial sums are combined by DPP in a fixed order; the
+// embeddings' fixed-point sums take one lane each.
+constexpr int kSmallLanes = 8;
 __global__ void __launch_bounds__(kBlock)
 mlp_small_adam(const float* __restrict__ partial, int32_t ntiles, unsigned long long* emb_acc,
                int32_t nk, Blob w, AdamArgs ad, float* grads, float* loss_step, float* loss_epoch,
                float epoch_scale, int32_t B) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int nsmall = kO_B3 - kO_W1 + 1;
+  const int64_t nsum = (int64_t)(nsmall + 1) * kSmallLanes;    // the small parameters and the loss
   int idx = -1;
   float g = 0.0f;
-  if (i < nsmall) {
-    // fixed summation order over the tiles; unrolled so that the loads are in flight together
-#pragma unroll 16
-    for (int t = 0; t < ntiles; ++t) g += partial[(int64_t)t * kPartialStride + i];
-    idx = kO_W1 + i;
-  } else if (i - nsmall < nk) {
-    const int k = i - nsmall;
+  if (gt < nsum) {                     // whole groups of 8 lanes: the DPP moves stay inside a group
+    const int i = (int)(gt / kSmallLanes), sub = (int)(gt % kSmallLanes);
+    const int slot = i < nsmall ? i : kLossSlot;
+    float s = 0.0f;
+#pragma unroll 8
+    for (int t = sub; t < ntiles; t += kSmallLanes) s += partial[(int64_t)t * kPartialStride + slot];
+    s += dpp_f<kDppXor1>(s);
+    s += dpp_f<kDppXor2>(s);
+    s += dpp_f<kDppHalfMirror>(s);
+    if (sub == 0) {
+      if (i < nsmall) {
+        g = s;
+        idx = kO_W1 + i;
+      } else {
+        const float L = s / (float)B;
+        if (loss_step) *loss_step = L;
+        if (loss_epoch) *loss_epoch += L * epoch_scale;
+      }
+    }
+  } else if (gt - nsum < nk) {
+    const int k = (int)(gt - nsum);
     g = (float)((double)(long long)emb_acc[k] * 0x1p-44);
     emb_acc[k] = 0ull;
     idx = kO_EMB + k;
@@ -434,14 +473,6 @@ mlp_small_adam(const float* __restrict__ partial, int32_t ntiles, unsigned long 
     w.M[idx] = m;
     w.V[idx] = v;
     w.P[idx] = w.P[idx] - ad.lr * (m / ad.bc1) / (sqrtf(v / ad.bc2) + ad.eps);
-  }
-  if (i == 0) {
-    float L = 0.0f;
-#pragma unroll 16
-    for (int t = 0; t < ntiles; ++t) L += partial[(int64_t)t * kPartialStride + kLossSlot];
-    L /= (float)B;
-    if (loss_step) *loss_step = L;
-    if (loss_epoch) *loss_epoch += L * epoch_scale;
   }
 }
 
@@ -704,12 +735,12 @@ hipError_t launch_train_step(const TrainTile& t, const Blob& w, const AdamArgs& 
   hipLaunchKernelGGL(mlp_fwd_bwd, dim3(ntiles), dim3(kBlock), 0, s, t, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mlp_dw2_adam, dim3((H / 16) * (H / 16)), dim3(kBlock), 0, s, t.dH2T, t.H1T, t.B, w,
-                     ad, grads);
+  hipLaunchKernelGGL(mlp_dw2_adam, dim3((H / 16) * (H / 16)), dim3(64 * kDw2Waves), 0, s, t.dH2T, t.H1T, t.B,
+                     w, ad, grads);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nsmall = kO_B3 - kO_W1 + 1;
-  const int nthr = nsmall + t.nk;
+  const int64_t nthr = (int64_t)(nsmall + 1) * kSmallLanes + t.nk;
   hipLaunchKernelGGL(mlp_small_adam, dim3((nthr + kBlock - 1) / kBlock), dim3(kBlock), 0, s, t.partial,
                      ntiles, t.emb_acc, t.nk, w, ad, grads, loss_step, loss_epoch, epoch_scale, t.B);
   return hipGetLastError();
