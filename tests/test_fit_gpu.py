@@ -130,10 +130,10 @@ def test_refined_reduced_precision_within_1e5(klr, prec):
         assert np.linalg.norm(A @ (y - yo)) / np.linalg.norm(fi) <= 1e-7
 
 
-def test_size_classes_and_variables(klr):
-    """n in each launch class (padded widths 32, 64, 96, 112, 128 and the one-wavefront classes
-    with 8 and 16 rows per lane), v = 1..5, ragged chunks; the n = 119 case has denominator
-    exponents up to 4."""
+def _class_batch():
+    """Fits in every launch class (padded widths 32, 64, 96, 112, 128 and the one-wavefront
+    classes with 8 and 16 rows per lane), v = 1..5, ragged chunks; the n = 119 case has
+    denominator exponents up to 4."""
     rng = np.random.default_rng(3)
     samples, exps_rows, num0, nn, den0, nd, scales = [], [], [], [], [], [], []
     row = 0
@@ -158,7 +158,12 @@ def test_size_classes_and_variables(klr):
         row += En.shape[0] + Ed.shape[0]
         sc = np.zeros(8, np.int8); sc[:v] = 12
         scales.append(sc)
-    fb = synth._pack_fits(samples, np.concatenate(exps_rows), num0, nn, den0, nd, np.array(scales))
+    return synth._pack_fits(samples, np.concatenate(exps_rows), num0, nn, den0, nd, np.array(scales))
+
+
+def test_size_classes_and_variables(klr):
+    """FP64 fits in every launch class against the oracle."""
+    fb = _class_batch()
     ora, oinf = of.fit_batch(fb)
     cg, ig = _run(klr, fb)
     for i in range(fb.n_fits):
@@ -166,6 +171,22 @@ def test_size_classes_and_variables(klr):
         assert ig["status"][i] & of.BAD_INPUT == 0, i
         assert _values_rel_err(fb, i, y, yo) < 1e-8, i
         assert np.isclose(ig["resid_norm"][i], oinf[i]["resid_norm"], rtol=1e-7), i
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_refined_reduced_precision_every_class(klr, prec):
+    """FP32 / BF16 Gram (on the matrix cores of both kernels) + FP64-residual refinement in
+    every launch class: converged (or redone in FP64) with the fitted linearised values within
+    1e-7 ||f|| of the oracle's."""
+    fb = _class_batch()
+    ora, _ = of.fit_batch(fb)
+    cg, ig = _run(klr, fb, prec=prec, max_iter=256, tol=1e-8)
+    for i in range(fb.n_fits):
+        y, yo = _coefs(fb, cg, i), _coefs(fb, ora, i)
+        assert ig["status"][i] & (of.BAD_INPUT | of.NOT_CONVERGED) == 0, (i, int(ig["status"][i]))
+        Xi, fi, En, Ed, s = fb.fit_arrays(i)
+        A, _ = of.design_matrix(Xi, fi, En, Ed, s)
+        assert np.linalg.norm(A @ (y - yo)) / np.linalg.norm(fi) <= 1e-7, i
 
 
 def test_degenerate_inputs(klr):
@@ -202,11 +223,13 @@ def test_deterministic(klr):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_persistent_schedule_matches_plain(klr, prec):
+@pytest.mark.parametrize("batch", ["c2b_uneven", "every_class"])
+def test_persistent_schedule_matches_plain(klr, prec, batch):
     """The longest-first persistent schedule computes every fit exactly as the one-workgroup-
-    per-fit launch does (uneven m, all three size classes, invalid descriptors)."""
+    (or one-wavefront-) per-fit launch does: uneven m across both row classes of the wavefront
+    kernel with m < n cases, and a batch with a fit in every launch class."""
     from paper_1911_02373_amd.klr import OPT_FIT_PERSISTENT
-    fb = synth.config2_fits(21, 300, "2b", m_range=(20, 700))
+    fb = synth.config2_fits(21, 300, "2b", m_range=(20, 700)) if batch == "c2b_uneven" else _class_batch()
     try:
         klr.set_option(OPT_FIT_PERSISTENT, 0)
         a, ia = _run(klr, fb, prec=prec, tol=1e-9)
