@@ -98,6 +98,7 @@ def measured_traffic():
 # 6e-3 with the cosine schedule; 300 epochs over the 4.2 M samples.
 SURR_BATCH = 16384
 SURR_LR = 6e-3
+LARGE_SURR_QUERIES = 12       # training queries per program of the large batch
 
 
 def surrogate_component(lib, klr, synth, pb, de, exact_ms, seed, epochs, regret_programs=64):
@@ -157,7 +158,77 @@ def surrogate_component(lib, klr, synth, pb, de, exact_ms, seed, epochs, regret_
                                        "p99": float(np.quantile(r0, 0.99))}}
 
 
-def large_batch_component(lib, klr, synth, seed, replays=3):
+def large_surrogate(lib, klr, synth, pb, coef, seed, epochs, regret_programs=64):
+    """The surrogate beside the exact path on the large batch's programs with two launch
+    parameters (the network's inputs are N and one launch pair): trained on samples that the
+    fitted programs generate (12 fresh queries x every configuration per program), then selection
+    with the 2 % fallback over the programs' full query sets, the exact evaluation of the same
+    programs timed beside it, and the picks of `regret_programs` programs judged by exact costs."""
+    import numpy as np
+    import torch
+    idx = np.nonzero(pb.v_launch == 2)[0]
+    sub = synth.select_programs(pb, idx)
+    nk = sub.n_progs
+    tq = synth.surrogate_training_queries(seed + 3, sub, n_q=LARGE_SURR_QUERIES)
+    de_t = klr.DeviceEval.from_batch(lib, tq, with_costs=True, coef=coef)
+    _, _, costs, _ = lib.eval_argmin(de_t, want_costs=True)
+    kid, N, L, cost = klr.program_samples(tq, de_t, costs)
+    n_samples = int(kid.numel())
+    blob = lib.surrogate_alloc(synth.mlp_init(seed, nk), nk)
+    torch.cuda.synchronize()
+    lib.profile_enable(True)
+    lib.surrogate_train(blob, nk, kid, N, L, cost, lr=SURR_LR, batch=SURR_BATCH, epochs=epochs, seed=seed)
+    train_ms, _ = lib.profile_read(klr.K_MLP)
+    lib.profile_enable(False)
+    del de_t, costs, kid, N, L, cost
+    de = klr.DeviceEval.from_batch(lib, sub, coef=coef)
+    points = int((sub.n_cfg.astype(np.int64) * sub.n_q).sum())
+    ex = lib.eval_argmin(de)                                     # tunes the shape for this set
+    out = lib.surrogate_eval(blob, nk, de, margin=0.02)         # warm-up
+    torch.cuda.synchronize()
+    lib.profile_enable(True)
+    lib.eval_argmin(de, out=ex)
+    exact_ms, _ = lib.profile_read(klr.K_EVAL)
+    exact_col, _ = lib.profile_read(klr.K_COLLAPSE)
+    lib.profile_enable(False)
+    lib.profile_enable(True)
+    am, _, fb = lib.surrogate_eval(blob, nk, de, margin=0.02, out=out)
+    sel_ms, _ = lib.profile_read(klr.K_SURR)
+    fb_ms, _ = lib.profile_read(klr.K_FALLBACK)
+    col_ms, _ = lib.profile_read(klr.K_COLLAPSE)
+    lib.profile_enable(False)
+    # outputs are indexed by global query position; the subset's queries are its programs' ranges
+    qpos = np.concatenate([np.arange(int(sub.q0[p]), int(sub.q0[p]) + int(sub.n_q[p])) for p in range(nk)])
+    fbr = float(fb[torch.from_numpy(qpos).to(fb.device)].float().mean().cpu())
+    # exact costs of the first programs, per program [n_cfg][n_q] at the program_descs offsets
+    rsub = synth.select_programs(sub, np.arange(min(regret_programs, nk)))
+    dr = klr.DeviceEval.from_batch(lib, rsub, with_costs=True, coef=coef)
+    xa, xb, xc, _ = lib.eval_argmin(dr, want_costs=True)
+    ra, _, rf = lib.surrogate_eval(blob, nk, dr, margin=0.02)
+    torch.cuda.synchronize()
+    xa, xb, xc = xa.cpu().numpy(), xb.cpu().numpy(), xc.cpu().numpy()
+    ra, rf = ra.cpu().numpy(), rf.cpu().numpy().astype(bool)
+    regrets, nonfb = [], []
+    co = 0
+    for p in range(rsub.n_progs):
+        nc, nq, qo = int(rsub.n_cfg[p]), int(rsub.n_q[p]), int(rsub.q0[p])
+        C = xc[co: co + nc * nq].reshape(nc, nq)
+        for q in range(nq):
+            if xa[qo + q] >= 0 and ra[qo + q] >= 0:
+                regrets.append(C[ra[qo + q], q] / xb[qo + q] - 1.0)
+                nonfb.append(not rf[qo + q])
+        co += nc * nq
+    r, nonfb = np.asarray(regrets), np.asarray(nonfb)
+    return {"programs": int(nk), "points": points, "train_samples": n_samples, "epochs": epochs,
+            "train_ms": train_ms, "exact_ms": exact_ms + exact_col, "select_ms": sel_ms,
+            "fallback_ms": fb_ms, "collapse_ms": col_ms, "fallback_rate": fbr,
+            "speedup_vs_exact": (exact_ms + exact_col) / (sel_ms + fb_ms + col_ms),
+            "regret_programs": int(rsub.n_progs),
+            "regret_with_fallback": {"frac_le_1pct": float(np.mean(r <= 0.01)), "p50": float(np.median(r)),
+                                     "nonfallback_frac_le_1pct": float(np.mean(r[nonfb] <= 0.01)) if nonfb.any() else None}}
+
+
+def large_batch_component(lib, klr, synth, seed, replays=3, surrogate_epochs=0):
     """The large persistent batch beside the step: 16384 programs with uneven launch grids
     (32..512 configurations of 2-4 launch parameters), all 131072 metric fits (degree <= 3,
     64..1024 samples, FP64 to tol 1e-5) and the evaluation/argmin of 4096 queries per program
@@ -199,11 +270,16 @@ def large_batch_component(lib, klr, synth, seed, replays=3):
     lib.graph_destroy(g)
     ms = e0.elapsed_time(e1) / replays
     ir = klr.info_records(fit_out[1])
-    return {"programs": int(pb.n_progs), "fits": int(fb.n_fits), "fit_rows": int(fb.m.sum()),
-            "points": points, "generate_s": gen_s, "graph_ms": ms,
-            "fit_ms": fit_ms, "eval_ms": ev_ms, "collapse_ms": col_ms,
-            "fits_per_s": fb.n_fits / (fit_ms / 1e3), "evals_per_s": points / (ev_ms / 1e3),
-            "iters_mean": float(ir["iters"].mean()), "not_converged": float(np.mean((ir["status"] & 4) > 0))}
+    res = {"programs": int(pb.n_progs), "fits": int(fb.n_fits), "fit_rows": int(fb.m.sum()),
+           "points": points, "generate_s": gen_s, "graph_ms": ms,
+           "fit_ms": fit_ms, "eval_ms": ev_ms, "collapse_ms": col_ms,
+           "fits_per_s": fb.n_fits / (fit_ms / 1e3), "evals_per_s": points / (ev_ms / 1e3),
+           "iters_mean": float(ir["iters"].mean()), "not_converged": float(np.mean((ir["status"] & 4) > 0))}
+    if surrogate_epochs > 0:
+        del de, ev_out
+        res["surrogate_two_launch_params"] = large_surrogate(lib, klr, synth, pb, fit_out[0], seed,
+                                                             surrogate_epochs)
+    return res
 
 
 def cpu_baseline(pb, fb, budget_s: float, points: int, n_fits: int):
@@ -252,6 +328,7 @@ def main() -> int:
                     help="run only this kernel --steps times (for hardware-counter runs); "
                          "'copy' is a plain 1 GiB device copy used to calibrate byte counters")
     ap.add_argument("--surrogate-epochs", type=int, default=300)
+    ap.add_argument("--large-surrogate-epochs", type=int, default=150)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -391,9 +468,15 @@ def main() -> int:
     if not args.no_large_batch:
         del de, df
         torch.cuda.empty_cache()
-        comps["large_batch"] = lb = large_batch_component(lib, klr, synth, args.seed)
+        comps["large_batch"] = lb = large_batch_component(
+            lib, klr, synth, args.seed, surrogate_epochs=0 if args.no_surrogate else args.large_surrogate_epochs)
         log(f"large batch: {lb['fits']} fits + {lb['points']:.3e} points, graph {lb['graph_ms']:.1f} ms "
             f"(fit {lb['fit_ms']:.1f}, eval {lb['eval_ms']:.1f}); generated in {lb['generate_s']:.0f} s")
+        if "surrogate_two_launch_params" in lb:
+            ls = lb["surrogate_two_launch_params"]
+            log(f"large batch surrogate ({ls['programs']} programs): train {ls['train_ms']:.0f} ms, select + "
+                f"fallback {ls['select_ms'] + ls['fallback_ms']:.0f} ms vs exact {ls['exact_ms']:.1f} ms, fallback "
+                f"rate {ls['fallback_rate']:.3f}, within 1 % {ls['regret_with_fallback']['frac_le_1pct']:.3f}")
 
     res = {
         "metric": METRIC,

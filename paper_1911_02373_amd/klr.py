@@ -231,7 +231,9 @@ def eval_fit_descs(pb) -> np.ndarray:
     n = pb.num0.shape[0]
     d = np.zeros(n, FIT_DESC)
     d["coef0"], d["m"] = pb.coef0, 0
-    d["v"] = np.repeat(1 + pb.v_launch, N_METRICS)
+    # each program's eight fits take its variable count (fits no program refers to keep v = 0)
+    fit_idx = (np.asarray(pb.fit0, np.int64)[:, None] + np.arange(N_METRICS)).reshape(-1)
+    d["v"][fit_idx] = np.repeat(1 + np.asarray(pb.v_launch), N_METRICS)
     d["num0"], d["n_num"], d["den0"], d["n_den"] = pb.num0, pb.n_num, pb.den0, pb.n_den
     d["scale_exp"] = pb.scale_exp
     return d
@@ -491,6 +493,33 @@ def info_records(info) -> np.ndarray:
     """Info bytes (device tensor or host array) -> numpy structured array of klr_fit_info."""
     arr = info.cpu().numpy() if hasattr(info, "cpu") else np.asarray(info)
     return arr.view(np.uint8).view(FIT_INFO)
+
+
+def program_samples(pb, de: DeviceEval, costs):
+    """Training samples (kernel id = program index, N, launch pair, exact cost) of every
+    (program, configuration, query) point of a batch of two-launch-parameter programs with
+    uneven configuration and query counts, from its cost array (laid out per program as
+    [n_cfg][n_q] at the offsets program_descs assigns); device tensors, index bookkeeping only."""
+    torch = _torch()
+    if not np.all(pb.v_launch == 2):
+        raise ValueError("program_samples needs programs with two launch parameters")
+    dev = de.queries.device
+    nc = pb.n_cfg.astype(np.int64)
+    nq = pb.n_q.astype(np.int64)
+    sizes = nc * nq
+    total = int(sizes.sum())
+    cost0 = np.zeros(pb.n_progs, np.int64)
+    cost0[1:] = np.cumsum(sizes)[:-1]
+    prog = np.repeat(np.arange(pb.n_progs, dtype=np.int64), sizes)
+    local = np.arange(total, dtype=np.int64) - cost0[prog]
+    c = local // nq[prog]
+    q = local % nq[prog]
+    qi = torch.from_numpy(pb.q0.astype(np.int64)[prog] + q).to(dev)
+    ci = torch.from_numpy(pb.cfg0.astype(np.int64)[prog] + 2 * c).to(dev)
+    kid = torch.from_numpy(prog.astype(np.int32)).to(dev)
+    N = de.queries[qi]
+    L = torch.stack([de.cfgs[ci], de.cfgs[ci + 1]], dim=1).reshape(-1)
+    return kid.contiguous(), N.contiguous(), L.contiguous(), costs[:total].contiguous()
 
 
 def grid_samples(pb, de: DeviceEval, costs):

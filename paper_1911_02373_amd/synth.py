@@ -536,6 +536,17 @@ def surrogate_training_queries(seed: int, pb: "ProgramBatch", n_q: int = 32,
     return out
 
 
+def select_programs(pb: "ProgramBatch", idx) -> "ProgramBatch":
+    """The programs `idx` of a batch as a new batch over the same fits, coefficients,
+    configurations and queries (only the per-program arrays are subset)."""
+    import copy
+    idx = np.asarray(idx, np.int64)
+    out = copy.copy(pb)
+    out.v_launch, out.fit0, out.cfg0 = pb.v_launch[idx], pb.fit0[idx], pb.cfg0[idx]
+    out.n_cfg, out.grid_kind, out.q0, out.n_q = pb.n_cfg[idx], pb.grid_kind[idx], pb.q0[idx], pb.n_q[idx]
+    return out
+
+
 def take_programs(pb: "ProgramBatch", n: int) -> "ProgramBatch":
     """The first n programs of a batch (their fits, configurations and queries), re-based."""
     import copy

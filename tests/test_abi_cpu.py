@@ -49,3 +49,28 @@ def test_invariant_divisor_multiplication_exact(lib):
     """floor(n / d) by multiply-high and shift, for every divisor up to 70000 (block sizes and
     CU counts) on dividends around its multiples and at the top of [0, 2^31)."""
     assert lib.klr_selftest_divisors(70000) == 0
+
+
+def test_program_samples_bookkeeping():
+    """The (program, configuration, query) training samples of uneven two-launch-parameter
+    programs, against a brute-force listing of the same points (host tensors)."""
+    import numpy as np
+    import torch
+    from paper_1911_02373_amd import klr as K
+    from paper_1911_02373_amd import synth
+    _, pb = synth.config5_batch(3, n_progs=24, n_q=5)
+    sub = synth.select_programs(pb, np.nonzero(pb.v_launch == 2)[0])
+    tq = synth.surrogate_training_queries(4, sub, n_q=3)
+
+    class _DE:
+        queries = torch.from_numpy(tq.queries.astype(np.int32))
+        cfgs = torch.from_numpy(tq.cfgs.astype(np.int32))
+    n = int((tq.n_cfg.astype(np.int64) * tq.n_q).sum())
+    kid, N, L, c = K.program_samples(tq, _DE, torch.arange(n, dtype=torch.float32))
+    rows = [(p, tq.queries[tq.q0[p] + q], tq.cfgs[tq.cfg0[p] + 2 * ci], tq.cfgs[tq.cfg0[p] + 2 * ci + 1])
+            for p in range(tq.n_progs) for ci in range(int(tq.n_cfg[p])) for q in range(int(tq.n_q[p]))]
+    rows = np.array(rows)
+    assert tq.n_progs > 1 and len(set(tq.n_cfg.tolist())) > 1
+    assert np.array_equal(kid.numpy(), rows[:, 0]) and np.array_equal(N.numpy(), rows[:, 1])
+    assert np.array_equal(L.numpy().reshape(-1, 2), rows[:, 2:4])
+    assert np.array_equal(c.numpy(), np.arange(n, dtype=np.float32))
