@@ -213,3 +213,39 @@ def test_training_gain_over_untrained_network(klr, trained):
           f"within 1 %: trained {alone_t:.3f}, untrained {alone_0:.3f}")
     assert settled_0 > 0.5                      # the untrained net is (over)confident
     assert fb_t >= 0.8 and fb_t >= fb_0 + 0.3, (fb_t, fb_0)
+
+
+def test_uneven_programs_train_and_select(klr):
+    """Programs with two launch parameters but uneven configuration lists and query counts
+    (including configurations that are not admissible), trained from klr.program_samples; with
+    an infinite margin the selection equals the exact path bit for bit, with 2 % the fallback
+    queries equal it and the others pick one of their program's configurations.  Data sizes
+    N >= 2^10.5 keep at least two configurations statically admissible per query (with a
+    single candidate the margin is infinite and no query falls back)."""
+    import torch
+    from paper_1911_02373_amd.klr import DeviceEval, program_samples
+    pb = synth.mixed_programs(31, 12, n_q_range=(1, 300), n_cfg_range=(8, 127), v_launch_choices=(2,),
+                              log2_range=(10.5, 26.0))
+    tq = synth.surrogate_training_queries(32, pb, n_q=16)
+    de_t = DeviceEval.from_batch(klr, tq, with_costs=True)
+    _, _, costs, _ = klr.eval_argmin(de_t, want_costs=True)
+    kid, N, L, cost = program_samples(tq, de_t, costs)
+    blob = klr.surrogate_alloc(synth.mlp_init(5, pb.n_progs), pb.n_progs)
+    loss = klr.surrogate_train(blob, pb.n_progs, kid, N, L, cost, lr=2e-3, batch=1024, epochs=4, seed=5)
+    de = DeviceEval.from_batch(klr, pb)
+    ea, eb, _, _ = klr.eval_argmin(de)
+    am, pc, fb = klr.surrogate_eval(blob, pb.n_progs, de, margin=1e9)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(loss.cpu().numpy()))
+    ea, eb = ea.cpu().numpy(), eb.cpu().numpy()
+    assert np.all(fb.cpu().numpy() == 1)
+    assert np.array_equal(am.cpu().numpy(), ea)
+    assert np.array_equal(pc.cpu().numpy().view(np.uint32), eb.view(np.uint32))
+    am, pc, fb = klr.surrogate_eval(blob, pb.n_progs, de, margin=0.02)
+    torch.cuda.synchronize()
+    am, pc, fb = am.cpu().numpy(), pc.cpu().numpy(), fb.cpu().numpy().astype(bool)
+    assert np.array_equal(am[fb], ea[fb])
+    for p in range(pb.n_progs):
+        q = np.arange(int(pb.q0[p]), int(pb.q0[p]) + int(pb.n_q[p]))
+        own = q[~fb[q]]
+        assert np.all((am[own] >= 0) & (am[own] < int(pb.n_cfg[p])))
