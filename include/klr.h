@@ -42,7 +42,7 @@ typedef int32_t klr_status;
 #define KLR_E_INVALID (-1)      /* bad argument detected on the host; nothing launched */
 #define KLR_E_WORKSPACE (-2)    /* workspace too small; nothing launched */
 #define KLR_E_HIP (-3)          /* a HIP runtime call failed; see klr_last_error */
-#define KLR_E_UNSUPPORTED (-4)  /* valid request outside what this build implements */
+#define KLR_E_UNSUPPORTED (-4)  /* valid request outside what the library implements */
 
 #define KLR_MAX_VARS 8          /* variables per fit (data parameters first, then launch) */
 #define KLR_N_METRICS 8         /* fitted metrics per rational program */
