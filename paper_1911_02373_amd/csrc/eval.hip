@@ -290,12 +290,20 @@ collapse_kernel(EvalArgs a, int chunks) {
       }
       sc = ldexpf(1.0f, -(int)d.scale_exp[0]);
     }
-    for (int e = 0; e <= kNdeg; ++e) {
-      out[j * 2 * (kNdeg + 1) + e] = (float)num[e];
-      out[j * 2 * (kNdeg + 1) + (kNdeg + 1) + e] = (float)den[e];
+    for (int e = 0; e <= kNdeg; ++e) {        // (numerator, denominator) pairs by power
+      out[j * 2 * (kNdeg + 1) + 2 * e] = (float)num[e];
+      out[j * 2 * (kNdeg + 1) + 2 * e + 1] = (float)den[e];
     }
     out[KLR_N_METRICS * 2 * (kNdeg + 1) + j] = sc;
   }
+}
+
+// Two adjacent wave-uniform floats (8-byte aligned) copied into a vector register pair.
+__device__ __forceinline__ float2 vgpr_pair(const float* p) {
+  const uint64_t s = *reinterpret_cast<const uint64_t*>(p);
+  uint64_t v;
+  asm("v_mov_b64 %0, %1" : "=v"(v) : "s"(s));
+  return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
 }
 
 struct Hw32 {
@@ -311,26 +319,40 @@ Hw32 make_hw32(const klr_hw& h) {
   return w;
 }
 
+// Scaled query size per metric, x_j = N * 2^-s_j with s_j the scale exponent of metric j's fit.
+// The collapse kernel writes the same scales into every configuration slot of a program (a
+// program whose fits are invalid gets 1 and an inadmissible record in every slot), so the
+// products are formed once per query from the first slot and reused across configurations.
+__device__ __forceinline__ void scaled_n(int32_t N, const float* __restrict__ slot0, float* x) {
+  const float fN = (float)N;
+#pragma unroll
+  for (int j = 0; j < KLR_N_METRICS; ++j) x[j] = fN * slot0[KLR_N_METRICS * 2 * (kNdeg + 1) + j];
+}
+
 // Cost of one (query, configuration) point; +inf where inadmissible.  DEG: the program's highest
 // power of N~ (Horner from there; the normative sequence starts at power 3 with zero
 // coefficients above DEG, which gives bit-identical values because fma(0, x, a) = a exactly for
 // finite x and a != -0, and collapsed coefficients are sums that start from +0).
 template <int GRID, int DEG = kNdeg>
-__device__ __forceinline__ float point_cost(int32_t N, const float* __restrict__ cf, const CfgRec& r,
-                                            const Hw32& hw) {
+__device__ __forceinline__ float point_cost(int32_t N, const float* xs, const float* __restrict__ cf,
+                                            const CfgRec& r, const Hw32& hw) {
+  static_assert(DEG >= 1 && DEG <= kNdeg, "Horner degree");
   bool ok = (r.ok != 0) & (N >= r.Lmax);
-  const float fN = (float)N;
   float g[KLR_N_METRICS];
 #pragma unroll
   for (int j = 0; j < KLR_N_METRICS; ++j) {
-    const float* c = cf + j * 2 * (kNdeg + 1);
-    const float x = fN * cf[KLR_N_METRICS * 2 * (kNdeg + 1) + j];
-    float p = c[DEG];
-    float q = c[kNdeg + 1 + DEG];
+    const float* c = cf + j * 2 * (kNdeg + 1);     // c[2 d] numerator, c[2 d + 1] denominator
+    const float x = xs[j];
+    // First Horner step: both addends enter vector registers through one 64-bit move (the
+    // wave-uniform coefficients sit in scalar registers, and a VALU instruction reads at most
+    // one of them).
+    const float2 lo = vgpr_pair(c + 2 * (DEG - 1));
+    float p = __builtin_fmaf(c[2 * DEG], x, lo.x);
+    float q = __builtin_fmaf(c[2 * DEG + 1], x, lo.y);
 #pragma unroll
-    for (int d = DEG - 1; d >= 0; --d) {
-      p = __builtin_fmaf(p, x, c[d]);
-      q = __builtin_fmaf(q, x, c[kNdeg + 1 + d]);
+    for (int d = DEG - 2; d >= 0; --d) {
+      p = __builtin_fmaf(p, x, c[2 * d]);
+      q = __builtin_fmaf(q, x, c[2 * d + 1]);
     }
     const float v = p / q;
     const bool good = (q > 0.0f) & (fabsf(v) <= 3.402823466e38f);
@@ -431,9 +453,11 @@ __device__ __forceinline__ void sweep(const float* __restrict__ slot0, const Cfg
   float best = INFINITY;
   int32_t bi = -1;
   float* costs = o.all_costs ? o.all_costs + P.cost0 + qi : nullptr;
+  float xs[KLR_N_METRICS];
+  if (P.n_cfg > 0) scaled_n(N, slot0, xs);
   for (int c = 0; c < P.n_cfg; ++c) {
     const CfgRec r = rec0[c];
-    const float cost = point_cost<GRID>(N, slot0 + (int64_t)c * kSlotFloats, r, hw);
+    const float cost = point_cost<GRID>(N, xs, slot0 + (int64_t)c * kSlotFloats, r, hw);
     if (costs && live) costs[(int64_t)c * P.n_q] = cost;
     if (cost < best) { best = cost; bi = c; }
   }
@@ -448,12 +472,16 @@ __device__ __forceinline__ void sweep_cfgs(const klr_program& P, const float* __
                                            const CfgRec* __restrict__ rec0, const Hw32& hw,
                                            const int32_t* N, const bool* live, const int* qi,
                                            float* costs, float* best, int32_t* bi) {
+  if (P.n_cfg <= 0) return;
+  float xs[QPL][KLR_N_METRICS];
+#pragma unroll
+  for (int u = 0; u < QPL; ++u) scaled_n(N[u], slot0, xs[u]);
   for (int c = 0; c < P.n_cfg; ++c) {
     const CfgRec r = rec0[c];
     const float* cf = slot0 + (int64_t)c * kSlotFloats;
 #pragma unroll
     for (int u = 0; u < QPL; ++u) {
-      const float cost = point_cost<GRID, DEG>(N[u], cf, r, hw);
+      const float cost = point_cost<GRID, DEG>(N[u], xs[u], cf, r, hw);
       if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost;
       if (cost < best[u]) { best[u] = cost; bi[u] = c; }
     }

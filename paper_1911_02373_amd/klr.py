@@ -231,9 +231,13 @@ def eval_fit_descs(pb) -> np.ndarray:
     n = pb.num0.shape[0]
     d = np.zeros(n, FIT_DESC)
     d["coef0"], d["m"] = pb.coef0, 0
-    # each program's eight fits take its variable count (fits no program refers to keep v = 0)
-    fit_idx = (np.asarray(pb.fit0, np.int64)[:, None] + np.arange(N_METRICS)).reshape(-1)
-    d["v"][fit_idx] = np.repeat(1 + np.asarray(pb.v_launch), N_METRICS)
+    # each program's eight fits take its variable count (fits no program refers to keep v = 0;
+    # a program whose fit range lies outside the batch is left to the device check, which
+    # reports it as a bad descriptor)
+    fit0 = np.asarray(pb.fit0, np.int64)
+    inb = (fit0 >= 0) & (fit0 + N_METRICS <= n)
+    fit_idx = (fit0[inb][:, None] + np.arange(N_METRICS)).reshape(-1)
+    d["v"][fit_idx] = np.repeat(1 + np.asarray(pb.v_launch)[inb], N_METRICS)
     d["num0"], d["n_num"], d["den0"], d["n_den"] = pb.num0, pb.n_num, pb.den0, pb.n_den
     d["scale_exp"] = pb.scale_exp
     return d

@@ -74,3 +74,20 @@ def test_program_samples_bookkeeping():
     assert np.array_equal(kid.numpy(), rows[:, 0]) and np.array_equal(N.numpy(), rows[:, 1])
     assert np.array_equal(L.numpy().reshape(-1, 2), rows[:, 2:4])
     assert np.array_equal(c.numpy(), np.arange(n, dtype=np.float32))
+
+
+def test_eval_fit_descs_out_of_range_program():
+    """A program whose fit range lies outside the batch leaves the descriptors alone (the
+    device reports it as a bad descriptor); the other programs' fits take 1 + v_launch."""
+    import numpy as np
+    from paper_1911_02373_amd import synth
+    pb = synth.config3_programs(5, n_progs=4, n_q=16)
+    pb.fit0 = np.asarray(pb.fit0).copy()
+    pb.fit0[1] = 10 ** 6
+    pb.fit0[2] = -3
+    d = klr.eval_fit_descs(pb)
+    n = pb.num0.shape[0]
+    want = np.zeros(n, np.int64)
+    for p in (0, 3):
+        want[pb.fit0[p]:pb.fit0[p] + 8] = 1 + pb.v_launch[p]
+    assert np.array_equal(d["v"].astype(np.int64), want)
