@@ -36,11 +36,11 @@ constexpr int kSlotFloats = KLR_N_METRICS * 2 * (kNdeg + 1) + KLR_N_METRICS;   /
 constexpr int kEvalBlock = 256;
 constexpr int kCollapseBlock = 128;
 
-struct CfgRec {          // per (program, configuration) integer terms
+struct CfgRec {          // per (program, configuration) occupancy terms
   int32_t T;             // threads per block = prod L
-  int32_t Wb;            // waves per block = T / wave
-  int32_t bwarp;         // floor(wave * w_max / T)
-  int32_t rT;            // floor(r_max / T); floor(r_max / (R T)) = floor(rT / R)
+  float Wb;              // waves per block = T / wave (an integer, exact in FP32)
+  float Bcap;            // min(b_max, floor(wave * w_max / T)) (an integer below 2^11)
+  float rTh;             // floor(r_max / T) + 1/2; floor(r_max / (R T)) = floor(floor(r_max / T) / R)
   int32_t Lmax;          // largest launch parameter (admissible only if <= N)
   int32_t L0, L1;        // first two launch parameters (two-dimensional grid)
   int32_t ok;            // configuration admissible and the program's fits valid
@@ -66,15 +66,13 @@ __device__ __forceinline__ uint32_t udiv_magic(uint32_t n, uint32_t m, int32_t s
   return sh < 0 ? n : (__umulhi(n, m) >> sh);
 }
 
-// Exact floor(a / b) for 0 <= a < 2^20 and 1 <= b <= 2^24: the approximate reciprocal (relative
-// error <= 2^-23) and the rounded product put a b^-1 within a 2^-22 < 1/4 of a / b, so the
-// truncated estimate is off by at most one and one correction step each way makes it exact.
-__device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
-  uint32_t q = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
-  int32_t r = (int32_t)a - (int32_t)__umul24(q, b);
-  if (r < 0) { q -= 1u; r += (int32_t)b; }
-  if (r >= (int32_t)b) q += 1u;
-  return q;
+// Exact floor(a / b) for integers 0 <= a < 2^20 and 1 <= b <= 2^24, given ah = a + 1/2 (exact
+// in FP32).  With a = k b + j, 0 <= j < b, the quotient (a + 1/2) / b = k + (j + 1/2) / b lies at
+// least 1/(2b) from every integer.  The reciprocal is within one ulp (relative error <= 2^-23)
+// and the product adds at most 2^-24, so ah b^-1 is within ((a + 1/2) / b) 2^-22 < 1/(2b) of
+// the quotient and its floor is k.  b = +0 gives +inf.
+__device__ __forceinline__ float floor_div(float ah, float b) {
+  return floorf(ah * __builtin_amdgcn_rcpf(b));
 }
 
 __device__ __forceinline__ float sel_min(float a, float b) { return b < a ? b : a; }
@@ -260,9 +258,10 @@ collapse_kernel(EvalArgs a, int chunks) {
   if (cfg_ok && (T % a.hw.wave) != 0) cfg_ok = false;
   CfgRec r;
   r.T = cfg_ok ? (int32_t)T : a.hw.wave;
-  r.Wb = r.T / a.hw.wave;
-  r.bwarp = (a.hw.wave * a.hw.w_max) / r.T;
-  r.rT = a.hw.r_max / r.T;
+  const int32_t bwarp = (a.hw.wave * a.hw.w_max) / r.T;
+  r.Wb = (float)(r.T / a.hw.wave);
+  r.Bcap = (float)(a.hw.b_max < bwarp ? a.hw.b_max : bwarp);
+  r.rTh = (float)(a.hw.r_max / r.T) + 0.5f;
   r.Lmax = Lmax;
   r.L0 = L[0] < 1 ? 1 : L[0];
   r.L1 = L[1] < 1 ? 1 : L[1];
@@ -307,14 +306,16 @@ __device__ __forceinline__ float2 vgpr_pair(const float* p) {
 }
 
 struct Hw32 {
-  int32_t n_cu, wave, w_max, b_max, z_max;
+  int32_t n_cu;
+  float w_max;           // integers below 2^11, exact in FP32
+  float zh;              // z_max + 1/2 (z_max < 2^20)
   float lat, dep, iss, bw;
   uint32_t mag_ncu;
   int32_t sh_ncu;
 };
 
 Hw32 make_hw32(const klr_hw& h) {
-  Hw32 w{h.n_cu, h.wave, h.w_max, h.b_max, h.z_max, h.mem_lat, h.dep_delay, h.issue_cycles, h.bw, 0u, -1};
+  Hw32 w{h.n_cu, (float)h.w_max, (float)h.z_max + 0.5f, h.mem_lat, h.dep_delay, h.issue_cycles, h.bw, 0u, -1};
   magic_u31((uint32_t)h.n_cu, &w.mag_ncu, &w.sh_ncu);
   return w;
 }
@@ -364,36 +365,35 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
   const float Imu = sel_max(g[2], 0.0f);
   const float U = sel_max(g[3], 1.0f);
   const float Isync = sel_max(g[4], 0.0f);
-  const int32_t R = (int32_t)sel_min(sel_max(ceilf(g[5]), 1.0f), 16777216.0f);
-  const int32_t Z = (int32_t)sel_min(sel_max(ceilf(g[6]), 0.0f), 16777216.0f);
+  const float R = sel_min(sel_max(ceilf(g[5]), 1.0f), 16777216.0f);
+  const float Z = sel_min(sel_max(ceilf(g[6]), 0.0f), 16777216.0f);
   const float Bw = sel_max(g[7], 1.0f);
 
-  // occupancy: min(b_max, floor(wave w_max / T), floor(r_max / (R T)), floor(z_max / Z))
-  int32_t B = hw.b_max < r.bwarp ? hw.b_max : r.bwarp;
-  const int32_t breg = (int32_t)udiv_small((uint32_t)r.rT, (uint32_t)R);
-  B = breg < B ? breg : B;
-  const int32_t blds = Z > 0 ? (int32_t)udiv_small((uint32_t)hw.z_max, (uint32_t)Z) : hw.b_max;
-  B = blds < B ? blds : B;
-  ok = ok & (B >= 1);
-  const int32_t Bs = B >= 1 ? B : 1;
-  int32_t Nw = Bs * r.Wb;
-  Nw = Nw < hw.w_max ? Nw : hw.w_max;
+  // occupancy: min(b_max, floor(wave w_max / T), floor(r_max / (R T)), floor(z_max / Z)).  Every
+  // term is an integer held exactly in FP32 (the LDS term is +inf when Z = 0: no LDS bound), so
+  // the minima and the products below equal their integer counterparts.
+  const float breg = floor_div(r.rTh, R);
+  const float blds = floor_div(hw.zh, Z);
+  const float B = fminf(fminf(r.Bcap, breg), blds);
+  ok = ok & (B >= 1.0f);
+  const float Bf = fmaxf(B, 1.0f);
+  const float Nwf = fminf(Bf * r.Wb, hw.w_max);     // a product above 2^24 is above w_max too
   const int32_t Nc = N >= 1 ? N : 1;
   float repf;
   if (GRID == KLR_GRID_1D) {
     // rep = ceil(blocks / (B n_cu)) = ceil(ceil(blocks / n_cu) / B)
     const uint32_t bm1 = udiv_magic((uint32_t)(Nc - 1), r.magT, r.shT);        // blocks - 1
     const uint32_t cm1 = udiv_magic(bm1, hw.mag_ncu, hw.sh_ncu);               // ceil(blocks/n_cu) - 1
-    const uint32_t rm1 = cm1 < (1u << 20) ? udiv_small(cm1, (uint32_t)Bs) : cm1 / (uint32_t)Bs;
-    repf = (float)(rm1 + 1u);
+    if (cm1 < (1u << 20))
+      repf = floor_div((float)cm1 + 0.5f, Bf) + 1.0f;
+    else
+      repf = (float)(cm1 / (uint32_t)Bf + 1u);
   } else {
     const uint64_t blocks = (uint64_t)((uint32_t)(Nc - 1) / (uint32_t)r.L0 + 1u) *
                             (uint64_t)((uint32_t)(Nc - 1) / (uint32_t)r.L1 + 1u);
-    const uint64_t rep = (blocks - 1u) / (uint64_t)(Bs * hw.n_cu) + 1u;
+    const uint64_t rep = (blocks - 1u) / (uint64_t)((uint32_t)Bf * (uint32_t)hw.n_cu) + 1u;
     repf = (float)rep;
   }
-  const float Nwf = (float)Nw;
-  const float Bf = (float)Bs;
 
   const float Im = Imc + Imu;
   const float Lu = __builtin_fmaf(U - 1.0f, hw.dep, hw.lat);      // (U - 1) dep + lat

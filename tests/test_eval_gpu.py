@@ -122,6 +122,32 @@ def test_all_inadmissible_and_small_N(klr):
     assert np.all(am == -1) and np.all(np.isinf(bc)) and np.all(np.isinf(costs))
 
 
+@pytest.mark.parametrize("grid", [0, 1])
+@pytest.mark.parametrize("n_cu", [1, 3])
+def test_occupancy_edges_and_huge_block_counts(klr, grid, n_cu):
+    """Few compute units and N up to 2^31 - 1, so ceil(blocks / n_cu) reaches 2^25 on both sides
+    of the 2^20 switch of the repetition count; register and LDS terms at their clamps: R = 1,
+    fractional R, R past 2^24, Z = 0 (no LDS bound), Z = z_max, Z = z_max + 1 (no block fits)."""
+    base = [40.0, 6.0, 3.0, 2.0, 1.0, 1.0, 0.0, 64.0]
+    rows = []
+    for r_val, z_val in [(1.0, 0.0), (37.2, 0.0), (1e9, 0.0), (2.0, 163840.0), (2.0, 163841.0),
+                         (5.0, 4096.0), (64.0, 1.5), (2048.0, 0.0)]:
+        m = list(base)
+        m[5], m[6] = r_val, z_val
+        rows.append(m)
+    cfgs = [[64, 1], [128, 1], [1024, 1], [96, 2], [1, 64], [32, 32]]
+    big = [2 ** 31 - 1, 2 ** 30 + 7, 2 ** 25 + 3, 123456789, 64 * 2 ** 20, 64 * 2 ** 20 + 1,
+           64 * 2 ** 20 - 1, 3 * 64 * 2 ** 20 + 5, 1, 0, 64, 65]
+    pb = constant_programs(rows, cfgs, [big] * len(rows), grid_kind=grid, hw=synth.HW(n_cu=n_cu))
+    am, bc, costs, st = _run(klr, pb)
+    assert np.all(st == 0)
+    off = 0
+    for p in range(pb.n_progs):
+        _check_program_exact(pb, p, am, bc, costs, off)
+        off += int(pb.n_cfg[p]) * int(pb.n_q[p])
+    assert np.isfinite(costs).any() and np.isinf(costs).any()
+
+
 def test_bad_descriptors_reported_not_read(klr):
     pb = synth.config3_programs(5, n_progs=4, n_q=100)
     pb.fit0[1] = 10 ** 6               # fit range out of bounds: program skipped
