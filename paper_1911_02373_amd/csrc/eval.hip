@@ -84,6 +84,10 @@ __host__ __device__ inline int32_t* prog_degree(const EvalArgs& a) {
   return reinterpret_cast<int32_t*>(base + slots * (kSlotFloats * (int64_t)sizeof(float) + (int64_t)sizeof(CfgRec)));
 }
 __device__ __forceinline__ float sel_max(float a, float b) { return b > a ? b : a; }
+// sel_max(good ? v : +0, lo) for lo in {+0, 1}: a failed metric yields lo either way.
+__device__ __forceinline__ float clean_max(bool good, float v, float lo) {
+  return (good && !(lo > v)) ? v : lo;
+}
 
 __device__ bool program_desc_ok(const klr_program& P, const EvalArgs& a) {
   if (P.reserved != 0) return false;
@@ -340,6 +344,7 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
   static_assert(DEG >= 1 && DEG <= kNdeg, "Horner degree");
   bool ok = (r.ok != 0) & (N >= r.Lmax);
   float g[KLR_N_METRICS];
+  bool good[KLR_N_METRICS];
 #pragma unroll
   for (int j = 0; j < KLR_N_METRICS; ++j) {
     const float* c = cf + j * 2 * (kNdeg + 1);     // c[2 d] numerator, c[2 d + 1] denominator
@@ -355,25 +360,26 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
       p = __builtin_fmaf(p, x, c[2 * d]);
       q = __builtin_fmaf(q, x, c[2 * d + 1]);
     }
-    const float v = p / q;
-    const bool good = (q > 0.0f) & (fabsf(v) <= 3.402823466e38f);
-    ok = ok & good;
-    g[j] = good ? v : 0.0f;
+    g[j] = p / q;
+    good[j] = (q > 0.0f) & (fabsf(g[j]) <= 3.402823466e38f);
+    ok = ok & good[j];
   }
-  const float Icomp = sel_max(g[0], 0.0f);
-  const float Imc = sel_max(g[1], 0.0f);
-  const float Imu = sel_max(g[2], 0.0f);
-  const float U = sel_max(g[3], 1.0f);
-  const float Isync = sel_max(g[4], 0.0f);
-  const float R = sel_min(sel_max(ceilf(g[5]), 1.0f), 16777216.0f);
-  const float Z = sel_min(sel_max(ceilf(g[6]), 0.0f), 16777216.0f);
-  const float Bw = sel_max(g[7], 1.0f);
+  // A metric failing the check is cleaned to +0 before its clamp; clean_max takes both steps.
+  // The upper clamps of R (>= 1) and Z (>= -0) see no NaN, so fminf equals the compare-select.
+  const float Icomp = clean_max(good[0], g[0], 0.0f);
+  const float Imc = clean_max(good[1], g[1], 0.0f);
+  const float Imu = clean_max(good[2], g[2], 0.0f);
+  const float U = clean_max(good[3], g[3], 1.0f);
+  const float Isync = clean_max(good[4], g[4], 0.0f);
+  const float R = fminf(clean_max(good[5], ceilf(g[5]), 1.0f), 16777216.0f);
+  const float Z = fminf(clean_max(good[6], ceilf(g[6]), 0.0f), 16777216.0f);   // -0 for g in (-1, 0)
+  const float Bw = clean_max(good[7], g[7], 1.0f);
 
   // occupancy: min(b_max, floor(wave w_max / T), floor(r_max / (R T)), floor(z_max / Z)).  Every
   // term is an integer held exactly in FP32 (the LDS term is +inf when Z = 0: no LDS bound), so
   // the minima and the products below equal their integer counterparts.
   const float breg = floor_div(r.rTh, R);
-  const float blds = floor_div(hw.zh, Z);
+  const float blds = floor_div(hw.zh, fabsf(Z));   // Z = -0 counts as 0
   const float B = fminf(fminf(r.Bcap, breg), blds);
   ok = ok & (B >= 1.0f);
   const float Bf = fmaxf(B, 1.0f);

@@ -127,11 +127,13 @@ def test_all_inadmissible_and_small_N(klr):
 def test_occupancy_edges_and_huge_block_counts(klr, grid, n_cu):
     """Few compute units and N up to 2^31 - 1, so ceil(blocks / n_cu) reaches 2^25 on both sides
     of the 2^20 switch of the repetition count; register and LDS terms at their clamps: R = 1,
-    fractional R, R past 2^24, Z = 0 (no LDS bound), Z = z_max, Z = z_max + 1 (no block fits)."""
+    fractional R, R past 2^24, Z = 0 (no LDS bound), Z = z_max, Z = z_max + 1 (no block fits), and
+    R, Z in (-1, 0) and below (ceil gives -0: clamped to 1 and to no LDS bound)."""
     base = [40.0, 6.0, 3.0, 2.0, 1.0, 1.0, 0.0, 64.0]
     rows = []
     for r_val, z_val in [(1.0, 0.0), (37.2, 0.0), (1e9, 0.0), (2.0, 163840.0), (2.0, 163841.0),
-                         (5.0, 4096.0), (64.0, 1.5), (2048.0, 0.0)]:
+                         (5.0, 4096.0), (64.0, 1.5), (2048.0, 0.0), (2.0, -0.5), (-0.5, 7.0),
+                         (-3.0, -2.0)]:
         m = list(base)
         m[5], m[6] = r_val, z_val
         rows.append(m)
