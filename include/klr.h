@@ -326,6 +326,11 @@ klr_status klr_profile_read(klr_handle h, int32_t kind, double* total_ms, int64_
  * dividends around its multiples and at the ends of the range; returns the mismatch count. */
 int64_t klr_selftest_divisors(uint32_t d_max);
 
+/* [host] The same check for n_ds listed divisors of up to 64 bits (the evaluation divides by
+ * T * n_cu, up to 2^32; divisors >= 2^31 give the quotient 0); ds is a host array; a zero
+ * divisor counts as one mismatch.  Returns the mismatch count. */
+int64_t klr_selftest_divisor_list(const uint64_t* ds, int32_t n_ds);
+
 /* [host] ABI self-description for binding checks: writes up to n entries of
  * {sizeof(klr_fit_desc), sizeof(klr_fit_info), sizeof(klr_hw), sizeof(klr_program), ...}
  * and returns the number of entries available. */

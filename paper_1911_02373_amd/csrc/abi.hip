@@ -212,6 +212,10 @@ klr_status klr_profile_read(klr_handle h, int32_t kind, double* total_ms, int64_
 
 int64_t klr_selftest_divisors(uint32_t d_max) { return klr::selftest_divisors(d_max); }
 
+int64_t klr_selftest_divisor_list(const uint64_t* ds, int32_t n_ds) {
+  return ds == nullptr || n_ds < 0 ? -1 : klr::selftest_divisor_list(ds, n_ds);
+}
+
 int32_t klr_abi_layout(int64_t* out, int32_t n) {
   const int64_t v[] = {
       (int64_t)sizeof(klr_fit_desc), (int64_t)sizeof(klr_fit_info), (int64_t)sizeof(klr_hw),

@@ -44,8 +44,8 @@ struct CfgRec {          // per (program, configuration) occupancy terms
   int32_t Lmax;          // largest launch parameter (admissible only if <= N)
   int32_t L0, L1;        // first two launch parameters (two-dimensional grid)
   int32_t ok;            // configuration admissible and the program's fits valid
-  uint32_t magT;         // floor(n / T) = mulhi(n, magT) >> shT for 0 <= n < 2^31
-  int32_t shT;
+  uint32_t magTC;        // floor(n / (T n_cu)) = mulhi(n, magTC) >> shTC for 0 <= n < 2^31
+  int32_t shTC;
   int32_t pad[2];
 };
 
@@ -60,6 +60,13 @@ __host__ __device__ inline void magic_u31(uint32_t d, uint32_t* m, int32_t* sh) 
   const uint64_t p = (uint64_t)1 << (31 + l);
   *m = (uint32_t)((p + d - 1) / d);
   *sh = l - 1;
+}
+
+// The same for a divisor d >= 1 of up to 64 bits: every d >= 2^31 gives the quotient 0 for
+// 0 <= n < 2^31, which m = 0, sh = 0 encode.
+__host__ __device__ inline void magic_u31_wide(uint64_t d, uint32_t* m, int32_t* sh) {
+  if (d >= ((uint64_t)1 << 31)) { *m = 0u; *sh = 0; return; }
+  magic_u31((uint32_t)d, m, sh);
 }
 
 __device__ __forceinline__ uint32_t udiv_magic(uint32_t n, uint32_t m, int32_t sh) {
@@ -270,7 +277,7 @@ collapse_kernel(EvalArgs a, int chunks) {
   r.L0 = L[0] < 1 ? 1 : L[0];
   r.L1 = L[1] < 1 ? 1 : L[1];
   r.ok = (cfg_ok && fits_ok) ? 1 : 0;
-  magic_u31((uint32_t)r.T, &r.magT, &r.shT);
+  magic_u31_wide((uint64_t)r.T * (uint64_t)a.hw.n_cu, &r.magTC, &r.shTC);
   r.pad[0] = r.pad[1] = 0;
   *rec = r;
 
@@ -314,14 +321,10 @@ struct Hw32 {
   float w_max;           // integers below 2^11, exact in FP32
   float zh;              // z_max + 1/2 (z_max < 2^20)
   float lat, dep, iss, bw;
-  uint32_t mag_ncu;
-  int32_t sh_ncu;
 };
 
 Hw32 make_hw32(const klr_hw& h) {
-  Hw32 w{h.n_cu, (float)h.w_max, (float)h.z_max + 0.5f, h.mem_lat, h.dep_delay, h.issue_cycles, h.bw, 0u, -1};
-  magic_u31((uint32_t)h.n_cu, &w.mag_ncu, &w.sh_ncu);
-  return w;
+  return Hw32{h.n_cu, (float)h.w_max, (float)h.z_max + 0.5f, h.mem_lat, h.dep_delay, h.issue_cycles, h.bw};
 }
 
 // Scaled query size per metric, x_j = N * 2^-s_j with s_j the scale exponent of metric j's fit.
@@ -387,9 +390,9 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
   const int32_t Nc = N >= 1 ? N : 1;
   float repf;
   if (GRID == KLR_GRID_1D) {
-    // rep = ceil(blocks / (B n_cu)) = ceil(ceil(blocks / n_cu) / B)
-    const uint32_t bm1 = udiv_magic((uint32_t)(Nc - 1), r.magT, r.shT);        // blocks - 1
-    const uint32_t cm1 = udiv_magic(bm1, hw.mag_ncu, hw.sh_ncu);               // ceil(blocks/n_cu) - 1
+    // rep = ceil(blocks / (B n_cu)) = ceil(ceil(blocks / n_cu) / B), blocks = ceil(N / T);
+    // ceil(blocks / n_cu) - 1 = floor(floor((N - 1) / T) / n_cu) = floor((N - 1) / (T n_cu))
+    const uint32_t cm1 = udiv_magic((uint32_t)(Nc - 1), r.magTC, r.shTC);
     if (cm1 < (1u << 20))
       repf = floor_div((float)cm1 + 0.5f, Bf) + 1.0f;
     else
@@ -700,6 +703,32 @@ hipError_t launch_fallback(const EvalArgs& a, const uint8_t* flags, float* best_
 }
 
 int eval_num_variants() { return kNumVariants; }
+
+int64_t selftest_divisor_list(const uint64_t* ds, int32_t n_ds) {
+  // each listed divisor (up to 64 bits) against dividends at and around its multiples, small
+  // values and the top of the range, with the host form of the device arithmetic
+  int64_t bad = 0;
+  for (int32_t i = 0; i < n_ds; ++i) {
+    const uint64_t d = ds[i];
+    if (d == 0) { ++bad; continue; }
+    uint32_t m = 0;
+    int32_t sh = 0;
+    magic_u31_wide(d, &m, &sh);
+    auto chk = [&](uint64_t n) {
+      if (n >= (1ull << 31)) return;
+      const uint32_t q = sh < 0 ? (uint32_t)n : (uint32_t)((n * m) >> 32) >> sh;
+      if ((uint64_t)q != n / d) ++bad;
+    };
+    for (uint64_t n = 0; n < 4096; ++n) chk(n);
+    for (uint64_t k = 0; k < 64; ++k) chk((1ull << 31) - 1 - k);
+    for (uint64_t k = d; k < (1ull << 31); k = k * 3 + 7) {
+      chk(k / d * d);
+      chk(k / d * d - 1);
+      chk(k / d * d + d - 1);
+    }
+  }
+  return bad;
+}
 
 int64_t selftest_divisors(uint32_t d_max) {
   // every divisor 1..d_max against dividends at and around its multiples, small values and the

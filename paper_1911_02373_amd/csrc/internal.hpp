@@ -93,6 +93,7 @@ size_t eval_workspace_bytes(int32_t n_progs, int32_t max_cfg);
 hipError_t launch_eval(const EvalArgs& a);
 int eval_num_variants();
 int64_t selftest_divisors(uint32_t d_max);
+int64_t selftest_divisor_list(const uint64_t* ds, int32_t n_ds);
 
 // ---- fit ----------------------------------------------------------------------------------
 struct FitArgs {

@@ -39,7 +39,8 @@ EXPORTS = ("klr_create", "klr_destroy", "klr_last_error", "klr_fit_workspace", "
            "klr_surrogate_train_workspace", "klr_surrogate_train", "klr_surrogate_predict",
            "klr_surrogate_step", "klr_surrogate_eval_workspace", "klr_surrogate_eval",
            "klr_surrogate_init", "klr_set_option", "klr_capture_begin", "klr_capture_end",
-           "klr_graph_launch", "klr_graph_destroy", "klr_selftest_divisors")
+           "klr_graph_launch", "klr_graph_destroy", "klr_selftest_divisors",
+           "klr_selftest_divisor_list")
 OPT_FIT_PERSISTENT, OPT_EVAL_VARIANT = 0, 1
 K_COLLAPSE, K_EVAL, K_FIT_GRAM, K_FIT_SOLVE, K_MLP, K_SURR, K_FALLBACK = 0, 1, 2, 3, 4, 5, 6
 TRAIN_CFG = np.dtype([("lr", "<f4"), ("beta1", "<f4"), ("beta2", "<f4"), ("eps", "<f4"),
@@ -93,6 +94,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.klr_graph_destroy.restype = None
     lib.klr_selftest_divisors.argtypes = [ctypes.c_uint32]
     lib.klr_selftest_divisors.restype = I64
+    lib.klr_selftest_divisor_list.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.klr_selftest_divisor_list.restype = I64
     lib.klr_set_option.argtypes = [P, I32, I64]
     lib.klr_set_option.restype = I32
     lib.klr_surrogate_init.argtypes = [P, P, I32, P]

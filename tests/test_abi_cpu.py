@@ -51,6 +51,22 @@ def test_invariant_divisor_multiplication_exact(lib):
     assert lib.klr_selftest_divisors(70000) == 0
 
 
+def test_invariant_divisor_products_exact(lib):
+    """The one-step divisor of the repetition count, T * n_cu: every wave multiple T up to 65536
+    times CU counts from 1 to 65536 (products up to 2^32; from 2^31 on the quotient is 0), and
+    seeded random divisors below 2^31."""
+    import numpy as np
+    t = np.arange(32, 65537, 32, dtype=np.uint64)
+    cus = np.array([1, 2, 3, 7, 80, 104, 120, 228, 256, 304, 1000, 32768, 65535, 65536], np.uint64)
+    ds = np.unique(np.concatenate([(t[:, None] * cus[None, :]).reshape(-1),
+                                   np.random.default_rng(5).integers(1, 1 << 31, 4000, dtype=np.int64).astype(np.uint64),
+                                   np.array([(1 << 31) - 1, 1 << 31, (1 << 31) + 1, 1 << 32], np.uint64)]))
+    ds = np.ascontiguousarray(ds)
+    assert lib.klr_selftest_divisor_list(ds.ctypes.data, int(ds.size)) == 0
+    zero = np.zeros(1, np.uint64)
+    assert lib.klr_selftest_divisor_list(zero.ctypes.data, 1) == 1
+
+
 def test_program_samples_bookkeeping():
     """The (program, configuration, query) training samples of uneven two-launch-parameter
     programs, against a brute-force listing of the same points (host tensors)."""

@@ -123,9 +123,9 @@ def test_all_inadmissible_and_small_N(klr):
 
 
 @pytest.mark.parametrize("grid", [0, 1])
-@pytest.mark.parametrize("n_cu", [1, 3])
+@pytest.mark.parametrize("n_cu", [1, 3, 32768])
 def test_occupancy_edges_and_huge_block_counts(klr, grid, n_cu):
-    """Few compute units and N up to 2^31 - 1, so ceil(blocks / n_cu) reaches 2^25 on both sides
+    """Few compute units (and a 32768-CU machine with 65536-thread blocks) and N up to 2^31 - 1, so ceil(blocks / n_cu) reaches 2^25 on both sides
     of the 2^20 switch of the repetition count; register and LDS terms at their clamps: R = 1,
     fractional R, R past 2^24, Z = 0 (no LDS bound), Z = z_max, Z = z_max + 1 (no block fits), and
     R, Z in (-1, 0) and below (ceil gives -0: clamped to 1 and to no LDS bound)."""
@@ -137,10 +137,12 @@ def test_occupancy_edges_and_huge_block_counts(klr, grid, n_cu):
         m = list(base)
         m[5], m[6] = r_val, z_val
         rows.append(m)
-    cfgs = [[64, 1], [128, 1], [1024, 1], [96, 2], [1, 64], [32, 32]]
+    cfgs = [[64, 1], [128, 1], [1024, 1], [96, 2], [1, 64], [32, 32], [65536, 1], [256, 256]]
     big = [2 ** 31 - 1, 2 ** 30 + 7, 2 ** 25 + 3, 123456789, 64 * 2 ** 20, 64 * 2 ** 20 + 1,
            64 * 2 ** 20 - 1, 3 * 64 * 2 ** 20 + 5, 1, 0, 64, 65]
-    pb = constant_programs(rows, cfgs, [big] * len(rows), grid_kind=grid, hw=synth.HW(n_cu=n_cu))
+    # the 32768-CU machine admits 65536-thread blocks (T n_cu = 2^31: repetition quotient 0)
+    hw = synth.HW(n_cu=n_cu) if n_cu < 32768 else synth.HW(n_cu=n_cu, w_max=1024, t_max=65536)
+    pb = constant_programs(rows, cfgs, [big] * len(rows), grid_kind=grid, hw=hw)
     am, bc, costs, st = _run(klr, pb)
     assert np.all(st == 0)
     off = 0
