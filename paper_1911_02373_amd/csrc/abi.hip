@@ -352,7 +352,8 @@ size_t mlp_train_ws_bytes(int32_t nk, int32_t B) {
   const size_t t = (size_t)KLR_MLP_HIDDEN * B * sizeof(uint16_t);
   const size_t part = (size_t)(B / 64) * kPartialStride * sizeof(float);
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  return 2 * al(t) + al(part) + al((size_t)nk * 8) + 256;
+  const size_t dw2 = (size_t)kDw2Slices * KLR_MLP_HIDDEN * KLR_MLP_HIDDEN * sizeof(float);
+  return 2 * al(t) + al(part) + al((size_t)nk * 8) + al(dw2) + 256;
 }
 
 namespace {
@@ -365,7 +366,10 @@ TrainTile tile_args(void* ws, int32_t nk, int32_t B) {
   tt.H1T = reinterpret_cast<uint16_t*>(c);
   tt.dH2T = reinterpret_cast<uint16_t*>(c + al(t));
   tt.partial = reinterpret_cast<float*>(c + 2 * al(t));
-  tt.emb_acc = reinterpret_cast<unsigned long long*>(c + 2 * al(t) + al((size_t)(B / 64) * kPartialStride * 4));
+  const size_t emb_off = 2 * al(t) + al((size_t)(B / 64) * kPartialStride * 4);
+  tt.emb_acc = reinterpret_cast<unsigned long long*>(c + emb_off);
+  const size_t dw2_off = emb_off + al((size_t)nk * 8);
+  tt.dw2_part = reinterpret_cast<float*>(c + dw2_off);
   tt.B = B;
   tt.nk = nk;
   return tt;

@@ -357,7 +357,9 @@ struct TrainTile {
   uint16_t* dH2T;          // [256][B] bf16
   float* partial;          // [B / 64][kPartialStride]
   unsigned long long* emb_acc;   // [nk] fixed point 2^-44
+  float* dw2_part;         // [kDw2Slices][256][256] slice partials of dW2
 };
+constexpr int kDw2Slices = 16;
 size_t mlp_train_ws_bytes(int32_t nk, int32_t B);
 
 struct SelectArgs {

@@ -14,11 +14,12 @@
 //                   of the small parameters, h1^T and dA2^T to global memory for dW2, embedding
 //                   gradients accumulated in 2^-44 fixed point with integer atomics (exact and
 //                   order independent, so results are deterministic)
-//   mlp_dw2_adam    dW2 = dA2^T h1 over the batch on v_mfma_f32_16x16x32_bf16 (one 16 x 16
-//                   output tile per workgroup, the batch split over its 16 waves and summed in a
-//                   fixed order), Adam on W2, refresh of W2b / W2Tb
-//   mlp_small_adam  fixed-order sum of the per-tile partials (8 lanes per parameter), Adam on
-//                   W1, b1, b2, w3, b3 and the embeddings, batch loss
+//   mlp_dw2_part    dW2 = dA2^T h1 over the batch on v_mfma_f32_16x16x32_bf16: 64 x 64 output
+//                   tiles x 16 batch slices, one slice partial per workgroup
+//   mlp_small_adam  fixed-order sums of the 16 dW2 slice partials (one thread per W2 entry,
+//                   Adam on W2 and refresh of W2b / W2Tb) and of the per-tile partials of the
+//                   small parameters (8 lanes per parameter), Adam on W1, b1, b2, w3, b3 and
+//                   the embeddings, batch loss
 //   mlp_predict     forward pass for arbitrary samples
 //   mlp_select      surrogate selection over the (query x configuration) grid of a program
 //
@@ -373,59 +374,68 @@ __global__ void __launch_bounds__(kBlock) mlp_fwd_bwd(TrainTile a, Blob w) {
   }
 }
 
-// dW2 tile (16 x 16 outputs per workgroup) over the batch: the 32-sample chunks are dealt
-// round-robin to 16 waves (four chunks per round, loads issued before the products), then the
-// waves' partial tiles are summed in a fixed order and Adam is applied.
-constexpr int kDw2Waves = 16;
+// dW2 over the batch, first half: workgroup (tile, slice) forms the 64 x 64 output tile `tile`
+// over batch slice `slice` (one sixteenth of the 32-sample chunks; its four waves take the
+// chunks round-robin with the next chunk's operands loaded ahead, each wave the whole tile as
+// 4 x 4 MFMA blocks), sums the four wave partials in a fixed order and stores the slice
+// partial.  mlp_small_adam sums the 16 slice partials in a fixed order and applies Adam.
+constexpr int kDw2Tile = 64;
+constexpr int kDw2Waves = 4;
+constexpr int kDw2Tiles = (H / kDw2Tile) * (H / kDw2Tile);
 __global__ void __launch_bounds__(64 * kDw2Waves)
-mlp_dw2_adam(const uint16_t* __restrict__ dH2T, const uint16_t* __restrict__ H1T, int32_t B, Blob w,
-             AdamArgs ad, float* grads) {
-  __shared__ float red[kDw2Waves][16][16];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int tj = blockIdx.x / (H / 16), tk = blockIdx.x % (H / 16);
-  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+mlp_dw2_part(const uint16_t* __restrict__ dH2T, const uint16_t* __restrict__ H1T, int32_t B,
+             float* __restrict__ part) {
+  __shared__ float red[kDw2Waves][kDw2Tile][kDw2Tile];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
+  const int tile = blockIdx.x % kDw2Tiles, slice = blockIdx.x / kDw2Tiles;
+  const int tj = tile / (H / kDw2Tile), tk = tile % (H / kDw2Tile);
   const int row = lane & 15, kh = 8 * (lane >> 4);
-  const uint16_t* pa = dH2T + (int64_t)(16 * tj + row) * B + kh;
-  const uint16_t* pb = H1T + (int64_t)(16 * tk + row) * B + kh;
+  const uint16_t* pa = dH2T + (int64_t)(kDw2Tile * tj + row) * B + kh;
+  const uint16_t* pb = H1T + (int64_t)(kDw2Tile * tk + row) * B + kh;
   const int nch = B / 32;
-  int c = wv;
-  for (; c + 3 * kDw2Waves < nch; c += 4 * kDw2Waves) {
-    bf16x8 av[4], bv[4];
+  const int c_lo = (int)((int64_t)slice * nch / kDw2Slices), c_hi = (int)((int64_t)(slice + 1) * nch / kDw2Slices);
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  int c = c_lo + wv;
+  bf16x8 av[4], bv[4];
+  if (c < c_hi) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      av[u] = ld8(pa + (int64_t)(c + u * kDw2Waves) * 32);
-      bv[u] = ld8(pb + (int64_t)(c + u * kDw2Waves) * 32);
+      av[u] = ld8(pa + (int64_t)16 * u * B + (int64_t)c * 32);
+      bv[u] = ld8(pb + (int64_t)16 * u * B + (int64_t)c * 32);
+    }
+  }
+  for (; c < c_hi; c += kDw2Waves) {
+    bf16x8 an[4], bn[4];
+    const int cn = c + kDw2Waves < c_hi ? c + kDw2Waves : c;   // reload of c on the last chunk
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      an[u] = ld8(pa + (int64_t)16 * u * B + (int64_t)cn * 32);
+      bn[u] = ld8(pb + (int64_t)16 * u * B + (int64_t)cn * 32);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[u], bv[u], acc, 0, 0, 0);
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { av[u] = an[u]; bv[u] = bn[u]; }
   }
-  for (; c < nch; c += kDw2Waves)
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(pa + (int64_t)c * 32), ld8(pb + (int64_t)c * 32), acc, 0, 0, 0);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) red[wv][4 * (lane >> 4) + r][lane & 15] = acc[r];
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wv][16 * a + 4 * (lane >> 4) + r][16 * b + (lane & 15)] = acc[a][b][r];
   __syncthreads();
-  if (threadIdx.x >= 256) return;
-  const int rr = threadIdx.x / 16, cc = threadIdx.x % 16;
-  float q[kDw2Waves / 2];
-#pragma unroll
-  for (int i = 0; i < kDw2Waves / 2; ++i) q[i] = red[2 * i][rr][cc] + red[2 * i + 1][rr][cc];
-#pragma unroll
-  for (int h = kDw2Waves / 4; h >= 1; h >>= 1)
-#pragma unroll
-    for (int i = 0; i < h; ++i) q[i] = q[2 * i] + q[2 * i + 1];
-  const float g = q[0];
-  const int j = 16 * tj + rr, k = 16 * tk + cc;
-  const int idx = kO_W2 + j * H + k;
-  if (grads) grads[idx] = g;
-  const float m = ad.b1 * w.M[idx] + (1.0f - ad.b1) * g;
-  const float v = ad.b2 * w.V[idx] + (1.0f - ad.b2) * g * g;
-  w.M[idx] = m;
-  w.V[idx] = v;
-  const float p = w.P[idx] - ad.lr * (m / ad.bc1) / (sqrtf(v / ad.bc2) + ad.eps);
-  w.P[idx] = p;
-  const uint16_t u = f2bf(p);
-  w.W2b[j * H + k] = u;
-  w.W2Tb[k * H + j] = u;
+  float* myp = part + (int64_t)slice * H * H;
+  for (int e = tid; e < kDw2Tile * kDw2Tile; e += 64 * kDw2Waves) {
+    const int rr = e / kDw2Tile, cc = e % kDw2Tile;
+    myp[(kDw2Tile * tj + rr) * H + kDw2Tile * tk + cc] =
+        (red[0][rr][cc] + red[1][rr][cc]) + (red[2][rr][cc] + red[3][rr][cc]);
+  }
 }
 
 // Small parameters: eight consecutive lanes per parameter sum interleaved tiles (lane s takes
@@ -435,8 +445,33 @@ constexpr int kSmallLanes = 8;
 __global__ void __launch_bounds__(kBlock)
 mlp_small_adam(const float* __restrict__ partial, int32_t ntiles, unsigned long long* emb_acc,
                int32_t nk, Blob w, AdamArgs ad, float* grads, float* loss_step, float* loss_epoch,
-               float epoch_scale, int32_t B) {
-  const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+               float epoch_scale, int32_t B, const float* __restrict__ dw2_part) {
+  int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gt < H * H) {                    // W2: the 16 slice partials of dW2 in a fixed order
+    const int j = (int)(gt / H), k = (int)(gt % H);
+    float q[kDw2Slices / 2];
+#pragma unroll
+    for (int i = 0; i < kDw2Slices / 2; ++i)
+      q[i] = dw2_part[(int64_t)(2 * i) * H * H + gt] + dw2_part[(int64_t)(2 * i + 1) * H * H + gt];
+#pragma unroll
+    for (int h = kDw2Slices / 4; h >= 1; h >>= 1)
+#pragma unroll
+      for (int i = 0; i < h; ++i) q[i] = q[2 * i] + q[2 * i + 1];
+    const float g = q[0];
+    const int idx = kO_W2 + (int)gt;
+    if (grads) grads[idx] = g;
+    const float m = ad.b1 * w.M[idx] + (1.0f - ad.b1) * g;
+    const float v = ad.b2 * w.V[idx] + (1.0f - ad.b2) * g * g;
+    w.M[idx] = m;
+    w.V[idx] = v;
+    const float p = w.P[idx] - ad.lr * (m / ad.bc1) / (sqrtf(v / ad.bc2) + ad.eps);
+    w.P[idx] = p;
+    const uint16_t u = f2bf(p);
+    w.W2b[j * H + k] = u;
+    w.W2Tb[k * H + j] = u;
+    return;
+  }
+  gt -= H * H;                         // a multiple of the block size: groups of 8 stay aligned
   const int nsmall = kO_B3 - kO_W1 + 1;
   const int64_t nsum = (int64_t)(nsmall + 1) * kSmallLanes;    // the small parameters and the loss
   int idx = -1;
@@ -735,14 +770,15 @@ hipError_t launch_train_step(const TrainTile& t, const Blob& w, const AdamArgs& 
   hipLaunchKernelGGL(mlp_fwd_bwd, dim3(ntiles), dim3(kBlock), 0, s, t, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mlp_dw2_adam, dim3((H / 16) * (H / 16)), dim3(64 * kDw2Waves), 0, s, t.dH2T, t.H1T, t.B,
-                     w, ad, grads);
+  hipLaunchKernelGGL(mlp_dw2_part, dim3(kDw2Tiles * kDw2Slices), dim3(64 * kDw2Waves), 0, s, t.dH2T, t.H1T,
+                     t.B, t.dw2_part);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nsmall = kO_B3 - kO_W1 + 1;
-  const int64_t nthr = (int64_t)(nsmall + 1) * kSmallLanes + t.nk;
+  const int64_t nthr = (int64_t)H * H + (int64_t)(nsmall + 1) * kSmallLanes + t.nk;
   hipLaunchKernelGGL(mlp_small_adam, dim3((nthr + kBlock - 1) / kBlock), dim3(kBlock), 0, s, t.partial,
-                     ntiles, t.emb_acc, t.nk, w, ad, grads, loss_step, loss_epoch, epoch_scale, t.B);
+                     ntiles, t.emb_acc, t.nk, w, ad, grads, loss_step, loss_epoch, epoch_scale, t.B,
+                     t.dw2_part);
   return hipGetLastError();
 }
 
