@@ -266,9 +266,11 @@ klr_status klr_surrogate_step(klr_handle h, void* params, int32_t n_kernels,
  * program p uses embedding p (p < n_kernels).  For each query the network predicts ln C of
  * every statically admissible configuration (T <= t_max, T % wave == 0, every L <= N); the
  * pick is the lowest prediction (lowest index on ties).  If the predicted margin to the second
- * best is below ln(1 + margin), the query falls back to the exact rational program
- * (klr_eval_argmin semantics) and fell_back[q] = 1.  pred_cost[q] = exp(predicted ln C) of the
- * pick, or the exact cost on fallback.  Needs klr_surrogate_eval_workspace bytes. */
+ * best is below ln(1 + margin), or the exact cost of the pick is +inf (a configuration that the
+ * occupancy terms rule out: the network never sees those in training), the query falls back to
+ * the exact rational program (klr_eval_argmin semantics) and fell_back[q] = 1.
+ * pred_cost[q] = exp(predicted ln C) of the pick, or the exact cost on fallback.  Needs
+ * klr_surrogate_eval_workspace bytes. */
 size_t klr_surrogate_eval_workspace(int32_t n_progs, int32_t max_cfg, int64_t q_len);
 klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernels,
                               const klr_program* progs, int32_t n_progs, int32_t max_cfg,
@@ -316,7 +318,7 @@ void klr_graph_destroy(klr_graph g);
 #define KLR_K_FIT_SOLVE 3      /* fit: factorisation + refinement + epilogue                   */
 #define KLR_K_MLP 4            /* surrogate network training kernels                           */
 #define KLR_K_SURR 5           /* surrogate selection (forward over the query x config grid)   */
-#define KLR_K_FALLBACK 6       /* compaction + exact re-evaluation of low-margin queries       */
+#define KLR_K_FALLBACK 6       /* pick check, compaction, exact re-evaluation of flagged queries */
 #define KLR_K_COUNT 7
 klr_status klr_profile_enable(klr_handle h, int32_t on);   /* on != 0: enable; 0: disable+reset */
 klr_status klr_profile_read(klr_handle h, int32_t kind, double* total_ms, int64_t* launches);

@@ -341,7 +341,9 @@ __device__ __forceinline__ void scaled_n(int32_t N, const float* __restrict__ sl
 // power of N~ (Horner from there; the normative sequence starts at power 3 with zero
 // coefficients above DEG, which gives bit-identical values because fma(0, x, a) = a exactly for
 // finite x and a != -0, and collapsed coefficients are sums that start from +0).
-template <int GRID, int DEG = kNdeg>
+// UNI: cf and r are the same in every lane (the coefficients then sit in scalar registers); a
+// per-lane configuration takes plain vector loads.
+template <int GRID, int DEG = kNdeg, bool UNI = true>
 __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const float* __restrict__ cf,
                                             const CfgRec& r, const Hw32& hw) {
   static_assert(DEG >= 1 && DEG <= kNdeg, "Horner degree");
@@ -355,7 +357,7 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
     // First Horner step: both addends enter vector registers through one 64-bit move (the
     // wave-uniform coefficients sit in scalar registers, and a VALU instruction reads at most
     // one of them).
-    const float2 lo = vgpr_pair(c + 2 * (DEG - 1));
+    const float2 lo = UNI ? vgpr_pair(c + 2 * (DEG - 1)) : make_float2(c[2 * (DEG - 1)], c[2 * DEG - 1]);
     float p = __builtin_fmaf(c[2 * DEG], x, lo.x);
     float q = __builtin_fmaf(c[2 * DEG + 1], x, lo.y);
 #pragma unroll
@@ -566,6 +568,31 @@ hipError_t launch_sweep(int v, const EvalArgs& a, const Hw32& hw, const float* c
 }
 
 // ---- exact re-evaluation of flagged queries --------------------------------------------------
+// pick_check: one lane per query; a query the network answered (flag 0) is flagged when the
+// exact cost of its pick is +inf (the network never sees inadmissible configurations in training,
+// so its prediction for one carries no information).
+__global__ void __launch_bounds__(kEvalBlock)
+pick_check(EvalArgs a, Hw32 hw, const float* __restrict__ coefs, const CfgRec* __restrict__ recs,
+           const int32_t* __restrict__ picks, uint8_t* flags, int chunks) {
+  const int p = blockIdx.x / chunks;
+  const int qi = (blockIdx.x % chunks) * kEvalBlock + (int)threadIdx.x;
+  if (p >= a.n_progs) return;
+  const klr_program P = a.progs[p];
+  if (!program_desc_ok(P, a) || qi >= P.n_q || P.n_cfg <= 0) return;
+  const int64_t o = P.q0 + qi;
+  if (flags[o] != 0) return;
+  const int c = picks[o];
+  if (c < 0 || c >= P.n_cfg) { flags[o] = 1; return; }
+  const float* slot0 = coefs + (int64_t)p * a.max_cfg * kSlotFloats;
+  const int32_t N = a.queries[o];
+  float xs[KLR_N_METRICS];
+  scaled_n(N, slot0, xs);
+  const float cost = P.grid_kind == KLR_GRID_1D
+      ? point_cost<KLR_GRID_1D, kNdeg, false>(N, xs, slot0 + (int64_t)c * kSlotFloats, recs[(int64_t)p * a.max_cfg + c], hw)
+      : point_cost<KLR_GRID_2D, kNdeg, false>(N, xs, slot0 + (int64_t)c * kSlotFloats, recs[(int64_t)p * a.max_cfg + c], hw);
+  if (!(cost < INFINITY)) flags[o] = 1;
+}
+
 // fb_count: flagged queries per program; fb_scan: exclusive offsets of queries and of 256-query
 // chunks; fb_compact: order-preserving list of flagged query indices per program; fb_exact: one
 // workgroup per chunk, the exact sweep over the listed queries (all lanes of a workgroup belong
@@ -671,15 +698,28 @@ size_t fallback_ws_bytes(int32_t n_progs, int64_t q_len) {
   return ((size_t)3 * (n_progs > 0 ? n_progs : 0) + 64 + (size_t)(q_len > 0 ? q_len : 0)) * sizeof(int32_t);
 }
 
-hipError_t launch_fallback(const EvalArgs& a, const uint8_t* flags, float* best_cost, void* fws) {
+hipError_t launch_fallback(const EvalArgs& a, uint8_t* flags, float* best_cost, void* fws) {
   int32_t* cnt = reinterpret_cast<int32_t*>(fws);
   int32_t* off = cnt + a.n_progs;
   int32_t* choff = off + a.n_progs;
   int32_t* total = choff + a.n_progs;
   int32_t* list = total + 64;
   int t = a.timer ? a.timer->begin(KLR_K_FALLBACK, a.stream) : -1;
-  hipLaunchKernelGGL(fb_count, dim3((unsigned)a.n_progs), dim3(kEvalBlock), 0, a.stream, a, flags, cnt);
-  hipError_t e = hipGetLastError();
+  hipError_t e = hipSuccess;
+  if (a.max_q > 0) {
+    const Hw32 hw = make_hw32(a.hw);
+    const float* coefs = reinterpret_cast<const float*>(a.ws);
+    const CfgRec* recs = reinterpret_cast<const CfgRec*>(
+        reinterpret_cast<const char*>(a.ws) + (int64_t)a.n_progs * a.max_cfg * kSlotFloats * sizeof(float));
+    const int chunks = (a.max_q + kEvalBlock - 1) / kEvalBlock;
+    hipLaunchKernelGGL(pick_check, dim3((unsigned)a.n_progs * chunks), dim3(kEvalBlock), 0, a.stream, a, hw,
+                       coefs, recs, a.argmin, flags, chunks);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(fb_count, dim3((unsigned)a.n_progs), dim3(kEvalBlock), 0, a.stream, a, flags, cnt);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(fb_scan, dim3(1), dim3(64), 0, a.stream, a.n_progs, cnt, off, choff, total);
     e = hipGetLastError();

@@ -388,7 +388,7 @@ hipError_t launch_select(const SelectArgs& a, const Blob& w, hipStream_t s);
 // exact sweep over the compacted list); the collapse workspace must already hold the program
 // coefficients (launch_eval's collapse).  Workspace beyond eval_workspace_bytes:
 size_t fallback_ws_bytes(int32_t n_progs, int64_t q_len);
-hipError_t launch_fallback(const EvalArgs& a, const uint8_t* flags, float* best_cost, void* fws);
+hipError_t launch_fallback(const EvalArgs& a, uint8_t* flags, float* best_cost, void* fws);
 hipError_t launch_collapse_only(const EvalArgs& a);
 
 }  // namespace klr
