@@ -172,6 +172,7 @@ def test_selection_regret_small(klr, trained):
     nq = int(pb.n_q[0])
     picked = C[np.repeat(np.arange(pb.n_progs), nq), am, np.tile(np.arange(nq), pb.n_progs)]
     ok = ea >= 0
+    assert np.all(np.isfinite(picked[ok & ~fb.cpu().numpy().astype(bool)]))
     regret = picked[ok].astype(np.float64) / eb[ok] - 1.0
     assert np.all(regret >= 0)
     assert np.median(regret) < 0.01
@@ -245,7 +246,17 @@ def test_uneven_programs_train_and_select(klr):
     torch.cuda.synchronize()
     am, pc, fb = am.cpu().numpy(), pc.cpu().numpy(), fb.cpu().numpy().astype(bool)
     assert np.array_equal(am[fb], ea[fb])
+    # every pick the network keeps has a finite exact cost (an inadmissible pick falls back)
+    dc = DeviceEval.from_batch(klr, pb, with_costs=True)
+    _, _, xc, _ = klr.eval_argmin(dc, want_costs=True)
+    torch.cuda.synchronize()
+    xc = xc.cpu().numpy()
+    co = 0
     for p in range(pb.n_progs):
-        q = np.arange(int(pb.q0[p]), int(pb.q0[p]) + int(pb.n_q[p]))
+        nc, nq, q0 = int(pb.n_cfg[p]), int(pb.n_q[p]), int(pb.q0[p])
+        q = np.arange(q0, q0 + nq)
         own = q[~fb[q]]
-        assert np.all((am[own] >= 0) & (am[own] < int(pb.n_cfg[p])))
+        assert np.all((am[own] >= 0) & (am[own] < nc))
+        Cp = xc[co: co + nc * nq].reshape(nc, nq)
+        assert np.all(np.isfinite(Cp[am[own], own - q0])), p
+        co += nc * nq
