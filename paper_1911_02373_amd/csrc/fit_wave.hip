@@ -328,17 +328,17 @@ __device__ __forceinline__ double dotw(const double* a, const double* b, int n) 
   return wsum(lane < n ? a[lane] * b[lane] : 0.0);
 }
 
-// Monomial x~^e of column e (packed exponents, wave-uniform) for each of the lane's rows.
-template <int RPL>
+// Monomial x~^e of column e (packed exponents, wave-uniform) for the lane's first NS rows.
+template <int NS, int RPL>
 __device__ __forceinline__ void mono_rows(const Rows<RPL>& R, int e, double* mo) {
 #pragma unroll
-  for (int s = 0; s < RPL; ++s) mo[s] = 1.0;
+  for (int s = 0; s < NS; ++s) mo[s] = 1.0;
 #pragma unroll
   for (int k = 0; k < kV; ++k) {
     const int ek = (e >> (8 * k)) & 0xFF;
     for (int q = 0; q < ek; ++q)
 #pragma unroll
-      for (int s = 0; s < RPL; ++s) mo[s] *= R.x[s][k];
+      for (int s = 0; s < NS; ++s) mo[s] *= R.x[s][k];
   }
 }
 
@@ -348,35 +348,37 @@ __device__ __forceinline__ void mono_rows(const Rows<RPL>& R, int e, double* mo)
 //   mode 1: d is the CGLS image q = A D dz: *qq = ||q||^2, alpha = gamma / ||q||^2, the FP64
 //           residual is updated in place (r -= alpha q) and g = D A^T r from the updated residual;
 //   mode 2: returns ||f - d||^2 and counts q(x~_i) = 1 + s_i <= 0 into *qneg.
-// Column exponents are read into scalar registers, so the monomial loops are uniform.
+// Column exponents are read into scalar registers, so the monomial loops are uniform.  Only the
+// lane's first NS row slots are visited (m <= 64 NS: the others hold no sample).
 // Returns alpha in mode 1.
-template <int MODE, int RPL>
-__device__ double row_pass(WaveLds& L, Rows<RPL>& R, int m, int n, int n_num, double gamma, double* qq, int* qneg) {
+template <int MODE, int RPL, int NS>
+__device__ double row_pass_ns(WaveLds& L, Rows<RPL>& R, int m, int n, int n_num, double gamma, double* qq,
+                              int* qneg) {
   const int lane = threadIdx.x & 63;
   // lane j holds column j's exponents and coefficient; the column loops broadcast them by
   // readlane instead of an LDS round trip per column
   const int exv = lane < kNP ? L.ex[lane] : 0;
   const double tv = lane < kNP ? L.t[lane] : 0.0;
-  double pn[RPL], pd[RPL], mo[RPL];
+  double pn[NS], pd[NS], mo[NS];
 #pragma unroll
-  for (int s = 0; s < RPL; ++s) pn[s] = pd[s] = 0.0;
+  for (int s = 0; s < NS; ++s) pn[s] = pd[s] = 0.0;
   for (int j = 0; j < n_num; ++j) {
-    mono_rows(R, __builtin_amdgcn_readlane(exv, j), mo);
+    mono_rows<NS>(R, __builtin_amdgcn_readlane(exv, j), mo);
     const double tj = readlane_d(tv, j);
 #pragma unroll
-    for (int s = 0; s < RPL; ++s) pn[s] += mo[s] * tj;
+    for (int s = 0; s < NS; ++s) pn[s] += mo[s] * tj;
   }
   for (int j = n_num; j < n; ++j) {
-    mono_rows(R, __builtin_amdgcn_readlane(exv, j), mo);
+    mono_rows<NS>(R, __builtin_amdgcn_readlane(exv, j), mo);
     const double tj = readlane_d(tv, j);
 #pragma unroll
-    for (int s = 0; s < RPL; ++s) pd[s] += mo[s] * tj;
+    for (int s = 0; s < NS; ++s) pd[s] += mo[s] * tj;
   }
   double sq = 0.0;
   int qn = 0;
-  double d[RPL];
+  double d[NS];
 #pragma unroll
-  for (int s = 0; s < RPL; ++s) {
+  for (int s = 0; s < NS; ++s) {
     const bool live = lane + 64 * s < m;
     d[s] = live ? pn[s] - R.f[s] * pd[s] : 0.0;
     if (MODE == 0 && live) R.r[s] = R.f[s] - d[s];
@@ -397,12 +399,12 @@ __device__ double row_pass(WaveLds& L, Rows<RPL>& R, int m, int n, int n_num, do
     *qq = qn2;
     alpha = qn2 > 0.0 ? gamma / qn2 : 0.0;
 #pragma unroll
-    for (int s = 0; s < RPL; ++s) R.r[s] -= alpha * d[s];
+    for (int s = 0; s < NS; ++s) R.r[s] -= alpha * d[s];
   }
   // g_j = D_j sum_i A_ij r_i: numerator columns weigh r_i, denominator columns -f_i r_i
-  double wf[RPL];
+  double wf[NS];
 #pragma unroll
-  for (int s = 0; s < RPL; ++s) wf[s] = -R.f[s] * R.r[s];
+  for (int s = 0; s < NS; ++s) wf[s] = -R.f[s] * R.r[s];
   // column sums collected in lane j of gv (one wavefront sum per column, two columns per step
   // so that their reductions overlap)
   double gv = 0.0;
@@ -411,14 +413,14 @@ __device__ double row_pass(WaveLds& L, Rows<RPL>& R, int m, int n, int n_num, do
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int j = j0 + u < n ? j0 + u : j0;
-      mono_rows(R, __builtin_amdgcn_readlane(exv, j), mo);
+      mono_rows<NS>(R, __builtin_amdgcn_readlane(exv, j), mo);
       double v = 0.0;
       if (j < n_num) {
 #pragma unroll
-        for (int s = 0; s < RPL; ++s) v += mo[s] * R.r[s];
+        for (int s = 0; s < NS; ++s) v += mo[s] * R.r[s];
       } else {
 #pragma unroll
-        for (int s = 0; s < RPL; ++s) v += mo[s] * wf[s];
+        for (int s = 0; s < NS; ++s) v += mo[s] * wf[s];
       }
       v2[u] = v;
     }
@@ -429,6 +431,20 @@ __device__ double row_pass(WaveLds& L, Rows<RPL>& R, int m, int n, int n_num, do
   if (lane < n) L.g[lane] = gv * L.D[lane];
   wave_sync();
   return alpha;
+}
+
+// row_pass_ns for the smallest listed slot count that covers the fit's m rows (wave-uniform):
+// 2, 4 or 8 slots with 8 rows per lane; 12 or 16 with 16 rows per lane (its fits have m > 512).
+template <int MODE, int RPL>
+__device__ __forceinline__ double row_pass(WaveLds& L, Rows<RPL>& R, int m, int n, int n_num, double gamma,
+                                           double* qq, int* qneg) {
+  if constexpr (RPL == 8) {
+    if (m <= 128) return row_pass_ns<MODE, RPL, 2>(L, R, m, n, n_num, gamma, qq, qneg);
+    if (m <= 256) return row_pass_ns<MODE, RPL, 4>(L, R, m, n, n_num, gamma, qq, qneg);
+  } else {
+    if (m <= 768) return row_pass_ns<MODE, RPL, 12>(L, R, m, n, n_num, gamma, qq, qneg);
+  }
+  return row_pass_ns<MODE, RPL, RPL>(L, R, m, n, n_num, gamma, qq, qneg);
 }
 
 template <int PREC, int RPL>
