@@ -260,3 +260,28 @@ def test_uneven_programs_train_and_select(klr):
         Cp = xc[co: co + nc * nq].reshape(nc, nq)
         assert np.all(np.isfinite(Cp[am[own], own - q0])), p
         co += nc * nq
+
+
+def test_pick_check_sends_inadmissible_picks_to_the_exact_path(klr):
+    """With sigma = 0 every prediction is equal, so the network's pick is the first statically
+    admissible configuration; that one (512 threads at R = 300 registers per thread) leaves no
+    block resident, so its exact cost is +inf.  With margin 0 the margin rule never fires, so
+    only the pick check can send a query to the exact path: every query falls back and the
+    result equals the exact path bit for bit."""
+    import torch
+    from paper_1911_02373_amd.klr import DeviceEval
+    from tests.helpers import constant_programs
+    rows = [[40.0, 6.0, 3.0, 2.0, 1.0, 300.0, 0.0, 64.0]] * 3
+    cfgs = [[512, 1], [1024, 1], [64, 1], [128, 1], [32, 8]]
+    pb = constant_programs(rows, cfgs, [[1024, 4096, 65536, 1 << 20]] * 3)
+    nk = pb.n_progs
+    blob = klr.surrogate_alloc(synth.mlp_init(9, nk), nk, mu=0.0, sigma=0.0)
+    de = DeviceEval.from_batch(klr, pb)
+    ea, eb, _, _ = klr.eval_argmin(de)
+    am, pc, fb = klr.surrogate_eval(blob, nk, de, margin=0.0)
+    torch.cuda.synchronize()
+    ea, eb = ea.cpu().numpy(), eb.cpu().numpy()
+    assert np.all(np.isin(ea, [2, 3, 4]))            # the exact picks are the admissible ones
+    assert np.all(fb.cpu().numpy() == 1)
+    assert np.array_equal(am.cpu().numpy(), ea)
+    assert np.array_equal(pc.cpu().numpy().view(np.uint32), eb.view(np.uint32))
