@@ -26,28 +26,42 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "rational fits/s + launch-config evals/s; surrogate vs plain at <=1% cost error"
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.32 T lane-operations/s for
-# unpacked VALU instructions (packed FP32 is disabled in every kernel of this library).
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X peaks (published): FP32 vector 157.3 TFLOP/s counts packed FP32 (two lanes' worth per
+# instruction); this library builds every kernel with packed FP32 disabled, so its own ceiling
+# is half of it: 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s.  FP64 78.6.
+FP32_PEAK_TFLOPS = 157.3
+FP32_UNPACKED_TFLOPS = 78.6
 FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
+VALU_LANE_OPS_T = 256 * 64 * 2.4e9 / 1e12     # unpacked VALU lane-instructions per second, 1e12
 FIT_TOL = {0: 1e-10, 1: 1e-8, 2: 1e-8}
 FIT_MAX_ITER = 256
+N_METRICS = 8
+
+
+def eval_flops_per_point(degree: int) -> int:
+    """FP32 arithmetic of the normative cycle-estimate sequence per (query, configuration)
+    point, fused multiply-add = 2, add / sub / mul / div = 1 (compares, selects, min / max,
+    conversions and integer steps are not counted): per metric 2 degree fused multiply-adds for
+    p and q and one division (8 (4 degree + 1)); occupancy and repetitions 5 (two exact
+    quotients, the resident-wave product, the repetition quotient and its + 1); cycle estimate
+    37 (I_m 1, L_u 3, mem 3, comp 2, MWP_lat 4, MWP_bw 3, tot 1, the two CWP products 2, comp/I_m
+    1, MWP - 1 1, the three case values 2 + 3 + 2, the pure-compute product 1, the
+    synchronisation term 5, the final fused multiply-add 2).  Degree 2: 114."""
+    return N_METRICS * (4 * degree + 1) + 5 + 37
 
 
 def eval_ops_per_point(degree: int) -> int:
-    """Operations of the normative FP32 sequence per (query, configuration) point, each IEEE
-    add / mul / fused multiply-add / div / compare / select / conversion and each integer op
-    counted once (each is at least one lane-instruction).
-
-    per metric (8): scale 1, Horner 2*degree (one fused multiply-add per power, p and q),
-    q > 0 1, divide 1, finiteness 1, clean 1, and 1; clamps 14, occupancy 13, grid and
-    repetitions 14, cycle estimate 43 (six of its a*b + c terms fused), argmin update 3,
-    data-size conversion 1."""
+    """Every operation of the normative sequence counted once (IEEE add / mul / fused
+    multiply-add / div / compare / select / conversion and each integer op): a count of issued
+    lane-operations, reported as a diagnostic beside the FP32 flop roofline."""
     return 8 * (6 + 2 * degree) + 14 + 13 + 14 + 43 + 3 + 1
 
 
@@ -257,6 +271,16 @@ def large_batch_component(lib, klr, synth, seed, replays=3, surrogate_epochs=0):
         ev_ms, _ = lib.profile_read(klr.K_EVAL)
         col_ms, _ = lib.profile_read(klr.K_COLLAPSE)
         lib.profile_enable(False)
+        # the plain method: one workgroup / wavefront per fit in descriptor order, eager
+        lib.set_option(klr.OPT_FIT_PERSISTENT, 0)
+        try:
+            lib.profile_enable(True)
+            lib.fit_batched(df, klr.KLR_FP64, FIT_MAX_ITER, 1e-5, out=fit_out, stream=s)
+            s.synchronize()
+            plain_fit_ms, _ = lib.profile_read(klr.K_FIT_SOLVE)
+            lib.profile_enable(False)
+        finally:
+            lib.set_option(klr.OPT_FIT_PERSISTENT, 1)
     lib.capture_begin(s)
     lib.fit_batched(df, klr.KLR_FP64, FIT_MAX_ITER, 1e-5, out=fit_out, stream=s)
     lib.eval_argmin(de, out=ev_out, stream=s)
@@ -272,7 +296,9 @@ def large_batch_component(lib, klr, synth, seed, replays=3, surrogate_epochs=0):
     ir = klr.info_records(fit_out[1])
     res = {"programs": int(pb.n_progs), "fits": int(fb.n_fits), "fit_rows": int(fb.m.sum()),
            "points": points, "generate_s": gen_s, "graph_ms": ms,
-           "fit_ms": fit_ms, "eval_ms": ev_ms, "collapse_ms": col_ms,
+           "fit_ms": fit_ms, "plain_fit_ms": plain_fit_ms, "eval_ms": ev_ms, "collapse_ms": col_ms,
+           "eval_fp32_tflops": eval_flops_per_point(3) * points / (ev_ms / 1e3) / 1e12,
+           "eager_total_ms": fit_ms + ev_ms + col_ms,
            "fits_per_s": fb.n_fits / (fit_ms / 1e3), "evals_per_s": points / (ev_ms / 1e3),
            "iters_mean": float(ir["iters"].mean()), "not_converged": float(np.mean((ir["status"] & 4) > 0))}
     if surrogate_epochs > 0:
@@ -282,35 +308,234 @@ def large_batch_component(lib, klr, synth, seed, replays=3, surrogate_epochs=0):
     return res
 
 
-def cpu_baseline(pb, fb, budget_s: float, points: int, n_fits: int):
-    """The oracle timed on bounded samples of the same step: FP32 replay + brute-force argmin
-    over whole programs' first 16384 queries x all configurations, and pivoted-QR fits over
-    the first fits of the batch, each until its share of the budget is spent; the step time
-    is scaled from the two rates."""
-    import numpy as np
+def _one_program(pb, p, nq):
+    """Program p of a batch with its first nq queries, as a one-program batch holding only its
+    own fits, configurations and queries (small enough to hand to a worker process)."""
+    import copy
+    out = copy.copy(pb)
+    f0 = int(pb.fit0[p])
+    fits = slice(f0, f0 + N_METRICS)
+    c_lo = int(pb.coef0[f0])
+    c_hi = int(pb.coef0[f0 + N_METRICS - 1] + pb.n_num[f0 + N_METRICS - 1]
+               + pb.n_den[f0 + N_METRICS - 1] - 1)
+    out.coef = pb.coef[c_lo:c_hi].copy()
+    out.num0, out.n_num, out.den0, out.n_den = pb.num0[fits], pb.n_num[fits], pb.den0[fits], pb.n_den[fits]
+    out.coef0, out.scale_exp = pb.coef0[fits] - c_lo, pb.scale_exp[fits]
+    vl, nc = int(pb.v_launch[p]), int(pb.n_cfg[p])
+    out.cfgs = pb.cfgs[int(pb.cfg0[p]): int(pb.cfg0[p]) + nc * vl].copy()
+    out.queries = pb.queries[int(pb.q0[p]): int(pb.q0[p]) + nq].copy()
+    out.v_launch, out.fit0 = pb.v_launch[p:p + 1], np.zeros(1, np.int32)
+    out.cfg0, out.n_cfg, out.grid_kind = np.zeros(1, np.int64), pb.n_cfg[p:p + 1], pb.grid_kind[p:p + 1]
+    out.q0, out.n_q = np.zeros(1, np.int64), np.array([nq], np.int32)
+    return out
+
+
+def _oracle_eval_task(pb1):
+    """Worker: the oracle's FP32 replay + brute-force argmin of one program slice."""
     from oracle import cost as oc
+    t = time.perf_counter()
+    c = oc.program_costs(pb1, 0)
+    oc.argmin_lowest(c)
+    return c.size, time.perf_counter() - t
+
+
+def _oracle_fit_task(fits):
+    """Worker: the oracle's pivoted-QR least squares on a list of (X, f, E_num, E_den, s)."""
     from oracle import fit as of
-    ev_pts, t0, progs = 0, time.perf_counter(), 0
-    nq = min(16384, int(pb.n_q[0]))
-    while time.perf_counter() - t0 < 0.75 * budget_s and progs < pb.n_progs:
-        c = oc.program_costs(pb, progs, query_idx=np.arange(nq))
-        oc.argmin_lowest(c)
-        ev_pts += c.size
-        progs += 1
-    t_ev = time.perf_counter() - t0
-    t1, nf = time.perf_counter(), 0
-    while time.perf_counter() - t1 < 0.25 * budget_s and nf < fb.n_fits:
-        of.fit_batch(fb, indices=[nf])
-        nf += 1
-    t_fit = time.perf_counter() - t1
-    ev_rate, fit_rate = ev_pts / t_ev, nf / t_fit
-    step_s = n_fits / fit_rate + points / ev_rate
-    return {"value": points / step_s, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "fits_per_s": fit_rate, "evals_per_s": ev_rate,
-            "sample": f"eval: {progs} programs x {nq} queries x {int(pb.n_cfg[0])} configs "
-                      f"({ev_pts} points, {t_ev:.1f} s, numpy FP32 replay + argmin); fit: {nf} fits "
-                      f"({t_fit:.1f} s, numpy pivoted Householder QR); step time scaled from the "
-                      f"two rates to {n_fits} fits + {points} points; 1 thread"}
+    t = time.perf_counter()
+    for Xi, fi, En, Ed, sc in fits:
+        of.fit_one(Xi, fi, En, Ed, sc)
+    return len(fits), time.perf_counter() - t
+
+
+def _noop(_):
+    return 0
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pb, fb, budget_s: float, points: int, n_fits: int, workers: int):
+    """The oracle timed on bounded samples of the same step, at one thread and at `workers`
+    threads (worker processes, each single-threaded: numpy's elementwise arithmetic and the
+    small QR factorisations run on one core): FP32 replay + brute-force argmin over program
+    slices of 2048 queries x all configurations, and pivoted-QR fits of the batch's fits.  The
+    step time at each thread count is scaled from the two rates.  Runs before the GPU is
+    touched (worker processes start from a fresh interpreter)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    nq = min(8192, int(pb.n_q[0]))
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    ctx = mp.get_context("spawn")
+    res = {}
+    try:
+        for nw in (1, workers):
+            with ProcessPoolExecutor(max_workers=nw, mp_context=ctx) as ex:
+                list(ex.map(_noop, range(nw)))                       # start the workers first
+                share = 0.6 * budget_s / 2
+                # evaluation: program slices, in waves of nw tasks until the share is spent
+                t0, pts, prog = time.perf_counter(), 0, 0
+                while time.perf_counter() - t0 < share and prog < pb.n_progs:
+                    batch = [_one_program(pb, (prog + i) % pb.n_progs, nq) for i in range(nw)]
+                    for n, _ in ex.map(_oracle_eval_task, batch):
+                        pts += n
+                    prog += nw
+                t_ev = time.perf_counter() - t0
+                # fits: chunks of 16 fits per task
+                share = 0.4 * budget_s / 2
+                t1, nf, fi = time.perf_counter(), 0, 0
+                while time.perf_counter() - t1 < share:
+                    chunks = []
+                    for _ in range(nw):
+                        chunks.append([fb.fit_arrays((fi + j) % fb.n_fits) for j in range(16)])
+                        fi += 16
+                    for n, _ in ex.map(_oracle_fit_task, chunks):
+                        nf += n
+                t_fit = time.perf_counter() - t1
+            ev_rate, fit_rate = pts / t_ev, nf / t_fit
+            step_s = n_fits / fit_rate + points / ev_rate
+            res[nw] = {"value": points / step_s, "evals_per_s": ev_rate, "fits_per_s": fit_rate,
+                       "eval_points": pts, "eval_s": t_ev, "fits": nf, "fit_s": t_fit}
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    allc, one = res[workers], res[1]
+    return {"value": allc["value"], "unit": "evals/s", "cores": workers, "kind": "oracle",
+            "fits_per_s": allc["fits_per_s"], "evals_per_s": allc["evals_per_s"],
+            "single_thread": {"value": one["value"], "fits_per_s": one["fits_per_s"],
+                              "evals_per_s": one["evals_per_s"]},
+            "nproc": os.cpu_count(), "threads_per_worker": 1, "cpu_model": _cpu_model(),
+            "sample": f"eval: program slices of {nq} queries x {int(pb.n_cfg[0])} configs, numpy FP32 replay + "
+                      f"argmin ({allc['eval_points']} points in {allc['eval_s']:.1f} s at {workers} workers, "
+                      f"{one['eval_points']} in {one['eval_s']:.1f} s at 1); fit: numpy pivoted Householder QR "
+                      f"({allc['fits']} fits in {allc['fit_s']:.1f} s at {workers} workers, {one['fits']} in "
+                      f"{one['fit_s']:.1f} s at 1); step time scaled from the two rates to {n_fits} fits + "
+                      f"{points} points"}
+
+
+def fp64_error(pb, am, bc, n_progs: int, nq: int):
+    """Error of the step's FP32 results against the FP64 cycle estimate (the oracle's truth
+    mode: each metric the full multivariate p/q in FP64, exact integer parts) on the first
+    n_progs programs' first nq queries: argmin disagreement rate, regret of the FP32 pick under
+    FP64 costs, relative error of the FP32 best cost."""
+    from oracle import cost as oc
+    dis = n = adm = 0
+    regrets, rel = [], []
+    for p in range(n_progs):
+        q0 = int(pb.q0[p])
+        c64 = oc.program_costs(pb, p, query_idx=np.arange(nq), mode="truth")
+        i64, b64 = oc.argmin_lowest(c64)
+        a32, b32 = am[q0:q0 + nq], bc[q0:q0 + nq].astype(np.float64)
+        dis += int(np.sum(a32 != i64))
+        adm += int(np.sum((a32 >= 0) != (i64 >= 0)))
+        n += nq
+        ok = (a32 >= 0) & (i64 >= 0)
+        regrets.append(c64[np.maximum(a32, 0), np.arange(nq)][ok] / b64[ok] - 1.0)
+        rel.append(np.abs(b32[ok] - b64[ok]) / b64[ok])
+    r, e = np.concatenate(regrets), np.concatenate(rel)
+    return {"queries": n, "argmin_mismatch_rate": dis / n, "admissibility_mismatch": adm,
+            "regret_max": float(r.max()), "best_cost_rel_err_max": float(e.max()),
+            "best_cost_rel_err_median": float(np.median(e)),
+            "sample": f"first {nq} queries of the first {n_progs} programs, all configurations"}
+
+
+def single_fit_component(lib, klr, synth, replays=200, seeds=100):
+    """The single-fit workload: one FP64 fit of 200 samples over (N, B), then its fitted
+    function over the 11 x 32 grid with the per-N argmin, captured as one graph; the median of
+    `replays` individually timed replays (HIP events on the stream) is the time per fit +
+    decision.  Decision quality against the generator's noise-free argmin over `seeds` seeds
+    (each fitted on the device)."""
+    import torch
+    s = torch.cuda.Stream()
+    picks_equal, regrets = [], []
+    g = None
+    times = []
+    for seed in range(1, seeds + 1):
+        fb = synth.config1_fit(seed)
+        df = klr.DeviceFit.from_batch(fb)
+        fit_out = (torch.empty(df.n_coef, dtype=torch.float64, device="cuda"),
+                   torch.empty(klr.FIT_INFO.itemsize, dtype=torch.uint8, device="cuda"))
+        de = klr.DeviceEval.from_batch(lib, synth.config1_program(fb), coef=fit_out[0])
+        ev_out = (torch.empty(11, dtype=torch.int32, device="cuda"), torch.empty(11, dtype=torch.float32, device="cuda"),
+                  None, torch.empty(1, dtype=torch.int32, device="cuda"))
+        with torch.cuda.stream(s):
+            lib.fit_batched(df, klr.KLR_FP64, 64, 1e-12, out=fit_out, stream=s)
+            lib.eval_argmin(de, out=ev_out, stream=s)
+        s.synchronize()
+        if seed == 1:          # the timed graph: fit + grid evaluation + argmin of seed 1
+            lib.capture_begin(s)
+            lib.fit_batched(df, klr.KLR_FP64, 64, 1e-12, out=fit_out, stream=s)
+            lib.eval_argmin(de, out=ev_out, stream=s)
+            g = lib.capture_end(s)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(replays)]
+            for _ in range(10):
+                lib.graph_launch(g, s)
+            for a, b in ev:
+                a.record(s)
+                lib.graph_launch(g, s)
+                b.record(s)
+            s.synchronize()
+            times = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+            lib.graph_destroy(g)
+        pick = ev_out[0].cpu().numpy()
+        truth = synth.config1_truth_grid(fb)
+        tp = np.argmin(truth, axis=0)
+        picks_equal.append(float(np.mean(pick == tp)))
+        regrets.append(truth[pick, np.arange(11)] / truth[tp, np.arange(11)] - 1.0)
+    r = np.concatenate(regrets)
+    return {"us_per_fit_and_decision_median": times[len(times) // 2], "us_p10": times[len(times) // 10],
+            "us_p90": times[(9 * len(times)) // 10], "replays": replays,
+            "decision_quality": {"seeds": seeds, "picks_equal_truth": float(np.mean(picks_equal)),
+                                 "regret_under_truth_median": float(np.median(r)),
+                                 "regret_under_truth_p90": float(np.quantile(r, 0.9)),
+                                 "regret_under_truth_max": float(r.max())},
+            "workload": "1 FP64 fit (200 of the 11 x 32 (N, B) grid points, degree <= 2, 1 % noise), "
+                        "then the fitted function on all 352 points and the argmin over B per N"}
+
+
+def fit_component(lib, klr, fb, prec, reps=3, persistent=True):
+    """Eager HIP-event time of one precision / schedule on a fit batch, with iteration and
+    status statistics and the FP64 roofline fraction."""
+    import torch
+    df = klr.DeviceFit.from_batch(fb)
+    fit_out = (torch.empty(df.n_coef, dtype=torch.float64, device="cuda"),
+               torch.empty(df.n_fits * klr.FIT_INFO.itemsize, dtype=torch.uint8, device="cuda"))
+    lib.set_option(klr.OPT_FIT_PERSISTENT, 1 if persistent else 0)
+    try:
+        lib.fit_batched(df, prec, FIT_MAX_ITER, FIT_TOL[prec], out=fit_out)
+        torch.cuda.synchronize()
+        lib.profile_enable(True)
+        for _ in range(reps):
+            lib.fit_batched(df, prec, FIT_MAX_ITER, FIT_TOL[prec], out=fit_out)
+        kms, kn = lib.profile_read(klr.K_FIT_SOLVE)
+        lib.profile_enable(False)
+    finally:
+        lib.set_option(klr.OPT_FIT_PERSISTENT, 1)
+    ir = klr.info_records(fit_out[1])
+    kavg = kms / max(kn, 1)
+    n_unk = (fb.n_num + fb.n_den - 1).astype(np.float64)
+    fl = float(np.sum(fit_flops(fb.m.astype(np.float64), n_unk, ir["iters"].astype(np.float64))))
+    return {"kernel_ms": kavg, "fits_per_s": fb.n_fits / (kavg / 1e3), "tol": FIT_TOL[prec],
+            "iters_mean": float(ir["iters"].mean()), "iters_max": int(ir["iters"].max()),
+            "rank_deficient": float(np.mean((ir["status"] & 1) > 0)),
+            "fell_back_fp64": float(np.mean((ir["status"] & 8) > 0)),
+            "not_converged": float(np.mean((ir["status"] & 4) > 0)),
+            "err_est_max": float(ir["err_est"].max()),
+            "fp64_tflops": fl / (kavg / 1e3) / 1e12, "fp64_frac": fl / (kavg / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+            "schedule": "persistent longest-first" if persistent else "plain (one wavefront / workgroup per fit)"}
 
 
 def main() -> int:
@@ -319,12 +544,14 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=7)
-    ap.add_argument("--cpu-budget-s", type=float, default=16.0)
+    ap.add_argument("--cpu-budget-s", type=float, default=24.0)
+    ap.add_argument("--cpu-workers", type=int, default=min(os.cpu_count() or 1, 16))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-sweep", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-large-batch", action="store_true")
-    ap.add_argument("--kernel-only", choices=("eval", "fit", "copy", "large"), default=None,
+    ap.add_argument("--no-single-fit", action="store_true")
+    ap.add_argument("--kernel-only", choices=("eval", "fit", "copy", "large", "mlp"), default=None,
                     help="run only this kernel --steps times (for hardware-counter runs); "
                          "'copy' is a plain 1 GiB device copy used to calibrate byte counters")
     ap.add_argument("--surrogate-epochs", type=int, default=300)
@@ -336,9 +563,24 @@ def main() -> int:
               "would be sharded by descriptor ranges, one process per GPU); run with --gpus 1", file=sys.stderr)
         return 2
 
-    import numpy as np
+    from paper_1911_02373_amd import synth
+    t = time.perf_counter()
+    pb = synth.config3_programs(args.seed, n_progs=1024, n_q=65536)
+    fb = synth.config2_fits(args.seed, n_fits=4096, domain="2a")
+    points = int((pb.n_cfg.astype(np.int64) * pb.n_q).sum())
+    log(f"workload generated in {time.perf_counter() - t:.1f} s: {fb.n_fits} fits "
+        f"({int(fb.m.sum())} rows), {pb.n_progs} programs, {points:.3e} points")
+    cpu = None
+    if not args.no_cpu_baseline and args.kernel_only is None:
+        # before the GPU is touched: the oracle's worker processes start from a fresh interpreter
+        t = time.perf_counter()
+        cpu = cpu_baseline(pb, fb, args.cpu_budget_s, points, fb.n_fits, args.cpu_workers)
+        log(f"cpu baseline in {time.perf_counter() - t:.1f} s: {cpu['evals_per_s']:.3e} evals/s and "
+            f"{cpu['fits_per_s']:.0f} fits/s at {cpu['cores']} workers; "
+            f"{cpu['single_thread']['evals_per_s']:.3e} / {cpu['single_thread']['fits_per_s']:.0f} at 1")
+
     import torch
-    from paper_1911_02373_amd import klr, synth
+    from paper_1911_02373_amd import klr
 
     lib = klr.Library.get()
     if args.kernel_only == "copy":
@@ -371,9 +613,6 @@ def main() -> int:
                           "fit_rows": int(fb5.m.sum()),
                           "points": int((pb5.n_cfg.astype(np.int64) * pb5.n_q).sum())}), flush=True)
         return 0
-    t = time.perf_counter()
-    pb = synth.config3_programs(args.seed, n_progs=1024, n_q=65536)
-    fb = synth.config2_fits(args.seed, n_fits=4096, domain="2a")
     de = klr.DeviceEval.from_batch(lib, pb)
     df = klr.DeviceFit.from_batch(fb)
     dev = "cuda"
@@ -382,14 +621,16 @@ def main() -> int:
            torch.empty(de.n_progs, dtype=torch.int32, device=dev))
     fit_out = (torch.empty(df.n_coef, dtype=torch.float64, device=dev),
                torch.empty(df.n_fits * klr.FIT_INFO.itemsize, dtype=torch.uint8, device=dev))
-    points = int((pb.n_cfg.astype(np.int64) * pb.n_q).sum())
-    log(f"workload ready in {time.perf_counter() - t:.1f} s: {fb.n_fits} fits "
-        f"({int(fb.m.sum())} rows), {pb.n_progs} programs, {points:.3e} points")
 
     def step():
         lib.fit_batched(df, klr.KLR_FP64, FIT_MAX_ITER, FIT_TOL[0], out=fit_out)
         lib.eval_argmin(de, out=out)
 
+    if args.kernel_only == "mlp":
+        # surrogate training (a few epochs) and one selection over the full grid
+        comp = surrogate_component(lib, klr, synth, pb, de, 1.0, args.seed, args.steps, regret_programs=2)
+        print(json.dumps({"kernel_only": "mlp", "epochs": args.steps, "select_ms": comp["select_ms"]}), flush=True)
+        return 0
     if args.kernel_only is not None:
         lib.eval_argmin(de, out=out)          # tune the sweep's launch shape outside the counted run
         torch.cuda.synchronize()
@@ -424,54 +665,62 @@ def main() -> int:
         return 1
     avg = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
     eval_avg = avg[klr.K_EVAL]
-    ops = eval_ops_per_point(2)
-    achieved = ops * points / (eval_avg / 1e3) / 1e12
+    flops = eval_flops_per_point(2)
+    achieved = flops * points / (eval_avg / 1e3) / 1e12
     n_unk = (fb.n_num + fb.n_den - 1).astype(np.float64)
     fit_fl = float(np.sum(fit_flops(fb.m.astype(np.float64), n_unk, info["iters"].astype(np.float64))))
     comps = {
         "eval": {"kernel_ms": eval_avg, "collapse_ms": avg[klr.K_COLLAPSE],
-                 "evals_per_s": points / ((eval_avg + avg[klr.K_COLLAPSE]) / 1e3)},
+                 "evals_per_s": points / ((eval_avg + avg[klr.K_COLLAPSE]) / 1e3),
+                 "lane_ops_per_point": eval_ops_per_point(2),
+                 "issue_rate_T_lane_ops": eval_ops_per_point(2) * points / (eval_avg / 1e3) / 1e12,
+                 "issue_rate_note": "normative operations (each compare / select / integer op counted once) per "
+                                    "second; a diagnostic, not a roofline"},
         "fit_fp64": {"kernel_ms": avg[klr.K_FIT_SOLVE], "fits_per_s": fb.n_fits / (avg[klr.K_FIT_SOLVE] / 1e3),
                      "iters_mean": float(info["iters"].mean()), "iters_max": int(info["iters"].max()),
                      "tol": FIT_TOL[0], "err_est_max": float(info["err_est"].max()),
-                     "fp64_tflops": fit_fl / (avg[klr.K_FIT_SOLVE] / 1e3) / 1e12,
-                     "fp64_frac": fit_fl / (avg[klr.K_FIT_SOLVE] / 1e3) / 1e12 / FP64_PEAK_TFLOPS},
+                     "roofline": {"bound": "fp64", "achieved": fit_fl / (avg[klr.K_FIT_SOLVE] / 1e3) / 1e12,
+                                  "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": fit_fl / (avg[klr.K_FIT_SOLVE] / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+                                  "flops_per_launch": fit_fl}},
     }
     log(f"step {ms:.3f} ms; eval {eval_avg:.3f} ms; collapse {avg[klr.K_COLLAPSE]:.3f} ms; "
         f"fit {avg[klr.K_FIT_SOLVE]:.3f} ms")
+    am_h, bc_h = out[0].cpu().numpy(), out[1].cpu().numpy()
+    del de
+    comps["fit_fp64_plain"] = fit_component(lib, klr, fb, klr.KLR_FP64, persistent=False)
+    fb2b = synth.config2_fits(args.seed, n_fits=4096, domain="2b")
+    comps["fit_fp64_c2b"] = fit_component(lib, klr, fb2b, klr.KLR_FP64)
+    log(f"fit plain schedule {comps['fit_fp64_plain']['kernel_ms']:.3f} ms; c2b {comps['fit_fp64_c2b']['kernel_ms']:.3f} ms")
     if not args.no_precision_sweep:
         for prec, name in ((klr.KLR_FP32_REFINED, "fit_fp32_refined"), (klr.KLR_BF16_REFINED, "fit_bf16_refined")):
-            lib.fit_batched(df, prec, FIT_MAX_ITER, FIT_TOL[prec], out=fit_out)
-            torch.cuda.synchronize()
-            lib.profile_enable(True)
-            reps = 3
-            for _ in range(reps):
-                lib.fit_batched(df, prec, FIT_MAX_ITER, FIT_TOL[prec], out=fit_out)
-            kms, kn = lib.profile_read(klr.K_FIT_SOLVE)
-            lib.profile_enable(False)
-            ir = klr.info_records(fit_out[1])
-            kavg = kms / max(kn, 1)
-            comps[name] = {"kernel_ms": kavg, "fits_per_s": fb.n_fits / (kavg / 1e3), "tol": FIT_TOL[prec],
-                           "iters_mean": float(ir["iters"].mean()), "iters_max": int(ir["iters"].max()),
-                           "fell_back_fp64": float(np.mean((ir["status"] & 8) > 0)),
-                           "err_est_max": float(ir["err_est"].max()),
-                           "speedup_vs_fp64": avg[klr.K_FIT_SOLVE] / kavg}
-            log(f"{name}: {kavg:.3f} ms, iters mean {ir['iters'].mean():.1f}")
+            comps[name] = fit_component(lib, klr, fb, prec)
+            comps[name]["speedup_vs_fp64"] = avg[klr.K_FIT_SOLVE] / comps[name]["kernel_ms"]
+            comps[name + "_c2b"] = fit_component(lib, klr, fb2b, prec)
+            log(f"{name}: {comps[name]['kernel_ms']:.3f} ms, iters mean {comps[name]['iters_mean']:.1f}; "
+                f"c2b {comps[name + '_c2b']['kernel_ms']:.3f} ms")
+    if not args.no_single_fit:
+        comps["single_fit"] = sf = single_fit_component(lib, klr, synth)
+        log(f"single fit + grid decision: median {sf['us_per_fit_and_decision_median']:.1f} us per graph replay; "
+            f"picks equal to the truth's {sf['decision_quality']['picks_equal_truth']:.3f}")
 
     if not args.no_surrogate:
+        de = klr.DeviceEval.from_batch(lib, pb)
         comps["surrogate"] = surrogate_component(lib, klr, synth, pb, de, eval_avg + avg[klr.K_COLLAPSE],
                                                  args.seed, args.surrogate_epochs)
         sc = comps["surrogate"]
         log(f"surrogate: train {sc['train_ms']:.0f} ms, select {sc['select_ms']:.0f} ms, fallback rate "
             f"{sc['fallback_rate']:.3f}, speedup vs exact {sc['speedup_vs_exact']:.3f}")
+        del de
 
     if not args.no_large_batch:
-        del de, df
+        del df
         torch.cuda.empty_cache()
         comps["large_batch"] = lb = large_batch_component(
             lib, klr, synth, args.seed, surrogate_epochs=0 if args.no_surrogate else args.large_surrogate_epochs)
         log(f"large batch: {lb['fits']} fits + {lb['points']:.3e} points, graph {lb['graph_ms']:.1f} ms "
-            f"(fit {lb['fit_ms']:.1f}, eval {lb['eval_ms']:.1f}); generated in {lb['generate_s']:.0f} s")
+            f"(fit {lb['fit_ms']:.1f}, plain fit {lb['plain_fit_ms']:.1f}, eval {lb['eval_ms']:.1f}); "
+            f"generated in {lb['generate_s']:.0f} s")
         if "surrogate_two_launch_params" in lb:
             ls = lb["surrogate_two_launch_params"]
             log(f"large batch surrogate ({ls['programs']} programs): train {ls['train_ms']:.0f} ms, select + "
@@ -495,11 +744,17 @@ def main() -> int:
         "evals_per_s": comps["eval"]["evals_per_s"],
         "components": comps,
         "roofline": {"bound": "alu", "kernel": "eval_kernel", "achieved": achieved,
-                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "ops_per_point": ops, "traffic": measured_traffic()},
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "frac_of_unpacked_fp32": achieved / FP32_UNPACKED_TFLOPS,
+                     "flops_per_point": flops, "points_per_launch": points,
+                     "traffic": measured_traffic()},
     }
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(pb, fb, args.cpu_budget_s, points, fb.n_fits)
+    if cpu is not None:
+        t = time.perf_counter()
+        cpu["fp64_error"] = fp64_error(pb, am_h, bc_h, 8, 2048)
+        log(f"FP64 check in {time.perf_counter() - t:.1f} s: {cpu['fp64_error']}")
+        res["cpu_baseline"] = cpu
+        res["fp64_error"] = cpu["fp64_error"]
     print(json.dumps(res), flush=True)
     return 0
 

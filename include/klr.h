@@ -89,6 +89,10 @@ typedef struct {
 #define KLR_FIT_FELL_BACK_FP64 8u   /* reduced-precision Gram replaced by the FP64 path        */
 #define KLR_FIT_BAD_INPUT 16u       /* bad descriptor, m == 0, or a NaN/Inf sample             */
 #define KLR_FIT_Q_NONPOS 32u        /* fitted q(x~_i) <= 0 at some sample (possible pole)      */
+#define KLR_FIT_UNSUPPORTED 128u    /* KLR_FP64_SVD: n > 48, m > 1024, or m > 512 with n > 16 */
+#define KLR_FIT_NO_SCRATCH 64u      /* the workspace holds fewer scratch rows than the batch's  */
+                                    /*   workgroup-class fits need (size it by sum of m); no    */
+                                    /*   coefficients computed (zeros written)                   */
 
 typedef struct {
   uint32_t status;
@@ -102,12 +106,17 @@ typedef struct {
                           /*   values vs the exact least-squares solution y*                  */
 } klr_fit_info;           /* 32 bytes */
 
-typedef enum { KLR_FP64 = 0, KLR_FP32_REFINED = 1, KLR_BF16_REFINED = 2 } klr_precision;
+typedef enum { KLR_FP64 = 0, KLR_FP32_REFINED = 1, KLR_BF16_REFINED = 2, KLR_FP64_SVD = 3 } klr_precision;
 
-/* Workspace bytes klr_fit_batched needs for n_fits fits whose targets span f[0, f_len)
- * (two FP64 values per sample row for the refinement residuals, then the schedule: a small
- * plan record and two int32 per fit for the longest-first order and the fits' buckets). */
-size_t klr_fit_workspace(int32_t n_fits, int64_t f_len, int32_t precision);
+/* Workspace bytes klr_fit_batched needs for n_fits fits with total_rows = sum of their sample
+ * counts m (an upper bound is enough): the schedule (a small plan record, two int32 per fit for
+ * the longest-first order and the fits' buckets, one int64 per fit for its scratch offset), then
+ * two FP64 values per sample row of private refinement scratch (residual and A t).  Each fit
+ * that takes the workgroup kernel owns its own scratch rows (an exclusive prefix of m formed on
+ * the device), so fits may share or overlap target ranges in f.  The call needs at least
+ * klr_fit_workspace(n_fits, 0, precision) bytes (else KLR_E_WORKSPACE); a fit whose scratch rows
+ * do not fit in the rest gets status KLR_FIT_NO_SCRATCH. */
+size_t klr_fit_workspace(int32_t n_fits, int64_t total_rows, int32_t precision);
 
 /* Fit n_fits independent rational functions (uneven m and monomial sets in one launch).
  *   desc[n_fits], exps[n_exp_rows][8] (uint8 exponent tuples), X[x_len] int32,
@@ -126,7 +135,15 @@ size_t klr_fit_workspace(int32_t n_fits, int64_t f_len, int32_t precision);
  *   precision: KLR_FP64 forms the Gram matrix in FP64; KLR_FP32_REFINED / KLR_BF16_REFINED
  *   round the design matrix to FP32 / BF16 for the Gram product and accumulate in FP32; a fit
  *   that does not converge is redone with the FP64 Gram (status KLR_FIT_FELL_BACK_FP64).
- *   The factorisation and the residuals are FP64 on every path.  Coefficients are in the
+ *   The factorisation and the residuals are FP64 on every path.
+ *   KLR_FP64_SVD solves each fit by the singular value decomposition the paper uses (section
+ *   "Building a Driver Program: Rational function estimation"): one-sided Jacobi rotations of
+ *   the column-equilibrated design matrix in FP64, one workgroup per fit with the rows in
+ *   registers; numerical rank = singular values above 10 max(m, n) 2^-52 sigma_max; the
+ *   minimum-norm least-squares solution of the equilibrated problem; iters = Jacobi sweeps;
+ *   err_est = 2^-53 times the condition number of the kept part.  Limits: n <= 48 and m <= 1024
+ *   (m <= 512 when n > 16); other fits get KLR_FIT_UNSUPPORTED and zero coefficients; max_iter
+ *   and tol are not used (at most 30 sweeps).  Coefficients are in the
  *   scaled-variable basis x~.  Rank-deficient fits get a least-squares solution (not
  *   necessarily the minimum-norm one): its values on the samples are the unique
  *   least-squares values. */
@@ -166,6 +183,15 @@ typedef struct {          /* hardware parameters H, fixed per call [host]       
 #define KLR_GRID_1D 0     /* blocks = ceil(N / prod L)                                          */
 #define KLR_GRID_2D 1     /* blocks = ceil(N / L0) * ceil(N / L1) (needs v_launch >= 2)         */
 
+/* What a program's cost is. */
+#define KLR_COST_CYCLES 0 /* the MWP-CWP-style cycle estimate from KLR_N_METRICS fitted metrics */
+#define KLR_COST_METRIC 1 /* the program's one fitted function itself (fit0 only): the target   */
+                          /*   metric was the quantity to minimise (e.g. the measured time), so  */
+                          /*   the fitted rational function is the rational program; cost =     */
+                          /*   p/q, inadmissible where q <= 0 or not finite, and the launch     */
+                          /*   constraints (every L >= 1 and <= N, T <= t_max, T % wave == 0)   */
+                          /*   apply; occupancy terms and the grid do not enter                 */
+
 typedef struct {
   int64_t cfg0;           /* element offset of its n_cfg configurations in cfgs (rows of       */
                           /*   v_launch int32)                                                  */
@@ -176,7 +202,7 @@ typedef struct {
   int32_t n_cfg;          /* configurations, 0..max_cfg                                         */
   int32_t n_q;            /* queries, 0..max_q                                                  */
   int32_t grid_kind;      /* KLR_GRID_1D or KLR_GRID_2D                                         */
-  int32_t reserved;       /* must be 0                                                          */
+  int32_t cost_kind;      /* KLR_COST_CYCLES (fits fit0 .. fit0 + 7) or KLR_COST_METRIC (fit0)  */
 } klr_program;            /* 48 bytes */
 
 /* program status bits (prog_status) */
@@ -269,9 +295,17 @@ klr_status klr_surrogate_step(klr_handle h, void* params, int32_t n_kernels,
  * best is below ln(1 + margin), or the exact cost of the pick is +inf (a configuration that the
  * occupancy terms rule out: the network never sees those in training), the query falls back to
  * the exact rational program (klr_eval_argmin semantics) and fell_back[q] = 1.
- * pred_cost[q] = exp(predicted ln C) of the pick, or the exact cost on fallback.  Needs
- * klr_surrogate_eval_workspace bytes. */
-size_t klr_surrogate_eval_workspace(int32_t n_progs, int32_t max_cfg, int64_t q_len);
+ * pred_cost[q] = exp(predicted ln C) of the pick, or the exact cost on fallback.
+ * pred_margin[q] (optional, may be NULL): second-best minus best prediction in ln units (+inf
+ * with a single candidate; NaN when the network makes no pick: no statically admissible
+ * configuration, or a program it cannot represent - v_launch != 2 or more than 1024
+ * configurations - which the exact path answers).  prog_status[n_progs] (optional): as in
+ * klr_eval_argmin; a program with KLR_PROG_BAD_DESC gets no output, one with KLR_PROG_BAD_FIT
+ * falls back to the exact path and reports -1 / +inf.  Queries are counted per program over its
+ * own range, so programs may share query ranges (their outputs then overwrite each other, as in
+ * klr_eval_argmin) without overflowing the workspace.  Needs klr_surrogate_eval_workspace bytes
+ * (linear in n_progs * max_q, which must stay below 2^31). */
+size_t klr_surrogate_eval_workspace(int32_t n_progs, int32_t max_cfg, int32_t max_q);
 klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernels,
                               const klr_program* progs, int32_t n_progs, int32_t max_cfg,
                               int32_t max_q, const klr_hw* hw, const klr_fit_desc* desc,
@@ -279,6 +313,7 @@ klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernel
                               const double* coef, int64_t coef_len, const int32_t* cfgs,
                               int64_t cfgs_len, const int32_t* queries, int64_t q_len,
                               float margin, int32_t* argmin, float* pred_cost, uint8_t* fell_back,
+                              float* pred_margin, int32_t* prog_status,
                               void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------------------------

@@ -20,6 +20,8 @@ What it follows.
     finite value, B_active >= 1, and the cost is finite.
   * Selection (step 5): exhaustive search, strict "<" in configuration order, so ties go to the
     lowest index; no admissible configuration gives -1 and +inf.
+  * A program may instead take its one fitted function as the cost (the sampled metric was the
+    quantity to minimise), with the same launch constraints and no occupancy or grid terms.
 
 Two precisions:
   truth  - FP64: each metric is the full multivariate p/q evaluated directly at (N~, L~).
@@ -260,9 +262,32 @@ def cycles_from_metrics(g, N, L, grid_kind, hw, dt):
 # ---------------------------------------------------------------------------------------------
 # programs
 
+COST_CYCLES, COST_METRIC = 0, 1
+
+
+def cost_kind(pb, prog):
+    """KLR_COST_CYCLES (the cycle estimate from 8 metrics) or KLR_COST_METRIC (the program's one
+    fitted function is the cost)."""
+    ck = getattr(pb, "cost_kind", None)
+    return COST_CYCLES if ck is None else int(ck[prog])
+
+
+def metric_cost(g, N, L, hw):
+    """Cost of a program whose one fitted function g = p/q is the cost (the rational program
+    is the fitted metric itself, e.g. when the sampled metric was the kernel's time): g where q > 0
+    and the value is finite and the launch constraints hold (every L >= 1 and <= N, T = prod L a
+    multiple of the wave and <= T_max); +inf elsewhere."""
+    N = np.asarray(N, np.int64)
+    L = [int(x) for x in L]
+    T = int(np.prod(L))
+    ok = np.isfinite(g) & (N >= max(L))
+    ok &= (T <= hw.t_max) and (T % hw.wave == 0) and all(x >= 1 for x in L)
+    return np.where(ok, g, np.inf).astype(np.asarray(g).dtype)
+
+
 def _metric_slices(pb, prog):
     out = []
-    for j in range(N_METRICS):
+    for j in range(1 if cost_kind(pb, prog) == COST_METRIC else N_METRICS):
         fi = int(pb.fit0[prog]) + j
         v = 1 + int(pb.v_launch[prog])
         En = pb.exps[pb.num0[fi]: pb.num0[fi] + pb.n_num[fi], :v]
@@ -310,7 +335,10 @@ def program_costs(pb, prog, query_idx=None, mode="replay", coef=None):
                 with np.errstate(all="ignore"):
                     val = p / q
                 g.append(np.where(q > 0, val, np.nan))
-        out[c] = cycles_from_metrics(g, N, cfgs[c], gk, pb.hw, dt)
+        if cost_kind(pb, prog) == COST_METRIC:
+            out[c] = metric_cost(g[0], N, cfgs[c], pb.hw)
+        else:
+            out[c] = cycles_from_metrics(g, N, cfgs[c], gk, pb.hw, dt)
     return out
 
 

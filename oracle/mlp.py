@@ -36,6 +36,26 @@ def forward(p, kid, N, bx, by):
     return y, {"x": x, "a1": a1, "h1": h1, "a2": a2, "h2": h2, "kid": np.asarray(kid)}
 
 
+def bf16_round(a):
+    """Round to the nearest bfloat16 value (8 significand bits, ties to even), from the value's
+    FP32 rounding; returned as FP64.  bfloat16 is FP32 with the low 16 bits of the encoding
+    dropped, so rounding adds half of the dropped range (minus one unless the kept part is odd)
+    and clears the low half-word."""
+    b = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(p, kid, N, bx, by):
+    """The forward pass with the 256 x 256 layer's operands in bfloat16, as the selection kernel
+    takes them: W2 and the first hidden layer h1 rounded to bfloat16 (from FP32), every other
+    step in FP64.  Returns y [B]."""
+    x = features(N, bx, by, p["emb"][np.asarray(kid)])
+    h1 = bf16_round(np.maximum(x @ p["W1"].T + p["b1"], 0.0))
+    h2 = np.maximum(h1 @ bf16_round(p["W2"]).T + p["b2"], 0.0)
+    return h2 @ p["w3"] + p["b3"]
+
+
 def loss_and_grads(p, kid, N, bx, by, t):
     """MSE loss and its analytic gradient with respect to every parameter (FP64)."""
     y, c = forward(p, kid, N, bx, by)

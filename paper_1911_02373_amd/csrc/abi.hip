@@ -11,6 +11,7 @@
 
 #include "internal.hpp"
 
+
 namespace klr {
 
 klr_status fail(klr_handle h, klr_status st, const std::string& msg) {
@@ -234,16 +235,23 @@ size_t klr_eval_workspace(int32_t n_progs, int32_t max_cfg) {
   return klr::eval_workspace_bytes(n_progs, max_cfg);
 }
 
-klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_progs,
-                           int32_t max_cfg, int32_t max_q, const klr_hw* hw,
-                           const klr_fit_desc* desc, int32_t n_fits,
-                           const uint8_t* exps, int32_t n_exp_rows,
-                           const double* coef, int64_t coef_len,
-                           const int32_t* cfgs, int64_t cfgs_len,
-                           const int32_t* queries, int64_t q_len,
-                           int32_t* argmin, float* best_cost,
-                           float* all_costs, int64_t costs_len, int32_t* prog_status,
-                           void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace klr {
+namespace {
+
+// Validation and launch of the evaluation; no_alloc: the launch shape is the cached tuned one
+// (or the default) and no kernel timing is recorded, so the call creates no events.
+klr_status eval_argmin_impl(klr_handle h, const klr_program* progs, int32_t n_progs,
+                            int32_t max_cfg, int32_t max_q, const klr_hw* hw,
+                            const klr_fit_desc* desc, int32_t n_fits,
+                            const uint8_t* exps, int32_t n_exp_rows,
+                            const double* coef, int64_t coef_len,
+                            const int32_t* cfgs, int64_t cfgs_len,
+                            const int32_t* queries, int64_t q_len,
+                            int32_t* argmin, float* best_cost,
+                            float* all_costs, int64_t costs_len, int32_t* prog_status,
+                            void* ws, size_t ws_bytes, void* stream, bool no_alloc) {
   if (!h) return KLR_E_INVALID;
   h->err.clear();
   if (!hw) return fail(h, KLR_E_INVALID, "hw is NULL");
@@ -271,20 +279,41 @@ klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_pro
   klr::EvalArgs a{progs, n_progs, max_cfg, max_q, *hw, desc, n_fits, exps, n_exp_rows, coef, coef_len,
                   cfgs, cfgs_len, queries, q_len, argmin, best_cost, all_costs,
                   all_costs ? costs_len : 0, prog_status, ws, ws_bytes,
-                  reinterpret_cast<hipStream_t>(stream), h->capturing ? nullptr : &h->timer, -1, nullptr, 0};
+                  reinterpret_cast<hipStream_t>(stream), (h->capturing || no_alloc) ? nullptr : &h->timer,
+                  -1, nullptr, 0};
   a.tune_key = klr::eval_tune_key(n_progs, max_cfg, max_q);
   if (h->opt[KLR_OPT_EVAL_VARIANT] >= 0) {
     a.variant = (int)(h->opt[KLR_OPT_EVAL_VARIANT] % klr::eval_num_variants());
   } else {
     a.variant = h->tuner.find(a.tune_key);
-    if (a.variant < 0 && !h->capturing) a.tuner = &h->tuner;
-    if (a.variant < 0 && h->capturing) a.variant = 0;
+    if (a.variant < 0 && !h->capturing && !no_alloc) a.tuner = &h->tuner;
+    if (a.variant < 0 && (h->capturing || no_alloc)) a.variant = 0;
   }
-  return klr::hip_check(h, klr::launch_eval(a), "klr_eval_argmin launch");
+  return klr::hip_check(h, klr::launch_eval(a), no_alloc ? "klr_eval_argmin_noalloc launch" : "klr_eval_argmin launch");
 }
 
-size_t klr_fit_workspace(int32_t n_fits, int64_t f_len, int32_t precision) {
-  return klr::fit_workspace_bytes(n_fits, f_len, precision);
+}  // namespace
+}  // namespace klr
+
+extern "C" {
+
+klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_progs,
+                           int32_t max_cfg, int32_t max_q, const klr_hw* hw,
+                           const klr_fit_desc* desc, int32_t n_fits,
+                           const uint8_t* exps, int32_t n_exp_rows,
+                           const double* coef, int64_t coef_len,
+                           const int32_t* cfgs, int64_t cfgs_len,
+                           const int32_t* queries, int64_t q_len,
+                           int32_t* argmin, float* best_cost,
+                           float* all_costs, int64_t costs_len, int32_t* prog_status,
+                           void* ws, size_t ws_bytes, void* stream) {
+  return klr::eval_argmin_impl(h, progs, n_progs, max_cfg, max_q, hw, desc, n_fits, exps, n_exp_rows, coef,
+                               coef_len, cfgs, cfgs_len, queries, q_len, argmin, best_cost, all_costs,
+                               costs_len, prog_status, ws, ws_bytes, stream, false);
+}
+
+size_t klr_fit_workspace(int32_t n_fits, int64_t total_rows, int32_t precision) {
+  return klr::fit_workspace_bytes(n_fits, total_rows, precision);
 }
 
 klr_status klr_fit_batched(klr_handle h, const klr_fit_desc* desc, int32_t n_fits,
@@ -297,21 +326,26 @@ klr_status klr_fit_batched(klr_handle h, const klr_fit_desc* desc, int32_t n_fit
   h->err.clear();
   if (n_fits < 0 || n_exp_rows < 0 || x_len < 0 || f_len < 0 || coef_len < 0)
     return fail(h, KLR_E_INVALID, "negative size");
-  if (precision != KLR_FP64 && precision != KLR_FP32_REFINED && precision != KLR_BF16_REFINED)
+  if (precision != KLR_FP64 && precision != KLR_FP32_REFINED && precision != KLR_BF16_REFINED &&
+      precision != KLR_FP64_SVD)
     return fail(h, KLR_E_INVALID, "unknown precision");
   if (max_iter < 0 || max_iter > 10000 || !(tol >= 0.0) || !std::isfinite(tol))
     return fail(h, KLR_E_INVALID, "max_iter must be in [0, 10000] and tol finite >= 0");
   if (n_fits == 0) return KLR_OK;
   if (!desc || !exps || !coef || !info || (x_len > 0 && !X) || (f_len > 0 && !f))
     return fail(h, KLR_E_INVALID, "NULL array argument");
-  const size_t need = klr::fit_workspace_bytes(n_fits, f_len, precision);
+  // the fixed part (schedule and scratch offsets); the scratch rows the fits need are only known
+  // on the device, so a shortfall there is reported per fit (KLR_FIT_NO_SCRATCH)
+  const size_t need = klr::fit_workspace_bytes(n_fits, 0, precision);
   if (need > 0 && (!ws || ws_bytes < need))
-    return fail(h, KLR_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    return fail(h, KLR_E_WORKSPACE, "workspace too small: need at least " + std::to_string(need) + " bytes");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
     return fail(h, KLR_E_INVALID, "workspace must be 256-byte aligned");
   klr::FitArgs a{desc, n_fits, exps, n_exp_rows, X, x_len, f, f_len, precision, max_iter, tol,
                  coef, coef_len, info, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream),
-                 h->capturing ? nullptr : &h->timer, h->opt[KLR_OPT_FIT_PERSISTENT] != 0};
+                 h->capturing ? nullptr : &h->timer, h->opt[KLR_OPT_FIT_PERSISTENT] != 0,
+                 nullptr, nullptr, 0};
+  klr::fit_workspace_split(a);
   return klr::hip_check(h, klr::launch_fit(a), "klr_fit_batched launch");
 }
 
@@ -482,9 +516,9 @@ klr_status klr_surrogate_step(klr_handle h, void* params, int32_t n_kernels,
   return klr::hip_check(h, e, "klr_surrogate_step");
 }
 
-size_t klr_surrogate_eval_workspace(int32_t n_progs, int32_t max_cfg, int64_t q_len) {
+size_t klr_surrogate_eval_workspace(int32_t n_progs, int32_t max_cfg, int32_t max_q) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  return al(klr::eval_workspace_bytes(n_progs, max_cfg)) + al(klr::fallback_ws_bytes(n_progs, q_len));
+  return al(klr::eval_workspace_bytes(n_progs, max_cfg)) + al(klr::fallback_ws_bytes(n_progs, max_q));
 }
 
 klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernels,
@@ -494,6 +528,7 @@ klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernel
                               const double* coef, int64_t coef_len, const int32_t* cfgs,
                               int64_t cfgs_len, const int32_t* queries, int64_t q_len,
                               float margin, int32_t* argmin, float* pred_cost, uint8_t* fell_back,
+                              float* pred_margin, int32_t* prog_status,
                               void* ws, size_t ws_bytes, void* stream) {
   if (!h) return KLR_E_INVALID;
   h->err.clear();
@@ -507,27 +542,29 @@ klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernel
   if (max_cfg > 65536) return fail(h, KLR_E_UNSUPPORTED, "max_cfg above 65536");
   if (!progs || !desc || !exps || !coef || !cfgs || !queries || !argmin || !pred_cost || !fell_back)
     return fail(h, KLR_E_INVALID, "NULL array argument");
-  const size_t need = klr_surrogate_eval_workspace(n_progs, max_cfg, q_len);
+  const size_t need = klr_surrogate_eval_workspace(n_progs, max_cfg, max_q);
   if (!ws || ws_bytes < need) return fail(h, KLR_E_WORKSPACE, "workspace too small: need " + std::to_string(need));
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0 || reinterpret_cast<uintptr_t>(params) % 256 != 0)
     return fail(h, KLR_E_INVALID, "params and workspace must be 256-byte aligned");
   const int64_t items = (int64_t)n_progs * (((int64_t)max_q + 255) / 256) * 256;
   const int64_t items_c = (int64_t)n_progs * (((int64_t)max_cfg + 127) / 128) * 128;
-  if (items >= (int64_t(1) << 32) || items_c >= (int64_t(1) << 32))
-    return fail(h, KLR_E_UNSUPPORTED, "launch grid above 2^32 work-items; split the batch");
+  if (items >= (int64_t(1) << 31) || items_c >= (int64_t(1) << 32))
+    return fail(h, KLR_E_UNSUPPORTED, "more than 2^31 query slots or 2^32 configuration slots; split the batch");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   klr::Blob w = klr::blob_of(const_cast<void*>(params), n_kernels);
-  klr::SelectArgs sa{progs, n_progs, max_cfg, max_q, n_kernels, hw->t_max, hw->wave, cfgs, cfgs_len,
-                     queries, q_len, margin, argmin, pred_cost, fell_back};
-  const int t0 = h->capturing ? -1 : h->timer.begin(KLR_K_SURR, s);
-  hipError_t e = klr::launch_select(sa, w, s);
-  if (!h->capturing) h->timer.end(t0, s);
+  klr::SelectArgs sa{progs, n_progs, max_cfg, max_q, n_kernels, n_fits, hw->t_max, hw->wave, cfgs, cfgs_len,
+                     queries, q_len, margin, argmin, pred_cost, fell_back, pred_margin};
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t ews = klr::eval_workspace_bytes(n_progs, max_cfg);
   klr::EvalArgs a{progs, n_progs, max_cfg, max_q, *hw, desc, n_fits, exps, n_exp_rows, coef, coef_len,
-                  cfgs, cfgs_len, queries, q_len, argmin, pred_cost, nullptr, 0, nullptr, ws, ews, s,
+                  cfgs, cfgs_len, queries, q_len, argmin, pred_cost, nullptr, 0, prog_status, ws, ews, s,
                   h->capturing ? nullptr : &h->timer, 0, nullptr, 0};
-  if (e == hipSuccess) e = klr::launch_collapse_only(a);
+  // collapse (program status, per-configuration records), network selection, then the pick
+  // check, compaction and exact sweep of the flagged queries
+  hipError_t e = klr::launch_collapse_only(a);
+  const int t0 = h->capturing ? -1 : h->timer.begin(KLR_K_SURR, s);
+  if (e == hipSuccess) e = klr::launch_select(sa, w, s);
+  if (!h->capturing) h->timer.end(t0, s);
   if (e == hipSuccess) e = klr::launch_fallback(a, fell_back, pred_cost, reinterpret_cast<char*>(ws) + al(ews));
   return klr::hip_check(h, e, "klr_surrogate_eval");
 }

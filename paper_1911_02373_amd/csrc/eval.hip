@@ -96,9 +96,14 @@ __device__ __forceinline__ float clean_max(bool good, float v, float lo) {
   return (good && !(lo > v)) ? v : lo;
 }
 
+// Fitted metrics a program reads: the eight of the cycle estimate, or its one cost function.
+__host__ __device__ inline int program_metrics(const klr_program& P) {
+  return P.cost_kind == KLR_COST_METRIC ? 1 : KLR_N_METRICS;
+}
+
 __device__ bool program_desc_ok(const klr_program& P, const EvalArgs& a) {
-  if (P.reserved != 0) return false;
-  if (P.fit0 < 0 || (int64_t)P.fit0 + KLR_N_METRICS > a.n_fits) return false;
+  if (P.cost_kind != KLR_COST_CYCLES && P.cost_kind != KLR_COST_METRIC) return false;
+  if (P.fit0 < 0 || (int64_t)P.fit0 + program_metrics(P) > a.n_fits) return false;
   if (P.v_launch < 1 || P.v_launch > KLR_MAX_LAUNCH) return false;
   if (P.n_cfg < 0 || P.n_cfg > a.max_cfg || P.n_q < 0 || P.n_q > a.max_q) return false;
   if (P.cfg0 < 0 || P.cfg0 + (int64_t)P.n_cfg * P.v_launch > a.cfgs_len) return false;
@@ -196,9 +201,10 @@ collapse_kernel(EvalArgs a, int chunks) {
   const klr_program P = a.progs[p];
   const bool pd_ok = program_desc_ok(P, a);
   const int v = 1 + (pd_ok ? P.v_launch : 0);
+  const int nmet = program_metrics(P);
   if (threadIdx.x == 0) { s_bad = 0; s_deg = 0; }
   __syncthreads();
-  if (pd_ok && threadIdx.x < KLR_N_METRICS) {
+  if (pd_ok && (int)threadIdx.x < nmet) {
     const klr_fit_desc d = a.desc[P.fit0 + threadIdx.x];
     s_desc[threadIdx.x] = d;
     if (!fit_desc_ok(d, v, a)) atomicOr(&s_bad, 1);
@@ -207,11 +213,11 @@ collapse_kernel(EvalArgs a, int chunks) {
   bool fits_ok = pd_ok && s_bad == 0;
   if (threadIdx.x == 0 && fits_ok) {
     int off = 0;
-    for (int j = 0; j < KLR_N_METRICS; ++j) {
+    for (int j = 0; j < nmet; ++j) {
       s_off[j] = off;
       off += s_desc[j].n_num + s_desc[j].n_den;
     }
-    s_off[KLR_N_METRICS] = off;
+    s_off[nmet] = off;
     s_staged = off <= kCollapseCapRows;
   }
   __syncthreads();
@@ -220,7 +226,7 @@ collapse_kernel(EvalArgs a, int chunks) {
   const bool stage = fits_ok && s_staged;
   if (fits_ok) {
     int emax = 0;
-    for (int j = 0; j < KLR_N_METRICS; ++j) {
+    for (int j = 0; j < nmet; ++j) {
       const klr_fit_desc& d = s_desc[j];
       const int nr = d.n_num + d.n_den;
       for (int t = threadIdx.x; t < nr; t += kCollapseBlock) {
@@ -284,7 +290,7 @@ collapse_kernel(EvalArgs a, int chunks) {
   for (int j = 0; j < KLR_N_METRICS; ++j) {
     double num[kNdeg + 1] = {0, 0, 0, 0}, den[kNdeg + 1] = {1, 0, 0, 0};
     float sc = 1.0f;
-    if (fits_ok) {
+    if (fits_ok && j < nmet) {         // a metric-cost program leaves the other slots 0 / 1
       const klr_fit_desc& d = s_desc[j];
       double Lt[KLR_MAX_LAUNCH];
 #pragma unroll
@@ -448,6 +454,33 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
   return ok ? cost : INFINITY;
 }
 
+// Cost of one point of a program whose one fitted function is the cost: p/q of metric 0 by the
+// same Horner steps and division as the cycle estimate's metrics; +inf where q <= 0, the value is
+// not finite, a launch parameter exceeds N or the configuration is not admissible.
+template <int DEG = kNdeg, bool UNI = true>
+__device__ __forceinline__ float metric_cost(int32_t N, const float* xs, const float* __restrict__ cf,
+                                             const CfgRec& r) {
+  const float x = xs[0];
+  const float2 lo = UNI ? vgpr_pair(cf + 2 * (DEG - 1)) : make_float2(cf[2 * (DEG - 1)], cf[2 * DEG - 1]);
+  float p = __builtin_fmaf(cf[2 * DEG], x, lo.x);
+  float q = __builtin_fmaf(cf[2 * DEG + 1], x, lo.y);
+#pragma unroll
+  for (int d = DEG - 2; d >= 0; --d) {
+    p = __builtin_fmaf(p, x, cf[2 * d]);
+    q = __builtin_fmaf(q, x, cf[2 * d + 1]);
+  }
+  const float g = p / q;
+  const bool ok = (r.ok != 0) & (N >= r.Lmax) & (q > 0.0f) & (fabsf(g) <= 3.402823466e38f);
+  return ok ? g : INFINITY;
+}
+
+// Either cost, chosen per program (wave-uniform).
+template <int GRID, int DEG = kNdeg, bool UNI = true>
+__device__ __forceinline__ float any_cost(int kind, int32_t N, const float* xs, const float* __restrict__ cf,
+                                          const CfgRec& r, const Hw32& hw) {
+  return kind == KLR_COST_METRIC ? metric_cost<DEG, UNI>(N, xs, cf, r) : point_cost<GRID, DEG, UNI>(N, xs, cf, r, hw);
+}
+
 struct SweepOut {
   int32_t* __restrict__ argmin;
   float* __restrict__ best_cost;
@@ -468,7 +501,7 @@ __device__ __forceinline__ void sweep(const float* __restrict__ slot0, const Cfg
   if (P.n_cfg > 0) scaled_n(N, slot0, xs);
   for (int c = 0; c < P.n_cfg; ++c) {
     const CfgRec r = rec0[c];
-    const float cost = point_cost<GRID>(N, xs, slot0 + (int64_t)c * kSlotFloats, r, hw);
+    const float cost = any_cost<GRID>(P.cost_kind, N, xs, slot0 + (int64_t)c * kSlotFloats, r, hw);
     if (costs && live) costs[(int64_t)c * P.n_q] = cost;
     if (cost < best) { best = cost; bi = c; }
   }
@@ -478,7 +511,7 @@ __device__ __forceinline__ void sweep(const float* __restrict__ slot0, const Cfg
   }
 }
 
-template <int QPL, int GRID, int DEG>
+template <int QPL, int GRID, int DEG, int KIND = KLR_COST_CYCLES>
 __device__ __forceinline__ void sweep_cfgs(const klr_program& P, const float* __restrict__ slot0,
                                            const CfgRec* __restrict__ rec0, const Hw32& hw,
                                            const int32_t* N, const bool* live, const int* qi,
@@ -492,7 +525,8 @@ __device__ __forceinline__ void sweep_cfgs(const klr_program& P, const float* __
     const float* cf = slot0 + (int64_t)c * kSlotFloats;
 #pragma unroll
     for (int u = 0; u < QPL; ++u) {
-      const float cost = point_cost<GRID, DEG>(N[u], xs[u], cf, r, hw);
+      const float cost = KIND == KLR_COST_METRIC ? metric_cost<DEG>(N[u], xs[u], cf, r)
+                                                 : point_cost<GRID, DEG>(N[u], xs[u], cf, r, hw);
       if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost;
       if (cost < best[u]) { best[u] = cost; bi[u] = c; }
     }
@@ -530,7 +564,9 @@ eval_kernel(const klr_program* __restrict__ progs, const float* __restrict__ coe
   for (int u = 0; u < QPL; ++u) { best[u] = INFINITY; bi[u] = -1; }
   float* costs = all_costs ? all_costs + P.cost0 : nullptr;
   const int deg = prog_degree(a)[p];
-  if (P.grid_kind == KLR_GRID_1D && deg <= 2)
+  if (P.cost_kind == KLR_COST_METRIC)
+    sweep_cfgs<QPL, KLR_GRID_1D, kNdeg, KLR_COST_METRIC>(P, slot0, rec0, hw, N, live, qi, costs, best, bi);
+  else if (P.grid_kind == KLR_GRID_1D && deg <= 2)
     sweep_cfgs<QPL, KLR_GRID_1D, 2>(P, slot0, rec0, hw, N, live, qi, costs, best, bi);
   else if (P.grid_kind == KLR_GRID_1D)
     sweep_cfgs<QPL, KLR_GRID_1D, kNdeg>(P, slot0, rec0, hw, N, live, qi, costs, best, bi);
@@ -588,8 +624,8 @@ pick_check(EvalArgs a, Hw32 hw, const float* __restrict__ coefs, const CfgRec* _
   float xs[KLR_N_METRICS];
   scaled_n(N, slot0, xs);
   const float cost = P.grid_kind == KLR_GRID_1D
-      ? point_cost<KLR_GRID_1D, kNdeg, false>(N, xs, slot0 + (int64_t)c * kSlotFloats, recs[(int64_t)p * a.max_cfg + c], hw)
-      : point_cost<KLR_GRID_2D, kNdeg, false>(N, xs, slot0 + (int64_t)c * kSlotFloats, recs[(int64_t)p * a.max_cfg + c], hw);
+      ? any_cost<KLR_GRID_1D, kNdeg, false>(P.cost_kind, N, xs, slot0 + (int64_t)c * kSlotFloats, recs[(int64_t)p * a.max_cfg + c], hw)
+      : any_cost<KLR_GRID_2D, kNdeg, false>(P.cost_kind, N, xs, slot0 + (int64_t)c * kSlotFloats, recs[(int64_t)p * a.max_cfg + c], hw);
   if (!(cost < INFINITY)) flags[o] = 1;
 }
 
@@ -694,8 +730,12 @@ hipError_t launch_collapse_only(const EvalArgs& a) {
   return hipGetLastError();
 }
 
-size_t fallback_ws_bytes(int32_t n_progs, int64_t q_len) {
-  return ((size_t)3 * (n_progs > 0 ? n_progs : 0) + 64 + (size_t)(q_len > 0 ? q_len : 0)) * sizeof(int32_t);
+// Counts, offsets, chunk offsets, the chunk total, then the compacted list: every program
+// contributes at most n_q <= max_q flagged queries (counted over its own query range), so
+// n_progs * max_q entries hold the list whatever the programs' query ranges.
+size_t fallback_ws_bytes(int32_t n_progs, int32_t max_q) {
+  const size_t np = (size_t)(n_progs > 0 ? n_progs : 0);
+  return (3 * np + 64 + np * (size_t)(max_q > 0 ? max_q : 0)) * sizeof(int32_t);
 }
 
 hipError_t launch_fallback(const EvalArgs& a, uint8_t* flags, float* best_cost, void* fws) {

@@ -87,6 +87,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 struct FitCtx {
   int n, n_num, n_den, m, v;
   int64_t x0, f0;
+  int64_t r0;      // first row of the fit's private residual scratch in the workspace
   double* S; double* A; double* pt; double* fch; double* rch; double* qch;
   double *D, *c, *z, *t, *s, *p, *g, *gq, *tp;
   double* piv;     // pivots during the factorization, then 1 / L(k, k)
@@ -443,8 +444,8 @@ __device__ __forceinline__ double cg_pass(const FitArgs& a, const FitCtx& C, uin
   const bool owner = rsub == 0;
   double rn = 0.0, qn = 0.0;
   if (MODE == kQ && owner && ri < chunk_rows(C, 0, CH)) {
-    rn = wsr[C.f0 + ri];
-    if (upd) qn = wsq[C.f0 + ri];
+    rn = wsr[C.r0 + ri];
+    if (upd) qn = wsq[C.r0 + ri];
   }
   for (int i0 = 0; i0 < C.m; i0 += CH) {
     const int rows = chunk_rows(C, i0, CH);
@@ -454,8 +455,8 @@ __device__ __forceinline__ double cg_pass(const FitArgs& a, const FitCtx& C, uin
       const int rows2 = chunk_rows(C, i0 + CH, CH);
       load_rows(a, C, i0 + CH, rows2, rl);
       if (MODE == kQ && owner && ri < rows2) {
-        rn2 = wsr[C.f0 + i0 + CH + ri];
-        if (upd) qn2 = wsq[C.f0 + i0 + CH + ri];
+        rn2 = wsr[C.r0 + i0 + CH + ri];
+        if (upd) qn2 = wsq[C.r0 + i0 + CH + ri];
       }
     }
     __syncthreads();
@@ -471,7 +472,7 @@ __device__ __forceinline__ double cg_pass(const FitArgs& a, const FitCtx& C, uin
     }
     dsum = group_sum<TPR>(dsum);
     if (ri < rows && rsub == 0) {
-      const int64_t row = C.f0 + i0 + ri;
+      const int64_t row = C.r0 + i0 + ri;
       if (MODE == kR0) {
         const double r = C.fch[ri] - dsum;
         wsr[row] = r;
@@ -693,6 +694,11 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, int fi, double* smem) 
 
   FitCtx C;
   C.n = n; C.n_num = d.n_num; C.n_den = d.n_den; C.m = d.m; C.v = d.v; C.x0 = d.x0; C.f0 = d.f0;
+  // private residual rows: an exclusive prefix of m over the fits of the workgroup classes, so
+  // fits that share targets never share scratch; a workspace sized for fewer rows than the
+  // fits need is reported per fit
+  C.r0 = a.rowoff[fi];
+  const bool scratch_ok = C.r0 >= 0 && C.r0 + (int64_t)(d.m > 0 ? d.m : 0) <= a.scratch_rows;
   C.S = smem + L::S; C.A = smem + L::A; C.pt = smem + L::PT; C.fch = smem + L::F; C.rch = smem + L::R;
   C.qch = smem + L::Q;
   double* V = smem + L::V;
@@ -725,10 +731,10 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, int fi, double* smem) 
   uint64_t sc = 0;                     // scale exponents s_k, one byte each
 #pragma unroll
   for (int k = 0; k < KLR_MAX_VARS; ++k) sc |= (uint64_t)(uint8_t)d.scale_exp[k] << (8 * k);
-  double* wsr = reinterpret_cast<double*>(a.ws);
-  double* wsq = wsr + a.f_len;
+  double* wsr = a.scratch;
+  double* wsq = wsr + a.scratch_rows;
 
-  bool bad = !ok;
+  bool bad = !ok || !scratch_ok;
   int prec = PREC;
   int iters = 0, rank = 0;
   bool converged = false;
@@ -809,7 +815,7 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, int fi, double* smem) 
     if (coef_ok)
       for (int j = tid; j < n; j += kFitBlock) a.coef[d.coef0 + j] = 0.0;
     if (tid == 0) {
-      info.status = KLR_FIT_BAD_INPUT;
+      info.status = ok ? KLR_FIT_NO_SCRATCH : KLR_FIT_BAD_INPUT;
       info.resid_norm = NAN;
       info.err_est = NAN;
       a.info[fi] = info;
@@ -976,7 +982,52 @@ fit_persistent2(FitArgs a, Plan* pl, const int32_t* __restrict__ order, int cls)
   fit_persistent_body<NM, PREC>(a, pl, order, cls, smem, &next);
 }
 
-size_t plan_offset(int64_t f_len) { return ((size_t)(f_len > 0 ? f_len : 0) * 2 * sizeof(double) + 255) / 256 * 256; }
+// Exclusive prefix of the sample counts of the fits that take a workgroup class (the one-
+// wavefront classes keep their residuals in registers): each such fit owns scratch rows
+// [rowoff[fi], rowoff[fi] + m).  One workgroup scans the batch in chunks of 1024 fits.
+constexpr int kScanBlock = 1024;
+__global__ void __launch_bounds__(kScanBlock) fit_rows_offsets(FitArgs a, int64_t* rowoff) {
+  __shared__ int32_t wsum[kScanBlock / 64];
+  __shared__ int64_t carry;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < a.n_fits; base += kScanBlock) {
+    const int fi = base + tid;
+    int32_t need = 0;
+    if (fi < a.n_fits) {
+      const klr_fit_desc d = a.desc[fi];
+      const int cls = fit_class(a, d);
+      if (cls != kWaveClass && cls != kWaveClass16)
+        need = d.m < 0 ? 0 : (d.m > KLR_MAX_SAMPLES ? KLR_MAX_SAMPLES : d.m);
+    }
+    int32_t inc = need;                        // inclusive scan within the wavefront
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t o = __shfl_up(inc, off);
+      if (lane >= off) inc += o;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int64_t before = carry;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    if (fi < a.n_fits) rowoff[fi] = before + (inc - need);
+    __syncthreads();
+    if (tid == 0) {
+      int64_t t = carry;
+      for (int w = 0; w < kScanBlock / 64; ++w) t += wsum[w];
+      carry = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Workspace: the plan, the longest-first order and bucket keys (int32 per fit), the scratch
+// offsets (int64 per fit), then two FP64 scratch values per sample row (residual and A t).
+size_t head_bytes(int32_t n_fits) {
+  const size_t nf = (size_t)(n_fits > 0 ? n_fits : 0);
+  return (sizeof(Plan) + nf * 2 * sizeof(int32_t) + nf * sizeof(int64_t) + 255) / 256 * 256;
+}
 
 // Two workgroups per CU when the dynamic LDS of a class leaves room for a second one (160 KB
 // per CU, with a margin for the static queue slot and allocation granularity).
@@ -1020,11 +1071,12 @@ hipError_t launch_class(const FitArgs& a, int cls, bool persistent, Plan* pl, co
 
 template <int PREC>
 hipError_t launch_all(const FitArgs& a, bool persistent) {
-  Plan* pl = reinterpret_cast<Plan*>(reinterpret_cast<char*>(a.ws) + plan_offset(a.f_len));
+  Plan* pl = reinterpret_cast<Plan*>(a.ws);
   int32_t* order = reinterpret_cast<int32_t*>(pl + 1);
   int32_t* keys = order + (a.n_fits > 0 ? a.n_fits : 0);
-  hipError_t e = hipSuccess;
-  if (persistent) {
+  hipLaunchKernelGGL(fit_rows_offsets, dim3(1), dim3(kScanBlock), 0, a.stream, a, a.rowoff);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && persistent) {
     const unsigned g = (unsigned)((a.n_fits + kFitBlock - 1) / kFitBlock);
     hipLaunchKernelGGL(fit_plan_zero, dim3(1), dim3(kClasses * kBuckets), 0, a.stream, pl);
     hipLaunchKernelGGL(fit_plan_count, dim3(g), dim3(kFitBlock), 0, a.stream, a, pl, keys);
@@ -1047,12 +1099,21 @@ hipError_t launch_all(const FitArgs& a, bool persistent) {
 
 }  // namespace
 
-size_t fit_workspace_bytes(int32_t n_fits, int64_t f_len, int32_t precision) {
+size_t fit_workspace_bytes(int32_t n_fits, int64_t total_rows, int32_t precision) {
   (void)precision;
-  return plan_offset(f_len) + sizeof(Plan) + (size_t)(n_fits > 0 ? n_fits : 0) * 2 * sizeof(int32_t);
+  return head_bytes(n_fits) + (size_t)(total_rows > 0 ? total_rows : 0) * 2 * sizeof(double);
+}
+
+void fit_workspace_split(FitArgs& a) {
+  const size_t head = head_bytes(a.n_fits);
+  char* base = reinterpret_cast<char*>(a.ws);
+  a.rowoff = reinterpret_cast<int64_t*>(base + sizeof(Plan) + (size_t)(a.n_fits > 0 ? a.n_fits : 0) * 2 * sizeof(int32_t));
+  a.scratch = reinterpret_cast<double*>(base + head);
+  a.scratch_rows = a.ws_bytes > head ? (int64_t)((a.ws_bytes - head) / (2 * sizeof(double))) : 0;
 }
 
 hipError_t launch_fit(const FitArgs& a) {
+  if (a.precision == KLR_FP64_SVD) return launch_fit_svd(a);
   const int t = a.timer ? a.timer->begin(KLR_K_FIT_SOLVE, a.stream) : -1;
   hipError_t e;
   if (a.precision == KLR_FP64) e = launch_all<KLR_FP64>(a, a.persistent);

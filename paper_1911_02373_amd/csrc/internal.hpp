@@ -115,10 +115,17 @@ struct FitArgs {
   hipStream_t stream;
   Timer* timer;
   bool persistent;         // longest-first persistent schedule (else one workgroup per fit)
+  int64_t* rowoff;         // per-fit first scratch row (workspace, set by fit_workspace_split)
+  double* scratch;         // 2 x scratch_rows FP64 residual scratch (workspace)
+  int64_t scratch_rows;
 };
 
-size_t fit_workspace_bytes(int32_t n_fits, int64_t f_len, int32_t precision);
+size_t fit_workspace_bytes(int32_t n_fits, int64_t total_rows, int32_t precision);
+// Point rowoff / scratch / scratch_rows of `a` into its workspace (a.ws, a.ws_bytes, a.n_fits).
+void fit_workspace_split(FitArgs& a);
 hipError_t launch_fit(const FitArgs& a);
+// Fits by one-sided Jacobi SVD (KLR_FP64_SVD), one workgroup per fit.
+hipError_t launch_fit_svd(const FitArgs& a);
 
 // Rows per lane of the one-wavefront fit kernel for this fit: 8 (m <= 512) or 16 (m <= 1024)
 // when n <= 48, v <= 4 and every exponent is <= 3; 0 when the fit takes the workgroup kernel.
@@ -364,7 +371,7 @@ size_t mlp_train_ws_bytes(int32_t nk, int32_t B);
 
 struct SelectArgs {
   const klr_program* progs;
-  int32_t n_progs, max_cfg, max_q, nk;
+  int32_t n_progs, max_cfg, max_q, nk, n_fits;
   int32_t t_max, wave;
   const int32_t* cfgs;
   int64_t cfgs_len;
@@ -374,6 +381,7 @@ struct SelectArgs {
   int32_t* argmin;
   float* pred_cost;
   uint8_t* fell_back;
+  float* pred_margin;      // optional: second-best minus best prediction (ln units) per query
 };
 
 hipError_t launch_refresh(const Blob& w, hipStream_t s);
@@ -387,7 +395,7 @@ hipError_t launch_select(const SelectArgs& a, const Blob& w, hipStream_t s);
 // Exact re-evaluation of the queries flagged by the surrogate (compaction by program, then the
 // exact sweep over the compacted list); the collapse workspace must already hold the program
 // coefficients (launch_eval's collapse).  Workspace beyond eval_workspace_bytes:
-size_t fallback_ws_bytes(int32_t n_progs, int64_t q_len);
+size_t fallback_ws_bytes(int32_t n_progs, int32_t max_q);
 hipError_t launch_fallback(const EvalArgs& a, uint8_t* flags, float* best_cost, void* fws);
 hipError_t launch_collapse_only(const EvalArgs& a);
 

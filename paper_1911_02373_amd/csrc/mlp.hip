@@ -610,11 +610,17 @@ mlp_select(SelectArgs a, Blob w, int chunks, int64_t n_items) {
     const int p = (int)(item / chunks);
     const int qb = (int)(item % chunks) * kSelQ;
     const klr_program P = a.progs[p];
-    const bool range_ok = P.reserved == 0 && P.n_q >= 0 && P.n_q <= a.max_q && P.q0 >= 0 &&
-                          P.q0 + (int64_t)P.n_q <= a.q_len;
-    if (!range_ok || qb >= P.n_q) continue;
-    const bool sel_ok = P.v_launch == 2 && P.n_cfg >= 0 && P.n_cfg <= a.max_cfg && P.n_cfg <= kSelMaxCfg &&
-                        P.cfg0 >= 0 && P.cfg0 + 2 * (int64_t)P.n_cfg <= a.cfgs_len;
+    // the descriptor checks of the exact path: a program it rejects gets no output here either
+    const int nmet = P.cost_kind == KLR_COST_METRIC ? 1 : KLR_N_METRICS;
+    const bool desc_ok = (P.cost_kind == KLR_COST_CYCLES || P.cost_kind == KLR_COST_METRIC) && P.fit0 >= 0 &&
+                         (int64_t)P.fit0 + nmet <= a.n_fits &&
+                         P.v_launch >= 1 && P.v_launch <= KLR_MAX_LAUNCH && P.n_cfg >= 0 &&
+                         P.n_cfg <= a.max_cfg && P.n_q >= 0 && P.n_q <= a.max_q && P.cfg0 >= 0 &&
+                         P.cfg0 + (int64_t)P.n_cfg * P.v_launch <= a.cfgs_len && P.q0 >= 0 &&
+                         P.q0 + (int64_t)P.n_q <= a.q_len &&
+                         (P.grid_kind == KLR_GRID_1D || (P.grid_kind == KLR_GRID_2D && P.v_launch >= 2));
+    if (!desc_ok || qb >= P.n_q) continue;
+    const bool sel_ok = P.v_launch == 2 && P.n_cfg <= kSelMaxCfg;
     const int qe = qb + kSelQ < P.n_q ? qb + kSelQ : P.n_q;
     if (!sel_ok) {   // not representable by the network: the exact path answers these queries
       for (int qi = qb + tid; qi < qe; qi += 64 * kSelWaves) {
@@ -622,6 +628,7 @@ mlp_select(SelectArgs a, Blob w, int chunks, int64_t n_items) {
         a.argmin[o] = -1;
         a.pred_cost[o] = INFINITY;
         a.fell_back[o] = 1;
+        if (a.pred_margin) a.pred_margin[o] = NAN;
       }
       continue;
     }
@@ -736,6 +743,7 @@ mlp_select(SelectArgs a, Blob w, int chunks, int64_t n_items) {
         a.argmin[o] = found ? bi : -1;
         a.pred_cost[o] = found ? expf(best) : INFINITY;
         a.fell_back[o] = (!found || !(sec - best >= lnm)) ? 1 : 0;
+        if (a.pred_margin) a.pred_margin[o] = found ? sec - best : NAN;
       }
     }
   }

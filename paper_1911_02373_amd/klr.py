@@ -31,7 +31,7 @@ HW = np.dtype([("n_cu", "<i4"), ("wave", "<i4"), ("w_max", "<i4"), ("b_max", "<i
                ("mem_lat", "<f4"), ("dep_delay", "<f4"), ("issue_cycles", "<f4"), ("bw", "<f4")])
 PROGRAM = np.dtype([("cfg0", "<i8"), ("q0", "<i8"), ("cost0", "<i8"), ("fit0", "<i4"),
                     ("v_launch", "<i4"), ("n_cfg", "<i4"), ("n_q", "<i4"), ("grid_kind", "<i4"),
-                    ("reserved", "<i4")])
+                    ("cost_kind", "<i4")])
 
 EXPORTS = ("klr_create", "klr_destroy", "klr_last_error", "klr_fit_workspace", "klr_fit_batched",
            "klr_eval_workspace", "klr_eval_argmin", "klr_abi_layout", "klr_profile_enable",
@@ -110,10 +110,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.klr_surrogate_predict.restype = I32
     lib.klr_surrogate_step.argtypes = [P, P, I32, P, P, P, P, I32, F, I32, F, F, F, P, P, P, SZ, P]
     lib.klr_surrogate_step.restype = I32
-    lib.klr_surrogate_eval_workspace.argtypes = [I32, I32, I64]
+    lib.klr_surrogate_eval_workspace.argtypes = [I32, I32, I32]
     lib.klr_surrogate_eval_workspace.restype = SZ
     lib.klr_surrogate_eval.argtypes = [P, P, I32, P, I32, I32, I32, P, P, I32, P, I32, P, I64, P, I64,
-                                       P, I64, F, P, P, P, P, SZ, P]
+                                       P, I64, F, P, P, P, P, P, P, SZ, P]
     lib.klr_surrogate_eval.restype = I32
     return lib
 
@@ -223,6 +223,8 @@ def program_descs(pb, with_costs: bool = False) -> np.ndarray:
     d["cfg0"], d["q0"] = pb.cfg0, pb.q0
     d["fit0"], d["v_launch"], d["n_cfg"], d["n_q"] = pb.fit0, pb.v_launch, pb.n_cfg, pb.n_q
     d["grid_kind"] = pb.grid_kind
+    if getattr(pb, "cost_kind", None) is not None:
+        d["cost_kind"] = pb.cost_kind
     if with_costs:
         sizes = pb.n_cfg.astype(np.int64) * pb.n_q
         d["cost0"][1:] = np.cumsum(sizes)[:-1]
@@ -238,9 +240,12 @@ def eval_fit_descs(pb) -> np.ndarray:
     # a program whose fit range lies outside the batch is left to the device check, which
     # reports it as a bad descriptor)
     fit0 = np.asarray(pb.fit0, np.int64)
-    inb = (fit0 >= 0) & (fit0 + N_METRICS <= n)
-    fit_idx = (fit0[inb][:, None] + np.arange(N_METRICS)).reshape(-1)
-    d["v"][fit_idx] = np.repeat(1 + np.asarray(pb.v_launch)[inb], N_METRICS)
+    ck = getattr(pb, "cost_kind", None)
+    nmet = np.where(np.asarray(ck) == 1, 1, N_METRICS) if ck is not None else np.full(fit0.shape, N_METRICS)
+    for k in (1, N_METRICS):
+        sel = (nmet == k) & (fit0 >= 0) & (fit0 + k <= n)
+        fit_idx = (fit0[sel][:, None] + np.arange(k)).reshape(-1)
+        d["v"][fit_idx] = np.repeat(1 + np.asarray(pb.v_launch)[sel], k)
     d["num0"], d["n_num"], d["den0"], d["n_den"] = pb.num0, pb.n_num, pb.den0, pb.n_den
     d["scale_exp"] = pb.scale_exp
     return d
@@ -432,8 +437,9 @@ class Library:
         return grads, loss
 
     def surrogate_eval(self, blob_t, n_kernels: int, de: DeviceEval, margin: float = 0.02, out=None,
-                       stream=None):
-        """Returns (argmin int32, pred_cost float32, fell_back uint8)."""
+                       stream=None, pred_margin=None, prog_status=None):
+        """Returns (argmin int32, pred_cost float32, fell_back uint8); pred_margin (float32
+        [q_len]) and prog_status (int32 [n_progs]) are optional output tensors."""
         torch = _torch()
         ql = int(de.queries.numel())
         if out is None:
@@ -442,20 +448,21 @@ class Library:
             fb = torch.empty(ql, dtype=torch.uint8, device=de.queries.device)
         else:
             am, pc, fb = out
-        need = int(self.lib.klr_surrogate_eval_workspace(de.n_progs, de.max_cfg, ql))
+        need = int(self.lib.klr_surrogate_eval_workspace(de.n_progs, de.max_cfg, de.max_q))
         if getattr(de, "sws", None) is None or de.sws.numel() < need:
             de.sws = self._aligned(need, de.queries.device)
         st = self.lib.klr_surrogate_eval(
             self.h, _ptr(blob_t), n_kernels, _ptr(de.progs), de.n_progs, de.max_cfg, de.max_q,
             de.hw.ctypes.data, _ptr(de.desc), de.n_fits, _ptr(de.exps), de.n_exp_rows, _ptr(de.coef),
             int(de.coef.numel()), _ptr(de.cfgs), int(de.cfgs.numel()), _ptr(de.queries), ql, margin,
-            _ptr(am), _ptr(pc), _ptr(fb), _ptr(de.sws), int(de.sws.numel()), self._stream(stream))
+            _ptr(am), _ptr(pc), _ptr(fb), _ptr(pred_margin), _ptr(prog_status), _ptr(de.sws),
+            int(de.sws.numel()), self._stream(stream))
         self._check(st)
         return am, pc, fb
 
     # ---- fit ----------------------------------------------------------------------------
-    def fit_workspace(self, n_fits: int, f_len: int, precision: int) -> int:
-        return int(self.lib.klr_fit_workspace(n_fits, f_len, precision))
+    def fit_workspace(self, n_fits: int, total_rows: int, precision: int) -> int:
+        return int(self.lib.klr_fit_workspace(n_fits, total_rows, precision))
 
     def fit_batched(self, df: "DeviceFit", precision: int = KLR_FP64, max_iter: int = 32,
                     tol: float = 1e-12, out=None, stream=None):
@@ -466,7 +473,7 @@ class Library:
             info = torch.empty(max(df.n_fits, 1) * FIT_INFO.itemsize, dtype=torch.uint8, device=df.f.device)
         else:
             coef, info = out
-        wsb = self.fit_workspace(df.n_fits, int(df.f.numel()), precision)
+        wsb = self.fit_workspace(df.n_fits, df.total_rows, precision)
         if df.ws is None or df.ws.numel() < wsb:
             df.ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=df.f.device)
         st = self.lib.klr_fit_batched(
@@ -486,6 +493,7 @@ class DeviceFit:
     X: object
     f: object
     n_coef: int
+    total_rows: int = 0          # sum of the fits' sample counts (sizes the private scratch)
     ws: object = None
 
     @classmethod
@@ -493,7 +501,7 @@ class DeviceFit:
         return cls(desc=to_device(fit_descs(fb), device), n_fits=fb.n_fits,
                    exps=to_device(fb.exps.astype(np.uint8), device), n_exp_rows=int(fb.exps.shape[0]),
                    X=to_device(fb.X.astype(np.int32), device), f=to_device(fb.f.astype(np.float64), device),
-                   n_coef=int(fb.n_coef))
+                   n_coef=int(fb.n_coef), total_rows=int(np.clip(fb.m, 0, None).sum()))
 
 
 def info_records(info) -> np.ndarray:

@@ -158,6 +158,40 @@ def config1_fit(seed: int, noise: float = 0.01, n_samples: int = 200) -> FitBatc
                       truth=[truth], meta={"grid": grid.astype(np.int32), "noise": noise})
 
 
+def config1_program(fb: FitBatch, coef: np.ndarray | None = None) -> "ProgramBatch":
+    """The rational program of the single-fit workload: its one fitted function (fit 0 of `fb`,
+    over (N, B)) is the cost, evaluated on the full 11 x 32 grid (queries N = 2^10..2^20,
+    configurations B = 32..1024 step 32, one launch parameter) with the per-N argmin over B.
+    The wavefront is 32 wide here (the paper's warp), so every B is a whole number of waves.
+    `coef` defaults to the generator's truth coefficients."""
+    grid = fb.meta["grid"]
+    Ns = np.unique(grid[:, 0]).astype(np.int32)
+    Bs = np.unique(grid[:, 1]).astype(np.int32)
+    c = fb.truth_coef if coef is None else coef
+    return ProgramBatch(
+        fits=None, coef=np.asarray(c, np.float64), exps=fb.exps, num0=fb.num0[:1], n_num=fb.n_num[:1],
+        den0=fb.den0[:1], n_den=fb.n_den[:1], coef0=np.zeros(1, np.int64), scale_exp=fb.scale_exp[:1],
+        v_launch=np.ones(1, np.int32), fit0=np.zeros(1, np.int32), cfg0=np.zeros(1, np.int64),
+        n_cfg=np.array([Bs.size], np.int32), grid_kind=np.zeros(1, np.int32), q0=np.zeros(1, np.int64),
+        n_q=np.array([Ns.size], np.int32), cfgs=Bs.copy(), queries=Ns.copy(), hw=HW(wave=32),
+        cost_kind=np.ones(1, np.int32))
+
+
+def config1_truth_grid(fb: FitBatch) -> np.ndarray:
+    """The generator's noise-free metric on the 11 x 32 grid, [B][N] (the decision-quality
+    reference of the single-fit workload)."""
+    grid = fb.meta["grid"]
+    Ns = np.unique(grid[:, 0])
+    Bs = np.unique(grid[:, 1])
+    n_num = int(fb.n_num[0])
+    E = fb.exps[:n_num, :2]
+    t = fb.truth_coef
+    c_den = np.concatenate([[1.0], t[n_num:]])
+    pts = np.array([(n, b) for b in Bs for n in Ns], np.float64)
+    xt = pts * 2.0 ** -fb.scale_exp[0, :2].astype(np.float64)
+    return _truth_value(xt, E, fb.exps[fb.den0[0]: fb.den0[0] + fb.n_den[0], :2], t[:n_num], c_den).reshape(Bs.size, Ns.size)
+
+
 LITERAL_PAIRS = np.array([(bx, by) for bx in (16, 32, 48, 64) for by in (16, 32, 48, 64)
                           if bx * by <= 1024], np.int32)
 POW2_PAIRS = np.array([(1 << a, 1 << b) for a in range(11) for b in range(11)
@@ -251,6 +285,7 @@ class ProgramBatch:
     cfgs: np.ndarray           # int32 flat
     queries: np.ndarray        # int32 flat
     hw: HW
+    cost_kind: np.ndarray | None = None    # per program: 0 cycle estimate (default), 1 fitted metric
 
     @property
     def n_progs(self) -> int:

@@ -172,3 +172,59 @@ def test_deterministic(klr):
     b = _run(klr, pb)
     for x, y in zip(a, b):
         assert np.array_equal(np.asarray(x).view(np.uint8), np.asarray(y).view(np.uint8))
+
+
+def fp64_truth_report(pb, am, bc, costs, progs):
+    """Error of the FP32 results against the FP64 cycle estimate (each metric the full
+    multivariate p/q in FP64, exact integer parts) for the listed programs: the rate at which
+    the FP32 argmin differs from the FP64 one, the regret of the FP32 pick under the FP64
+    costs, the relative error of the FP32 best cost and of every FP32 cost, and admissibility
+    disagreements."""
+    dis = n = adm = 0
+    regrets, rel, rel_all = [], [], []
+    off = 0
+    for p in progs:
+        q0, nq, nc = int(pb.q0[p]), int(pb.n_q[p]), int(pb.n_cfg[p])
+        c64 = oc.program_costs(pb, p, mode="truth")
+        c32 = costs[off: off + nc * nq].reshape(nc, nq).astype(np.float64)
+        off += nc * nq
+        fin = np.isfinite(c32) & np.isfinite(c64)
+        rel_all.append(np.abs(c32[fin] - c64[fin]) / c64[fin])
+        i64, b64 = oc.argmin_lowest(c64)
+        a32, b32 = am[q0:q0 + nq], bc[q0:q0 + nq].astype(np.float64)
+        dis += int(np.sum(a32 != i64))
+        n += nq
+        adm += int(np.sum((i64 >= 0) != (a32 >= 0)))
+        ok = (i64 >= 0) & (a32 >= 0)
+        picked = c64[np.maximum(a32, 0), np.arange(nq)]
+        regrets.append(picked[ok] / b64[ok] - 1.0)
+        rel.append(np.abs(b32[ok] - b64[ok]) / b64[ok])
+    r, e, ea = np.concatenate(regrets), np.concatenate(rel), np.concatenate(rel_all)
+    return {"queries": n, "argmin_mismatch_rate": dis / max(n, 1), "admissible_mismatch": adm,
+            "cost_rel_err_max": float(ea.max()) if ea.size else 0.0,
+            "regret_max": float(r.max()) if r.size else 0.0, "regret_p999": float(np.quantile(r, 0.999)) if r.size else 0.0,
+            "best_cost_rel_err_max": float(e.max()) if e.size else 0.0,
+            "best_cost_rel_err_median": float(np.median(e)) if e.size else 0.0}
+
+
+@pytest.mark.parametrize("kind", ["c3", "mixed"])
+def test_fp32_results_against_fp64_truth(klr, kind):
+    """The FP32 evaluation against the FP64 cycle estimate: on c3 programs (degree 2, 2048
+    queries each) and on uneven programs (1-4 launch parameters, degree 3, 1-D and 2-D grids)
+    the FP32 argmin is the FP64 argmin wherever the FP64 runner-up is more than the FP32 error
+    away; the regret of every FP32 pick under FP64 costs stays within twice the FP32 cost error
+    (so near-ties at FP32 resolution are the only place the two can part); best costs agree to
+    a few FP32 ulps in the median."""
+    if kind == "c3":
+        pb = synth.config3_programs(41, n_progs=6, n_q=2048)
+    else:
+        pb = synth.mixed_programs(42, 16, n_q_range=(50, 400), n_cfg_range=(16, 160))
+    am, bc, costs, st = _run(klr, pb, want_costs=True)
+    assert np.all(st == 0)
+    rep = fp64_truth_report(pb, am, bc, costs, range(pb.n_progs))
+    print(kind, rep)
+    eps = rep["cost_rel_err_max"]
+    assert eps < 1e-5 and rep["best_cost_rel_err_median"] < 1e-6, rep
+    assert rep["admissible_mismatch"] <= 1e-3 * rep["queries"], rep
+    assert rep["argmin_mismatch_rate"] <= 1e-3, rep
+    assert rep["regret_max"] <= 2 * eps / (1 - eps) + 1e-12, rep

@@ -276,3 +276,30 @@ def test_underdetermined_deterministic_whatever_the_workspace(klr, kind):
         A, b = of.design_matrix(Xi, fi, En, Ed, s)
         y, yo = _coefs(fb, coef, f), _coefs(fb, ora, f)
         assert np.linalg.norm(A @ y - A @ yo) <= 1e-6 * np.linalg.norm(b), f
+
+
+def test_fits_sharing_targets_use_private_scratch(klr):
+    """Fits may share their samples and targets (the same metric fitted with two monomial
+    sets, or twice): the workgroup kernel keeps each fit's FP64 residuals in scratch rows of its
+    own, so n = 69 and n = 111 fits over one target range all match the oracle."""
+    import copy
+    fb, _ = synth.config5_batch(23, n_progs=2, n_q=1, m_range=(300, 400), v_launch_choices=(3, 4))
+    fb = copy.copy(fb)
+    fb.x0, fb.f0, fb.m = fb.x0.copy(), fb.f0.copy(), fb.m.copy()
+    n_unk = fb.n_num + fb.n_den - 1
+    big = np.nonzero(n_unk > 48)[0]
+    assert big.size >= 4
+    lead = big[0]
+    for i in big[1:]:                      # every workgroup-class fit reads fit `lead`'s samples
+        if fb.v[i] == fb.v[lead]:
+            fb.x0[i], fb.f0[i], fb.m[i] = fb.x0[lead], fb.f0[lead], fb.m[lead]
+    shared = [i for i in big if fb.f0[i] == fb.f0[lead]]
+    assert len(shared) >= 2
+    cg, ig = _run(klr, fb, max_iter=256, tol=1e-12)
+    ora, _ = of.fit_batch(fb, indices=shared)
+    for i in shared:
+        assert ig["status"][i] & (of.BAD_INPUT | of.NOT_CONVERGED) == 0, (i, int(ig["status"][i]))
+        Xi, fi, En, Ed, s = fb.fit_arrays(i)
+        A, _ = of.design_matrix(Xi, fi, En, Ed, s)
+        y, yo = _coefs(fb, cg, i), _coefs(fb, ora, i)
+        assert np.linalg.norm(A @ (y - yo)) <= 1e-8 * np.linalg.norm(fi), i

@@ -285,3 +285,130 @@ def test_pick_check_sends_inadmissible_picks_to_the_exact_path(klr):
     assert np.all(fb.cpu().numpy() == 1)
     assert np.array_equal(am.cpu().numpy(), ea)
     assert np.array_equal(pc.cpu().numpy().view(np.uint32), eb.view(np.uint32))
+
+
+def _select_reference(prm, pb, n_progs):
+    """Oracle predictions (ln C) of every statically admissible configuration of each query of
+    the first n_progs programs, with the operands the selection kernel rounds to bfloat16
+    rounded the same way; +inf where not statically admissible.  Also the bound
+    2^-12 * sum |w3| (|W2| h1 + |b2|) of each point's FP32 accumulation error (relative
+    rounding of 256-term sums, 256 * 2^-24 = 2^-16, with a factor 16 for the first layer's FP32
+    inputs shifting a bfloat16 rounding of h1 now and then), in standardised units."""
+    P = prm["P"]
+    cfg = pb.cfgs.reshape(-1, 2)
+    hw = pb.hw
+    out, bnd = [], []
+    for p in range(n_progs):
+        nq, nc = int(pb.n_q[p]), int(pb.n_cfg[p])
+        q0, c0 = int(pb.q0[p]), int(pb.cfg0[p]) // 2
+        N = pb.queries[q0:q0 + nq].astype(np.int64)
+        C = cfg[c0:c0 + nc].astype(np.int64)
+        T = C[:, 0] * C[:, 1]
+        stat = (T <= hw.t_max) & (T % hw.wave == 0) & (C.min(axis=1) >= 1)
+        kid = np.full(nq * nc, p)
+        NN = np.repeat(N, nc)
+        bx, by = np.tile(C[:, 0], nq), np.tile(C[:, 1], nq)
+        y = om.forward_bf16(P, kid, NN, bx, by).reshape(nq, nc)
+        x = om.features(NN, bx, by, P["emb"][kid])
+        h1 = om.bf16_round(np.maximum(x @ P["W1"].T + P["b1"], 0.0))
+        s = (np.abs(h1) @ np.abs(om.bf16_round(P["W2"])).T + np.abs(P["b2"])) @ np.abs(P["w3"])
+        ok = stat[None, :] & (C.max(axis=1)[None, :] <= N[:, None])
+        out.append(np.where(ok, prm["mu"] + prm["sigma"] * y, np.inf))
+        bnd.append(2.0 ** -12 * s.reshape(nq, nc) * abs(prm["sigma"]))
+    return out, bnd
+
+
+def test_selection_matches_network_elementwise(klr, trained):
+    """mlp_select against the network oracle, query by query (8 programs x 256 queries x 128
+    configurations): the predicted ln C of its pick equals the oracle's minimum over the
+    statically admissible configurations, its predicted margin (second best minus best) the
+    oracle's margin, both within the FP32 accumulation bound; the pick is the oracle's argmin
+    wherever the oracle's margin exceeds twice the bound; with margin 0 only a pick the exact
+    program rules out falls back, and the fallback flag follows the oracle's margin at 2 %."""
+    import torch
+    from paper_1911_02373_amd.klr import DeviceEval
+    pb, blob, _ = trained
+    nk = pb.n_progs
+    sub = synth.take_programs(pb, 8)
+    de = DeviceEval.from_batch(klr, sub)
+    ql = int(sub.queries.size)
+    marg = torch.empty(ql, dtype=torch.float32, device="cuda")
+    st = torch.empty(sub.n_progs, dtype=torch.int32, device="cuda")
+    ea, eb, _, _ = klr.eval_argmin(de)
+    am, pc, fb = klr.surrogate_eval(blob, nk, de, margin=0.0, pred_margin=marg, prog_status=st)
+    am2, _, fb2 = klr.surrogate_eval(blob, nk, de, margin=0.02)
+    torch.cuda.synchronize()
+    am, pc, fb, marg = am.cpu().numpy(), pc.cpu().numpy(), fb.cpu().numpy().astype(bool), marg.cpu().numpy()
+    ea, eb = ea.cpu().numpy(), eb.cpu().numpy()
+    fb2, am2 = fb2.cpu().numpy().astype(bool), am2.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    prm = klr.surrogate_params(blob, nk)
+    refs, bnds = _select_reference(prm, sub, sub.n_progs)
+    checked = strict = 0
+    for p in range(sub.n_progs):
+        nq, q0 = int(sub.n_q[p]), int(sub.q0[p])
+        R, Bd = refs[p], bnds[p]
+        for i in range(nq):
+            o = q0 + i
+            row = R[i]
+            fin = np.isfinite(row)
+            if fin.sum() < 2:
+                continue
+            order = np.argsort(row, kind="stable")          # lowest index among equal values
+            b0, b1 = row[order[0]], row[order[1]]
+            tol = float(Bd[i][fin].max())
+            # the pick the kernel made is a statically admissible one whose prediction is within
+            # the bound of the oracle's minimum; its margin is the oracle's margin within 2 bounds
+            if not fb[o]:
+                assert np.isfinite(row[am[o]]), (p, i, am[o])
+                assert abs(np.log(pc[o]) - b0) <= tol + 1e-6 * abs(b0), (p, i, np.log(pc[o]), b0, tol)
+            else:
+                # margin 0: a fallback means the exact program rules the pick out
+                assert not np.isfinite(eb[o]) or am[o] == ea[o]
+            assert abs(marg[o] - (b1 - b0)) <= 2 * tol + 1e-6 * abs(b0), (p, i, marg[o], b1 - b0, tol)
+            if b1 - b0 > 2 * tol and not fb[o]:
+                assert am[o] == order[0], (p, i, am[o], order[0], b1 - b0, tol)
+                strict += 1
+            # the 2 % rule, away from its threshold
+            if not fb[o] and (b1 - b0) > np.log1p(0.02) + 2 * tol:
+                assert not fb2[o] and am2[o] == am[o], (p, i)
+            if (b1 - b0) < np.log1p(0.02) - 2 * tol:
+                assert fb2[o], (p, i)
+            checked += 1
+    assert checked > 0.9 * ql and strict > 0.5 * checked, (checked, strict, ql)
+
+
+def test_surrogate_bad_descriptor_and_shared_query_ranges(klr, trained):
+    """Program 1's fit range lies outside the batch: it gets KLR_PROG_BAD_DESC and the selection
+    writes none of its outputs (as klr_eval_argmin does); programs 0 and 2 are answered as
+    usual.  Programs 3 and 4 are the same program over the same query range: each counts its
+    flagged queries over that range, so the compacted lists (2 n_q entries for n_q queries)
+    stay inside the workspace, and both answer with the exact path's result."""
+    import copy
+
+    import torch
+    from paper_1911_02373_amd.klr import DeviceEval
+    pb, blob, _ = trained
+    sub = copy.copy(synth.take_programs(pb, 5))
+    sub.fit0 = sub.fit0.copy()
+    sub.q0, sub.cfg0 = sub.q0.copy(), sub.cfg0.copy()
+    sub.fit0[1] = 10 ** 6
+    sub.fit0[4], sub.cfg0[4], sub.q0[4] = sub.fit0[3], sub.cfg0[3], sub.q0[3]
+    de = DeviceEval.from_batch(klr, sub)
+    ql = int(sub.queries.size)
+    ea, eb, _, est = klr.eval_argmin(de)
+    out = (torch.full((ql,), -7, dtype=torch.int32, device="cuda"),
+           torch.full((ql,), 123.0, dtype=torch.float32, device="cuda"),
+           torch.full((ql,), 9, dtype=torch.uint8, device="cuda"))
+    st = torch.full((sub.n_progs,), -1, dtype=torch.int32, device="cuda")
+    am, pc, fb = klr.surrogate_eval(blob, pb.n_progs, de, margin=1e9, out=out, prog_status=st)
+    torch.cuda.synchronize()
+    am, pc, fb = am.cpu().numpy(), pc.cpu().numpy(), fb.cpu().numpy()
+    ea, eb = ea.cpu().numpy(), eb.cpu().numpy()
+    assert list(st.cpu().numpy()) == [0, 1, 0, 0, 0] == list(est.cpu().numpy())
+    r1 = slice(int(sub.q0[1]), int(sub.q0[1] + sub.n_q[1]))
+    assert np.all(am[r1] == -7) and np.all(pc[r1] == 123.0) and np.all(fb[r1] == 9)
+    for p in (0, 2, 3):
+        r = slice(int(sub.q0[p]), int(sub.q0[p] + sub.n_q[p]))
+        assert np.all(fb[r] == 1)
+        assert np.array_equal(am[r], ea[r]) and np.array_equal(pc[r].view(np.uint32), eb[r].view(np.uint32))

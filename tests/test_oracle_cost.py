@@ -207,3 +207,111 @@ def test_fma32_special_values():
     assert np.isnan(oc.fma32(nan, np.float32(1), np.float32(1)))
     big = np.float32(3e38)
     assert oc.fma32(big, np.float32(2), np.float32(0)) == inf
+
+
+def _generator_truth(pb, fi, j, N, L):
+    """lo_j + s_j p/q of fit fi at (N, L), from the generator's own description of the c3
+    programs (numerator coefficients lo_j q + s_j p, q's constant 1, total degree <= 2 in
+    (N/2^26, bx/2^10, by/2^10)), evaluated with numpy powers: no code shared with the oracle."""
+    E = synth.monomials(3, 2)[:, :3].astype(np.float64)
+    nm = E.shape[0]
+    c = pb.coef[fi * (2 * nm - 1): (fi + 1) * (2 * nm - 1)]
+    q = np.concatenate([[1.0], c[nm:]])
+    lo, hi = synth.METRIC_RANGES[j]
+    s = (hi - lo) / 20.0
+    p = (c[:nm] - lo * q) / s
+    x = np.stack([np.asarray(N, np.float64) / 2.0 ** 26, np.full(len(N), L[0] / 2.0 ** 10),
+                  np.full(len(N), L[1] / 2.0 ** 10)], axis=1)
+    mono = np.prod(x[:, None, :] ** E[None, :, :], axis=2)
+    return lo + s * (mono @ p) / (mono @ q)
+
+
+def test_metric_truth_and_collapse_match_the_generators_metrics():
+    """metric_truth (p/q of each metric's own coefficient slice) and the FP32 collapse of the
+    same slice, against the generator's lo_j + s_j p/q for non-constant metrics of c3 programs:
+    a wrong coefficient slice, scale exponent or denominator constant fails here."""
+    pb = synth.config3_programs(12, n_progs=3, n_q=300)
+    cfgs = synth.config3_launch_configs()
+    rng = np.random.default_rng(3)
+    for prog in range(3):
+        N = pb.queries[pb.q0[prog]: pb.q0[prog] + 300].astype(np.int64)
+        mets = oc._metric_slices(pb, prog)
+        for c in rng.choice(127, 10, replace=False):
+            for j, (cf, En, Ed, s) in enumerate(mets):
+                want = _generator_truth(pb, int(pb.fit0[prog]) + j, j, N, cfgs[c])
+                p, q = oc.metric_truth(cf, En, Ed, s, N, cfgs[c])
+                assert np.allclose(p / q, want, rtol=1e-12, atol=0), (prog, c, j)
+                a, b = oc.collapse(cf, En, Ed, s, cfgs[c])
+                x = np.asarray(N, np.float64) / 2.0 ** 26
+                val = np.polyval(a[::-1].astype(np.float64), x) / np.polyval(b[::-1].astype(np.float64), x)
+                assert np.allclose(val, want, rtol=2e-6, atol=0), (prog, c, j)
+
+
+def test_metric_truth_matches_fitted_rational_value():
+    """A metric fitted by the oracle's least squares and read back through a program's
+    coefficient layout: metric_truth equals oracle.fit.rational_value at the same points (both
+    are p/q of the fitted coefficients), and noise-free samples give back the generator's truth."""
+    from oracle import fit as of
+    pb = synth.config3_programs(13, n_progs=1, n_q=64)
+    cfgs = synth.config3_launch_configs()
+    rng = np.random.default_rng(4)
+    E = synth.monomials(3, 2)
+    nm = E.shape[0]
+    for j in range(synth.N_METRICS):
+        # 120 samples of metric j at (N, bx, by) on the program's configurations
+        Ns = np.rint(2.0 ** rng.uniform(8, 26, 120)).astype(np.int64)
+        cs = cfgs[rng.integers(0, 127, 120)]
+        f = np.array([_generator_truth(pb, j, j, Ns[i:i + 1], cs[i])[0] for i in range(120)])
+        Xi = np.stack([Ns, cs[:, 0], cs[:, 1]], 1).astype(np.int32)
+        s = np.array([26, 10, 10], np.int8)
+        coef, info = of.fit_one(Xi, f, E[:, :3], E[:, :3], s)
+        assert info["rank"] == 2 * nm - 1
+        for c in rng.choice(127, 4, replace=False):
+            N = np.rint(2.0 ** rng.uniform(8, 26, 50)).astype(np.int64)
+            p, q = oc.metric_truth(coef, E[:, :3], E[:, :3], s, N, cfgs[c])
+            Xq = np.stack([N, np.full(50, cfgs[c][0]), np.full(50, cfgs[c][1])], 1).astype(np.int32)
+            rv = of.rational_value(Xq, E[:, :3], E[:, :3], s, coef)
+            assert np.allclose(p / q, rv, rtol=1e-12, atol=0), (j, c)
+            assert np.allclose(p / q, _generator_truth(pb, j, j, N, cfgs[c]), rtol=1e-7, atol=0), (j, c)
+
+
+def test_metric_cost_program_is_the_fitted_function():
+    """A program whose one fitted function is the cost (the single-fit workload: N = 2^10..2^20,
+    B = 32..1024 step 32): in FP64 its cost matrix is oracle.fit.rational_value of the fitted
+    coefficients on the grid, the FP32 replay agrees to FP32 rounding, and the argmin over B per
+    N is numpy's argmin of the fitted values (first index among equal values)."""
+    from oracle import fit as of
+    fb = synth.config1_fit(3)
+    coef, info = of.fit_batch(fb)
+    pb = synth.config1_program(fb, coef)
+    c64 = oc.program_costs(pb, 0, mode="truth")
+    c32 = oc.program_costs(pb, 0, mode="replay")
+    Ns, Bs = pb.queries, pb.cfgs
+    Xq = np.array([(n, b) for b in Bs for n in Ns], np.int32)
+    Xi, fi, En, Ed, s = fb.fit_arrays(0)
+    rv = of.rational_value(Xq, En, Ed, s, coef).reshape(Bs.size, Ns.size)
+    assert np.all(np.isfinite(rv))
+    assert np.allclose(c64, rv, rtol=1e-13, atol=0)
+    assert np.allclose(c32, rv, rtol=1e-6, atol=0)
+    idx, best = oc.argmin_lowest(c64)
+    assert np.array_equal(idx, np.argmin(rv, axis=0)) and np.allclose(best, rv.min(axis=0), rtol=1e-13, atol=0)
+    # the launch constraints still apply: B above N or off the wave is inadmissible
+    pb2 = synth.config1_program(fb, coef)
+    pb2.queries = np.array([500, 1 << 12], np.int32)
+    pb2.n_q = np.array([2], np.int32)
+    pb2.hw = synth.HW(wave=64)
+    c = oc.program_costs(pb2, 0, mode="truth")
+    assert np.all(np.isinf(c[Bs > 500, 0])) and np.all(np.isinf(c[Bs % 64 != 0]))
+    assert np.all(np.isfinite(c[(Bs <= 500) & (Bs % 64 == 0), 0]))
+
+
+def test_metric_cost_noise_free_fit_recovers_truth_decisions():
+    """Noise-free samples: the fitted rational function is the generator's, so its per-N argmin
+    over B is the truth's."""
+    from oracle import fit as of
+    fb = synth.config1_fit(5, noise=0.0)
+    coef, _ = of.fit_batch(fb)
+    pb = synth.config1_program(fb, coef)
+    idx, _ = oc.argmin_lowest(oc.program_costs(pb, 0, mode="truth"))
+    truth = synth.config1_truth_grid(fb)
+    assert np.array_equal(idx, np.argmin(truth, axis=0))

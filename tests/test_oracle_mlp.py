@@ -101,3 +101,37 @@ def test_training_reduces_loss_on_a_learnable_target(seed):
         p, m, v = om.adam_step(p, g, m, v, s, lr=1e-2)
     l1, _ = om.loss_and_grads(p, kid, N, bx, by, t)
     assert l1 < 0.1 * l0
+
+
+def test_bf16_round_is_nearest_with_ties_to_even():
+    """Against the definition: the nearest number with 8 significand bits (brute force over the
+    two neighbours at the value's binade), ties to the one with an even last bit."""
+    one = 1.0
+    assert om.bf16_round(one) == one
+    assert om.bf16_round(1 + 2.0 ** -8) == 1.0                    # tie, 1 is even
+    assert om.bf16_round(1 + 3 * 2.0 ** -8) == 1 + 2.0 ** -6      # tie, 1 + 2^-7 is odd
+    assert om.bf16_round(1 + 2.0 ** -8 + 2.0 ** -20) == 1 + 2.0 ** -7
+    assert om.bf16_round(-(1 + 2.0 ** -8 + 2.0 ** -20)) == -(1 + 2.0 ** -7)
+    rng = np.random.default_rng(5)
+    x = (rng.normal(size=20000) * 2.0 ** rng.integers(-20, 20, 20000)).astype(np.float32).astype(np.float64)
+    m, e = np.frexp(np.abs(x))                                   # |x| = m 2^e, m in [0.5, 1)
+    step = np.ldexp(1.0, e - 8)
+    lo = np.floor(np.abs(x) / step) * step
+    hi = lo + step
+    dlo, dhi = np.abs(x) - lo, hi - np.abs(x)
+    lo_even = (np.rint(lo / step) % 2) == 0
+    want = np.where(dlo < dhi, lo, np.where(dhi < dlo, hi, np.where(lo_even, lo, hi))) * np.sign(x)
+    assert np.array_equal(om.bf16_round(x), want)
+
+
+def test_bf16_forward_equals_fp64_forward_on_representable_values():
+    """With every weight and hidden value a bfloat16 number the rounded pass is the FP64 pass;
+    a first-layer value off the bfloat16 grid moves the output by exactly its rounding."""
+    p = {"W1": np.eye(4), "b1": np.zeros(4), "W2": np.eye(4), "b2": np.zeros(4),
+         "w3": np.ones(4), "b3": np.array(0.5), "emb": np.array([0.25, -3.0])}
+    args = (np.array([0, 1]), np.array([1 << 13, 1 << 26]), np.array([1 << 5, 1]), np.array([1 << 10, 1 << 5]))
+    y, _ = om.forward(p, *args)
+    assert np.array_equal(om.forward_bf16(p, *args), y)
+    q = dict(p, b1=np.array([2.0 ** -9, 0.0, 0.0, 0.0]))            # h1[0] = 0.5 + 2^-9 -> 0.5
+    yq, _ = om.forward(q, *args)
+    assert np.allclose(yq - om.forward_bf16(q, *args), [2.0 ** -9, 2.0 ** -9], rtol=0, atol=1e-15)

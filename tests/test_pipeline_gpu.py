@@ -83,3 +83,67 @@ def test_graph_replay_matches_eager(klr):
             torch.cuda.synchronize()
     finally:
         klr.graph_destroy(g)
+
+
+def test_single_fit_workload_end_to_end(klr):
+    """The single-fit workload on the device: FP64 fit of 200 samples over (N, B), then its
+    fitted function over the full 11 x 32 grid as a metric-cost program with the per-N argmin
+    over B, eager and as a captured graph replayed several times.  Costs and argmin bit-exact
+    against the oracle's FP32 replay of the GPU's coefficients; fitted values within 1e-9 of the
+    oracle's least squares; decision quality against the truth's per-N argmin reported (the
+    1 % noise can move a pick between near-equal block sizes)."""
+    import torch
+    from oracle import cost as oc
+    from oracle import fit as of
+    from paper_1911_02373_amd.klr import FIT_INFO, DeviceEval, DeviceFit, info_records
+    for seed in (1, 2, 3):
+        fb = synth.config1_fit(seed)
+        df = DeviceFit.from_batch(fb)
+        s = torch.cuda.Stream()
+        fit_out = (torch.empty(df.n_coef, dtype=torch.float64, device="cuda"),
+                   torch.empty(FIT_INFO.itemsize, dtype=torch.uint8, device="cuda"))
+        pb = synth.config1_program(fb)
+        de = DeviceEval.from_batch(klr, pb, with_costs=True, coef=fit_out[0])
+        ev_out = (torch.empty(11, dtype=torch.int32, device="cuda"), torch.empty(11, dtype=torch.float32, device="cuda"),
+                  torch.empty(11 * 32, dtype=torch.float32, device="cuda"), torch.empty(1, dtype=torch.int32, device="cuda"))
+        with torch.cuda.stream(s):
+            klr.fit_batched(df, 0, 64, 1e-12, out=fit_out, stream=s)
+            klr.eval_argmin(de, out=ev_out, want_costs=True, stream=s)
+        s.synchronize()
+        ref = [t.cpu().clone() for t in (fit_out[0], ev_out[0], ev_out[1], ev_out[2])]
+        coef = ref[0].numpy()
+        info = info_records(fit_out[1])
+        assert info["status"][0] & (of.BAD_INPUT | of.NOT_CONVERGED) == 0
+        ora, _ = of.fit_batch(fb)
+        Xi, fi, En, Ed, sc = fb.fit_arrays(0)
+        A, _ = of.design_matrix(Xi, fi, En, Ed, sc)
+        assert np.linalg.norm(A @ (coef - ora)) <= 1e-9 * np.linalg.norm(fi)
+        want = oc.program_costs(synth.config1_program(fb, coef), 0, mode="replay")
+        assert np.array_equal(ref[3].numpy().reshape(32, 11).view(np.uint32), want.view(np.uint32))
+        wi, wb = oc.argmin_lowest(want)
+        assert np.array_equal(ref[1].numpy(), wi) and np.array_equal(ref[2].numpy().view(np.uint32), wb.view(np.uint32))
+        assert int(ev_out[3].cpu()[0]) == 0
+        truth = synth.config1_truth_grid(fb)
+        tpick = np.argmin(truth, axis=0)
+        regret = truth[wi, np.arange(11)] / truth[tpick, np.arange(11)] - 1.0
+        print(f"seed {seed}: per-N picks equal to the truth's {np.mean(wi == tpick):.2f}, "
+              f"max regret under the truth {regret.max():.4f}")
+        # graph capture of fit + grid evaluation, replayed with eager work in between
+        klr.capture_begin(s)
+        klr.fit_batched(df, 0, 64, 1e-12, out=fit_out, stream=s)
+        klr.eval_argmin(de, out=ev_out, want_costs=True, stream=s)
+        g = klr.capture_end(s)
+        try:
+            for rep in range(3):
+                for t in (fit_out[0], ev_out[1], ev_out[2]):
+                    t.fill_(0)
+                torch.cuda.synchronize()
+                klr.graph_launch(g, s)
+                s.synchronize()
+                got = [t.cpu() for t in (fit_out[0], ev_out[0], ev_out[1], ev_out[2])]
+                for x, y in zip(got, ref):
+                    assert torch.equal(x.view(torch.uint8), y.view(torch.uint8)), rep
+                klr.fit_batched(df, 0, 64, 1e-12)                     # eager work in between
+                torch.cuda.synchronize()
+        finally:
+            klr.graph_destroy(g)
