@@ -233,6 +233,30 @@ klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_pro
                            float* all_costs, int64_t costs_len, int32_t* prog_status,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): klr_eval_argmin with the same arguments and results,
+ * minus the workspace.  The workspace is a fixed array of KLR_NOALLOC_SCRATCH_BYTES in device
+ * memory, one per GPU, held from the library's load until the process ends; its address on a
+ * device is looked up by klr_create, so the handle's device must be current.  A batch whose
+ * klr_eval_workspace(n_progs, max_cfg) exceeds the array returns KLR_E_WORKSPACE and launches
+ * nothing.  The call allocates nothing, creates no events, does not autotune (it uses the
+ * launch shape already tuned for this batch shape on the handle, else the default) and records
+ * no kernel timing.  Every call on one GPU shares that GPU's array (it keeps the last call's
+ * contents; nothing in it needs clearing, since the collapse rewrites every slot the sweep
+ * reads): calls that overlap in time on one GPU - other streams, other handles or threads -
+ * race and must be serialised by the caller. */
+#define KLR_NOALLOC_SCRATCH_BYTES (64u << 20)
+klr_status klr_eval_argmin_noalloc(klr_handle h, const klr_program* progs, int32_t n_progs,
+                                   int32_t max_cfg, int32_t max_q, const klr_hw* hw,
+                                   const klr_fit_desc* desc, int32_t n_fits,
+                                   const uint8_t* exps, int32_t n_exp_rows,
+                                   const double* coef, int64_t coef_len,
+                                   const int32_t* cfgs, int64_t cfgs_len,
+                                   const int32_t* queries, int64_t q_len,
+                                   int32_t* argmin, float* best_cost,
+                                   float* all_costs, int64_t costs_len, int32_t* prog_status,
+                                   void* stream);
+
 /* ------------------------------------------------------------------------------------------
  * Learned surrogate (not in the paper): one network shared by all kernels (programs),
  * conditioned on a learned scalar embedding e_k per kernel, predicting standardised log-cycles:

@@ -6,11 +6,17 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
 #include "internal.hpp"
 
+// Workspace of klr_eval_argmin_noalloc: one copy of this array per GPU, resident from the
+// library's load until the process ends.  In host code `scratch` is a host-side stand-in, not
+// a device address: each GPU's copy is found with hipGetSymbolAddress while that GPU is current
+// (in klr_create), and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[KLR_NOALLOC_SCRATCH_BYTES];
 
 namespace klr {
 
@@ -93,6 +99,22 @@ void Tuner::load() {
 
 namespace {
 
+// Device address of `scratch` on each GPU (found once per device by klr_create).
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+void find_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) g_scratch_ptr[device] = p;
+  else g_scratch_err[device] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+}
+
 uint64_t eval_tune_key(int32_t n_progs, int32_t max_cfg, int32_t max_q) {
   auto lg = [](int64_t x) { int b = 0; while ((int64_t(1) << b) < x && b < 40) ++b; return (uint64_t)b; };
   return (1ull << 56) | (lg(n_progs) << 32) | (lg(max_cfg) << 16) | lg(max_q);
@@ -131,6 +153,7 @@ klr_status klr_create(klr_handle* out, int device) {
   klr_handle h = new (std::nothrow) klr_handle_s;
   if (!h) return KLR_E_HIP;
   h->device = device;
+  klr::find_scratch(device);     // with `device` current: its copy of the no-allocation workspace
   h->tuner.load();
   *out = h;
   return KLR_OK;
@@ -240,8 +263,9 @@ size_t klr_eval_workspace(int32_t n_progs, int32_t max_cfg) {
 namespace klr {
 namespace {
 
-// Validation and launch of the evaluation; no_alloc: the launch shape is the cached tuned one
-// (or the default) and no kernel timing is recorded, so the call creates no events.
+// Validation and launch of the evaluation; no_alloc: the workspace is this GPU's `scratch`, the
+// launch shape is the cached tuned one (or the default) and no kernel timing is recorded, so
+// the call creates no events and allocates nothing.
 klr_status eval_argmin_impl(klr_handle h, const klr_program* progs, int32_t n_progs,
                             int32_t max_cfg, int32_t max_q, const klr_hw* hw,
                             const klr_fit_desc* desc, int32_t n_fits,
@@ -310,6 +334,43 @@ klr_status klr_eval_argmin(klr_handle h, const klr_program* progs, int32_t n_pro
   return klr::eval_argmin_impl(h, progs, n_progs, max_cfg, max_q, hw, desc, n_fits, exps, n_exp_rows, coef,
                                coef_len, cfgs, cfgs_len, queries, q_len, argmin, best_cost, all_costs,
                                costs_len, prog_status, ws, ws_bytes, stream, false);
+}
+
+klr_status klr_eval_argmin_noalloc(klr_handle h, const klr_program* progs, int32_t n_progs,
+                                   int32_t max_cfg, int32_t max_q, const klr_hw* hw,
+                                   const klr_fit_desc* desc, int32_t n_fits,
+                                   const uint8_t* exps, int32_t n_exp_rows,
+                                   const double* coef, int64_t coef_len,
+                                   const int32_t* cfgs, int64_t cfgs_len,
+                                   const int32_t* queries, int64_t q_len,
+                                   int32_t* argmin, float* best_cost,
+                                   float* all_costs, int64_t costs_len, int32_t* prog_status,
+                                   void* stream) {
+  if (!h) return KLR_E_INVALID;
+  h->err.clear();
+  if (n_progs < 0 || max_cfg < 0) return fail(h, KLR_E_INVALID, "negative size");
+  const size_t need = klr::eval_workspace_bytes(n_progs, max_cfg);
+  if (need > (size_t)KLR_NOALLOC_SCRATCH_BYTES)
+    return fail(h, KLR_E_WORKSPACE, "klr_eval_argmin_noalloc: the batch needs " + std::to_string(need) +
+                                    " bytes of workspace, above the fixed " +
+                                    std::to_string((size_t)KLR_NOALLOC_SCRATCH_BYTES) +
+                                    " (KLR_NOALLOC_SCRATCH_BYTES); split the batch");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != h->device)
+    return fail(h, KLR_E_INVALID, "klr_eval_argmin_noalloc: the handle's device must be current");
+  void* ws = nullptr;
+  if (dev >= 0 && dev < klr::kMaxDevices) {
+    std::lock_guard<std::mutex> lk(klr::g_scratch_mu);
+    ws = klr::g_scratch_ptr[dev];
+    if (!ws)
+      return fail(h, KLR_E_HIP, std::string("klr_eval_argmin_noalloc: no device address for the fixed workspace: ") +
+                                    hipGetErrorString(klr::g_scratch_err[dev]));
+  } else {
+    return fail(h, KLR_E_UNSUPPORTED, "klr_eval_argmin_noalloc: device index above the supported range");
+  }
+  return klr::eval_argmin_impl(h, progs, n_progs, max_cfg, max_q, hw, desc, n_fits, exps, n_exp_rows, coef,
+                               coef_len, cfgs, cfgs_len, queries, q_len, argmin, best_cost, all_costs,
+                               costs_len, prog_status, ws, (size_t)KLR_NOALLOC_SCRATCH_BYTES, stream, true);
 }
 
 size_t klr_fit_workspace(int32_t n_fits, int64_t total_rows, int32_t precision) {

@@ -40,7 +40,7 @@ EXPORTS = ("klr_create", "klr_destroy", "klr_last_error", "klr_fit_workspace", "
            "klr_surrogate_step", "klr_surrogate_eval_workspace", "klr_surrogate_eval",
            "klr_surrogate_init", "klr_set_option", "klr_capture_begin", "klr_capture_end",
            "klr_graph_launch", "klr_graph_destroy", "klr_selftest_divisors",
-           "klr_selftest_divisor_list")
+           "klr_selftest_divisor_list", "klr_eval_argmin_noalloc")
 OPT_FIT_PERSISTENT, OPT_EVAL_VARIANT = 0, 1
 K_COLLAPSE, K_EVAL, K_FIT_GRAM, K_FIT_SOLVE, K_MLP, K_SURR, K_FALLBACK = 0, 1, 2, 3, 4, 5, 6
 TRAIN_CFG = np.dtype([("lr", "<f4"), ("beta1", "<f4"), ("beta2", "<f4"), ("eps", "<f4"),
@@ -77,6 +77,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.klr_eval_argmin.argtypes = [P, P, I32, I32, I32, P, P, I32, P, I32, P, I64, P, I64, P, I64,
                                     P, P, P, I64, P, P, SZ, P]
     lib.klr_eval_argmin.restype = I32
+    lib.klr_eval_argmin_noalloc.argtypes = [P, P, I32, I32, I32, P, P, I32, P, I32, P, I64, P, I64, P, I64,
+                                            P, P, P, I64, P, P]
+    lib.klr_eval_argmin_noalloc.restype = I32
     lib.klr_profile_enable.argtypes = [P, I32]
     lib.klr_profile_enable.restype = I32
     lib.klr_profile_read.argtypes = [P, I32, ctypes.POINTER(D), ctypes.POINTER(I64)]
