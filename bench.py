@@ -41,7 +41,7 @@ FP32_UNPACKED_TFLOPS = 78.6
 FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0
 VALU_LANE_OPS_T = 256 * 64 * 2.4e9 / 1e12     # unpacked VALU lane-instructions per second, 1e12
-FIT_TOL = {0: 1e-10, 1: 1e-8, 2: 1e-8}
+FIT_TOL = {0: 1e-10, 1: 1e-8, 2: 1e-8, 3: 0.0}
 FIT_MAX_ITER = 256
 N_METRICS = 8
 
@@ -506,6 +506,114 @@ def single_fit_component(lib, klr, synth, replays=200, seeds=100):
                         "then the fitted function on all 352 points and the argmin over B per N"}
 
 
+def collection_component(lib, klr, synth, seed):
+    """Data collection on this GPU: each target kernel timed at 240 sample points (N, bx, by),
+    the times fitted (FP64, degree <= 2 rational), the fitted time minimised over the 45 block
+    shapes at 13 data sizes, and the pick compared with the exhaustively measured best shape
+    (best time / chosen time, the paper's Table 1 measure; >= 0.85 counts as a good choice)."""
+    import torch
+    shapes = synth.block_shapes()
+    out = {}
+    for target, name in ((klr.TARGET_TRANSPOSE, "transpose"), (klr.TARGET_STENCIL, "stencil")):
+        t0 = time.perf_counter()
+        plan = synth.collection_plan(seed + target, 240)
+        times = lib.collect_times(target, plan, reps=5)
+        collect_s = time.perf_counter() - t0
+        fb = synth.measured_fit(plan, times)
+        df = klr.DeviceFit.from_batch(fb)
+        coef, info = lib.fit_batched(df, klr.KLR_FP64, FIT_MAX_ITER, 1e-12)
+        queries = np.rint(2.0 ** (8 + np.arange(13) / 3.0)).astype(np.int32)
+        pb = synth.measured_program(fb, shapes, queries)
+        de = klr.DeviceEval.from_batch(lib, pb, coef=coef)
+        am, _, _, _ = lib.eval_argmin(de)
+        torch.cuda.synchronize()
+        am = am.cpu().numpy()
+        grid = np.array([(n, bx, by) for n in queries for bx, by in shapes if max(bx, by) <= n], np.int32)
+        tg = lib.collect_times(target, grid, reps=5)
+        ratios = []
+        for qi, n in enumerate(queries):
+            sel = grid[:, 0] == n
+            meas = dict(zip(map(tuple, grid[sel, 1:]), tg[sel]))
+            chosen = meas.get(tuple(shapes[am[qi]]), np.inf) if am[qi] >= 0 else np.inf
+            ratios.append(min(meas.values()) / chosen)
+        r = np.array(ratios)
+        ir = klr.info_records(info)
+        out[name] = {"samples": int(plan.shape[0]), "collect_s": collect_s, "attributes": lib.target_attributes(target),
+                     "fit_rel_resid": float(ir["resid_norm"][0] / np.linalg.norm(times)),
+                     "best_over_chosen": [round(float(x), 4) for x in r], "median_ratio": float(np.median(r)),
+                     "frac_ge_0.85": float(np.mean(r >= 0.85)), "sizes": [int(x) for x in queries]}
+    return out
+
+
+def piecewise_component(lib, klr, synth, seed):
+    """Piecewise rational programs with a fitted decision node: 256 programs (3 fits each: the
+    decision, and the two regime costs), 4096 queries x 128 configurations; fit and evaluation
+    times, and the picks' regret under the generator's costs on 16 programs."""
+    import copy
+    import torch
+    fb, pb, truth = synth.piecewise_batch(seed, n_progs=256, n_q=4096)
+    df = klr.DeviceFit.from_batch(fb)
+    coef, _ = lib.fit_batched(df, klr.KLR_FP64, FIT_MAX_ITER, 1e-12)
+    torch.cuda.synchronize()
+    lib.profile_enable(True)
+    coef, _ = lib.fit_batched(df, klr.KLR_FP64, FIT_MAX_ITER, 1e-12)
+    fit_ms, _ = lib.profile_read(klr.K_FIT_SOLVE)
+    lib.profile_enable(False)
+    pb2 = copy.copy(pb)
+    de = klr.DeviceEval.from_batch(lib, pb2, coef=coef)
+    am, _, _, _ = lib.eval_argmin(de)
+    torch.cuda.synchronize()
+    lib.profile_enable(True)
+    am, _, _, _ = lib.eval_argmin(de)
+    ev_ms, _ = lib.profile_read(klr.K_EVAL)
+    col_ms, _ = lib.profile_read(klr.K_COLLAPSE)
+    lib.profile_enable(False)
+    am = am.cpu().numpy()
+    regrets = []
+    for p in range(16):
+        q0, nq = int(pb.q0[p]), int(pb.n_q[p])
+        t = truth(p, pb.queries[q0:q0 + nq])
+        best = t.min(axis=0)
+        a = am[q0:q0 + nq]
+        ok = np.isfinite(best) & (a >= 0)
+        regrets.append(t[a[ok], np.nonzero(ok)[0]] / best[ok] - 1.0)
+    r = np.concatenate(regrets)
+    points = int((pb.n_cfg.astype(np.int64) * pb.n_q).sum())
+    return {"programs": int(pb.n_progs), "fits": int(fb.n_fits), "points": points, "fit_ms": fit_ms,
+            "eval_ms": ev_ms, "collapse_ms": col_ms, "evals_per_s": points / ((ev_ms + col_ms) / 1e3),
+            "regret_under_truth": {"median": float(np.median(r)), "frac_le_1pct": float(np.mean(r <= 0.01)),
+                                   "frac_le_5pct": float(np.mean(r <= 0.05)), "queries": int(r.size)}}
+
+
+def service_component(lib, klr, synth, pb, de, n_calls=2000):
+    """The launch-time decision service over the 1024 c3 programs: single-size decisions as a
+    launching program makes them, first for sizes never seen (each an evaluation on the GPU)
+    and then repeated (answered from the history); microseconds per decision on the host."""
+    svc = klr.Service(lib, de, pb, max_batch=256)
+    try:
+        rng = np.random.default_rng(5)
+        progs = rng.integers(0, pb.n_progs, n_calls)
+        sizes = np.rint(2.0 ** rng.uniform(8, 26, n_calls)).astype(np.int32)
+        svc.decide(0, sizes[:4])                       # warm-up
+        t = time.perf_counter()
+        for p, n in zip(progs, sizes):
+            svc.decide(int(p), [int(n)])
+        miss_us = (time.perf_counter() - t) / n_calls * 1e6
+        t = time.perf_counter()
+        for p, n in zip(progs, sizes):
+            svc.decide(int(p), [int(n)])
+        hit_us = (time.perf_counter() - t) / n_calls * 1e6
+        t = time.perf_counter()
+        batch = svc.decide(7, np.rint(2.0 ** rng.uniform(8, 26, 4096)).astype(np.int32))
+        batch_ms = (time.perf_counter() - t) * 1e3
+        st = svc.stats()
+        return {"decision_us_new_size": miss_us, "decision_us_from_history": hit_us,
+                "batch_4096_new_sizes_ms": batch_ms, "stats": st,
+                "admissible_picks": float(np.mean(batch["config"] >= 0))}
+    finally:
+        svc.close()
+
+
 def fit_component(lib, klr, fb, prec, reps=3, persistent=True):
     """Eager HIP-event time of one precision / schedule on a fit batch, with iteration and
     status statistics and the FP64 roofline fraction."""
@@ -527,7 +635,14 @@ def fit_component(lib, klr, fb, prec, reps=3, persistent=True):
     ir = klr.info_records(fit_out[1])
     kavg = kms / max(kn, 1)
     n_unk = (fb.n_num + fb.n_den - 1).astype(np.float64)
-    fl = float(np.sum(fit_flops(fb.m.astype(np.float64), n_unk, ir["iters"].astype(np.float64))))
+    m = fb.m.astype(np.float64)
+    it = ir["iters"].astype(np.float64)
+    if prec == klr.KLR_FP64_SVD:
+        # one-sided Jacobi: per sweep n (n - 1) / 2 column pairs, each an inner product (2 m) and
+        # a rotation of both columns (6 m), plus the column norms (2 m n)
+        fl = float(np.sum(it * (4.0 * m * n_unk * (n_unk - 1.0) + 2.0 * m * n_unk)))
+    else:
+        fl = float(np.sum(fit_flops(m, n_unk, it)))
     return {"kernel_ms": kavg, "fits_per_s": fb.n_fits / (kavg / 1e3), "tol": FIT_TOL[prec],
             "iters_mean": float(ir["iters"].mean()), "iters_max": int(ir["iters"].max()),
             "rank_deficient": float(np.mean((ir["status"] & 1) > 0)),
@@ -551,6 +666,8 @@ def main() -> int:
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-large-batch", action="store_true")
     ap.add_argument("--no-single-fit", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the data-collection, piecewise-program and decision-service components")
     ap.add_argument("--kernel-only", choices=("eval", "fit", "copy", "large", "mlp"), default=None,
                     help="run only this kernel --steps times (for hardware-counter runs); "
                          "'copy' is a plain 1 GiB device copy used to calibrate byte counters")
@@ -699,6 +816,19 @@ def main() -> int:
             comps[name + "_c2b"] = fit_component(lib, klr, fb2b, prec)
             log(f"{name}: {comps[name]['kernel_ms']:.3f} ms, iters mean {comps[name]['iters_mean']:.1f}; "
                 f"c2b {comps[name + '_c2b']['kernel_ms']:.3f} ms")
+    comps["fit_svd_c2a"] = fit_component(lib, klr, fb, klr.KLR_FP64_SVD, reps=1)
+    comps["fit_svd_c2b"] = fit_component(lib, klr, fb2b, klr.KLR_FP64_SVD, reps=1)
+    log(f"SVD fits: c2a {comps['fit_svd_c2a']['kernel_ms']:.2f} ms, c2b {comps['fit_svd_c2b']['kernel_ms']:.2f} ms")
+    if not args.no_extras:
+        comps["data_collection"] = dc = collection_component(lib, klr, synth, args.seed)
+        log("data collection: " + ", ".join(f"{k} median best/chosen {v['median_ratio']:.3f}" for k, v in dc.items()))
+        comps["piecewise"] = pw = piecewise_component(lib, klr, synth, args.seed)
+        log(f"piecewise: eval {pw['eval_ms']:.2f} ms, median regret {pw['regret_under_truth']['median']:.4f}")
+        de_s = klr.DeviceEval.from_batch(lib, pb)
+        comps["service"] = sv = service_component(lib, klr, synth, pb, de_s)
+        log(f"service: {sv['decision_us_new_size']:.1f} us per new size, {sv['decision_us_from_history']:.2f} us "
+            f"from the history")
+        del de_s
     if not args.no_single_fit:
         comps["single_fit"] = sf = single_fit_component(lib, klr, synth)
         log(f"single fit + grid decision: median {sf['us_per_fit_and_decision_median']:.1f} us per graph replay; "

@@ -191,6 +191,10 @@ typedef struct {          /* hardware parameters H, fixed per call [host]       
                           /*   p/q, inadmissible where q <= 0 or not finite, and the launch     */
                           /*   constraints (every L >= 1 and <= N, T <= t_max, T % wave == 0)   */
                           /*   apply; occupancy terms and the grid do not enter                 */
+#define KLR_COST_PIECEWISE 2 /* a piecewise rational program with a fitted decision node (fits    */
+                          /*   fit0, fit0 + 1, fit0 + 2 = d, g_a, g_b): cost = g_a where d >= 0,  */
+                          /*   else g_b; inadmissible where d or the branch taken has q <= 0 or  */
+                          /*   is not finite, and under the launch constraints of KLR_COST_METRIC */
 
 typedef struct {
   int64_t cfg0;           /* element offset of its n_cfg configurations in cfgs (rows of       */
@@ -202,7 +206,8 @@ typedef struct {
   int32_t n_cfg;          /* configurations, 0..max_cfg                                         */
   int32_t n_q;            /* queries, 0..max_q                                                  */
   int32_t grid_kind;      /* KLR_GRID_1D or KLR_GRID_2D                                         */
-  int32_t cost_kind;      /* KLR_COST_CYCLES (fits fit0 .. fit0 + 7) or KLR_COST_METRIC (fit0)  */
+  int32_t cost_kind;      /* KLR_COST_CYCLES (fits fit0 .. fit0 + 7), KLR_COST_METRIC (fit0),   */
+                          /*   KLR_COST_PIECEWISE (fit0 .. fit0 + 2)                            */
 } klr_program;            /* 48 bytes */
 
 /* program status bits (prog_status) */
@@ -341,6 +346,82 @@ klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernel
                               void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Launch-time decision service: the driver program's run-time role (paper: section "KLARAPTOR: A
+ * Dynamic Optimization tool for CUDA" - at a kernel's launch its data parameters are known, the
+ * rational program is evaluated for the admissible configurations and the best is used, and the
+ * decision is kept in a history for later launches with the same data; section "Input/Output
+ * Builder" - the result is the launch's grid and block dimensions; section "Annotating the source
+ * code" - constraints on the launch parameters are Python-syntax expressions).
+ *
+ * A service holds host copies of the programs and configurations, per-program constraints and the
+ * decision history (a hash map from (program, data size) to the decision; cleared when it would
+ * exceed its limit, default 2^20 entries, and whenever a constraint is added).  A decision call
+ * answers data sizes found in the history at once and evaluates the others with klr_eval_argmin
+ * (one program, up to max_batch sizes per evaluation) in the caller's device workspace; with
+ * constraints the cost rows come back to the host and the argmin is taken over the configurations
+ * every constraint admits (strict "<" in configuration order).  Calls are synchronous on
+ * `stream`; one thread at a time per service. */
+typedef struct {
+  int32_t gx, gy, gz;     /* grid: 1-D ceil(N / prod L), 1, 1; 2-D ceil(N / L0), ceil(N / L1), 1 */
+  int32_t bx, by, bz;     /* block: the first three launch parameters (1 where absent)           */
+  int32_t config;         /* configuration index in the program's list; -1: none admissible       */
+  float cost;             /* the rational program's value there (+inf when none)                 */
+} klr_launch;             /* 32 bytes */
+typedef struct klr_service_s* klr_service;
+
+/* Device workspace bytes of a service whose programs have at most max_cfg configurations and that
+ * evaluates at most max_batch data sizes at once. */
+size_t klr_service_workspace(int32_t max_cfg, int32_t max_batch);
+/* progs [host] (n_progs; q0, n_q, cost0 ignored), hw [host], desc / exps / coef device arrays as
+ * for klr_eval_argmin (they must stay valid while the service lives), configurations both as a
+ * host copy (cfgs_host) and on the device (cfgs_dev), cfgs_len entries each; ws: device
+ * workspace of klr_service_workspace(max over programs of n_cfg, max_batch) bytes, 256-byte
+ * aligned, owned by the caller for the service's life. */
+klr_status klr_service_create(klr_handle h, klr_service* out, const klr_program* progs, int32_t n_progs,
+                              const klr_hw* hw, const klr_fit_desc* desc, int32_t n_fits, const uint8_t* exps,
+                              int32_t n_exp_rows, const double* coef, int64_t coef_len, const int32_t* cfgs_host,
+                              const int32_t* cfgs_dev, int64_t cfgs_len, int32_t max_batch, void* ws,
+                              size_t ws_bytes);
+void klr_service_destroy(klr_service s);
+/* Add a constraint (a Python boolean expression over N, bx, by, bz (also L0..L3) and T = their
+ * product, with or / and / not, chained comparisons, + - * / // % **, min / max / abs) to program
+ * `prog`, or to every program when prog = -1.  KLR_E_INVALID with the parse error in
+ * klr_last_error. */
+klr_status klr_service_add_constraint(klr_service s, int32_t prog, const char* expr);
+/* Decisions for program `prog` at n data sizes N [host]; out [host] receives n records. */
+klr_status klr_service_decide(klr_service s, int32_t prog, const int32_t* N, int32_t n, klr_launch* out,
+                              void* stream);
+/* [host] counters: answers from the history, sizes evaluated, klr_eval_argmin calls, history size. */
+klr_status klr_service_stats(klr_service s, int64_t* hits, int64_t* misses, int64_t* evaluations,
+                             int64_t* entries);
+klr_status klr_service_set_history_limit(klr_service s, int64_t max_entries);
+/* [host] Compile `expr` and evaluate it at (N, L[0 .. v_launch)): 1 true, 0 false (a division by
+ * zero is false), -1 on a parse error (message in err[err_len]). */
+int32_t klr_constraint_check(const char* expr, int32_t N, const int32_t* L, int32_t v_launch, char* err,
+                             int32_t err_len);
+
+/* ------------------------------------------------------------------------------------------
+ * Data collection (paper: step 1 of the section "An Algorithm to Build and Deploy a
+ * Performance-Predicting Rational Program" and section "Building a Driver Program: Data
+ * collection": the program is run at sample points and a metric is measured at each).  The
+ * library carries target kernels with a two-dimensional launch configuration (bx, by) over
+ * N x N single-precision grids; klr_collect_times measures each sample's kernel time (HIP events
+ * around `reps` launches after one warm-up launch, on `stream`), the metric that a
+ * KLR_COST_METRIC program fits and minimises; klr_target_attributes reports the compiled
+ * kernel's registers per thread and LDS bytes per block (the R and Z metrics). */
+#define KLR_TARGET_TRANSPOSE 0  /* out[x][y] = in[y][x]                                          */
+#define KLR_TARGET_STENCIL 1    /* five-point Jacobi step, fixed boundary                        */
+#define KLR_COLLECT_MAX_N 16384
+/* Device buffer bytes for samples up to data size max_n (two N x N float grids). */
+size_t klr_collect_buffer(int32_t target, int32_t max_n);
+klr_status klr_target_attributes(klr_handle h, int32_t target, int32_t* regs, int32_t* lds_bytes);
+/* samples [host]: n_samples rows (N, bx, by), 1 <= N <= KLR_COLLECT_MAX_N, bx, by >= 1,
+ * bx * by <= 1024 (checked before any launch); time_us [host, out]: mean microseconds per launch;
+ * buf: device buffer of klr_collect_buffer(target, max N) bytes (its contents are overwritten). */
+klr_status klr_collect_times(klr_handle h, int32_t target, const int32_t* samples, int32_t n_samples,
+                             int32_t reps, double* time_us, void* buf, size_t buf_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------------
  * Options of a handle. */
 #define KLR_OPT_FIT_PERSISTENT 0  /* 1 (default): fits are ordered longest first (m n^2) on the */
                                   /*   device; small fits (one wavefront each) are started in   */
@@ -349,6 +430,11 @@ klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernel
                                   /*   wavefront or workgroup each.  Results are identical.     */
 #define KLR_OPT_EVAL_VARIANT 1    /* -1 (default): launch shape of the evaluation sweep chosen by */
                                   /*   the autotuner; >= 0: a fixed variant index                 */
+#define KLR_OPT_FIT_VARIANT 2     /* -1 (default): fits per workgroup of the one-wavefront fit  */
+                                  /*   kernel (4, 2 or 1) chosen by the autotuner (HIP-event     */
+                                  /*   timing of each on the first batch of a shape, cached in   */
+                                  /*   the handle and KLR_TUNE_CACHE); >= 0: variant 0, 1, 2.    */
+                                  /*   Every variant gives bit-identical results                 */
 #define KLR_OPT_COUNT 8
 klr_status klr_set_option(klr_handle h, int32_t option, int64_t value);
 

@@ -21,7 +21,8 @@ What it follows.
   * Selection (step 5): exhaustive search, strict "<" in configuration order, so ties go to the
     lowest index; no admissible configuration gives -1 and +inf.
   * A program may instead take its one fitted function as the cost (the sampled metric was the
-    quantity to minimise), with the same launch constraints and no occupancy or grid terms.
+    quantity to minimise), with the same launch constraints and no occupancy or grid terms; or
+    be piecewise, a fitted decision function choosing between two fitted cost functions.
 
 Two precisions:
   truth  - FP64: each metric is the full multivariate p/q evaluated directly at (N~, L~).
@@ -262,7 +263,7 @@ def cycles_from_metrics(g, N, L, grid_kind, hw, dt):
 # ---------------------------------------------------------------------------------------------
 # programs
 
-COST_CYCLES, COST_METRIC = 0, 1
+COST_CYCLES, COST_METRIC, COST_PIECEWISE = 0, 1, 2
 
 
 def cost_kind(pb, prog):
@@ -285,9 +286,25 @@ def metric_cost(g, N, L, hw):
     return np.where(ok, g, np.inf).astype(np.asarray(g).dtype)
 
 
+def piecewise_cost(d, ga, gb, N, L, hw):
+    """A piecewise rational program whose decision node is a fitted function too (the paper
+    remarks that a decision node is given by rational functions, so it can be determined by
+    curve fitting like the metrics): cost ga where d >= 0, gb elsewhere; +inf where d or the
+    branch taken is invalid (q <= 0 or not finite) or the launch constraints fail.  Invalid
+    values arrive as NaN."""
+    d = np.asarray(d)
+    take_a = d >= 0
+    g = np.where(take_a, ga, gb)
+    return metric_cost(np.where(np.isfinite(d), g, np.nan).astype(d.dtype), N, L, hw)
+
+
+def program_metrics(pb, prog):
+    return {COST_METRIC: 1, COST_PIECEWISE: 3}.get(cost_kind(pb, prog), N_METRICS)
+
+
 def _metric_slices(pb, prog):
     out = []
-    for j in range(1 if cost_kind(pb, prog) == COST_METRIC else N_METRICS):
+    for j in range(program_metrics(pb, prog)):
         fi = int(pb.fit0[prog]) + j
         v = 1 + int(pb.v_launch[prog])
         En = pb.exps[pb.num0[fi]: pb.num0[fi] + pb.n_num[fi], :v]
@@ -337,6 +354,8 @@ def program_costs(pb, prog, query_idx=None, mode="replay", coef=None):
                 g.append(np.where(q > 0, val, np.nan))
         if cost_kind(pb, prog) == COST_METRIC:
             out[c] = metric_cost(g[0], N, cfgs[c], pb.hw)
+        elif cost_kind(pb, prog) == COST_PIECEWISE:
+            out[c] = piecewise_cost(g[0], g[1], g[2], N, cfgs[c], pb.hw)
         else:
             out[c] = cycles_from_metrics(g, N, cfgs[c], gk, pb.hw, dt)
     return out

@@ -27,7 +27,7 @@ COMMON = [
 EXTRA = {
     "eval.hip": ["-ffp-contract=off"],
 }
-SOURCES = ["abi.hip", "eval.hip", "fit.hip", "fit_svd.hip", "fit_wave.hip", "mlp.hip"]
+SOURCES = ["abi.hip", "collect.hip", "eval.hip", "fit.hip", "fit_svd.hip", "fit_wave.hip", "mlp.hip", "service.hip"]
 
 
 def _compile(src: str) -> str:

@@ -92,8 +92,10 @@ void Tuner::load() {
   unsigned long long k = 0;
   int v = 0;
   float ms = 0.0f;
-  while (std::fscanf(f, "%llu %d %f", &k, &v, &ms) == 3)
-    if (v >= 0 && v < eval_num_variants() && find(k) < 0) entries.emplace_back((uint64_t)k, v);
+  while (std::fscanf(f, "%llu %d %f", &k, &v, &ms) == 3) {
+    const int nv = (k & kTuneFitTag) ? kFitVariants : eval_num_variants();
+    if (v >= 0 && v < nv && find(k) < 0) entries.emplace_back((uint64_t)k, v);
+  }
   std::fclose(f);
 }
 
@@ -115,9 +117,22 @@ void find_scratch(int device) {
   else g_scratch_err[device] = e == hipSuccess ? hipErrorInvalidSymbol : e;
 }
 
+uint64_t ceil_log2(int64_t x) {
+  int b = 0;
+  while ((int64_t(1) << b) < x && b < 40) ++b;
+  return (uint64_t)b;
+}
+
 uint64_t eval_tune_key(int32_t n_progs, int32_t max_cfg, int32_t max_q) {
-  auto lg = [](int64_t x) { int b = 0; while ((int64_t(1) << b) < x && b < 40) ++b; return (uint64_t)b; };
-  return (1ull << 56) | (lg(n_progs) << 32) | (lg(max_cfg) << 16) | lg(max_q);
+  return kTuneEvalTag | (ceil_log2(n_progs) << 32) | (ceil_log2(max_cfg) << 16) | ceil_log2(max_q);
+}
+
+// A fit batch's shape: precision, schedule, and the batch size and sample rows per fit in
+// powers of two.
+uint64_t fit_tune_key(int32_t n_fits, int64_t f_len, int32_t precision, bool persistent) {
+  const int64_t per = n_fits > 0 ? f_len / n_fits : 0;
+  return kTuneFitTag | ((uint64_t)precision << 48) | ((uint64_t)persistent << 44) | (ceil_log2(n_fits) << 16) |
+         ceil_log2(per);
 }
 
 bool hw_ok(const klr_hw& hw, std::string& why) {
@@ -407,6 +422,14 @@ klr_status klr_fit_batched(klr_handle h, const klr_fit_desc* desc, int32_t n_fit
                  h->capturing ? nullptr : &h->timer, h->opt[KLR_OPT_FIT_PERSISTENT] != 0,
                  nullptr, nullptr, 0};
   klr::fit_workspace_split(a);
+  a.tune_key = klr::fit_tune_key(n_fits, f_len, precision, a.persistent);
+  if (h->opt[KLR_OPT_FIT_VARIANT] >= 0) {
+    a.variant = (int)(h->opt[KLR_OPT_FIT_VARIANT] % klr::kFitVariants);
+  } else {
+    a.variant = h->tuner.find(a.tune_key);
+    if (a.variant < 0 && !h->capturing) a.tuner = &h->tuner;
+    if (a.variant < 0 && h->capturing) a.variant = 0;
+  }
   return klr::hip_check(h, klr::launch_fit(a), "klr_fit_batched launch");
 }
 

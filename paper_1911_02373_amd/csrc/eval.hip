@@ -98,11 +98,12 @@ __device__ __forceinline__ float clean_max(bool good, float v, float lo) {
 
 // Fitted metrics a program reads: the eight of the cycle estimate, or its one cost function.
 __host__ __device__ inline int program_metrics(const klr_program& P) {
-  return P.cost_kind == KLR_COST_METRIC ? 1 : KLR_N_METRICS;
+  return P.cost_kind == KLR_COST_METRIC ? 1 : (P.cost_kind == KLR_COST_PIECEWISE ? 3 : KLR_N_METRICS);
 }
 
 __device__ bool program_desc_ok(const klr_program& P, const EvalArgs& a) {
-  if (P.cost_kind != KLR_COST_CYCLES && P.cost_kind != KLR_COST_METRIC) return false;
+  if (P.cost_kind != KLR_COST_CYCLES && P.cost_kind != KLR_COST_METRIC && P.cost_kind != KLR_COST_PIECEWISE)
+    return false;
   if (P.fit0 < 0 || (int64_t)P.fit0 + program_metrics(P) > a.n_fits) return false;
   if (P.v_launch < 1 || P.v_launch > KLR_MAX_LAUNCH) return false;
   if (P.n_cfg < 0 || P.n_cfg > a.max_cfg || P.n_q < 0 || P.n_q > a.max_q) return false;
@@ -457,28 +458,57 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
 // Cost of one point of a program whose one fitted function is the cost: p/q of metric 0 by the
 // same Horner steps and division as the cycle estimate's metrics; +inf where q <= 0, the value is
 // not finite, a launch parameter exceeds N or the configuration is not admissible.
+// One fitted function j of a configuration slot at the scaled size x: p / q by the Horner steps
+// of the cycle estimate's metrics; *good = q > 0 and the value finite.
+template <int DEG = kNdeg, bool UNI = true>
+__device__ __forceinline__ float fitted_value(const float* __restrict__ cf, int j, float x, bool* good) {
+  const float* c = cf + j * 2 * (kNdeg + 1);
+  const float2 lo = UNI ? vgpr_pair(c + 2 * (DEG - 1)) : make_float2(c[2 * (DEG - 1)], c[2 * DEG - 1]);
+  float p = __builtin_fmaf(c[2 * DEG], x, lo.x);
+  float q = __builtin_fmaf(c[2 * DEG + 1], x, lo.y);
+#pragma unroll
+  for (int d = DEG - 2; d >= 0; --d) {
+    p = __builtin_fmaf(p, x, c[2 * d]);
+    q = __builtin_fmaf(q, x, c[2 * d + 1]);
+  }
+  const float g = p / q;
+  *good = (q > 0.0f) & (fabsf(g) <= 3.402823466e38f);
+  return g;
+}
+
 template <int DEG = kNdeg, bool UNI = true>
 __device__ __forceinline__ float metric_cost(int32_t N, const float* xs, const float* __restrict__ cf,
                                              const CfgRec& r) {
-  const float x = xs[0];
-  const float2 lo = UNI ? vgpr_pair(cf + 2 * (DEG - 1)) : make_float2(cf[2 * (DEG - 1)], cf[2 * DEG - 1]);
-  float p = __builtin_fmaf(cf[2 * DEG], x, lo.x);
-  float q = __builtin_fmaf(cf[2 * DEG + 1], x, lo.y);
-#pragma unroll
-  for (int d = DEG - 2; d >= 0; --d) {
-    p = __builtin_fmaf(p, x, cf[2 * d]);
-    q = __builtin_fmaf(q, x, cf[2 * d + 1]);
-  }
-  const float g = p / q;
-  const bool ok = (r.ok != 0) & (N >= r.Lmax) & (q > 0.0f) & (fabsf(g) <= 3.402823466e38f);
+  bool good;
+  const float g = fitted_value<DEG, UNI>(cf, 0, xs[0], &good);
+  const bool ok = (r.ok != 0) & (N >= r.Lmax) & good;
   return ok ? g : INFINITY;
 }
 
-// Either cost, chosen per program (wave-uniform).
+// A piecewise rational program with a fitted decision node (paper: the decision nodes of a
+// rational program are themselves rational functions, so they can be fitted like the metrics):
+// fits 0, 1, 2 are the decision d, the cost where d >= 0 and the cost where d < 0.  The point
+// is inadmissible where d or the branch taken is (q <= 0 or not finite), or where the launch
+// constraints fail.
+template <int DEG = kNdeg, bool UNI = true>
+__device__ __forceinline__ float piecewise_cost(int32_t N, const float* xs, const float* __restrict__ cf,
+                                                const CfgRec& r) {
+  bool gd, ga, gb;
+  const float d = fitted_value<DEG, UNI>(cf, 0, xs[0], &gd);
+  const float a = fitted_value<DEG, UNI>(cf, 1, xs[1], &ga);
+  const float b = fitted_value<DEG, UNI>(cf, 2, xs[2], &gb);
+  const bool first = d >= 0.0f;
+  const bool ok = (r.ok != 0) & (N >= r.Lmax) & gd & (first ? ga : gb);
+  return ok ? (first ? a : b) : INFINITY;
+}
+
+// Any cost, chosen per program (wave-uniform).
 template <int GRID, int DEG = kNdeg, bool UNI = true>
 __device__ __forceinline__ float any_cost(int kind, int32_t N, const float* xs, const float* __restrict__ cf,
                                           const CfgRec& r, const Hw32& hw) {
-  return kind == KLR_COST_METRIC ? metric_cost<DEG, UNI>(N, xs, cf, r) : point_cost<GRID, DEG, UNI>(N, xs, cf, r, hw);
+  if (kind == KLR_COST_METRIC) return metric_cost<DEG, UNI>(N, xs, cf, r);
+  if (kind == KLR_COST_PIECEWISE) return piecewise_cost<DEG, UNI>(N, xs, cf, r);
+  return point_cost<GRID, DEG, UNI>(N, xs, cf, r, hw);
 }
 
 struct SweepOut {
@@ -525,8 +555,9 @@ __device__ __forceinline__ void sweep_cfgs(const klr_program& P, const float* __
     const float* cf = slot0 + (int64_t)c * kSlotFloats;
 #pragma unroll
     for (int u = 0; u < QPL; ++u) {
-      const float cost = KIND == KLR_COST_METRIC ? metric_cost<DEG>(N[u], xs[u], cf, r)
-                                                 : point_cost<GRID, DEG>(N[u], xs[u], cf, r, hw);
+      const float cost = KIND == KLR_COST_METRIC      ? metric_cost<DEG>(N[u], xs[u], cf, r)
+                         : KIND == KLR_COST_PIECEWISE ? piecewise_cost<DEG>(N[u], xs[u], cf, r)
+                                                      : point_cost<GRID, DEG>(N[u], xs[u], cf, r, hw);
       if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost;
       if (cost < best[u]) { best[u] = cost; bi[u] = c; }
     }
@@ -566,6 +597,8 @@ eval_kernel(const klr_program* __restrict__ progs, const float* __restrict__ coe
   const int deg = prog_degree(a)[p];
   if (P.cost_kind == KLR_COST_METRIC)
     sweep_cfgs<QPL, KLR_GRID_1D, kNdeg, KLR_COST_METRIC>(P, slot0, rec0, hw, N, live, qi, costs, best, bi);
+  else if (P.cost_kind == KLR_COST_PIECEWISE)
+    sweep_cfgs<QPL, KLR_GRID_1D, kNdeg, KLR_COST_PIECEWISE>(P, slot0, rec0, hw, N, live, qi, costs, best, bi);
   else if (P.grid_kind == KLR_GRID_1D && deg <= 2)
     sweep_cfgs<QPL, KLR_GRID_1D, 2>(P, slot0, rec0, hw, N, live, qi, costs, best, bi);
   else if (P.grid_kind == KLR_GRID_1D)

@@ -1112,13 +1112,43 @@ void fit_workspace_split(FitArgs& a) {
   a.scratch_rows = a.ws_bytes > head ? (int64_t)((a.ws_bytes - head) / (2 * sizeof(double))) : 0;
 }
 
-hipError_t launch_fit(const FitArgs& a) {
-  if (a.precision == KLR_FP64_SVD) return launch_fit_svd(a);
+hipError_t launch_fit_once(const FitArgs& a) {
+  if (a.precision == KLR_FP64) return launch_all<KLR_FP64>(a, a.persistent);
+  if (a.precision == KLR_FP32_REFINED) return launch_all<KLR_FP32_REFINED>(a, a.persistent);
+  return launch_all<KLR_BF16_REFINED>(a, a.persistent);
+}
+
+hipError_t launch_fit(const FitArgs& a0) {
+  if (a0.precision == KLR_FP64_SVD) return launch_fit_svd(a0);
+  FitArgs a = a0;
+  int v = a.variant;
+  if (v < 0 && a.tuner) {
+    // autotune: every variant once on this batch (they give identical results), HIP events on
+    // the caller's stream; the fastest is cached under the batch's shape key
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = 0.0f;
+    int bv = 0;
+    for (int i = 0; i < kFitVariants && e == hipSuccess; ++i) {
+      a.wave_group = kFitWaveGroups[i];
+      e = hipEventRecord(e0, a.stream);
+      if (e == hipSuccess) e = launch_fit_once(a);
+      if (e == hipSuccess) e = hipEventRecord(e1, a.stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && (i == 0 || ms < best)) { best = ms; bv = i; }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    a.tuner->record(a.tune_key, bv, best);
+    v = bv;
+  }
+  a.wave_group = kFitWaveGroups[v >= 0 && v < kFitVariants ? v : 0];
   const int t = a.timer ? a.timer->begin(KLR_K_FIT_SOLVE, a.stream) : -1;
-  hipError_t e;
-  if (a.precision == KLR_FP64) e = launch_all<KLR_FP64>(a, a.persistent);
-  else if (a.precision == KLR_FP32_REFINED) e = launch_all<KLR_FP32_REFINED>(a, a.persistent);
-  else e = launch_all<KLR_BF16_REFINED>(a, a.persistent);
+  const hipError_t e = launch_fit_once(a);
   if (a.timer) a.timer->end(t, a.stream);
   return e;
 }

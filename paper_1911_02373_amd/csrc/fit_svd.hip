@@ -141,14 +141,14 @@ __device__ void svd_fit(const FitArgs& a, int fi, SvdLds<NC, W>& L) {
       if (a.exps[(int64_t)d.den0 * KLR_MAX_VARS + k] != 0) ok = false;
     }
   if (t == 0) L.flag = 0;
-  if (ok && t < NC * 8) {
-    const int j = t / 8, k = t % 8;
+  for (int q = t; ok && q < NC * 8; q += W) {      // NC * 8 entries: more than the threads when NC = 48
+    const int j = q / 8, k = q % 8;
     uint8_t e = 0;
     if (j < n && k < v) {
       const int64_t row = j < d.n_num ? (int64_t)d.num0 + j : (int64_t)d.den0 + (j - d.n_num + 1);
       e = a.exps[row * KLR_MAX_VARS + k];
     }
-    L.ex[t] = e;
+    L.ex[q] = e;
   }
   __syncthreads();
   // the sample row: design-matrix row from the scaled variables and the target (the variables

@@ -36,7 +36,6 @@ namespace {
 constexpr int kNP = 48;            // padded unknowns: three 16-column tiles
 static_assert(kNP <= 48, "the 8 x 8 update grid of the factorization covers 48 rows");
 constexpr int kV = 4;              // variables
-constexpr int kWavesPerGroup = 4;
 constexpr int kSP = kNP * (kNP + 1) / 2;
 
 
@@ -588,61 +587,70 @@ __device__ void fit_wave_one(const FitArgs& a, int fi, WaveLds& L) {
   wave_sync();
 }
 
-// Longest-first schedule: wave w of workgroup b takes position 4 b + w of its row class's part
+// Longest-first schedule: wave w of workgroup b takes position WG b + w of its row class's part
 // of the plan's order (the dispatcher starts workgroups in index order, so the longest fits
 // start first); positions past the class's count leave at once.  Fits with 8 rows per lane run
-// two waves per SIMD; those with 16 rows per lane need the whole register file of one.
-template <int PREC, int RPL>
+// two waves per SIMD; those with 16 rows per lane need the whole register file of one.  WG
+// (fits per workgroup: 1, 2 or 4) changes only how the fits are grouped into workgroups (a
+// workgroup's LDS is released when its last fit ends), never a fit's arithmetic.
+template <int PREC, int RPL, int WG>
 __device__ __forceinline__ void ordered_body(const FitArgs& a, const WavePlanView& pv, WaveLds* lds) {
-  const int i = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+  const int i = blockIdx.x * WG + (threadIdx.x >> 6);
   if (i >= *pv.total) return;
   fit_wave_one<PREC, RPL>(a, pv.order[*pv.base + i], lds[threadIdx.x >> 6]);
 }
-template <int PREC, int RPL>
+template <int PREC, int RPL, int WG>
 __device__ __forceinline__ void plain_body(const FitArgs& a, WaveLds* lds) {
-  const int fi = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+  const int fi = blockIdx.x * WG + (threadIdx.x >> 6);
   if (fi >= a.n_fits || wave_fit_rows(a, a.desc[fi]) != RPL) return;
   fit_wave_one<PREC, RPL>(a, fi, lds[threadIdx.x >> 6]);
 }
 
-template <int PREC>
-__global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(2)))
+template <int PREC, int WG>
+__global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(2)))
 fit_wave_ordered(FitArgs a, WavePlanView pv) {
-  __shared__ WaveLds lds[kWavesPerGroup];
-  ordered_body<PREC, 8>(a, pv, lds);
+  __shared__ WaveLds lds[WG];
+  ordered_body<PREC, 8, WG>(a, pv, lds);
 }
-template <int PREC>
-__global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(1)))
+template <int PREC, int WG>
+__global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(1)))
 fit_wave_ordered16(FitArgs a, WavePlanView pv) {
-  __shared__ WaveLds lds[kWavesPerGroup];
-  ordered_body<PREC, 16>(a, pv, lds);
+  __shared__ WaveLds lds[WG];
+  ordered_body<PREC, 16, WG>(a, pv, lds);
 }
 
 // One wave per fit in descriptor order; waves whose fit is not of the kernel's row class leave.
-template <int PREC>
-__global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(2)))
+template <int PREC, int WG>
+__global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(2)))
 fit_wave_plain(FitArgs a) {
-  __shared__ WaveLds lds[kWavesPerGroup];
-  plain_body<PREC, 8>(a, lds);
+  __shared__ WaveLds lds[WG];
+  plain_body<PREC, 8, WG>(a, lds);
 }
-template <int PREC>
-__global__ void __launch_bounds__(64 * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(1)))
+template <int PREC, int WG>
+__global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(1)))
 fit_wave_plain16(FitArgs a) {
-  __shared__ WaveLds lds[kWavesPerGroup];
-  plain_body<PREC, 16>(a, lds);
+  __shared__ WaveLds lds[WG];
+  plain_body<PREC, 16, WG>(a, lds);
+}
+
+template <int PREC, int WG>
+hipError_t launch_wave_g(const FitArgs& a, bool ordered, const WavePlanView& pv8, const WavePlanView& pv16) {
+  const dim3 grid((unsigned)((a.n_fits + WG - 1) / WG)), block(64 * WG);
+  if (ordered) {
+    hipLaunchKernelGGL((fit_wave_ordered16<PREC, WG>), grid, block, 0, a.stream, a, pv16);
+    hipLaunchKernelGGL((fit_wave_ordered<PREC, WG>), grid, block, 0, a.stream, a, pv8);
+  } else {
+    hipLaunchKernelGGL((fit_wave_plain16<PREC, WG>), grid, block, 0, a.stream, a);
+    hipLaunchKernelGGL((fit_wave_plain<PREC, WG>), grid, block, 0, a.stream, a);
+  }
+  return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t launch_wave_t(const FitArgs& a, bool ordered, const WavePlanView& pv8, const WavePlanView& pv16) {
-  const dim3 grid((unsigned)((a.n_fits + kWavesPerGroup - 1) / kWavesPerGroup)), block(64 * kWavesPerGroup);
-  if (ordered) {
-    hipLaunchKernelGGL(fit_wave_ordered16<PREC>, grid, block, 0, a.stream, a, pv16);
-    hipLaunchKernelGGL(fit_wave_ordered<PREC>, grid, block, 0, a.stream, a, pv8);
-  } else {
-    hipLaunchKernelGGL(fit_wave_plain16<PREC>, grid, block, 0, a.stream, a);
-    hipLaunchKernelGGL(fit_wave_plain<PREC>, grid, block, 0, a.stream, a);
-  }
-  return hipGetLastError();
+  if (a.wave_group == 1) return launch_wave_g<PREC, 1>(a, ordered, pv8, pv16);
+  if (a.wave_group == 2) return launch_wave_g<PREC, 2>(a, ordered, pv8, pv16);
+  return launch_wave_g<PREC, 4>(a, ordered, pv8, pv16);
 }
 
 }  // namespace

@@ -42,6 +42,9 @@ struct Tuner {
   void record(uint64_t key, int variant, float ms);
   void load();
 };
+// Tune-cache keys: bit 56 marks an evaluation shape, bit 57 a fit batch.
+constexpr uint64_t kTuneEvalTag = 1ull << 56;
+constexpr uint64_t kTuneFitTag = 2ull << 56;
 
 }  // namespace klr
 
@@ -51,7 +54,7 @@ struct klr_handle_s {
   klr::Timer timer;
   klr::Tuner tuner;
   bool capturing = false;
-  int64_t opt[8] = {1, -1, 0, 0, 0, 0, 0, 0};   // see KLR_OPT_* in klr.h
+  int64_t opt[8] = {1, -1, -1, 0, 0, 0, 0, 0};   // see KLR_OPT_* in klr.h
 };
 
 namespace klr {
@@ -118,7 +121,15 @@ struct FitArgs {
   int64_t* rowoff;         // per-fit first scratch row (workspace, set by fit_workspace_split)
   double* scratch;         // 2 x scratch_rows FP64 residual scratch (workspace)
   int64_t scratch_rows;
+  int wave_group = 4;      // fits per workgroup of the one-wavefront kernel (1, 2 or 4)
+  int variant = -1;        // index into the fit launch variants; < 0: autotune with `tuner`
+  Tuner* tuner = nullptr;
+  uint64_t tune_key = 0;
 };
+// Fit launch variants (all give bit-identical results): fits per workgroup of the one-wavefront
+// kernel.
+constexpr int kFitVariants = 3;
+constexpr int kFitWaveGroups[kFitVariants] = {4, 2, 1};
 
 size_t fit_workspace_bytes(int32_t n_fits, int64_t total_rows, int32_t precision);
 // Point rowoff / scratch / scratch_rows of `a` into its workspace (a.ws, a.ws_bytes, a.n_fits).

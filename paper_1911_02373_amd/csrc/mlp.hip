@@ -611,8 +611,9 @@ mlp_select(SelectArgs a, Blob w, int chunks, int64_t n_items) {
     const int qb = (int)(item % chunks) * kSelQ;
     const klr_program P = a.progs[p];
     // the descriptor checks of the exact path: a program it rejects gets no output here either
-    const int nmet = P.cost_kind == KLR_COST_METRIC ? 1 : KLR_N_METRICS;
-    const bool desc_ok = (P.cost_kind == KLR_COST_CYCLES || P.cost_kind == KLR_COST_METRIC) && P.fit0 >= 0 &&
+    const int nmet = P.cost_kind == KLR_COST_METRIC ? 1 : (P.cost_kind == KLR_COST_PIECEWISE ? 3 : KLR_N_METRICS);
+    const bool desc_ok = (P.cost_kind == KLR_COST_CYCLES || P.cost_kind == KLR_COST_METRIC ||
+                          P.cost_kind == KLR_COST_PIECEWISE) && P.fit0 >= 0 &&
                          (int64_t)P.fit0 + nmet <= a.n_fits &&
                          P.v_launch >= 1 && P.v_launch <= KLR_MAX_LAUNCH && P.n_cfg >= 0 &&
                          P.n_cfg <= a.max_cfg && P.n_q >= 0 && P.n_q <= a.max_q && P.cfg0 >= 0 &&

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libklr.so")
 
 KLR_OK, KLR_E_INVALID, KLR_E_WORKSPACE, KLR_E_HIP, KLR_E_UNSUPPORTED = 0, -1, -2, -3, -4
-KLR_FP64, KLR_FP32_REFINED, KLR_BF16_REFINED = 0, 1, 2
+KLR_FP64, KLR_FP32_REFINED, KLR_BF16_REFINED, KLR_FP64_SVD = 0, 1, 2, 3
 GRID_1D, GRID_2D = 0, 1
 N_METRICS = 8
 MAX_VARS = 8
@@ -40,8 +40,12 @@ EXPORTS = ("klr_create", "klr_destroy", "klr_last_error", "klr_fit_workspace", "
            "klr_surrogate_step", "klr_surrogate_eval_workspace", "klr_surrogate_eval",
            "klr_surrogate_init", "klr_set_option", "klr_capture_begin", "klr_capture_end",
            "klr_graph_launch", "klr_graph_destroy", "klr_selftest_divisors",
-           "klr_selftest_divisor_list", "klr_eval_argmin_noalloc")
-OPT_FIT_PERSISTENT, OPT_EVAL_VARIANT = 0, 1
+           "klr_selftest_divisor_list", "klr_eval_argmin_noalloc", "klr_service_workspace",
+           "klr_service_create", "klr_service_destroy", "klr_service_add_constraint", "klr_service_decide",
+           "klr_service_stats", "klr_service_set_history_limit", "klr_constraint_check",
+           "klr_collect_buffer", "klr_target_attributes", "klr_collect_times")
+TARGET_TRANSPOSE, TARGET_STENCIL = 0, 1
+OPT_FIT_PERSISTENT, OPT_EVAL_VARIANT, OPT_FIT_VARIANT = 0, 1, 2
 K_COLLAPSE, K_EVAL, K_FIT_GRAM, K_FIT_SOLVE, K_MLP, K_SURR, K_FALLBACK = 0, 1, 2, 3, 4, 5, 6
 TRAIN_CFG = np.dtype([("lr", "<f4"), ("beta1", "<f4"), ("beta2", "<f4"), ("eps", "<f4"),
                       ("batch", "<i4"), ("epochs", "<i4"), ("seed", "<u8")])
@@ -118,7 +122,46 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.klr_surrogate_eval.argtypes = [P, P, I32, P, I32, I32, I32, P, P, I32, P, I32, P, I64, P, I64,
                                        P, I64, F, P, P, P, P, P, P, SZ, P]
     lib.klr_surrogate_eval.restype = I32
+    lib.klr_service_workspace.argtypes = [I32, I32]
+    lib.klr_service_workspace.restype = SZ
+    lib.klr_service_create.argtypes = [P, ctypes.POINTER(P), P, I32, P, P, I32, P, I32, P, I64, P, P, I64, I32,
+                                       P, SZ]
+    lib.klr_service_create.restype = I32
+    lib.klr_service_destroy.argtypes = [P]
+    lib.klr_service_destroy.restype = None
+    lib.klr_service_add_constraint.argtypes = [P, I32, ctypes.c_char_p]
+    lib.klr_service_add_constraint.restype = I32
+    lib.klr_service_decide.argtypes = [P, I32, P, I32, P, P]
+    lib.klr_service_decide.restype = I32
+    lib.klr_service_stats.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64),
+                                      ctypes.POINTER(I64)]
+    lib.klr_service_stats.restype = I32
+    lib.klr_service_set_history_limit.argtypes = [P, I64]
+    lib.klr_service_set_history_limit.restype = I32
+    lib.klr_constraint_check.argtypes = [ctypes.c_char_p, I32, P, I32, ctypes.c_char_p, I32]
+    lib.klr_constraint_check.restype = I32
+    lib.klr_collect_buffer.argtypes = [I32, I32]
+    lib.klr_collect_buffer.restype = SZ
+    lib.klr_target_attributes.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.klr_target_attributes.restype = I32
+    lib.klr_collect_times.argtypes = [P, I32, P, I32, I32, P, P, SZ, P]
+    lib.klr_collect_times.restype = I32
     return lib
+
+
+def constraint_check(lib, expr: str, N: int, L) -> int:
+    """[host] 1 / 0 for the constraint at (N, L), -1 on a parse error (raises KlrError)."""
+    arr = np.ascontiguousarray(np.asarray(L, np.int32))
+    err = ctypes.create_string_buffer(256)
+    r = lib.klr_constraint_check(expr.encode(), int(N), arr.ctypes.data if arr.size else None, int(arr.size),
+                                 err, 256)
+    if r < 0:
+        raise KlrError(KLR_E_INVALID, err.value.decode())
+    return int(r)
+
+
+LAUNCH = np.dtype([("gx", "<i4"), ("gy", "<i4"), ("gz", "<i4"), ("bx", "<i4"), ("by", "<i4"), ("bz", "<i4"),
+                   ("config", "<i4"), ("cost", "<f4")])
 
 
 def surrogate_layout(lib, n_kernels: int) -> dict:
@@ -244,8 +287,9 @@ def eval_fit_descs(pb) -> np.ndarray:
     # reports it as a bad descriptor)
     fit0 = np.asarray(pb.fit0, np.int64)
     ck = getattr(pb, "cost_kind", None)
-    nmet = np.where(np.asarray(ck) == 1, 1, N_METRICS) if ck is not None else np.full(fit0.shape, N_METRICS)
-    for k in (1, N_METRICS):
+    ck_a = np.asarray(ck) if ck is not None else np.zeros(fit0.shape, np.int32)
+    nmet = np.where(ck_a == 1, 1, np.where(ck_a == 2, 3, N_METRICS))
+    for k in (1, 3, N_METRICS):
         sel = (nmet == k) & (fit0 >= 0) & (fit0 + k <= n)
         fit_idx = (fit0[sel][:, None] + np.arange(k)).reshape(-1)
         d["v"][fit_idx] = np.repeat(1 + np.asarray(pb.v_launch)[sel], k)
@@ -463,6 +507,28 @@ class Library:
         self._check(st)
         return am, pc, fb
 
+    # ---- data collection ----------------------------------------------------------------
+    def target_attributes(self, target: int) -> dict:
+        r, z = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.klr_target_attributes(self.h, target, ctypes.byref(r), ctypes.byref(z)))
+        return {"regs": int(r.value), "lds_bytes": int(z.value)}
+
+    def collect_times(self, target: int, samples, reps: int = 5, stream=None) -> np.ndarray:
+        """Mean kernel time in microseconds at each (N, bx, by) row of `samples`."""
+        torch = _torch()
+        smp = np.ascontiguousarray(np.asarray(samples, np.int32).reshape(-1, 3))
+        out = np.zeros(smp.shape[0], np.float64)
+        if smp.shape[0] == 0:
+            return out
+        need = int(self.lib.klr_collect_buffer(target, int(smp[:, 0].max())))
+        buf = getattr(self, "_collect_buf", None)
+        if buf is None or buf.numel() < need:
+            buf = torch.zeros(max(need, 1), dtype=torch.uint8, device="cuda")
+            self._collect_buf = buf
+        self._check(self.lib.klr_collect_times(self.h, target, smp.ctypes.data, smp.shape[0], reps,
+                                               out.ctypes.data, _ptr(buf), int(buf.numel()), self._stream(stream)))
+        return out
+
     # ---- fit ----------------------------------------------------------------------------
     def fit_workspace(self, n_fits: int, total_rows: int, precision: int) -> int:
         return int(self.lib.klr_fit_workspace(n_fits, total_rows, precision))
@@ -555,3 +621,53 @@ def grid_samples(pb, de: DeviceEval, costs):
     c0 = int(pb.cfg0[0])
     L = de.cfgs[c0: c0 + 2 * C].view(1, C, 1, 2).expand(P, C, Q, 2).reshape(-1)
     return kid.contiguous(), N.contiguous(), L.contiguous(), costs[: P * C * Q].contiguous()
+
+
+class Service:
+    """Launch-time decision service over the programs of a DeviceEval (klr_service_*): decisions
+    for data sizes with a history, optional Python-syntax constraints per program."""
+
+    def __init__(self, lib: "Library", de: DeviceEval, pb, max_batch: int = 1024):
+        torch = _torch()
+        self.lib, self.L = lib, lib.lib
+        self.progs_host = program_descs(pb)
+        self.cfgs_host = np.ascontiguousarray(pb.cfgs.astype(np.int32))
+        max_cfg = int(max(1, pb.n_cfg.max()))
+        self.ws = lib._aligned(int(self.L.klr_service_workspace(max_cfg, max_batch)), de.queries.device)
+        self.de = de                                   # keeps the device arrays alive
+        s = ctypes.c_void_p()
+        st = self.L.klr_service_create(lib.h, ctypes.byref(s), self.progs_host.ctypes.data, int(pb.n_progs),
+                                       de.hw.ctypes.data, _ptr(de.desc), de.n_fits, _ptr(de.exps), de.n_exp_rows,
+                                       _ptr(de.coef), int(de.coef.numel()), self.cfgs_host.ctypes.data,
+                                       _ptr(de.cfgs), int(self.cfgs_host.size), max_batch, _ptr(self.ws),
+                                       int(self.ws.numel()))
+        lib._check(st)
+        self.s = s
+        del torch
+
+    def close(self):
+        if self.s:
+            self.L.klr_service_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_constraint(self, prog: int, expr: str):
+        self.lib._check(self.L.klr_service_add_constraint(self.s, int(prog), expr.encode()))
+
+    def decide(self, prog: int, N, stream=None) -> np.ndarray:
+        Nh = np.ascontiguousarray(np.asarray(N, np.int32))
+        out = np.zeros(Nh.size, LAUNCH)
+        self.lib._check(self.L.klr_service_decide(self.s, int(prog), Nh.ctypes.data if Nh.size else None,
+                                                  int(Nh.size), out.ctypes.data if Nh.size else None,
+                                                  self.lib._stream(stream)))
+        return out
+
+    def stats(self) -> dict:
+        v = [ctypes.c_int64() for _ in range(4)]
+        self.lib._check(self.L.klr_service_stats(self.s, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("hits", "misses", "evaluations", "entries"), (int(x.value) for x in v)))

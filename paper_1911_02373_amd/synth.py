@@ -192,6 +192,45 @@ def config1_truth_grid(fb: FitBatch) -> np.ndarray:
     return _truth_value(xt, E, fb.exps[fb.den0[0]: fb.den0[0] + fb.n_den[0], :2], t[:n_num], c_den).reshape(Bs.size, Ns.size)
 
 
+def block_shapes(t_min: int = 64, t_max: int = 1024) -> np.ndarray:
+    """Power-of-two block shapes (bx, by) with t_min <= bx by <= t_max (45 shapes for 64..1024)."""
+    return pow2_launch_tuples(2, t_min, t_max)
+
+
+def collection_plan(seed: int, n_samples: int = 200, log2_range=(8.0, 12.5), shapes=None) -> np.ndarray:
+    """Sample points K for timing a target kernel: rows (N, bx, by), N = round(2^u) with
+    u ~ U(log2_range), the block shape uniform over `shapes` (default block_shapes())."""
+    rng = np.random.default_rng(seed)
+    shapes = block_shapes() if shapes is None else shapes
+    N = np.rint(2.0 ** rng.uniform(log2_range[0], log2_range[1], n_samples)).astype(np.int32)
+    S = shapes[rng.integers(0, shapes.shape[0], n_samples)]
+    return np.stack([N, S[:, 0], S[:, 1]], 1).astype(np.int32)
+
+
+def measured_fit(samples: np.ndarray, values: np.ndarray, degree: int = 2, scale=(13, 10, 10)) -> FitBatch:
+    """One fit of measured values at sample rows (N, bx, by): numerator and denominator over the
+    monomials of total degree <= `degree` in the scaled variables (N / 2^13, bx / 2^10, by / 2^10)."""
+    E = monomials(3, degree)
+    sc = np.zeros((1, MAX_VARS), np.int8)
+    sc[0, :3] = scale
+    return _pack_fits([(np.asarray(samples, np.int32), np.asarray(values, np.float64))], np.concatenate([E, E]),
+                      [0], [E.shape[0]], [E.shape[0]], [E.shape[0]], sc, meta={"kind": "measured"})
+
+
+def measured_program(fb: FitBatch, shapes: np.ndarray, queries, coef=None) -> "ProgramBatch":
+    """A metric-cost program over fit 0 of `fb` (a fitted kernel time): configurations `shapes`
+    (bx, by), queries the data sizes `queries`, wavefront 64."""
+    q = np.asarray(queries, np.int32)
+    c = np.zeros(fb.n_coef) if coef is None else np.asarray(coef, np.float64)
+    return ProgramBatch(
+        fits=None, coef=c, exps=fb.exps, num0=fb.num0[:1], n_num=fb.n_num[:1], den0=fb.den0[:1],
+        n_den=fb.n_den[:1], coef0=np.zeros(1, np.int64), scale_exp=fb.scale_exp[:1],
+        v_launch=np.full(1, 2, np.int32), fit0=np.zeros(1, np.int32), cfg0=np.zeros(1, np.int64),
+        n_cfg=np.array([shapes.shape[0]], np.int32), grid_kind=np.ones(1, np.int32), q0=np.zeros(1, np.int64),
+        n_q=np.array([q.size], np.int32), cfgs=np.ascontiguousarray(shapes.reshape(-1).astype(np.int32)),
+        queries=q, hw=HW(), cost_kind=np.ones(1, np.int32))
+
+
 LITERAL_PAIRS = np.array([(bx, by) for bx in (16, 32, 48, 64) for by in (16, 32, 48, 64)
                           if bx * by <= 1024], np.int32)
 POW2_PAIRS = np.array([(1 << a, 1 << b) for a in range(11) for b in range(11)
@@ -409,6 +448,106 @@ def mixed_programs(seed: int, n_progs: int, n_q_range=(1, 700), n_cfg_range=(1, 
         cfg0=np.array(cfg0, np.int64), n_cfg=np.array(n_cfg, np.int32),
         grid_kind=np.array(gk, np.int32), q0=np.array(q0, np.int64), n_q=np.array(n_q, np.int32),
         cfgs=np.concatenate(cfg_parts).astype(np.int32), queries=np.concatenate(q_parts), hw=HW())
+
+
+def piecewise_batch(seed: int, n_progs: int = 64, n_q: int = 512, m: int = 240, noise: float = 0.01):
+    """Programs with two regimes and a decision between them (a piecewise rational program):
+    over (N, bx, by) scaled by (2^26, 2^10, 2^10), the decision d = (c - x_N (1 + a x_bx)) /
+    (1 + b x_by) (c ~ U(0.002, 0.05), a, b ~ U(0.1, 2); positive below a data size that moves with
+    the block shape) and two costs g_a, g_b, polynomials of total degree <= 2 with coefficients
+    U(0.1, 2) (g_b scaled up by 1.5 - 3, the slower regime).  Each program has three fits over
+    the monomials of total degree <= 2: d as a rational function (numerator and denominator) from
+    m samples over the whole domain (its exact value, a measured quantity such as a working set
+    minus a cache size), g_a and g_b as polynomials (denominator 1) from m samples where d >= 0,
+    respectively d < 0 (each regime is observed only where it holds), times exp(noise z).  Configurations: the c3 launch set; queries N = round(2^u),
+    u ~ U(8, 26).  Returns (FitBatch of 3 n_progs fits, ProgramBatch with the truth's
+    coefficients in the fit layout, truth function)."""
+    rng = np.random.default_rng(seed)
+    E = monomials(3, 2)
+    nm = E.shape[0]
+    cfgs = config3_launch_configs()
+    adm = cfgs[:127]
+    sc = np.array([26, 10, 10], np.int8)
+
+    def scaled(X):
+        return X.astype(np.float64) * 2.0 ** -sc.astype(np.float64)
+
+    params = []
+    samples, truth = [], []
+    for p in range(n_progs):
+        c = rng.uniform(0.002, 0.05)
+        a, b = rng.uniform(0.1, 2.0, 2)
+        one = np.zeros(nm)
+        one[0] = 1.0
+        ga_n, ga_d = rng.uniform(0.1, 2.0, nm), one
+        gb_n, gb_d = rng.uniform(0.1, 2.0, nm) * rng.uniform(1.5, 3.0), one
+        # d in the monomial basis 1, x_N, x_bx, x_by, x_N^2, x_N x_bx, ...: numerator c - x_N - a x_N x_bx
+        d_n = np.zeros(nm)
+        d_d = np.zeros(nm)
+        d_d[0] = 1.0
+        for r in range(nm):
+            e = tuple(E[r, :3])
+            if e == (0, 0, 0):
+                d_n[r] = c
+            elif e == (1, 0, 0):
+                d_n[r] = -1.0
+            elif e == (1, 1, 0):
+                d_n[r] = -a
+            elif e == (0, 0, 1):
+                d_d[r] = b
+        params.append((d_n, d_d, ga_n, ga_d, gb_n, gb_d))
+        for j, (cn, cd) in enumerate(((d_n, d_d), (ga_n, ga_d), (gb_n, gb_d))):
+            Xs = []
+            while sum(len(x) for x in Xs) < m:
+                N = np.rint(2.0 ** rng.uniform(8, 26, 4 * m)).astype(np.int64)
+                L = adm[rng.integers(0, adm.shape[0], 4 * m)]
+                X = np.stack([N, L[:, 0], L[:, 1]], 1)
+                if j > 0:
+                    dv = _truth_value(scaled(X), E[:, :3], E[:, :3], d_n, d_d)
+                    X = X[dv >= 0] if j == 1 else X[dv < 0]
+                Xs.append(X)
+            X = np.concatenate(Xs)[:m]
+            f = _truth_value(scaled(X), E[:, :3], E[:, :3], cn, cd)
+            if j > 0:
+                f = f * np.exp(noise * rng.normal(size=f.shape[0]))
+            samples.append((X.astype(np.int32), f))
+            truth.append(np.concatenate([cn, cd[1:]]) if j == 0 else cn.copy())
+    n_fits = 3 * n_progs
+    exps = np.concatenate([E, E])
+    # the decision is a full rational fit; the regime costs are polynomials (denominator 1)
+    n_den = [nm if i % 3 == 0 else 1 for i in range(n_fits)]
+    fb = _pack_fits(samples, exps, [0] * n_fits, [nm] * n_fits, [nm] * n_fits, n_den,
+                    np.tile(np.concatenate([sc, np.zeros(5, np.int8)]), (n_fits, 1)), truth=truth,
+                    meta={"kind": "piecewise"})
+    queries = np.rint(2.0 ** rng.uniform(8, 26, n_progs * n_q)).astype(np.int32)
+    pb = ProgramBatch(
+        fits=None, coef=fb.truth_coef.copy(), exps=exps, num0=fb.num0, n_num=fb.n_num, den0=fb.den0,
+        n_den=fb.n_den, coef0=fb.coef0, scale_exp=fb.scale_exp, v_launch=np.full(n_progs, 2, np.int32),
+        fit0=np.arange(n_progs, dtype=np.int32) * 3, cfg0=np.zeros(n_progs, np.int64),
+        n_cfg=np.full(n_progs, cfgs.shape[0], np.int32), grid_kind=np.zeros(n_progs, np.int32),
+        q0=np.arange(n_progs, dtype=np.int64) * n_q, n_q=np.full(n_progs, n_q, np.int32),
+        cfgs=cfgs.reshape(-1).astype(np.int32), queries=queries, hw=HW(), cost_kind=np.full(n_progs, 2, np.int32))
+
+    def truth_costs(prog, N):
+        """The generator's regime cost at data sizes N, [n_cfg][len(N)] (+inf where the launch
+        constraints fail)."""
+        d_n, d_d, ga_n, ga_d, gb_n, gb_d = params[prog]
+        out = np.full((cfgs.shape[0], len(N)), np.inf)
+        for k in range(cfgs.shape[0]):
+            bx, by = int(cfgs[k, 0]), int(cfgs[k, 1])
+            T = bx * by
+            if T % 64 or T > 1024:
+                continue
+            X = np.stack([np.asarray(N, np.int64), np.full(len(N), bx), np.full(len(N), by)], 1)
+            xt = scaled(X)
+            dv = _truth_value(xt, E[:, :3], E[:, :3], d_n, d_d)
+            va = _truth_value(xt, E[:, :3], E[:, :3], ga_n, ga_d)
+            vb = _truth_value(xt, E[:, :3], E[:, :3], gb_n, gb_d)
+            v = np.where(dv >= 0, va, vb)
+            out[k] = np.where(np.asarray(N) >= max(bx, by), v, np.inf)
+        return out
+
+    return fb, pb, truth_costs
 
 
 def config5_batch(seed: int, n_progs: int = 16384, n_q: int = 4096, m_range=(64, 1024),

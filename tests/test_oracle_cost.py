@@ -315,3 +315,46 @@ def test_metric_cost_noise_free_fit_recovers_truth_decisions():
     idx, _ = oc.argmin_lowest(oc.program_costs(pb, 0, mode="truth"))
     truth = synth.config1_truth_grid(fb)
     assert np.array_equal(idx, np.argmin(truth, axis=0))
+
+
+def test_piecewise_program_matches_the_generators_regimes():
+    """A piecewise program built from the generator's own decision and regime functions: the
+    oracle's FP64 cost is the generator's regime cost (d >= 0: g_a, else g_b) wherever the
+    launch constraints hold, and +inf elsewhere; the FP32 replay agrees to FP32 rounding except
+    where the decision is within FP32 resolution of 0."""
+    fb, pb, truth = synth.piecewise_batch(5, n_progs=3, n_q=200)
+    for p in range(3):
+        q0 = int(pb.q0[p])
+        N = pb.queries[q0:q0 + 200]
+        want = truth(p, N)
+        c64 = oc.program_costs(pb, p, mode="truth")
+        c32 = oc.program_costs(pb, p, mode="replay").astype(np.float64)
+        assert np.array_equal(np.isinf(c64), np.isinf(want))
+        fin = np.isfinite(want)
+        assert np.allclose(c64[fin], want[fin], rtol=1e-12, atol=0)
+        close = np.isclose(c32[fin], want[fin], rtol=2e-6, atol=0)
+        assert close.mean() > 0.999
+
+
+def test_piecewise_fits_recover_the_decision_and_pick_well():
+    """Fitted from the generator's samples by the oracle's least squares: the decision function
+    (exact samples, representable in the monomial set) comes back to rounding, and the per-query
+    argmin of the fitted piecewise program has small regret under the generator's costs."""
+    from oracle import fit as of
+    fb, pb, truth = synth.piecewise_batch(6, n_progs=4, n_q=256)
+    coef, infos = of.fit_batch(fb)
+    for p in range(4):
+        d0 = int(fb.coef0[3 * p])
+        n = int(fb.n_num[0] + fb.n_den[0] - 1)
+        assert np.allclose(coef[d0:d0 + n], fb.truth_coef[d0:d0 + n], rtol=0, atol=1e-8)
+    regrets = []
+    for p in range(4):
+        q0 = int(pb.q0[p])
+        N = pb.queries[q0:q0 + 256]
+        idx, _ = oc.argmin_lowest(oc.program_costs(pb, p, mode="truth", coef=coef))
+        t = truth(p, N)
+        best = t.min(axis=0)
+        ok = np.isfinite(best) & (idx >= 0)
+        regrets.append(t[idx[ok], np.nonzero(ok)[0]] / best[ok] - 1.0)
+    r = np.concatenate(regrets)
+    assert np.median(r) < 0.01 and np.mean(r <= 0.05) > 0.9, (np.median(r), np.mean(r <= 0.05))

@@ -147,3 +147,29 @@ def test_single_fit_workload_end_to_end(klr):
                 torch.cuda.synchronize()
         finally:
             klr.graph_destroy(g)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_fit_variants_bit_identical(klr, prec):
+    """Every fit launch variant (fits per workgroup of the one-wavefront kernel: 4, 2, 1), under
+    both schedules, gives bit-identical coefficients and info records; the autotuned call too."""
+    import torch
+    from paper_1911_02373_amd.klr import OPT_FIT_PERSISTENT, OPT_FIT_VARIANT, DeviceFit, info_records
+    fb = synth.config2_fits(91, 333, "2b", m_range=(20, 1000))
+    df = DeviceFit.from_batch(fb)
+    ref = None
+    try:
+        for pers in (1, 0):
+            klr.set_option(OPT_FIT_PERSISTENT, pers)
+            for v in (-1, 0, 1, 2):
+                klr.set_option(OPT_FIT_VARIANT, v)
+                c, i = klr.fit_batched(df, prec, 256, 1e-9)
+                torch.cuda.synchronize()
+                cur = (c.cpu().numpy().view(np.uint64), info_records(i).view(np.uint8))
+                if ref is None:
+                    ref = cur
+                else:
+                    assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1]), (pers, v)
+    finally:
+        klr.set_option(OPT_FIT_PERSISTENT, 1)
+        klr.set_option(OPT_FIT_VARIANT, -1)
