@@ -77,20 +77,24 @@ def log(*a):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "eval_kernel_hbm_traffic.md")
-EVAL_SOURCE = os.path.join(ROOT, "paper_1911_02373_amd", "csrc", "eval.hip")
+EVAL_SOURCES = [os.path.join(ROOT, "paper_1911_02373_amd", "csrc", f) for f in ("eval.hip", "eval_point.hpp")]
 
 
 def measured_traffic():
     """HBM bytes per launch of the evaluation kernel from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each divided by what the same counter reads
     for a plain device copy of known size), or None when the kernel source changed since the
-    counters were taken or no summary exists."""
+    counters were taken or no summary exists (the digest covers eval.hip and eval_point.hpp, in
+    that order)."""
     import hashlib
     try:
         with open(TRAFFIC_PROFILE) as f:
             lines = f.read().splitlines()
-        with open(EVAL_SOURCE, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for src in EVAL_SOURCES:
+            with open(src, "rb") as f:
+                h.update(f.read())
+        digest = h.hexdigest()
     except OSError:
         return None
     kv = {}
@@ -99,7 +103,7 @@ def measured_traffic():
             k, v = ln[2:].split(": ", 1)
             kv[k.strip()] = v.strip().strip("`")
     try:
-        if kv.get("eval.hip sha256") != digest:
+        if kv.get("eval sources sha256") != digest:
             return None
         fetch = float(kv["FETCH_SIZE KiB per launch"]) / float(kv["FETCH_SIZE copy factor"])
         write = float(kv["WRITE_SIZE KiB per launch"]) / float(kv["WRITE_SIZE copy factor"])

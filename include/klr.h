@@ -319,16 +319,18 @@ klr_status klr_surrogate_step(klr_handle h, void* params, int32_t n_kernels,
                               void* ws, size_t ws_bytes, void* stream);
 /* Surrogate selection over the same programs, configurations and queries as klr_eval_argmin:
  * program p uses embedding p (p < n_kernels).  For each query the network predicts ln C of
- * every statically admissible configuration (T <= t_max, T % wave == 0, every L <= N); the
- * pick is the lowest prediction (lowest index on ties).  If the predicted margin to the second
- * best is below ln(1 + margin), or the exact cost of the pick is +inf (a configuration that the
- * occupancy terms rule out: the network never sees those in training), the query falls back to
- * the exact rational program (klr_eval_argmin semantics) and fell_back[q] = 1.
+ * every configuration the exact program admits at that N (T <= t_max, T % wave == 0, every
+ * L <= N, every fitted metric defined - q > 0 and a finite value - and at least one block
+ * resident: the exact sweep's own FP32 steps, so a configuration left out has exact cost
+ * +inf); the pick is the lowest prediction (lowest index on ties).  If the predicted margin to
+ * the second best is below ln(1 + margin), or the exact cost of the pick is +inf (possible only
+ * where the cycle estimate overflows FP32), the query falls back to the exact rational program
+ * (klr_eval_argmin semantics) and fell_back[q] = 1.
  * pred_cost[q] = exp(predicted ln C) of the pick, or the exact cost on fallback.
  * pred_margin[q] (optional, may be NULL): second-best minus best prediction in ln units (+inf
- * with a single candidate; NaN when the network makes no pick: no statically admissible
- * configuration, or a program it cannot represent - v_launch != 2 or more than 1024
- * configurations - which the exact path answers).  prog_status[n_progs] (optional): as in
+ * with a single candidate; NaN when the network makes no pick: no admissible configuration, or
+ * a program it cannot represent - v_launch != 2 or more than 1024 configurations - which the
+ * exact path answers).  prog_status[n_progs] (optional): as in
  * klr_eval_argmin; a program with KLR_PROG_BAD_DESC gets no output, one with KLR_PROG_BAD_FIT
  * falls back to the exact path and reports -1 / +inf.  Queries are counted per program over its
  * own range, so programs may share query ranges (their outputs then overwrite each other, as in

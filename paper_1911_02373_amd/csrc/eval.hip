@@ -26,28 +26,14 @@
 #include <cmath>
 #include <cstdint>
 
+#include "eval_point.hpp"
 #include "internal.hpp"
 
 namespace klr {
 namespace {
 
-constexpr int kNdeg = KLR_MAX_NDEG;            // powers 0..3 of N~
-constexpr int kSlotFloats = KLR_N_METRICS * 2 * (kNdeg + 1) + KLR_N_METRICS;   // 72
 constexpr int kEvalBlock = 256;
 constexpr int kCollapseBlock = 128;
-
-struct CfgRec {          // per (program, configuration) occupancy terms
-  int32_t T;             // threads per block = prod L
-  float Wb;              // waves per block = T / wave (an integer, exact in FP32)
-  float Bcap;            // min(b_max, floor(wave * w_max / T)) (an integer below 2^11)
-  float rTh;             // floor(r_max / T) + 1/2; floor(r_max / (R T)) = floor(floor(r_max / T) / R)
-  int32_t Lmax;          // largest launch parameter (admissible only if <= N)
-  int32_t L0, L1;        // first two launch parameters (two-dimensional grid)
-  int32_t ok;            // configuration admissible and the program's fits valid
-  uint32_t magTC;        // floor(n / (T n_cu)) = mulhi(n, magTC) >> shTC for 0 <= n < 2^31
-  int32_t shTC;
-  int32_t pad[2];
-};
 
 // Division by an invariant divisor d in [1, 2^31): with l = ceil(log2 d) and
 // m = ceil(2^(31 + l) / d) (fits 32 bits), floor(n / d) = floor(n m / 2^(31 + l)) for every
@@ -73,27 +59,55 @@ __device__ __forceinline__ uint32_t udiv_magic(uint32_t n, uint32_t m, int32_t s
   return sh < 0 ? n : (__umulhi(n, m) >> sh);
 }
 
-// Exact floor(a / b) for integers 0 <= a < 2^20 and 1 <= b <= 2^24, given ah = a + 1/2 (exact
-// in FP32).  With a = k b + j, 0 <= j < b, the quotient (a + 1/2) / b = k + (j + 1/2) / b lies at
-// least 1/(2b) from every integer.  The reciprocal is within one ulp (relative error <= 2^-23)
-// and the product adds at most 2^-24, so ah b^-1 is within ((a + 1/2) / b) 2^-22 < 1/(2b) of
-// the quotient and its floor is k.  b = +0 gives +inf.
-__device__ __forceinline__ float floor_div(float ah, float b) {
-  return floorf(ah * __builtin_amdgcn_rcpf(b));
-}
 
-__device__ __forceinline__ float sel_min(float a, float b) { return b < a ? b : a; }
-
-// Per-program highest power of N~, stored after the configuration records.
+// Per-program highest power of N~, stored after the configuration records, then each program's
+// smallest and largest query size.
 __host__ __device__ inline int32_t* prog_degree(const EvalArgs& a) {
   char* base = reinterpret_cast<char*>(a.ws);
   const int64_t slots = (int64_t)a.n_progs * a.max_cfg;
   return reinterpret_cast<int32_t*>(base + slots * (kSlotFloats * (int64_t)sizeof(float) + (int64_t)sizeof(CfgRec)));
 }
-__device__ __forceinline__ float sel_max(float a, float b) { return b > a ? b : a; }
-// sel_max(good ? v : +0, lo) for lo in {+0, 1}: a failed metric yields lo either way.
-__device__ __forceinline__ float clean_max(bool good, float v, float lo) {
-  return (good && !(lo > v)) ? v : lo;
+__host__ __device__ inline int32_t* prog_nrange(const EvalArgs& a) { return prog_degree(a) + a.n_progs; }
+
+// Quotient a / b by the steps of the correctly rounded FP32 division without its range
+// scaling and special-case fix-up: reciprocal estimate, one Newton step, then two corrections
+// of the quotient by its exact FMA remainder.  For finite a, b with |a| and |b| in
+// [2^-40, 2^40] the scaling steps of the full sequence leave both operands unchanged (the
+// exponents differ by less than 96, neither 1/b nor a/b is subnormal, a is far above the
+// subnormal range) and the fix-up returns the last correction unchanged, so the result is the
+// IEEE quotient bit for bit.
+__device__ __forceinline__ float div_moderate(float a, float b) {
+  const float y0 = __builtin_amdgcn_rcpf(b);
+  const float e0 = __builtin_fmaf(-b, y0, 1.0f);
+  const float y1 = __builtin_fmaf(e0, y0, y0);
+  const float q0 = a * y1;
+  const float r0 = __builtin_fmaf(-b, q0, a);
+  const float q1 = __builtin_fmaf(r0, y1, q0);
+  const float r1 = __builtin_fmaf(-b, q1, a);
+  return __builtin_fmaf(r1, y1, q1);
+}
+
+// Enclosure of every FP32 Horner value (fused multiply-adds from power 3, c[2 d] the coefficient
+// of power d) at FP32 points x in [xl, xh]: interval Horner in FP64 over the exact coefficients,
+// widened by 2^-20 sum |c_d| max|x|^d, above the FP32 Horner error bound 3 u sum |c_d| |x|^d
+// (u = 2^-24) and the FP64 rounding of the interval steps.  Returns false when a partial value
+// could leave the FP32 range.
+__device__ inline bool horner_enclosure(const float* c, double xl, double xh, double* lo, double* hi) {
+  const double xm = fmax(fabs(xl), fabs(xh));
+  double pl = c[2 * kNdeg], ph = pl, sa = fabs(pl);
+  bool fin = sa <= 0x1p100;
+  for (int d = kNdeg - 1; d >= 0; --d) {
+    const double a0 = pl * xl, a1 = pl * xh, a2 = ph * xl, a3 = ph * xh;
+    const double cd = c[2 * d];
+    pl = fmin(fmin(a0, a1), fmin(a2, a3)) + cd;
+    ph = fmax(fmax(a0, a1), fmax(a2, a3)) + cd;
+    sa = sa * xm + fabs(cd);
+    fin = fin && sa <= 0x1p100;
+  }
+  const double E = sa * 0x1p-20;
+  *lo = pl - E;
+  *hi = ph + E;
+  return fin && xm <= 0x1p100;
 }
 
 // Fitted metrics a program reads: the eight of the cycle estimate, or its one cost function.
@@ -182,6 +196,56 @@ __device__ __forceinline__ void collapse_poly(const uint64_t* srows, const uint8
     }
   }
   for (int e = 0; e <= kNdeg; ++e) out[e] = o[e];
+}
+
+// Smallest and largest query size of each program (one workgroup per program); a program
+// without queries gets an empty range (lo > hi).
+constexpr int kRangeBlock = 256;
+__global__ void __launch_bounds__(kRangeBlock) query_range_kernel(EvalArgs a) {
+  __shared__ int32_t s_lo[kRangeBlock / 64], s_hi[kRangeBlock / 64];
+  const int p = blockIdx.x;
+  const klr_program P = a.progs[p];
+  int32_t lo = 0x7fffffff, hi = (int32_t)0x80000000;
+  if (program_desc_ok(P, a))
+    for (int i = threadIdx.x; i < P.n_q; i += kRangeBlock) {
+      const int32_t N = a.queries[P.q0 + i];
+      lo = N < lo ? N : lo;
+      hi = N > hi ? N : hi;
+    }
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int32_t ol = __shfl_xor(lo, off), oh = __shfl_xor(hi, off);
+    lo = ol < lo ? ol : lo;
+    hi = oh > hi ? oh : hi;
+  }
+  if ((threadIdx.x & 63) == 0) { s_lo[threadIdx.x >> 6] = lo; s_hi[threadIdx.x >> 6] = hi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kRangeBlock / 64; ++w) {
+      lo = s_lo[w] < lo ? s_lo[w] : lo;
+      hi = s_hi[w] > hi ? s_hi[w] : hi;
+    }
+    prog_nrange(a)[2 * p] = lo;
+    prog_nrange(a)[2 * p + 1] = hi;
+  }
+}
+
+// Whether the eight metric quotients of a configuration slot can take the short division at
+// every query of the program: over the program's range of scaled sizes, every numerator and
+// denominator stays in [2^-40, 2^40] in magnitude and every denominator is positive (so every
+// metric is defined there, as the exact sweep would find).
+__device__ inline bool slot_divides_short(const float* out, int32_t n_lo, int32_t n_hi) {
+  if (n_lo > n_hi) return false;
+  const double xn_lo = (double)(float)n_lo, xn_hi = (double)(float)n_hi;
+  for (int j = 0; j < KLR_N_METRICS; ++j) {
+    const double sc = out[KLR_N_METRICS * 2 * (kNdeg + 1) + j];     // a power of two
+    const double xl = xn_lo * sc, xh = xn_hi * sc;
+    double pl, ph, ql, qh;
+    if (!horner_enclosure(out + j * 2 * (kNdeg + 1), xl, xh, &pl, &ph)) return false;
+    if (!horner_enclosure(out + j * 2 * (kNdeg + 1) + 1, xl, xh, &ql, &qh)) return false;
+    if (!(ql >= 0x1p-40 && qh <= 0x1p40)) return false;
+    if (!(pl >= -0x1p40 && ph <= 0x1p40 && (pl >= 0x1p-40 || ph <= -0x1p-40))) return false;
+  }
+  return true;
 }
 
 // One workgroup per (program, block of configurations).  The program's eight fit descriptors
@@ -285,8 +349,8 @@ collapse_kernel(EvalArgs a, int chunks) {
   r.L1 = L[1] < 1 ? 1 : L[1];
   r.ok = (cfg_ok && fits_ok) ? 1 : 0;
   magic_u31_wide((uint64_t)r.T * (uint64_t)a.hw.n_cu, &r.magTC, &r.shTC);
-  r.pad[0] = r.pad[1] = 0;
-  *rec = r;
+  r.fast = 0;
+  r.pad = 0;
 
   for (int j = 0; j < KLR_N_METRICS; ++j) {
     double num[kNdeg + 1] = {0, 0, 0, 0}, den[kNdeg + 1] = {1, 0, 0, 0};
@@ -313,35 +377,9 @@ collapse_kernel(EvalArgs a, int chunks) {
     }
     out[KLR_N_METRICS * 2 * (kNdeg + 1) + j] = sc;
   }
-}
-
-// Two adjacent wave-uniform floats (8-byte aligned) copied into a vector register pair.
-__device__ __forceinline__ float2 vgpr_pair(const float* p) {
-  const uint64_t s = *reinterpret_cast<const uint64_t*>(p);
-  uint64_t v;
-  asm("v_mov_b64 %0, %1" : "=v"(v) : "s"(s));
-  return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
-}
-
-struct Hw32 {
-  int32_t n_cu;
-  float w_max;           // integers below 2^11, exact in FP32
-  float zh;              // z_max + 1/2 (z_max < 2^20)
-  float lat, dep, iss, bw;
-};
-
-Hw32 make_hw32(const klr_hw& h) {
-  return Hw32{h.n_cu, (float)h.w_max, (float)h.z_max + 0.5f, h.mem_lat, h.dep_delay, h.issue_cycles, h.bw};
-}
-
-// Scaled query size per metric, x_j = N * 2^-s_j with s_j the scale exponent of metric j's fit.
-// The collapse kernel writes the same scales into every configuration slot of a program (a
-// program whose fits are invalid gets 1 and an inadmissible record in every slot), so the
-// products are formed once per query from the first slot and reused across configurations.
-__device__ __forceinline__ void scaled_n(int32_t N, const float* __restrict__ slot0, float* x) {
-  const float fN = (float)N;
-#pragma unroll
-  for (int j = 0; j < KLR_N_METRICS; ++j) x[j] = fN * slot0[KLR_N_METRICS * 2 * (kNdeg + 1) + j];
+  if (r.ok && P.cost_kind == KLR_COST_CYCLES)
+    r.fast = slot_divides_short(out, prog_nrange(a)[2 * p], prog_nrange(a)[2 * p + 1]) ? 1 : 0;
+  *rec = r;
 }
 
 // Cost of one (query, configuration) point; +inf where inadmissible.  DEG: the program's highest
@@ -349,8 +387,11 @@ __device__ __forceinline__ void scaled_n(int32_t N, const float* __restrict__ sl
 // coefficients above DEG, which gives bit-identical values because fma(0, x, a) = a exactly for
 // finite x and a != -0, and collapsed coefficients are sums that start from +0).
 // UNI: cf and r are the same in every lane (the coefficients then sit in scalar registers); a
-// per-lane configuration takes plain vector loads.
-template <int GRID, int DEG = kNdeg, bool UNI = true>
+// per-lane configuration takes plain vector loads.  SHORT: the configuration's record says every
+// metric's numerator and denominator stay in [2^-40, 2^40] (denominators positive) over the
+// program's queries, so each quotient takes div_moderate (the same bits as the IEEE division)
+// and every metric is defined.
+template <int GRID, int DEG = kNdeg, bool UNI = true, bool SHORT = false>
 __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const float* __restrict__ cf,
                                             const CfgRec& r, const Hw32& hw) {
   static_assert(DEG >= 1 && DEG <= kNdeg, "Horner degree");
@@ -372,9 +413,14 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
       p = __builtin_fmaf(p, x, c[2 * d]);
       q = __builtin_fmaf(q, x, c[2 * d + 1]);
     }
-    g[j] = p / q;
-    good[j] = (q > 0.0f) & (fabsf(g[j]) <= 3.402823466e38f);
-    ok = ok & good[j];
+    if (SHORT) {
+      g[j] = div_moderate(p, q);
+      good[j] = true;
+    } else {
+      g[j] = p / q;
+      good[j] = (q > 0.0f) & (fabsf(g[j]) <= 3.402823466e38f);
+      ok = ok & good[j];
+    }
   }
   // A metric failing the check is cleaned to +0 before its clamp; clean_max takes both steps.
   // The upper clamps of R (>= 1) and Z (>= -0) see no NaN, so fminf equals the compare-select.
@@ -383,16 +429,11 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
   const float Imu = clean_max(good[2], g[2], 0.0f);
   const float U = clean_max(good[3], g[3], 1.0f);
   const float Isync = clean_max(good[4], g[4], 0.0f);
-  const float R = fminf(clean_max(good[5], ceilf(g[5]), 1.0f), 16777216.0f);
-  const float Z = fminf(clean_max(good[6], ceilf(g[6]), 0.0f), 16777216.0f);   // -0 for g in (-1, 0)
   const float Bw = clean_max(good[7], g[7], 1.0f);
 
-  // occupancy: min(b_max, floor(wave w_max / T), floor(r_max / (R T)), floor(z_max / Z)).  Every
-  // term is an integer held exactly in FP32 (the LDS term is +inf when Z = 0: no LDS bound), so
-  // the minima and the products below equal their integer counterparts.
-  const float breg = floor_div(r.rTh, R);
-  const float blds = floor_div(hw.zh, fabsf(Z));   // Z = -0 counts as 0
-  const float B = fminf(fminf(r.Bcap, breg), blds);
+  // occupancy from the register and LDS metrics; the minima and the products below equal their
+  // integer counterparts
+  const float B = resident_blocks(g[5], good[5], g[6], good[6], r, hw);
   ok = ok & (B >= 1.0f);
   const float Bf = fmaxf(B, 1.0f);
   const float Nwf = fminf(Bf * r.Wb, hw.w_max);     // a product above 2^24 is above w_max too
@@ -458,24 +499,6 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
 // Cost of one point of a program whose one fitted function is the cost: p/q of metric 0 by the
 // same Horner steps and division as the cycle estimate's metrics; +inf where q <= 0, the value is
 // not finite, a launch parameter exceeds N or the configuration is not admissible.
-// One fitted function j of a configuration slot at the scaled size x: p / q by the Horner steps
-// of the cycle estimate's metrics; *good = q > 0 and the value finite.
-template <int DEG = kNdeg, bool UNI = true>
-__device__ __forceinline__ float fitted_value(const float* __restrict__ cf, int j, float x, bool* good) {
-  const float* c = cf + j * 2 * (kNdeg + 1);
-  const float2 lo = UNI ? vgpr_pair(c + 2 * (DEG - 1)) : make_float2(c[2 * (DEG - 1)], c[2 * DEG - 1]);
-  float p = __builtin_fmaf(c[2 * DEG], x, lo.x);
-  float q = __builtin_fmaf(c[2 * DEG + 1], x, lo.y);
-#pragma unroll
-  for (int d = DEG - 2; d >= 0; --d) {
-    p = __builtin_fmaf(p, x, c[2 * d]);
-    q = __builtin_fmaf(q, x, c[2 * d + 1]);
-  }
-  const float g = p / q;
-  *good = (q > 0.0f) & (fabsf(g) <= 3.402823466e38f);
-  return g;
-}
-
 template <int DEG = kNdeg, bool UNI = true>
 __device__ __forceinline__ float metric_cost(int32_t N, const float* xs, const float* __restrict__ cf,
                                              const CfgRec& r) {
@@ -553,6 +576,15 @@ __device__ __forceinline__ void sweep_cfgs(const klr_program& P, const float* __
   for (int c = 0; c < P.n_cfg; ++c) {
     const CfgRec r = rec0[c];
     const float* cf = slot0 + (int64_t)c * kSlotFloats;
+    if (KIND == KLR_COST_CYCLES && r.fast) {     // wave-uniform
+#pragma unroll
+      for (int u = 0; u < QPL; ++u) {
+        const float cost = point_cost<GRID, DEG, true, true>(N[u], xs[u], cf, r, hw);
+        if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost;
+        if (cost < best[u]) { best[u] = cost; bi[u] = c; }
+      }
+      continue;
+    }
 #pragma unroll
     for (int u = 0; u < QPL; ++u) {
       const float cost = KIND == KLR_COST_METRIC      ? metric_cost<DEG>(N[u], xs[u], cf, r)
@@ -751,12 +783,13 @@ fb_exact(const klr_program* __restrict__ progs, const float* __restrict__ coefs,
 size_t eval_workspace_bytes(int32_t n_progs, int32_t max_cfg) {
   if (n_progs <= 0) return 0;
   const size_t slots = (size_t)(n_progs > 0 ? n_progs : 0) * (size_t)(max_cfg > 0 ? max_cfg : 0);
-  return slots * (kSlotFloats * sizeof(float) + sizeof(CfgRec)) + (size_t)(n_progs > 0 ? n_progs : 0) * 4 + 256;
+  return slots * (kSlotFloats * sizeof(float) + sizeof(CfgRec)) + (size_t)(n_progs > 0 ? n_progs : 0) * 12 + 256;
 }
 
 hipError_t launch_collapse_only(const EvalArgs& a) {
   const int cchunks = a.max_cfg > 0 ? (a.max_cfg + kCollapseBlock - 1) / kCollapseBlock : 1;
   int t = a.timer ? a.timer->begin(KLR_K_COLLAPSE, a.stream) : -1;
+  hipLaunchKernelGGL(query_range_kernel, dim3((unsigned)a.n_progs), dim3(kRangeBlock), 0, a.stream, a);
   hipLaunchKernelGGL(collapse_kernel, dim3((unsigned)a.n_progs * cchunks), dim3(kCollapseBlock), 0,
                      a.stream, a, cchunks);
   if (a.timer) a.timer->end(t, a.stream);

@@ -393,6 +393,8 @@ struct SelectArgs {
   float* pred_cost;
   uint8_t* fell_back;
   float* pred_margin;      // optional: second-best minus best prediction (ln units) per query
+  const void* eval_ws;     // the collapse workspace of the same programs (launch_collapse_only)
+  klr_hw hw;
 };
 
 hipError_t launch_refresh(const Blob& w, hipStream_t s);

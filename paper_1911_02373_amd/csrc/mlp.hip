@@ -33,6 +33,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "eval_point.hpp"
 #include "internal.hpp"
 
 namespace klr {
@@ -552,6 +553,10 @@ mlp_predict(const int32_t* __restrict__ kid, const int32_t* __restrict__ Nq, con
 //            32 x 32 FP32 output of layer 1 keeps them, so H1 never leaves registers);
 //   layer 3: y = w3 . relu(D2^T) + b3 summed over the lane's 16 output registers, then the two
 //            lane groups in a fixed order.
+// Only configurations the exact program admits at the query's N enter the ranking (the fitted
+// metrics defined, at least one block resident, the launch constraints met: the same FP32 steps
+// as the exact sweep, so a configuration left out has cost +inf there); the network never sees
+// inadmissible points in training, so its predictions for them carry no information.
 // Each lane keeps the running (best, index, second best) of its configurations; one wave
 // reduction per query gives the pick and the margin.
 constexpr int kSelMaxCfg = 1024;
@@ -564,7 +569,6 @@ struct SelLds {
   float b2f[8][2][16];
   float w3f[8][2][16];
   float2 cfx[kSelMaxCfg];            // (log2 bx / 10, log2 by / 10)
-  int32_t cL[kSelMaxCfg];            // max(bx, by); INT_MAX if not statically admissible
 };
 
 __device__ __forceinline__ int out_hidden(int tile, int g, int r) {   // 32 x 32 output row index
@@ -604,6 +608,7 @@ mlp_select(SelectArgs a, Blob w, int chunks, int64_t n_items) {
 #pragma unroll
     for (int st = 0; st < 2; ++st) w1r[t][st] = w.P[kO_W1 + 4 * (32 * t + (lane & 31)) + 2 * st + g];
   const float mu = w.hdr[0], sig = w.hdr[1], b3 = w.P[kO_B3];
+  const Hw32 hw = make_hw32(a.hw);
   const float lnm = logf(1.0f + a.margin);
   int loaded = -1;
   for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
@@ -637,22 +642,35 @@ mlp_select(SelectArgs a, Blob w, int chunks, int64_t n_items) {
       __syncthreads();               // every wave is done with the previous program's tables
       for (int c = tid; c < P.n_cfg; c += 64 * kSelWaves) {
         const int32_t bx = a.cfgs[P.cfg0 + 2 * c], by = a.cfgs[P.cfg0 + 2 * c + 1];
-        const bool pos = bx >= 1 && by >= 1;
-        const int64_t T = pos ? (int64_t)bx * by : 0;
-        const bool ok = pos && T <= a.t_max && (T % a.wave) == 0;
         S.cfx[c] = make_float2(log2f((float)(bx >= 1 ? bx : 1)) * 0.1f, log2f((float)(by >= 1 ? by : 1)) * 0.1f);
-        S.cL[c] = ok ? (bx > by ? bx : by) : 0x7fffffff;
       }
       __syncthreads();
       loaded = p;
     }
     const float emb = p < a.nk ? w.P[kO_EMB + p] : 0.0f;
+    const float* slot0 = slot_coefs(a.eval_ws) + (int64_t)p * a.max_cfg * kSlotFloats;
+    const CfgRec* rec0 = slot_recs(a.eval_ws, a.n_progs, a.max_cfg) + (int64_t)p * a.max_cfg;
     for (int qi = qb + wv; qi < qe; qi += kSelWaves) {
       const int32_t N = a.queries[P.q0 + qi];
       const float fN = log2f((float)(N >= 1 ? N : 1)) * (1.0f / 26.0f);
+      float xs[KLR_N_METRICS];
+      scaled_n(N, slot0, xs);
       float best = INFINITY, sec = INFINITY;
       int bi = 0x7fffffff;
       for (int c0 = 0; c0 < P.n_cfg; c0 += 64) {
+        // the network ranks only the configurations the exact program admits at this N: lane
+        // group g checks configuration c0 + 32 g + lane % 32, the other group's result arrives by
+        // one lane swap
+        bool adm[2];
+        {
+          const int c = c0 + 32 * g + (lane & 31);
+          const int cc = c < P.n_cfg ? c : P.n_cfg - 1;
+          const bool mine = c < P.n_cfg &&
+                            point_admissible(P.cost_kind, N, xs, slot0 + (int64_t)cc * kSlotFloats, rec0[cc], hw);
+          const bool theirs = __shfl_xor((int)mine, 32) != 0;
+          adm[0] = g == 0 ? mine : theirs;
+          adm[1] = g == 0 ? theirs : mine;
+        }
         // layer 1 for two tiles of 32 configurations
         bf16x8 h1[2][16];
 #pragma unroll
@@ -712,7 +730,7 @@ mlp_select(SelectArgs a, Blob w, int chunks, int64_t n_items) {
           const float other = __shfl_xor(yp[rt], 32);
           const float y = (g == 0 ? yp[rt] + other : other + yp[rt]) + b3;   // same order in both groups
           const int c = c0 + 32 * rt + (lane & 31);
-          if (c < P.n_cfg && S.cL[c] <= N) {
+          if (adm[rt]) {
             const float v = mu + sig * y;
             if (v < best) {       // configurations arrive in increasing index order per lane
               sec = fminf(sec, best);

@@ -56,6 +56,62 @@ def test_config3_small_bit_exact(klr):
         off += int(pb.n_cfg[p]) * int(pb.n_q[p])
 
 
+def _slot_records(de):
+    """Configuration records of the collapse workspace after an evaluation, as int32 rows of 12:
+    T, Wb, Bcap, rTh, Lmax, L0, L1, ok, magTC, shTC, fast, pad (slot p * max_cfg + c)."""
+    ws = de.ws.cpu().numpy()
+    off = de.n_progs * de.max_cfg * 72 * 4
+    return ws[off: off + de.n_progs * de.max_cfg * 48].view(np.int32).reshape(de.n_progs, de.max_cfg, 12)
+
+
+def test_short_division_taken_on_config3(klr):
+    """Every admissible configuration of the c3 workload's programs (metric numerators and
+    denominators far inside [2^-40, 2^40] over the queries) takes the short division; the pad
+    configuration, ruled out statically, does not."""
+    import torch
+    from paper_1911_02373_amd.klr import DeviceEval
+    pb = synth.config3_programs(104, n_progs=8, n_q=1000)
+    de = DeviceEval.from_batch(klr, pb)
+    klr.eval_argmin(de)
+    torch.cuda.synchronize()
+    rec = _slot_records(de)
+    ok, fast = rec[:, :, 7], rec[:, :, 10]
+    assert np.array_equal(fast, ok)
+    assert ok.sum() == 8 * 127 and not ok[:, 127].any()
+
+
+def test_short_division_wide_exponents_bit_exact(klr):
+    """Metric numerators scaled by 2^k (k in [-36, 36]) and denominators' non-constant terms by
+    2^m (m in [0, 30]) per fit, so the quotients span most of [2^-40, 2^40]: some configurations
+    take the short division, others (an enclosure reaching past the range) the IEEE one, and
+    every cost and argmin equals the oracle's replay bit for bit."""
+    import dataclasses
+
+    import torch
+    from paper_1911_02373_amd.klr import DeviceEval
+    pb = synth.config3_programs(105, n_progs=16, n_q=700)
+    rng = np.random.default_rng(105)
+    coef = pb.coef.copy()
+    nm = int(pb.n_num[0])
+    for fi in range(pb.num0.shape[0]):
+        c0 = int(pb.coef0[fi])
+        coef[c0: c0 + nm] *= 2.0 ** int(rng.integers(-36, 37))
+        coef[c0 + nm: c0 + 2 * nm - 1] *= 2.0 ** int(rng.integers(0, 31))
+    pb = dataclasses.replace(pb, coef=coef)
+    de = DeviceEval.from_batch(klr, pb, with_costs=True)
+    am, bc, costs, st = klr.eval_argmin(de, want_costs=True)
+    torch.cuda.synchronize()
+    am, bc, costs, st = am.cpu().numpy(), bc.cpu().numpy(), costs.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0)
+    rec = _slot_records(de)
+    fast = rec[:, :127, 10]
+    assert 0 < fast.sum() < fast.size, fast.sum()
+    off = 0
+    for p in range(pb.n_progs):
+        _check_program_exact(pb, p, am, bc, costs, off)
+        off += int(pb.n_cfg[p]) * int(pb.n_q[p])
+
+
 def test_mixed_uneven_programs_bit_exact(klr):
     """1-4 launch parameters, degree-3 metrics, 1-D and 2-D grids, uneven n_cfg and n_q,
     inadmissible configurations, tiny and huge N."""

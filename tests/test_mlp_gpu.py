@@ -3,6 +3,7 @@ surrogate selection with exact fallback."""
 import numpy as np
 import pytest
 
+from oracle import cost as oc
 from oracle import mlp as om
 from paper_1911_02373_amd import synth
 
@@ -144,7 +145,7 @@ def test_selection_fallback_semantics(klr, trained):
     assert np.all(fb.cpu().numpy() == 1)
     assert np.array_equal(am.cpu().numpy(), ea)
     assert np.array_equal(pc.cpu().numpy().view(np.uint32), eb.view(np.uint32))
-    # the 2 % margin: fallback queries equal the exact path; the others are statically admissible
+    # the 2 % margin: fallback queries equal the exact path; the others are admissible
     am, pc, fb = klr.surrogate_eval(blob, nk, de, margin=0.02)
     torch.cuda.synchronize()
     am, pc, fb = am.cpu().numpy(), pc.cpu().numpy(), fb.cpu().numpy().astype(bool)
@@ -262,12 +263,12 @@ def test_uneven_programs_train_and_select(klr):
         co += nc * nq
 
 
-def test_pick_check_sends_inadmissible_picks_to_the_exact_path(klr):
-    """With sigma = 0 every prediction is equal, so the network's pick is the first statically
-    admissible configuration; that one (512 threads at R = 300 registers per thread) leaves no
-    block resident, so its exact cost is +inf.  With margin 0 the margin rule never fires, so
-    only the pick check can send a query to the exact path: every query falls back and the
-    result equals the exact path bit for bit."""
+def test_selection_ranks_only_admissible_configurations(klr):
+    """With sigma = 0 every prediction is equal, so the network's pick is the first
+    configuration it ranks.  Configurations 0 and 1 (512 and 1024 threads at R = 300 registers
+    per thread) leave no block resident, so the exact program rules them out; the selection
+    never ranks them, and with margin 0 (the margin rule never fires) every query keeps the
+    first admissible configuration, 2, without falling back."""
     import torch
     from paper_1911_02373_amd.klr import DeviceEval
     from tests.helpers import constant_programs
@@ -277,20 +278,45 @@ def test_pick_check_sends_inadmissible_picks_to_the_exact_path(klr):
     nk = pb.n_progs
     blob = klr.surrogate_alloc(synth.mlp_init(9, nk), nk, mu=0.0, sigma=0.0)
     de = DeviceEval.from_batch(klr, pb)
+    ea, _, _, _ = klr.eval_argmin(de)
+    am, pc, fb = klr.surrogate_eval(blob, nk, de, margin=0.0)
+    torch.cuda.synchronize()
+    assert np.all(np.isin(ea.cpu().numpy(), [2, 3, 4]))      # the exact picks are the admissible ones
+    assert np.all(fb.cpu().numpy() == 0)
+    assert np.all(am.cpu().numpy() == 2)
+    assert np.all(pc.cpu().numpy() == 1.0)                     # exp(mu + 0 * y)
+
+
+def test_pick_check_sends_inadmissible_picks_to_the_exact_path(klr):
+    """A pick whose cycle estimate overflows FP32 is admissible by every constraint the
+    selection checks (metrics defined, blocks resident) but has exact cost +inf: I_comp = 1e38
+    makes the compute cycles 4 (I_comp + I_m) overflow.  With margin 0 only the pick check can
+    send a query to the exact path: every query falls back and the result equals the exact
+    path bit for bit (no admissible configuration: -1 and +inf)."""
+    import torch
+    from paper_1911_02373_amd.klr import DeviceEval
+    from tests.helpers import constant_programs
+    rows = [[1e38, 6.0, 3.0, 2.0, 1.0, 300.0, 0.0, 64.0]] * 3
+    cfgs = [[512, 1], [1024, 1], [64, 1], [128, 1], [32, 8]]
+    pb = constant_programs(rows, cfgs, [[1024, 4096, 65536, 1 << 20]] * 3)
+    nk = pb.n_progs
+    blob = klr.surrogate_alloc(synth.mlp_init(9, nk), nk, mu=0.0, sigma=0.0)
+    de = DeviceEval.from_batch(klr, pb)
     ea, eb, _, _ = klr.eval_argmin(de)
     am, pc, fb = klr.surrogate_eval(blob, nk, de, margin=0.0)
     torch.cuda.synchronize()
     ea, eb = ea.cpu().numpy(), eb.cpu().numpy()
-    assert np.all(np.isin(ea, [2, 3, 4]))            # the exact picks are the admissible ones
+    assert np.all(ea == -1) and np.all(np.isinf(eb))
     assert np.all(fb.cpu().numpy() == 1)
     assert np.array_equal(am.cpu().numpy(), ea)
     assert np.array_equal(pc.cpu().numpy().view(np.uint32), eb.view(np.uint32))
 
 
 def _select_reference(prm, pb, n_progs):
-    """Oracle predictions (ln C) of every statically admissible configuration of each query of
-    the first n_progs programs, with the operands the selection kernel rounds to bfloat16
-    rounded the same way; +inf where not statically admissible.  Also S = sum |w3| (|W2| h1 +
+    """Oracle predictions (ln C) of every admissible configuration of each query of the first
+    n_progs programs (finite cost in the oracle's FP32 replay of the exact program; these
+    programs' costs never overflow, so that is exactly the set the selection ranks), with the
+    operands the selection kernel rounds to bfloat16 rounded the same way; +inf elsewhere.  Also S = sum |w3| (|W2| h1 +
     |b2|) per point (times sigma): the FP32 accumulations of layers 2 and 3 (exact bfloat16
     products, 257-term sums) stay within 2 * 257 * 2^-24 S < 2^-15 S of the FP64 values; a
     first-layer value that the kernel's FP32 products round to the other neighbour in bfloat16
@@ -298,15 +324,12 @@ def _select_reference(prm, pb, n_progs):
     bfloat16 step of that value's term, below 2^-8 S."""
     P = prm["P"]
     cfg = pb.cfgs.reshape(-1, 2)
-    hw = pb.hw
     out, scale = [], []
     for p in range(n_progs):
         nq, nc = int(pb.n_q[p]), int(pb.n_cfg[p])
         q0, c0 = int(pb.q0[p]), int(pb.cfg0[p]) // 2
         N = pb.queries[q0:q0 + nq].astype(np.int64)
         C = cfg[c0:c0 + nc].astype(np.int64)
-        T = C[:, 0] * C[:, 1]
-        stat = (T <= hw.t_max) & (T % hw.wave == 0) & (C.min(axis=1) >= 1)
         kid = np.full(nq * nc, p)
         NN = np.repeat(N, nc)
         bx, by = np.tile(C[:, 0], nq), np.tile(C[:, 1], nq)
@@ -314,7 +337,7 @@ def _select_reference(prm, pb, n_progs):
         x = om.features(NN, bx, by, P["emb"][kid])
         h1 = om.bf16_round(np.maximum(x @ P["W1"].T + P["b1"], 0.0))
         s = (np.abs(h1) @ np.abs(om.bf16_round(P["W2"])).T + np.abs(P["b2"])) @ np.abs(P["w3"])
-        ok = stat[None, :] & (C.max(axis=1)[None, :] <= N[:, None])
+        ok = np.isfinite(oc.program_costs(pb, p)).T
         out.append(np.where(ok, prm["mu"] + prm["sigma"] * y, np.inf))
         scale.append(s.reshape(nq, nc) * abs(prm["sigma"]))
     return out, scale
@@ -324,7 +347,7 @@ def test_selection_matches_network_elementwise(klr, trained):
     """mlp_select against the network oracle, query by query (8 programs x 256 queries x 128
     configurations).  Every query: the predicted ln C of its pick and its predicted margin
     (second best minus best) are within the bfloat16-flip bound 2^-8 S of the oracle's minimum
-    and margin over the statically admissible configurations, and 99 % within the accumulation
+    and margin over the admissible configurations, and 99 % within the accumulation
     bound 2^-15 S.  Wherever the oracle's margin exceeds twice the accumulation bound the pick
     is the oracle's argmin, except for at most 1 % of those queries (a first-layer bfloat16
     flip), whose pick is then within the flip bound of the oracle's minimum (at least a tenth of
