@@ -229,23 +229,56 @@ __global__ void __launch_bounds__(kRangeBlock) query_range_kernel(EvalArgs a) {
   }
 }
 
-// Whether the eight metric quotients of a configuration slot can take the short division at
-// every query of the program: over the program's range of scaled sizes, every numerator and
-// denominator stays in [2^-40, 2^40] in magnitude and every denominator is positive (so every
-// metric is defined there, as the exact sweep would find).
-__device__ inline bool slot_divides_short(const float* out, int32_t n_lo, int32_t n_hi) {
-  if (n_lo > n_hi) return false;
+// Enclosures of nonnegative FP32 results: each FP32 step below rounds once, so widening the
+// exact-arithmetic bounds by 2^-22 per step (relative) keeps every FP32 value inside.
+struct Ival { double lo, hi; };
+__device__ inline Ival iv_round(Ival a) { return Ival{a.lo * (1.0 - 0x1p-22), a.hi * (1.0 + 0x1p-22)}; }
+__device__ inline Ival iv_add(Ival a, Ival b) { return iv_round(Ival{a.lo + b.lo, a.hi + b.hi}); }
+__device__ inline Ival iv_mul(Ival a, Ival b) { return iv_round(Ival{a.lo * b.lo, a.hi * b.hi}); }
+__device__ inline Ival iv_max(Ival a, double c) { return Ival{fmax(a.lo, c), fmax(a.hi, c)}; }
+__device__ inline bool iv_moderate(Ival a) { return a.lo >= 0x1p-40 && a.hi <= 0x1p40; }
+
+// Which quotients of a configuration slot can take the short division at every query of the
+// program (0: none; 1: the eight metric quotients; 2: those and the four of the cycle
+// estimate).  Over the program's range of scaled sizes every metric numerator and denominator
+// must stay in [2^-40, 2^40] in magnitude with positive denominators (so every metric is also
+// defined there, as the exact sweep would find); then the clamped metric values are enclosed
+// and carried through the cycle estimate's sums and products (all nonnegative), and the
+// operands of its quotients must stay in [2^-40, 2^40] as well.
+__device__ inline int slot_divides_short(const float* out, int32_t n_lo, int32_t n_hi, const klr_hw& hw) {
+  if (n_lo > n_hi) return 0;
   const double xn_lo = (double)(float)n_lo, xn_hi = (double)(float)n_hi;
+  Ival g[KLR_N_METRICS];
   for (int j = 0; j < KLR_N_METRICS; ++j) {
     const double sc = out[KLR_N_METRICS * 2 * (kNdeg + 1) + j];     // a power of two
     const double xl = xn_lo * sc, xh = xn_hi * sc;
     double pl, ph, ql, qh;
-    if (!horner_enclosure(out + j * 2 * (kNdeg + 1), xl, xh, &pl, &ph)) return false;
-    if (!horner_enclosure(out + j * 2 * (kNdeg + 1) + 1, xl, xh, &ql, &qh)) return false;
-    if (!(ql >= 0x1p-40 && qh <= 0x1p40)) return false;
-    if (!(pl >= -0x1p40 && ph <= 0x1p40 && (pl >= 0x1p-40 || ph <= -0x1p-40))) return false;
+    if (!horner_enclosure(out + j * 2 * (kNdeg + 1), xl, xh, &pl, &ph)) return 0;
+    if (!horner_enclosure(out + j * 2 * (kNdeg + 1) + 1, xl, xh, &ql, &qh)) return 0;
+    if (!(ql >= 0x1p-40 && qh <= 0x1p40)) return 0;
+    if (!(pl >= -0x1p40 && ph <= 0x1p40 && (pl >= 0x1p-40 || ph <= -0x1p-40))) return 0;
+    // p / q over the box, then the quotient's own rounding
+    const double a = pl / ql, b = pl / qh, c = ph / ql, d = ph / qh;
+    const double lo = fmin(fmin(a, b), fmin(c, d)), hi = fmax(fmax(a, b), fmax(c, d));
+    g[j] = Ival{lo - fabs(lo) * 0x1p-22, hi + fabs(hi) * 0x1p-22};
   }
-  return true;
+  if (!(hw.mem_lat > 0.0f && hw.dep_delay > 0.0f && hw.issue_cycles > 0.0f && hw.bw > 0.0f && hw.w_max >= 1 &&
+        hw.mem_lat <= 0x1p40f && hw.dep_delay <= 0x1p40f && hw.issue_cycles <= 0x1p40f && hw.bw <= 0x1p40f))
+    return 1;
+  const Ival Icomp = iv_max(g[0], 0.0), Imc = iv_max(g[1], 0.0), Imu = iv_max(g[2], 0.0);
+  const Ival U = iv_max(g[3], 1.0), Bw = iv_max(g[7], 1.0);
+  const Ival lat{hw.mem_lat, hw.mem_lat}, dep{hw.dep_delay, hw.dep_delay};
+  const Ival iss{hw.issue_cycles, hw.issue_cycles}, bw{hw.bw, hw.bw};
+  const Ival Nw{1.0, (double)hw.w_max};
+  const Ival Im = iv_add(Imc, Imu);
+  const Ival Lu = iv_round(Ival{(U.lo - 1.0) * dep.lo + lat.lo, (U.hi - 1.0) * dep.hi + lat.hi});
+  const Ival mem = iv_add(iv_mul(Lu, Imu), iv_mul(lat, Imc));
+  const Ival comp = iv_mul(iss, iv_add(Icomp, Im));
+  const Ival d1 = iv_mul(dep, iv_add(iv_mul(U, Imu), Imc));
+  const Ival n2 = iv_mul(bw, mem), d2 = iv_mul(Im, Bw), t2 = iv_mul(mem, Nw);
+  const bool cyc = iv_moderate(mem) && iv_moderate(d1) && iv_moderate(n2) && iv_moderate(d2) &&
+                   iv_moderate(comp) && iv_moderate(Im) && iv_moderate(t2) && hw.w_max <= (1 << 11);
+  return cyc ? 2 : 1;
 }
 
 // One workgroup per (program, block of configurations).  The program's eight fit descriptors
@@ -378,7 +411,7 @@ collapse_kernel(EvalArgs a, int chunks) {
     out[KLR_N_METRICS * 2 * (kNdeg + 1) + j] = sc;
   }
   if (r.ok && P.cost_kind == KLR_COST_CYCLES)
-    r.fast = slot_divides_short(out, prog_nrange(a)[2 * p], prog_nrange(a)[2 * p + 1]) ? 1 : 0;
+    r.fast = slot_divides_short(out, prog_nrange(a)[2 * p], prog_nrange(a)[2 * p + 1], a.hw);
   *rec = r;
 }
 
@@ -387,11 +420,12 @@ collapse_kernel(EvalArgs a, int chunks) {
 // coefficients above DEG, which gives bit-identical values because fma(0, x, a) = a exactly for
 // finite x and a != -0, and collapsed coefficients are sums that start from +0).
 // UNI: cf and r are the same in every lane (the coefficients then sit in scalar registers); a
-// per-lane configuration takes plain vector loads.  SHORT: the configuration's record says every
-// metric's numerator and denominator stay in [2^-40, 2^40] (denominators positive) over the
-// program's queries, so each quotient takes div_moderate (the same bits as the IEEE division)
-// and every metric is defined.
-template <int GRID, int DEG = kNdeg, bool UNI = true, bool SHORT = false>
+// per-lane configuration takes plain vector loads.  SHORT (the configuration record's `fast`):
+// 1 - every metric's numerator and denominator stay in [2^-40, 2^40] (denominators positive)
+// over the program's queries, so each metric quotient takes div_moderate (the same bits as the
+// IEEE division), every metric is defined and finite and nonzero, and the clamps reduce to
+// maxima; 2 - the four quotients of the cycle estimate take div_moderate as well.
+template <int GRID, int DEG = kNdeg, bool UNI = true, int SHORT = 0>
 __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const float* __restrict__ cf,
                                             const CfgRec& r, const Hw32& hw) {
   static_assert(DEG >= 1 && DEG <= kNdeg, "Horner degree");
@@ -424,16 +458,18 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
   }
   // A metric failing the check is cleaned to +0 before its clamp; clean_max takes both steps.
   // The upper clamps of R (>= 1) and Z (>= -0) see no NaN, so fminf equals the compare-select.
-  const float Icomp = clean_max(good[0], g[0], 0.0f);
-  const float Imc = clean_max(good[1], g[1], 0.0f);
-  const float Imu = clean_max(good[2], g[2], 0.0f);
-  const float U = clean_max(good[3], g[3], 1.0f);
-  const float Isync = clean_max(good[4], g[4], 0.0f);
-  const float Bw = clean_max(good[7], g[7], 1.0f);
+  // (with SHORT every value is finite and nonzero, so the compare-select equals the maximum)
+  const float Icomp = SHORT ? fmaxf(g[0], 0.0f) : clean_max(good[0], g[0], 0.0f);
+  const float Imc = SHORT ? fmaxf(g[1], 0.0f) : clean_max(good[1], g[1], 0.0f);
+  const float Imu = SHORT ? fmaxf(g[2], 0.0f) : clean_max(good[2], g[2], 0.0f);
+  const float U = SHORT ? fmaxf(g[3], 1.0f) : clean_max(good[3], g[3], 1.0f);
+  const float Isync = SHORT ? fmaxf(g[4], 0.0f) : clean_max(good[4], g[4], 0.0f);
+  const float Bw = SHORT ? fmaxf(g[7], 1.0f) : clean_max(good[7], g[7], 1.0f);
 
   // occupancy from the register and LDS metrics; the minima and the products below equal their
   // integer counterparts
-  const float B = resident_blocks(g[5], good[5], g[6], good[6], r, hw);
+  const float B = SHORT ? resident_blocks_defined(g[5], g[6], r, hw)
+                        : resident_blocks(g[5], good[5], g[6], good[6], r, hw);
   ok = ok & (B >= 1.0f);
   const float Bf = fmaxf(B, 1.0f);
   const float Nwf = fminf(Bf * r.Wb, hw.w_max);     // a product above 2^24 is above w_max too
@@ -462,21 +498,21 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
 
   float d1 = __builtin_fmaf(U, Imu, Imc);                          // I_mc + U I_mu
   d1 = hw.dep * d1;
-  const float mwp_lat = mem / d1;
+  const float mwp_lat = SHORT == 2 ? div_moderate(mem, d1) : mem / d1;
   const float n2 = hw.bw * mem;
   const float d2 = Im * Bw;
-  const float mwp_bw = n2 / d2;
+  const float mwp_bw = SHORT == 2 ? div_moderate(n2, d2) : n2 / d2;
   float mwp = sel_min(mwp_lat, mwp_bw);
   mwp = sel_min(mwp, Nwf);
   mwp = sel_max(mwp, 1.0f);
   const float tot = mem + comp;
   const bool cwp_full = tot >= Nwf * comp;
   const bool cwp_ge_mwp = tot >= mwp * comp;
-  const float cpm = comp / Im;
+  const float cpm = SHORT == 2 ? div_moderate(comp, Im) : comp / Im;
   const float m1 = mwp - 1.0f;
   const float e1 = __builtin_fmaf(cpm, m1, tot);                   // tot + cpm (MWP - 1)
   float t2 = mem * Nwf;
-  t2 = t2 / mwp;
+  t2 = SHORT == 2 ? div_moderate(t2, mwp) : t2 / mwp;
   const float e2 = __builtin_fmaf(cpm, m1, t2);                    // mem N_w / MWP + cpm (MWP - 1)
   const float e3 = __builtin_fmaf(comp, Nwf, hw.lat);              // lat + comp N_w
   const bool case1 = (mwp >= Nwf) & cwp_full;
@@ -576,10 +612,19 @@ __device__ __forceinline__ void sweep_cfgs(const klr_program& P, const float* __
   for (int c = 0; c < P.n_cfg; ++c) {
     const CfgRec r = rec0[c];
     const float* cf = slot0 + (int64_t)c * kSlotFloats;
-    if (KIND == KLR_COST_CYCLES && r.fast) {     // wave-uniform
+    if (KIND == KLR_COST_CYCLES && r.fast == 2) {     // wave-uniform
 #pragma unroll
       for (int u = 0; u < QPL; ++u) {
-        const float cost = point_cost<GRID, DEG, true, true>(N[u], xs[u], cf, r, hw);
+        const float cost = point_cost<GRID, DEG, true, 2>(N[u], xs[u], cf, r, hw);
+        if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost;
+        if (cost < best[u]) { best[u] = cost; bi[u] = c; }
+      }
+      continue;
+    }
+    if (KIND == KLR_COST_CYCLES && r.fast == 1) {
+#pragma unroll
+      for (int u = 0; u < QPL; ++u) {
+        const float cost = point_cost<GRID, DEG, true, 1>(N[u], xs[u], cf, r, hw);
         if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost;
         if (cost < best[u]) { best[u] = cost; bi[u] = c; }
       }

@@ -30,7 +30,8 @@ struct CfgRec {          // per (program, configuration) occupancy terms
   int32_t ok;            // configuration admissible and the program's fits valid
   uint32_t magTC;        // floor(n / (T n_cu)) = mulhi(n, magTC) >> shTC for 0 <= n < 2^31
   int32_t shTC;
-  int32_t fast;          // every metric quotient takes the short division at every query
+  int32_t fast;          // quotients taking the short division at every query: 0 none, 1 the
+                         //   metrics', 2 the metrics' and the cycle estimate's
   int32_t pad;
 };
 
@@ -120,6 +121,17 @@ __device__ __forceinline__ float resident_blocks(float g5, bool good5, float g6,
   const float Z = fminf(clean_max(good6, ceilf(g6), 0.0f), 16777216.0f);   // -0 for g in (-1, 0)
   const float breg = floor_div(r.rTh, R);
   const float blds = floor_div(hw.zh, fabsf(Z));   // Z = -0 counts as 0
+  return fminf(fminf(r.Bcap, breg), blds);
+}
+
+// The same for metrics known to be defined, finite and nonzero (the clamps are then maxima; a
+// ceiling of -0 for Z counts as 0 through the absolute value either way).
+__device__ __forceinline__ float resident_blocks_defined(float g5, float g6, const CfgRec& r, const Hw32& hw) {
+#pragma clang fp contract(off)
+  const float R = fminf(fmaxf(ceilf(g5), 1.0f), 16777216.0f);
+  const float Z = fminf(fmaxf(ceilf(g6), 0.0f), 16777216.0f);
+  const float breg = floor_div(r.rTh, R);
+  const float blds = floor_div(hw.zh, fabsf(Z));
   return fminf(fminf(r.Bcap, breg), blds);
 }
 

@@ -261,17 +261,25 @@ __device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uin
     build_chunk<NM>(C, rows);
     for (int e = threadIdx.x; e < (rows4 - rows) * NM; e += kFitBlock) C.A[rows * NM + e] = 0.0;
     __syncthreads();
-    for (int i = 0; i < rows4; i += 4) {
-      const double* ar = C.A + (i + grp) * NM + col;
-      double xa[PPW], xb[PPW];
+    // blocks of 4 SUB rows: sub-step e gives reduction slot e the block's row 4 e + grp
+    for (int i = 0; i < rows4; i += 4 * GT::SUB) {
+      typename GT::op_t xa[PPW], xb[PPW];
 #pragma unroll
-      for (int q = 0; q < PPW; ++q) {
-        xa[q] = ar[16 * tj[q]];
-        xb[q] = ar[16 * tk[q]];
+      for (int q = 0; q < PPW; ++q) xa[q] = xb[q] = GT::zero();
+#pragma unroll
+      for (int e = 0; e < GT::SUB; ++e) {
+        if (i + 4 * e < rows4) {
+          const double* ar = C.A + (i + 4 * e + grp) * NM + col;
+#pragma unroll
+          for (int q = 0; q < PPW; ++q) {
+            GT::put(xa[q], e, ar[16 * tj[q]]);
+            GT::put(xb[q], e, ar[16 * tk[q]]);
+          }
+        }
       }
 #pragma unroll
       for (int q = 0; q < PPW; ++q)
-        if (q < mine) acc[q] = GT::mfma(GT::in(xa[q]), GT::in(xb[q]), acc[q]);
+        if (q < mine) acc[q] = GT::mma(xa[q], xb[q], acc[q]);
     }
     if (cj < C.n && csub < TPC) {
 #pragma unroll 4

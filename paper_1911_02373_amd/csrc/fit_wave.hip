@@ -7,7 +7,7 @@
 //   * lane l owns sample rows l, l + 64, ... (scaled variables, target and residual in VGPRs;
 //     8 rows per lane for m <= 512 at two waves per SIMD, 16 for m <= 1024 at one);
 //   * Gram on MFMA (v_mfma_f64_16x16x4f64 for the FP64 path, v_mfma_f32_16x16x4f32 with FP32
-//     or BF16-rounded design-matrix values for the reduced paths): for each step of 4 rows the
+//     values, v_mfma_f32_16x16x16_bf16 with BF16 values over four steps): for each step of 4 rows the
 //     lanes build a table of x_k^p (p <= 3) of the step's rows in LDS, one entry per lane, and
 //     every lane forms exactly the design-matrix elements of its MFMA operand slots (column
 //     l % 16 of each 16-column tile, row l / 16 of the step) from four table entries, so A is
@@ -20,9 +20,7 @@
 //     FP64 residual is updated in place and A^T r accumulated in the same pass; column
 //     exponents are read into scalar registers so the monomial loops are uniform; stopping by
 //     the delayed Hestenes-Stiefel estimate of ||A(y - y*)||.
-// MFMA layouts (wave64): for both v_mfma_f64_16x16x4f64 and v_mfma_f32_16x16x4f32 lane l
-// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane l is
-// D[4 r + l / 16][l % 16] for the FP64 instruction and D[4 (l / 16) + r][l % 16] for the FP32 one.
+// MFMA layouts (wave64): see GramTypes in internal.hpp.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -108,6 +106,7 @@ __device__ void gram(WaveLds& L, const Rows<RPL>& R, int m, int n, int n_num) {
   const int tk_var = (lane >> 2) & 3, tk_pow = lane & 3;   // the table entry this lane writes
   const char* Tb = reinterpret_cast<const char*>(L.T);
   double cacc[3] = {0.0, 0.0, 0.0};
+  typename GT::op_t op[3];
   const int steps = (m + 3) / 4;
   for (int st = 0; st < steps; ++st) {
     const int row = 4 * st + grp;             // this lane's row of the step
@@ -141,12 +140,21 @@ __device__ void gram(WaveLds& L, const Rows<RPL>& R, int m, int n, int n_num) {
     }
 #pragma unroll
     for (int ct = 0; ct < 3; ++ct) cacc[ct] += a[ct] * fv;
-    acc[0] = GT::mfma(GT::in(a[0]), GT::in(a[0]), acc[0]);   // tile (0, 0)
-    acc[1] = GT::mfma(GT::in(a[1]), GT::in(a[0]), acc[1]);   // tile (1, 0)
-    acc[2] = GT::mfma(GT::in(a[1]), GT::in(a[1]), acc[2]);   // tile (1, 1)
-    acc[3] = GT::mfma(GT::in(a[2]), GT::in(a[0]), acc[3]);   // tile (2, 0)
-    acc[4] = GT::mfma(GT::in(a[2]), GT::in(a[1]), acc[4]);   // tile (2, 1)
-    acc[5] = GT::mfma(GT::in(a[2]), GT::in(a[2]), acc[5]);   // tile (2, 2)
+    const int e = st % GT::SUB;                // sub-step of the MFMA's reduction block
+    if (e == 0) {
+#pragma unroll
+      for (int ct = 0; ct < 3; ++ct) op[ct] = GT::zero();
+    }
+#pragma unroll
+    for (int ct = 0; ct < 3; ++ct) GT::put(op[ct], e, a[ct]);
+    if (e == GT::SUB - 1 || st == steps - 1) {
+      acc[0] = GT::mma(op[0], op[0], acc[0]);   // tile (0, 0)
+      acc[1] = GT::mma(op[1], op[0], acc[1]);   // tile (1, 0)
+      acc[2] = GT::mma(op[1], op[1], acc[2]);   // tile (1, 1)
+      acc[3] = GT::mma(op[2], op[0], acc[3]);   // tile (2, 0)
+      acc[4] = GT::mma(op[2], op[1], acc[4]);   // tile (2, 1)
+      acc[5] = GT::mma(op[2], op[2], acc[5]);   // tile (2, 2)
+    }
   }
   const int tj[6] = {0, 1, 1, 2, 2, 2}, tk[6] = {0, 0, 1, 0, 1, 2};
 #pragma unroll

@@ -286,38 +286,59 @@ __device__ __forceinline__ float round_bf16(float x) {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Gram products on the matrix cores, per Gram precision.  For v_mfma_f64_16x16x4f64 and
-// v_mfma_f32_16x16x4f32 alike, lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result
-// register r of lane l is D[out_row(l / 16, r)][l % 16]: row 4 r + l / 16 for the FP64
-// instruction, 4 (l / 16) + r for the FP32 one.  The reduced paths round the design-matrix
-// values to FP32 or BF16 and accumulate in FP32 (products of BF16 values are exact in FP32).
+// Gram products on the matrix cores, per Gram precision.  One MFMA covers SUB steps of 4 sample
+// rows.  FP64 and FP32 (SUB = 1, v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16].  BF16 (SUB = 4, v_mfma_f32_16x16x16_bf16): lane l
+// supplies A[l % 16][4 (l / 16) + e] and B[4 (l / 16) + e][l % 16], e = 0..3; the callers give
+// reduction index 4 (l / 16) + e the row of sub-step e that the lane's group reads (row 4 e +
+// l / 16 of the 16-row block), the same for both operands, so every product pairs two values of
+// one row.  Result register r of lane l is D[out_row(l / 16, r)][l % 16]: row 4 r + l / 16 for
+// the FP64 instruction, 4 (l / 16) + r for the FP32 and BF16 ones.  The reduced paths round the
+// design-matrix values to FP32 or BF16 (through FP32) and accumulate in FP32 (products of BF16
+// values are exact in FP32).
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 template <int GP>
 struct GramTypes;
 template <>
 struct GramTypes<KLR_FP64> {
   typedef f64x4 acc_t;
-  static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+  typedef double op_t;
+  static constexpr int SUB = 1;
+  static __device__ __forceinline__ void put(op_t& o, int, double v) { o = v; }
+  static __device__ __forceinline__ op_t zero() { return 0.0; }
+  static __device__ __forceinline__ acc_t mma(op_t a, op_t b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ double in(double v) { return v; }
   static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * r + grp; }
 };
 template <>
 struct GramTypes<KLR_FP32_REFINED> {
   typedef f32x4 acc_t;
-  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+  typedef float op_t;
+  static constexpr int SUB = 1;
+  static __device__ __forceinline__ void put(op_t& o, int, double v) { o = (float)v; }
+  static __device__ __forceinline__ op_t zero() { return 0.0f; }
+  static __device__ __forceinline__ acc_t mma(op_t a, op_t b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ float in(double v) { return (float)v; }
   static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * grp + r; }
 };
 template <>
 struct GramTypes<KLR_BF16_REFINED> {
   typedef f32x4 acc_t;
-  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  typedef s16x4 op_t;
+  static constexpr int SUB = 4;
+  static __device__ __forceinline__ void put(op_t& o, int e, double v) {
+    const short b = (short)(__float_as_uint(round_bf16((float)v)) >> 16);
+    if (e == 0) o[0] = b;
+    else if (e == 1) o[1] = b;
+    else if (e == 2) o[2] = b;
+    else o[3] = b;
   }
-  static __device__ __forceinline__ float in(double v) { return round_bf16((float)v); }
+  static __device__ __forceinline__ op_t zero() { return (op_t){0, 0, 0, 0}; }
+  static __device__ __forceinline__ acc_t mma(op_t a, op_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
   static __device__ __forceinline__ int out_row(int grp, int r) { return 4 * grp + r; }
 };
 
