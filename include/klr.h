@@ -143,10 +143,14 @@ size_t klr_fit_workspace(int32_t n_fits, int64_t total_rows, int32_t precision);
  *   minimum-norm least-squares solution of the equilibrated problem; iters = Jacobi sweeps;
  *   err_est = 2^-53 times the condition number of the kept part.  Limits: n <= 48 and m <= 1024
  *   (m <= 512 when n > 16); other fits get KLR_FIT_UNSUPPORTED and zero coefficients; max_iter
- *   and tol are not used (at most 30 sweeps).  Coefficients are in the
- *   scaled-variable basis x~.  Rank-deficient fits get a least-squares solution (not
- *   necessarily the minimum-norm one): its values on the samples are the unique
- *   least-squares values. */
+ *   and tol are not used (at most 30 sweeps).
+ * Coefficients are in the scaled-variable basis x~ (x~_k = x_k 2^-scale_exp[k]; the raw-basis
+ * coefficient of a monomial with exponents e is this one times 2^-(sum_k scale_exp[k] e_k), an
+ * exact scaling the caller can apply, but one whose range overflows FP32 consumers at degree 3,
+ * so the library keeps the scaled basis throughout).  On the Cholesky + CGLS paths a
+ * rank-deficient fit gets a least-squares solution that is not necessarily the minimum-norm
+ * one: its values on the samples are the unique least-squares values; KLR_FP64_SVD returns the
+ * minimum-norm solution. */
 klr_status klr_fit_batched(klr_handle h, const klr_fit_desc* desc, int32_t n_fits,
                            const uint8_t* exps, int32_t n_exp_rows,
                            const int32_t* X, int64_t x_len, const double* f, int64_t f_len,
