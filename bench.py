@@ -116,6 +116,7 @@ def measured_traffic():
 # 6e-3 with the cosine schedule; 300 epochs over the 4.2 M samples.
 SURR_BATCH = 16384
 SURR_LR = 6e-3
+SURR_SHORTLIST = 4            # the library default: the network's 4 best predictions re-ranked exactly
 LARGE_SURR_QUERIES = 12       # training queries per program of the large batch
 
 
@@ -160,10 +161,23 @@ def surrogate_component(lib, klr, synth, pb, de, exact_ms, seed, epochs, regret_
     r = regret(am)
     am0, _, _ = lib.surrogate_eval(blob, pb.n_progs, dex, margin=0.0)
     r0 = regret(am0)
+    lib.set_option(klr.OPT_SURR_SHORTLIST, 1)              # the network's own picks, same rule
+    try:
+        am1, _, fb1 = lib.surrogate_eval(blob, pb.n_progs, dex, margin=0.02)
+        am10, _, _ = lib.surrogate_eval(blob, pb.n_progs, dex, margin=0.0)
+    finally:
+        lib.set_option(klr.OPT_SURR_SHORTLIST, SURR_SHORTLIST)
+    r1, r10 = regret(am1), regret(am10)
     torch.cuda.synchronize()
     nonfb = ~fb[: sub * nq][ok].cpu().numpy().astype(bool)
     total_ms = sel_ms + fb_ms + col_ms
-    return {"train_ms": train_ms, "epochs": epochs, "batch": SURR_BATCH, "lr": SURR_LR,
+    picks = am[: sub * nq].cpu().numpy()
+
+    def stats(x):
+        return {"frac_le_1pct": float(np.mean(x <= 0.01)), "p50": float(np.median(x)),
+                "p99": float(np.quantile(x, 0.99)), "max": float(x.max())}
+    return {"_picks": picks, "shortlist": SURR_SHORTLIST,
+            "train_ms": train_ms, "epochs": epochs, "batch": SURR_BATCH, "lr": SURR_LR,
             "train_samples": int(tq.n_progs * 32 * 128),
             "final_loss_std": float(loss[-1].cpu()), "select_ms": sel_ms, "fallback_ms": fb_ms,
             "collapse_ms": col_ms, "fallback_rate": fbr, "margin": 0.02,
@@ -172,8 +186,10 @@ def surrogate_component(lib, klr, synth, pb, de, exact_ms, seed, epochs, regret_
             "regret_with_fallback": {"frac_le_1pct": float(np.mean(r <= 0.01)), "p50": float(np.median(r)),
                                      "p99": float(np.quantile(r, 0.99)), "max": float(r.max()),
                                      "nonfallback_frac_le_1pct": float(np.mean(r[nonfb] <= 0.01)) if nonfb.any() else None},
-            "regret_surrogate_alone": {"frac_le_1pct": float(np.mean(r0 <= 0.01)), "p50": float(np.median(r0)),
-                                       "p99": float(np.quantile(r0, 0.99))}}
+            "regret_surrogate_alone": stats(r0),
+            "regret_shortlist_1_with_fallback": stats(r1),
+            "fallback_rate_shortlist_1": float(fb1[: sub * nq].float().mean().cpu()),
+            "regret_shortlist_1_alone": stats(r10)}
 
 
 def large_surrogate(lib, klr, synth, pb, coef, seed, epochs, regret_programs=64):
@@ -454,6 +470,25 @@ def fp64_error(pb, am, bc, n_progs: int, nq: int):
             "regret_max": float(r.max()), "best_cost_rel_err_max": float(e.max()),
             "best_cost_rel_err_median": float(np.median(e)),
             "sample": f"first {nq} queries of the first {n_progs} programs, all configurations"}
+
+
+def surrogate_fp64_regret(pb, picks, n_progs: int, nq: int):
+    """Regret of the surrogate's picks (shortlist and 2 % fallback) under the FP64 cycle estimate
+    (the oracle's truth mode) on the first n_progs programs' first nq queries: the FP64 cost of
+    the pick over the FP64 optimum, minus one."""
+    from oracle import cost as oc
+    regrets = []
+    n_all = int(pb.n_q[0])
+    for p in range(n_progs):
+        c64 = oc.program_costs(pb, p, query_idx=np.arange(nq), mode="truth")
+        i64, b64 = oc.argmin_lowest(c64)
+        a = picks[p * n_all: p * n_all + nq]
+        ok = (a >= 0) & (i64 >= 0)
+        regrets.append(c64[np.maximum(a, 0), np.arange(nq)][ok] / b64[ok] - 1.0)
+    r = np.concatenate(regrets)
+    return {"queries": int(r.size), "frac_le_1pct": float(np.mean(r <= 0.01)), "p50": float(np.median(r)),
+            "p99": float(np.quantile(r, 0.99)), "max": float(r.max()),
+            "sample": f"first {nq} queries of the first {n_progs} programs"}
 
 
 def single_fit_component(lib, klr, synth, replays=200, seeds=100):
@@ -838,11 +873,13 @@ def main() -> int:
         log(f"single fit + grid decision: median {sf['us_per_fit_and_decision_median']:.1f} us per graph replay; "
             f"picks equal to the truth's {sf['decision_quality']['picks_equal_truth']:.3f}")
 
+    surr_picks = None
     if not args.no_surrogate:
         de = klr.DeviceEval.from_batch(lib, pb)
         comps["surrogate"] = surrogate_component(lib, klr, synth, pb, de, eval_avg + avg[klr.K_COLLAPSE],
                                                  args.seed, args.surrogate_epochs)
         sc = comps["surrogate"]
+        surr_picks = sc.pop("_picks")
         log(f"surrogate: train {sc['train_ms']:.0f} ms, select {sc['select_ms']:.0f} ms, fallback rate "
             f"{sc['fallback_rate']:.3f}, speedup vs exact {sc['speedup_vs_exact']:.3f}")
         del de
@@ -887,6 +924,9 @@ def main() -> int:
         t = time.perf_counter()
         cpu["fp64_error"] = fp64_error(pb, am_h, bc_h, 8, 2048)
         log(f"FP64 check in {time.perf_counter() - t:.1f} s: {cpu['fp64_error']}")
+        if surr_picks is not None:
+            comps["surrogate"]["regret_fp64_truth"] = surrogate_fp64_regret(pb, surr_picks, 8, 2048)
+            log(f"surrogate regret under FP64 truth: {comps['surrogate']['regret_fp64_truth']}")
         res["cpu_baseline"] = cpu
         res["fp64_error"] = cpu["fp64_error"]
     print(json.dumps(res), flush=True)

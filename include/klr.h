@@ -330,6 +330,10 @@ klr_status klr_surrogate_step(klr_handle h, void* params, int32_t n_kernels,
  * the second best is below ln(1 + margin), or the exact cost of the pick is +inf (possible only
  * where the cycle estimate overflows FP32), the query falls back to the exact rational program
  * (klr_eval_argmin semantics) and fell_back[q] = 1.
+ * Queries that do not fall back take a shortlist (KLR_OPT_SURR_SHORTLIST, K = 4 by default): the
+ * network's K best-predicted admissible configurations are evaluated exactly (the FP32 cost of
+ * klr_eval_argmin) and the pick is the lowest exact cost among them, lowest index on ties; a
+ * shortlist whose exact costs are all +inf falls back.  With K = 1 the pick is the network's.
  * pred_cost[q] = exp(predicted ln C) of the pick, or the exact cost on fallback.
  * pred_margin[q] (optional, may be NULL): second-best minus best prediction in ln units (+inf
  * with a single candidate; NaN when the network makes no pick: no admissible configuration, or
@@ -441,6 +445,11 @@ klr_status klr_collect_times(klr_handle h, int32_t target, const int32_t* sample
                                   /*   timing of each on the first batch of a shape, cached in   */
                                   /*   the handle and KLR_TUNE_CACHE); >= 0: variant 0, 1, 2.    */
                                   /*   Every variant gives bit-identical results                 */
+#define KLR_OPT_SURR_SHORTLIST 3  /* 4 (default): klr_surrogate_eval re-ranks the network's K   */
+                                  /*   best-predicted configurations of a query that does not   */
+                                  /*   fall back by their exact costs and picks the lowest      */
+                                  /*   (lowest index on ties); 1: the network's pick as it is;  */
+                                  /*   values are clamped to [1, 4]                             */
 #define KLR_OPT_COUNT 8
 klr_status klr_set_option(klr_handle h, int32_t option, int64_t value);
 

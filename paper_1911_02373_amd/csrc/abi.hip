@@ -637,7 +637,10 @@ klr_status klr_surrogate_eval(klr_handle h, const void* params, int32_t n_kernel
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   klr::Blob w = klr::blob_of(const_cast<void*>(params), n_kernels);
   klr::SelectArgs sa{progs, n_progs, max_cfg, max_q, n_kernels, n_fits, hw->t_max, hw->wave, cfgs, cfgs_len,
-                     queries, q_len, margin, argmin, pred_cost, fell_back, pred_margin, ws, *hw};
+                     queries, q_len, margin, argmin, pred_cost, fell_back, pred_margin, ws, *hw,
+                     (int32_t)(h->opt[KLR_OPT_SURR_SHORTLIST] < 1 ? 1
+                               : (h->opt[KLR_OPT_SURR_SHORTLIST] > klr::kMaxShortlist ? klr::kMaxShortlist
+                                                                                       : h->opt[KLR_OPT_SURR_SHORTLIST]))};
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t ews = klr::eval_workspace_bytes(n_progs, max_cfg);
   klr::EvalArgs a{progs, n_progs, max_cfg, max_q, *hw, desc, n_fits, exps, n_exp_rows, coef, coef_len,

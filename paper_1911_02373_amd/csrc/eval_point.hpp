@@ -1,7 +1,8 @@
 // Per-point pieces of the rational-program evaluation, shared by the exact sweep (eval.hip) and
 // the surrogate selection (mlp.hip): the layout of the collapse workspace, the fitted metric
-// values and the occupancy terms.  One definition of each FP32 step keeps the selection's
-// admissibility mask identical to the exact sweep's decisions.
+// values, the occupancy terms and the normative FP32 cost of a point.  One definition of each
+// FP32 step keeps the selection's admissibility mask and its exact re-ranking identical to the
+// exact sweep's decisions.
 //
 // Paper: step 4 ("Rational program evaluation") of the section "An Algorithm to Build and Deploy
 // a Performance-Predicting Rational Program" and the occupancy flowchart of Example "Hardware
@@ -78,6 +79,29 @@ __device__ __forceinline__ float2 vgpr_pair(const float* p) {
   return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
 }
 
+__device__ __forceinline__ uint32_t udiv_magic(uint32_t n, uint32_t m, int32_t sh) {
+  return sh < 0 ? n : (__umulhi(n, m) >> sh);
+}
+
+// Quotient a / b by the steps of the correctly rounded FP32 division without its range
+// scaling and special-case fix-up: reciprocal estimate, one Newton step, then two corrections
+// of the quotient by its exact FMA remainder.  For finite a, b with |a| and |b| in
+// [2^-40, 2^40] the scaling steps of the full sequence leave both operands unchanged (the
+// exponents differ by less than 96, neither 1/b nor a/b is subnormal, a is far above the
+// subnormal range) and the fix-up returns the last correction unchanged, so the result is the
+// IEEE quotient bit for bit.
+__device__ __forceinline__ float div_moderate(float a, float b) {
+#pragma clang fp contract(off)
+  const float y0 = __builtin_amdgcn_rcpf(b);
+  const float e0 = __builtin_fmaf(-b, y0, 1.0f);
+  const float y1 = __builtin_fmaf(e0, y0, y0);
+  const float q0 = a * y1;
+  const float r0 = __builtin_fmaf(-b, q0, a);
+  const float q1 = __builtin_fmaf(r0, y1, q0);
+  const float r1 = __builtin_fmaf(-b, q1, a);
+  return __builtin_fmaf(r1, y1, q1);
+}
+
 // Scaled query size per metric, x_j = N * 2^-s_j with s_j the scale exponent of metric j's fit.
 // The collapse kernel writes the same scales into every configuration slot of a program (a
 // program whose fits are invalid gets 1 and an inadmissible record in every slot), so the
@@ -135,13 +159,16 @@ __device__ __forceinline__ float resident_blocks_defined(float g5, float g6, con
   return fminf(fminf(r.Bcap, breg), blds);
 }
 
-// Whether the exact evaluation can give a point a finite cost: the configuration is admissible
-// for the program, no launch parameter exceeds N, every fitted function the cost reads is
-// defined (q > 0, finite value) and, for the cycle estimate, at least one block is resident.
-// A point this rejects has cost +inf in the exact sweep; the converse fails only where the
-// cycle estimate itself overflows.  Slots are per lane (UNI = false); powers from kNdeg.
+// Whether the exact evaluation can give a point a finite cost, from the cheap part of the
+// rational program: the configuration is admissible for the program and no launch parameter
+// exceeds N; for a cycle-estimate program every metric denominator is positive and, from the
+// register and LDS metrics, at least one block is resident; for the other kinds every fitted
+// function the cost reads is defined (q > 0, finite value).  A point this rejects has cost +inf
+// in the exact sweep (the same FP32 steps); the converse fails where a metric value or the
+// cycle estimate overflows FP32.  Slots are per lane (UNI = false); powers from kNdeg.
 __device__ __forceinline__ bool point_admissible(int kind, int32_t N, const float* xs, const float* __restrict__ cf,
                                                  const CfgRec& r, const Hw32& hw) {
+#pragma clang fp contract(off)
   bool ok = (r.ok != 0) & (N >= r.Lmax);
   if (kind == KLR_COST_METRIC) {
     bool g0;
@@ -155,17 +182,175 @@ __device__ __forceinline__ bool point_admissible(int kind, int32_t N, const floa
     (void)fitted_value<kNdeg, false>(cf, 2, xs[2], &gb);
     return ok & gd & (d >= 0.0f ? ga : gb);
   }
-  float g5 = 0.0f, g6 = 0.0f;
-  bool good5 = false, good6 = false;
 #pragma unroll
   for (int j = 0; j < KLR_N_METRICS; ++j) {
-    bool gj;
-    const float g = fitted_value<kNdeg, false>(cf, j, xs[j], &gj);
-    ok = ok & gj;
-    if (j == 5) { g5 = g; good5 = gj; }
-    if (j == 6) { g6 = g; good6 = gj; }
+    if (j == 5 || j == 6) continue;
+    const float* c = cf + j * 2 * (kNdeg + 1);       // the denominator: odd entries, by power
+    float q = __builtin_fmaf(c[2 * kNdeg + 1], xs[j], c[2 * kNdeg - 1]);
+#pragma unroll
+    for (int d = kNdeg - 2; d >= 0; --d) q = __builtin_fmaf(q, xs[j], c[2 * d + 1]);
+    ok = ok & (q > 0.0f);
   }
-  return ok & (resident_blocks(g5, good5, g6, good6, r, hw) >= 1.0f);
+  bool good5, good6;
+  const float g5 = fitted_value<kNdeg, false>(cf, 5, xs[5], &good5);
+  const float g6 = fitted_value<kNdeg, false>(cf, 6, xs[6], &good6);
+  return ok & good5 & good6 & (resident_blocks(g5, good5, g6, good6, r, hw) >= 1.0f);
+}
+
+// Cost of one (query, configuration) point; +inf where inadmissible.  DEG: the program's highest
+// power of N~ (Horner from there; the normative sequence starts at power 3 with zero
+// coefficients above DEG, which gives bit-identical values because fma(0, x, a) = a exactly for
+// finite x and a != -0, and collapsed coefficients are sums that start from +0).
+// UNI: cf and r are the same in every lane (the coefficients then sit in scalar registers); a
+// per-lane configuration takes plain vector loads.  SHORT (the configuration record's `fast`):
+// 1 - every metric's numerator and denominator stay in [2^-40, 2^40] (denominators positive)
+// over the program's queries, so each metric quotient takes div_moderate (the same bits as the
+// IEEE division), every metric is defined and finite and nonzero, and the clamps reduce to
+// maxima; 2 - the four quotients of the cycle estimate take div_moderate as well.
+template <int GRID, int DEG = kNdeg, bool UNI = true, int SHORT = 0>
+__device__ __forceinline__ float point_cost(int32_t N, const float* xs, const float* __restrict__ cf,
+                                            const CfgRec& r, const Hw32& hw) {
+#pragma clang fp contract(off)
+  static_assert(DEG >= 1 && DEG <= kNdeg, "Horner degree");
+  bool ok = (r.ok != 0) & (N >= r.Lmax);
+  float g[KLR_N_METRICS];
+  bool good[KLR_N_METRICS];
+#pragma unroll
+  for (int j = 0; j < KLR_N_METRICS; ++j) {
+    const float* c = cf + j * 2 * (kNdeg + 1);     // c[2 d] numerator, c[2 d + 1] denominator
+    const float x = xs[j];
+    // First Horner step: both addends enter vector registers through one 64-bit move (the
+    // wave-uniform coefficients sit in scalar registers, and a VALU instruction reads at most
+    // one of them).
+    const float2 lo = UNI ? vgpr_pair(c + 2 * (DEG - 1)) : make_float2(c[2 * (DEG - 1)], c[2 * DEG - 1]);
+    float p = __builtin_fmaf(c[2 * DEG], x, lo.x);
+    float q = __builtin_fmaf(c[2 * DEG + 1], x, lo.y);
+#pragma unroll
+    for (int d = DEG - 2; d >= 0; --d) {
+      p = __builtin_fmaf(p, x, c[2 * d]);
+      q = __builtin_fmaf(q, x, c[2 * d + 1]);
+    }
+    if (SHORT) {
+      g[j] = div_moderate(p, q);
+      good[j] = true;
+    } else {
+      g[j] = p / q;
+      good[j] = (q > 0.0f) & (fabsf(g[j]) <= 3.402823466e38f);
+      ok = ok & good[j];
+    }
+  }
+  // A metric failing the check is cleaned to +0 before its clamp; clean_max takes both steps.
+  // The upper clamps of R (>= 1) and Z (>= -0) see no NaN, so fminf equals the compare-select.
+  // (with SHORT every value is finite and nonzero, so the compare-select equals the maximum)
+  const float Icomp = SHORT ? fmaxf(g[0], 0.0f) : clean_max(good[0], g[0], 0.0f);
+  const float Imc = SHORT ? fmaxf(g[1], 0.0f) : clean_max(good[1], g[1], 0.0f);
+  const float Imu = SHORT ? fmaxf(g[2], 0.0f) : clean_max(good[2], g[2], 0.0f);
+  const float U = SHORT ? fmaxf(g[3], 1.0f) : clean_max(good[3], g[3], 1.0f);
+  const float Isync = SHORT ? fmaxf(g[4], 0.0f) : clean_max(good[4], g[4], 0.0f);
+  const float Bw = SHORT ? fmaxf(g[7], 1.0f) : clean_max(good[7], g[7], 1.0f);
+
+  // occupancy from the register and LDS metrics; the minima and the products below equal their
+  // integer counterparts
+  const float B = SHORT ? resident_blocks_defined(g[5], g[6], r, hw)
+                        : resident_blocks(g[5], good[5], g[6], good[6], r, hw);
+  ok = ok & (B >= 1.0f);
+  const float Bf = fmaxf(B, 1.0f);
+  const float Nwf = fminf(Bf * r.Wb, hw.w_max);     // a product above 2^24 is above w_max too
+  const int32_t Nc = N >= 1 ? N : 1;
+  float repf;
+  if (GRID == KLR_GRID_1D) {
+    // rep = ceil(blocks / (B n_cu)) = ceil(ceil(blocks / n_cu) / B), blocks = ceil(N / T);
+    // ceil(blocks / n_cu) - 1 = floor(floor((N - 1) / T) / n_cu) = floor((N - 1) / (T n_cu))
+    const uint32_t cm1 = udiv_magic((uint32_t)(Nc - 1), r.magTC, r.shTC);
+    if (cm1 < (1u << 20))
+      repf = floor_div((float)cm1 + 0.5f, Bf) + 1.0f;
+    else
+      repf = (float)(cm1 / (uint32_t)Bf + 1u);
+  } else {
+    const uint64_t blocks = (uint64_t)((uint32_t)(Nc - 1) / (uint32_t)r.L0 + 1u) *
+                            (uint64_t)((uint32_t)(Nc - 1) / (uint32_t)r.L1 + 1u);
+    const uint64_t rep = (blocks - 1u) / (uint64_t)((uint32_t)Bf * (uint32_t)hw.n_cu) + 1u;
+    repf = (float)rep;
+  }
+
+  const float Im = Imc + Imu;
+  const float Lu = __builtin_fmaf(U - 1.0f, hw.dep, hw.lat);      // (U - 1) dep + lat
+  const float mem = __builtin_fmaf(Lu, Imu, hw.lat * Imc);         // lat I_mc + L_u I_mu
+  float comp = Icomp + Im;
+  comp = hw.iss * comp;
+
+  float d1 = __builtin_fmaf(U, Imu, Imc);                          // I_mc + U I_mu
+  d1 = hw.dep * d1;
+  const float mwp_lat = SHORT == 2 ? div_moderate(mem, d1) : mem / d1;
+  const float n2 = hw.bw * mem;
+  const float d2 = Im * Bw;
+  const float mwp_bw = SHORT == 2 ? div_moderate(n2, d2) : n2 / d2;
+  float mwp = sel_min(mwp_lat, mwp_bw);
+  mwp = sel_min(mwp, Nwf);
+  mwp = sel_max(mwp, 1.0f);
+  const float tot = mem + comp;
+  const bool cwp_full = tot >= Nwf * comp;
+  const bool cwp_ge_mwp = tot >= mwp * comp;
+  const float cpm = SHORT == 2 ? div_moderate(comp, Im) : comp / Im;
+  const float m1 = mwp - 1.0f;
+  const float e1 = __builtin_fmaf(cpm, m1, tot);                   // tot + cpm (MWP - 1)
+  float t2 = mem * Nwf;
+  t2 = SHORT == 2 ? div_moderate(t2, mwp) : t2 / mwp;
+  const float e2 = __builtin_fmaf(cpm, m1, t2);                    // mem N_w / MWP + cpm (MWP - 1)
+  const float e3 = __builtin_fmaf(comp, Nwf, hw.lat);              // lat + comp N_w
+  const bool case1 = (mwp >= Nwf) & cwp_full;
+  const bool case2 = cwp_ge_mwp | (comp > mem);
+  float ex = case1 ? e1 : (case2 ? e2 : e3);
+  const bool pure = (Im == 0.0f);
+  mwp = pure ? 1.0f : mwp;
+  ex = pure ? comp * Nwf : ex;
+
+  float sy = mwp - 1.0f;
+  sy = hw.dep * sy;
+  sy = sy * Isync;
+  sy = sy * Bf;
+  sy = sy * repf;
+  const float cost = __builtin_fmaf(ex, repf, sy);                 // exec rep + sync
+  ok = ok & (fabsf(cost) <= 3.402823466e38f);
+  return ok ? cost : INFINITY;
+}
+
+// Cost of one point of a program whose one fitted function is the cost: p/q of metric 0 by the
+// same Horner steps and division as the cycle estimate's metrics; +inf where q <= 0, the value is
+// not finite, a launch parameter exceeds N or the configuration is not admissible.
+template <int DEG = kNdeg, bool UNI = true>
+__device__ __forceinline__ float metric_cost(int32_t N, const float* xs, const float* __restrict__ cf,
+                                             const CfgRec& r) {
+  bool good;
+  const float g = fitted_value<DEG, UNI>(cf, 0, xs[0], &good);
+  const bool ok = (r.ok != 0) & (N >= r.Lmax) & good;
+  return ok ? g : INFINITY;
+}
+
+// A piecewise rational program with a fitted decision node (paper: the decision nodes of a
+// rational program are themselves rational functions, so they can be fitted like the metrics):
+// fits 0, 1, 2 are the decision d, the cost where d >= 0 and the cost where d < 0.  The point
+// is inadmissible where d or the branch taken is (q <= 0 or not finite), or where the launch
+// constraints fail.
+template <int DEG = kNdeg, bool UNI = true>
+__device__ __forceinline__ float piecewise_cost(int32_t N, const float* xs, const float* __restrict__ cf,
+                                                const CfgRec& r) {
+  bool gd, ga, gb;
+  const float d = fitted_value<DEG, UNI>(cf, 0, xs[0], &gd);
+  const float a = fitted_value<DEG, UNI>(cf, 1, xs[1], &ga);
+  const float b = fitted_value<DEG, UNI>(cf, 2, xs[2], &gb);
+  const bool first = d >= 0.0f;
+  const bool ok = (r.ok != 0) & (N >= r.Lmax) & gd & (first ? ga : gb);
+  return ok ? (first ? a : b) : INFINITY;
+}
+
+// Any cost, chosen per program (wave-uniform).
+template <int GRID, int DEG = kNdeg, bool UNI = true>
+__device__ __forceinline__ float any_cost(int kind, int32_t N, const float* xs, const float* __restrict__ cf,
+                                          const CfgRec& r, const Hw32& hw) {
+  if (kind == KLR_COST_METRIC) return metric_cost<DEG, UNI>(N, xs, cf, r);
+  if (kind == KLR_COST_PIECEWISE) return piecewise_cost<DEG, UNI>(N, xs, cf, r);
+  return point_cost<GRID, DEG, UNI>(N, xs, cf, r, hw);
 }
 
 }  // namespace klr

@@ -54,7 +54,7 @@ struct klr_handle_s {
   klr::Timer timer;
   klr::Tuner tuner;
   bool capturing = false;
-  int64_t opt[8] = {1, -1, -1, 0, 0, 0, 0, 0};   // see KLR_OPT_* in klr.h
+  int64_t opt[8] = {1, -1, -1, 4, 0, 0, 0, 0};   // see KLR_OPT_* in klr.h
 };
 
 namespace klr {
@@ -401,6 +401,7 @@ struct TrainTile {
 constexpr int kDw2Slices = 16;
 size_t mlp_train_ws_bytes(int32_t nk, int32_t B);
 
+constexpr int kMaxShortlist = 4;      // configurations the selection re-ranks exactly per query
 struct SelectArgs {
   const klr_program* progs;
   int32_t n_progs, max_cfg, max_q, nk, n_fits;
@@ -416,6 +417,7 @@ struct SelectArgs {
   float* pred_margin;      // optional: second-best minus best prediction (ln units) per query
   const void* eval_ws;     // the collapse workspace of the same programs (launch_collapse_only)
   klr_hw hw;
+  int32_t shortlist;       // predicted-best configurations re-ranked by their exact costs (1..4)
 };
 
 hipError_t launch_refresh(const Blob& w, hipStream_t s);

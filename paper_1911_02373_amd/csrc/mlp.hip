@@ -557,8 +557,9 @@ mlp_predict(const int32_t* __restrict__ kid, const int32_t* __restrict__ Nq, con
 // metrics defined, at least one block resident, the launch constraints met: the same FP32 steps
 // as the exact sweep, so a configuration left out has cost +inf there); the network never sees
 // inadmissible points in training, so its predictions for them carry no information.
-// Each lane keeps the running (best, index, second best) of its configurations; one wave
-// reduction per query gives the pick and the margin.
+// Each lane keeps its lowest predictions; rounds of 32-lane minima give the query's best
+// predictions in order, hence the pick and the margin; a query that does not fall back has its
+// shortlist (the best a.shortlist predictions) evaluated exactly, and the lowest exact cost wins.
 constexpr int kSelMaxCfg = 1024;
 constexpr int kSelWaves = 8;
 constexpr int kSelQ = 64;            // queries per work item
@@ -655,8 +656,12 @@ mlp_select(SelectArgs a, Blob w, int chunks, int64_t n_items) {
       const float fN = log2f((float)(N >= 1 ? N : 1)) * (1.0f / 26.0f);
       float xs[KLR_N_METRICS];
       scaled_n(N, slot0, xs);
-      float best = INFINITY, sec = INFINITY;
-      int bi = 0x7fffffff;
+      // the lane's kMaxShortlist lowest predictions (value, index), ascending; configurations
+      // arrive in increasing index order, so an equal value stays behind the earlier one
+      float tv[kMaxShortlist];
+      int ti[kMaxShortlist];
+#pragma unroll
+      for (int s2 = 0; s2 < kMaxShortlist; ++s2) { tv[s2] = INFINITY; ti[s2] = 0x7fffffff; }
       for (int c0 = 0; c0 < P.n_cfg; c0 += 64) {
         // the network ranks only the configurations the exact program admits at this N: lane
         // group g checks configuration c0 + 32 g + lane % 32, the other group's result arrives by
@@ -731,38 +736,93 @@ mlp_select(SelectArgs a, Blob w, int chunks, int64_t n_items) {
           const float y = (g == 0 ? yp[rt] + other : other + yp[rt]) + b3;   // same order in both groups
           const int c = c0 + 32 * rt + (lane & 31);
           if (adm[rt]) {
-            const float v = mu + sig * y;
-            if (v < best) {       // configurations arrive in increasing index order per lane
-              sec = fminf(sec, best);
-              best = v;
-              bi = c;
-            } else {
-              sec = fminf(sec, v);
+            float nv = mu + sig * y;
+            int ni = c;
+#pragma unroll
+            for (int s2 = 0; s2 < kMaxShortlist; ++s2) {
+              const bool lt = nv < tv[s2];
+              const float t = tv[s2];
+              const int u = ti[s2];
+              tv[s2] = lt ? nv : t;
+              ti[s2] = lt ? ni : u;
+              nv = lt ? t : nv;
+              ni = lt ? u : ni;
             }
           }
         }
       }
-      // (best, index) lexicographic minimum over the 32 configuration lanes; the second best
-      // collects the loser of every comparison, so equal values give a zero margin
+      // the group's lowest predictions in order: each round takes the (value, index) minimum of
+      // the 32 configuration lanes' list heads and the lane that held it drops its head (both
+      // lane groups hold the same lists and take the same steps); at least two rounds, for the
+      // margin
+      const int rounds = a.shortlist > 2 ? a.shortlist : 2;
+      float cv[kMaxShortlist];
+      int ci[kMaxShortlist];
 #pragma unroll
-      for (int off = 1; off <= 16; off <<= 1) {
-        const float ob = __shfl_xor(best, off), os = __shfl_xor(sec, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob < best || (ob == best && oi < bi)) {
-          sec = fminf(best, os);
-          best = ob;
-          bi = oi;
+      for (int r = 0; r < kMaxShortlist; ++r) {
+        cv[r] = INFINITY;
+        ci[r] = 0x7fffffff;
+        if (r < rounds) {
+          float hv = tv[0];
+          int hi = ti[0];
+#pragma unroll
+          for (int off = 1; off <= 16; off <<= 1) {
+            const float ov = __shfl_xor(hv, off);
+            const int oi = __shfl_xor(hi, off);
+            if (ov < hv || (ov == hv && oi < hi)) { hv = ov; hi = oi; }
+          }
+          cv[r] = hv;
+          ci[r] = hi;
+          if (ti[0] == hi) {
+#pragma unroll
+            for (int s2 = 0; s2 + 1 < kMaxShortlist; ++s2) { tv[s2] = tv[s2 + 1]; ti[s2] = ti[s2 + 1]; }
+            tv[kMaxShortlist - 1] = INFINITY;
+            ti[kMaxShortlist - 1] = 0x7fffffff;
+          }
+        }
+      }
+      const bool found = ci[0] != 0x7fffffff;
+      const float marg = cv[1] - cv[0];                 // +inf with a single candidate
+      bool fell = !found || !(marg >= lnm);
+      int pick = found ? ci[0] : -1;
+      float pv = cv[0];
+      if (!fell) {                                      // wave-uniform
+        // exact costs of the shortlist, lane r < shortlist taking candidate r; the lowest exact
+        // cost wins, lowest index on ties; none finite falls back
+        int c = 0x7fffffff;
+        float cp = INFINITY;
+#pragma unroll
+        for (int r = 0; r < kMaxShortlist; ++r)
+          if (lane == r && r < a.shortlist) { c = ci[r]; cp = cv[r]; }
+        float xc = INFINITY;
+        if (c != 0x7fffffff) {
+          const float* cf = slot0 + (int64_t)c * kSlotFloats;
+          xc = P.grid_kind == KLR_GRID_1D ? any_cost<KLR_GRID_1D, kNdeg, false>(P.cost_kind, N, xs, cf, rec0[c], hw)
+                                          : any_cost<KLR_GRID_2D, kNdeg, false>(P.cost_kind, N, xs, cf, rec0[c], hw);
+        }
+#pragma unroll
+        for (int off = 1; off < kMaxShortlist; off <<= 1) {
+          const float ox = __shfl_xor(xc, off);
+          const int oc = __shfl_xor(c, off);
+          const float op = __shfl_xor(cp, off);
+          if (ox < xc || (ox == xc && oc < c)) { xc = ox; c = oc; cp = op; }
+        }
+        xc = __shfl(xc, 0);
+        c = __shfl(c, 0);
+        cp = __shfl(cp, 0);
+        if (xc < INFINITY) {
+          pick = c;
+          pv = cp;
         } else {
-          sec = fminf(sec, ob);
+          fell = true;
         }
       }
       if (lane == 0) {
         const int64_t o = P.q0 + qi;
-        const bool found = bi != 0x7fffffff;
-        a.argmin[o] = found ? bi : -1;
-        a.pred_cost[o] = found ? expf(best) : INFINITY;
-        a.fell_back[o] = (!found || !(sec - best >= lnm)) ? 1 : 0;
-        if (a.pred_margin) a.pred_margin[o] = found ? sec - best : NAN;
+        a.argmin[o] = pick;
+        a.pred_cost[o] = found ? expf(pv) : INFINITY;
+        a.fell_back[o] = fell ? 1 : 0;
+        if (a.pred_margin) a.pred_margin[o] = found ? marg : NAN;
       }
     }
   }

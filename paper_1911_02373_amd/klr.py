@@ -45,7 +45,7 @@ EXPORTS = ("klr_create", "klr_destroy", "klr_last_error", "klr_fit_workspace", "
            "klr_service_stats", "klr_service_set_history_limit", "klr_constraint_check",
            "klr_collect_buffer", "klr_target_attributes", "klr_collect_times")
 TARGET_TRANSPOSE, TARGET_STENCIL = 0, 1
-OPT_FIT_PERSISTENT, OPT_EVAL_VARIANT, OPT_FIT_VARIANT = 0, 1, 2
+OPT_FIT_PERSISTENT, OPT_EVAL_VARIANT, OPT_FIT_VARIANT, OPT_SURR_SHORTLIST = 0, 1, 2, 3
 K_COLLAPSE, K_EVAL, K_FIT_GRAM, K_FIT_SOLVE, K_MLP, K_SURR, K_FALLBACK = 0, 1, 2, 3, 4, 5, 6
 TRAIN_CFG = np.dtype([("lr", "<f4"), ("beta1", "<f4"), ("beta2", "<f4"), ("eps", "<f4"),
                       ("batch", "<i4"), ("epochs", "<i4"), ("seed", "<u8")])

@@ -264,13 +264,14 @@ def test_uneven_programs_train_and_select(klr):
 
 
 def test_selection_ranks_only_admissible_configurations(klr):
-    """With sigma = 0 every prediction is equal, so the network's pick is the first
-    configuration it ranks.  Configurations 0 and 1 (512 and 1024 threads at R = 300 registers
-    per thread) leave no block resident, so the exact program rules them out; the selection
-    never ranks them, and with margin 0 (the margin rule never fires) every query keeps the
-    first admissible configuration, 2, without falling back."""
+    """With sigma = 0 every prediction is equal, so the network ranks configurations by index.
+    Configurations 0 and 1 (512 and 1024 threads at R = 300 registers per thread) leave no
+    block resident, so the exact program rules them out and the selection never ranks them.
+    With margin 0 (the margin rule never fires) and a shortlist of one, every query keeps the
+    first admissible configuration, 2; with a shortlist of four the three admissible
+    configurations are re-ranked by their exact costs, so the pick is the exact argmin."""
     import torch
-    from paper_1911_02373_amd.klr import DeviceEval
+    from paper_1911_02373_amd.klr import OPT_SURR_SHORTLIST, DeviceEval
     from tests.helpers import constant_programs
     rows = [[40.0, 6.0, 3.0, 2.0, 1.0, 300.0, 0.0, 64.0]] * 3
     cfgs = [[512, 1], [1024, 1], [64, 1], [128, 1], [32, 8]]
@@ -279,12 +280,76 @@ def test_selection_ranks_only_admissible_configurations(klr):
     blob = klr.surrogate_alloc(synth.mlp_init(9, nk), nk, mu=0.0, sigma=0.0)
     de = DeviceEval.from_batch(klr, pb)
     ea, _, _, _ = klr.eval_argmin(de)
-    am, pc, fb = klr.surrogate_eval(blob, nk, de, margin=0.0)
-    torch.cuda.synchronize()
-    assert np.all(np.isin(ea.cpu().numpy(), [2, 3, 4]))      # the exact picks are the admissible ones
+    klr.set_option(OPT_SURR_SHORTLIST, 1)
+    try:
+        am, pc, fb = klr.surrogate_eval(blob, nk, de, margin=0.0)
+        torch.cuda.synchronize()
+    finally:
+        klr.set_option(OPT_SURR_SHORTLIST, 4)
+    ea = ea.cpu().numpy()
+    assert np.all(np.isin(ea, [2, 3, 4]))                       # the exact picks are the admissible ones
     assert np.all(fb.cpu().numpy() == 0)
     assert np.all(am.cpu().numpy() == 2)
     assert np.all(pc.cpu().numpy() == 1.0)                     # exp(mu + 0 * y)
+    am4, pc4, fb4 = klr.surrogate_eval(blob, nk, de, margin=0.0)
+    torch.cuda.synchronize()
+    assert np.all(fb4.cpu().numpy() == 0)
+    assert np.array_equal(am4.cpu().numpy(), ea)
+    assert np.all(pc4.cpu().numpy() == 1.0)
+
+
+def test_shortlist_reranks_the_networks_best_by_exact_cost(klr, trained):
+    """Shortlist of four with margin 0 (only an all-inadmissible shortlist falls back), query by
+    query (8 programs x 256 queries): where the oracle network's four best predictions are
+    separated from the rest by more than twice the accumulation bound 2^-15 S (so the shortlist
+    is unambiguous up to a rare first-layer bfloat16 flip), a query falls back exactly when the
+    four exact costs are all +inf, and otherwise picks the configuration of lowest exact FP32
+    cost (oracle replay, lowest index on ties) among those four - all but at most 1 % of them -
+    and never one worse than the network's own pick."""
+    import torch
+    from paper_1911_02373_amd.klr import OPT_SURR_SHORTLIST, DeviceEval
+    pb, blob, _ = trained
+    nk = pb.n_progs
+    sub = synth.take_programs(pb, 8)
+    de = DeviceEval.from_batch(klr, sub)
+    am4, _, fb4 = klr.surrogate_eval(blob, nk, de, margin=0.0)
+    klr.set_option(OPT_SURR_SHORTLIST, 1)
+    try:
+        am1, _, fb1 = klr.surrogate_eval(blob, nk, de, margin=0.0)
+        torch.cuda.synchronize()
+    finally:
+        klr.set_option(OPT_SURR_SHORTLIST, 4)
+    am4, fb4 = am4.cpu().numpy(), fb4.cpu().numpy().astype(bool)
+    am1, fb1 = am1.cpu().numpy(), fb1.cpu().numpy().astype(bool)
+    prm = klr.surrogate_params(blob, nk)
+    refs, scales = _select_reference(prm, sub, sub.n_progs)
+    checked = off = 0
+    for p in range(sub.n_progs):
+        nq, q0 = int(sub.n_q[p]), int(sub.q0[p])
+        X = oc.program_costs(sub, p)                         # exact FP32 costs [n_cfg][nq]
+        R, S = refs[p], scales[p]
+        for i in range(nq):
+            o = q0 + i
+            row = R[i]
+            fin = np.isfinite(row)
+            if fin.sum() < 5:
+                continue
+            order = np.argsort(row, kind="stable")
+            acc = 2.0 ** -15 * float(S[i][fin].max())
+            if row[order[4]] - row[order[3]] <= 2 * acc:
+                continue
+            short = order[:4]
+            xs = X[short, i]
+            assert fb4[o] == (not np.isfinite(xs).any()), (p, i)
+            if fb4[o]:
+                continue
+            if not fb1[o]:
+                assert X[am4[o], i] <= X[am1[o], i], (p, i)
+            want = short[np.lexsort((short, xs))[0]]
+            checked += 1
+            off += int(am4[o] != want)
+    print(f"shortlist picks checked: {checked}, different from the oracle shortlist's best: {off}")
+    assert checked > 100 and off <= 0.01 * checked, (checked, off)
 
 
 def test_pick_check_sends_inadmissible_picks_to_the_exact_path(klr):
@@ -345,7 +410,7 @@ def _select_reference(prm, pb, n_progs):
 
 def test_selection_matches_network_elementwise(klr, trained):
     """mlp_select against the network oracle, query by query (8 programs x 256 queries x 128
-    configurations).  Every query: the predicted ln C of its pick and its predicted margin
+    configurations), with a shortlist of one (the network's own pick).  Every query: the predicted ln C of its pick and its predicted margin
     (second best minus best) are within the bfloat16-flip bound 2^-8 S of the oracle's minimum
     and margin over the admissible configurations, and 99 % within the accumulation
     bound 2^-15 S.  Wherever the oracle's margin exceeds twice the accumulation bound the pick
@@ -356,6 +421,7 @@ def test_selection_matches_network_elementwise(klr, trained):
     oracle's margin away from the threshold."""
     import torch
     from paper_1911_02373_amd.klr import DeviceEval
+    from paper_1911_02373_amd.klr import OPT_SURR_SHORTLIST
     pb, blob, _ = trained
     nk = pb.n_progs
     sub = synth.take_programs(pb, 8)
@@ -364,9 +430,13 @@ def test_selection_matches_network_elementwise(klr, trained):
     marg = torch.empty(ql, dtype=torch.float32, device="cuda")
     st = torch.empty(sub.n_progs, dtype=torch.int32, device="cuda")
     ea, eb, _, _ = klr.eval_argmin(de)
-    am, pc, fb = klr.surrogate_eval(blob, nk, de, margin=0.0, pred_margin=marg, prog_status=st)
-    am2, _, fb2 = klr.surrogate_eval(blob, nk, de, margin=0.02)
-    torch.cuda.synchronize()
+    klr.set_option(OPT_SURR_SHORTLIST, 1)                    # the network's own picks
+    try:
+        am, pc, fb = klr.surrogate_eval(blob, nk, de, margin=0.0, pred_margin=marg, prog_status=st)
+        am2, _, fb2 = klr.surrogate_eval(blob, nk, de, margin=0.02)
+        torch.cuda.synchronize()
+    finally:
+        klr.set_option(OPT_SURR_SHORTLIST, 4)
     am, pc, fb, marg = am.cpu().numpy(), pc.cpu().numpy(), fb.cpu().numpy().astype(bool), marg.cpu().numpy()
     ea, eb = ea.cpu().numpy(), eb.cpu().numpy()
     fb2, am2 = fb2.cpu().numpy().astype(bool), am2.cpu().numpy()
