@@ -387,7 +387,7 @@ def cpu_baseline(pb, fb, budget_s: float, points: int, n_fits: int, workers: int
     """The oracle timed on bounded samples of the same step, at one thread and at `workers`
     threads (worker processes, each single-threaded: numpy's elementwise arithmetic and the
     small QR factorisations run on one core): FP32 replay + brute-force argmin over program
-    slices of 2048 queries x all configurations, and pivoted-QR fits of the batch's fits.  The
+    slices of up to 8192 queries x all configurations, and pivoted-QR fits of the batch's fits.  The
     step time at each thread count is scaled from the two rates.  Runs before the GPU is
     touched (worker processes start from a fresh interpreter)."""
     import multiprocessing as mp
