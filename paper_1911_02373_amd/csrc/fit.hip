@@ -198,8 +198,27 @@ __device__ __forceinline__ void build_chunk(const FitCtx& C, int rows) {
       C.A[i * NM + j] = num ? mono : -fi * mono;
     };
     if (rows == CH) {
-#pragma unroll 2
-      for (int u = 0; u < CH / G; ++u) row(g + u * G);
+      // four rows per step with every table load issued before the stores (the chunk and the
+      // power table are separate LDS arrays, which the compiler cannot see through C)
+      constexpr int RPT = CH / G, NB = 2;
+      static_assert(RPT % NB == 0, "rows per thread");
+#pragma unroll 1
+      for (int u0 = 0; u0 < RPT; u0 += NB) {
+        double pv[NB][KLR_MAX_VARS], fv[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const double* pw = C.pt + (g + (u0 + b) * G) * 32;
+#pragma unroll
+          for (int k = 0; k < KLR_MAX_VARS; ++k) pv[b][k] = pw[off[k]];
+          fv[b] = C.fch[g + (u0 + b) * G];
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const double mono = ((pv[b][0] * pv[b][1]) * (pv[b][2] * pv[b][3])) *
+                              ((pv[b][4] * pv[b][5]) * (pv[b][6] * pv[b][7]));
+          C.A[(g + (u0 + b) * G) * NM + j] = num ? mono : -fv[b] * mono;
+        }
+      }
     } else {
       for (int i = g; i < rows; i += G) row(i);
     }
@@ -535,6 +554,225 @@ __device__ __forceinline__ double cg_pass(const FitArgs& a, const FitCtx& C, uin
   return 0.0;
 }
 
+// ---- row-parallel passes (every exponent of the fit <= 3) --------------------------------------
+// Sixteen threads share a row: thread `sub` owns the columns j = sub + 16 u (u < NM / 16) and
+// forms their design-matrix elements straight from the row's power table, so no chunk of A is
+// staged.  A t is a sum over the sixteen threads of the row (DPP); the column sums A^T r and
+// A^T q stay in registers for the whole pass and are reduced once at its end.  Each chunk needs
+// one barrier after its rows are staged and one before they are overwritten.
+
+// Byte offsets of a column's table entries k * 4 + e_k (one byte each: variables 0-3 in o0,
+// 4-7 in o1).
+__device__ __forceinline__ void col_offsets(uint32_t w, uint32_t& o0, uint32_t& o1) {
+  o0 = 0;
+  o1 = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    o0 |= (uint32_t)((k * 4 + (int)((w >> (2 * k)) & 3u)) * 8) << (8 * k);
+    o1 |= (uint32_t)(((k + 4) * 4 + (int)((w >> (2 * (k + 4))) & 3u)) * 8) << (8 * k);
+  }
+}
+
+// Monomial of one column at a staged row: the product tree of build_chunk over the eight table
+// entries.  VV = 4: variables 4-7 are unused, their entries are exactly 1 and the tree reduces
+// exactly to (p0 p1)(p2 p3).
+template <int VV>
+__device__ __forceinline__ double row_mono(const double* pw, uint32_t o0, uint32_t o1) {
+  const char* b = reinterpret_cast<const char*>(pw);
+  double p[8];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[k] = *reinterpret_cast<const double*>(b + ((o0 >> (8 * k)) & 255u));
+  if (VV <= 4) return (p[0] * p[1]) * (p[2] * p[3]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[4 + k] = *reinterpret_cast<const double*>(b + ((o1 >> (8 * k)) & 255u));
+  return ((p[0] * p[1]) * (p[2] * p[3])) * ((p[4] * p[5]) * (p[6] * p[7]));
+}
+
+// Per-thread column set of the row-parallel passes.
+template <int NM>
+struct RowCols {
+  static constexpr int CPT = NM / 16;
+  uint32_t o0[CPT], o1[CPT];
+  double tpj[CPT];     // tp of the column (0 past n)
+  bool num[CPT];       // numerator column
+  __device__ __forceinline__ void load(const FitCtx& C, int sub) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int j = sub + 16 * u;
+      col_offsets(j < C.n ? C.ep[j] : 0u, o0[u], o1[u]);
+      tpj[u] = j < C.n ? C.tp[j] : 0.0;
+      num[u] = j < C.n_num;
+    }
+  }
+};
+
+// Column sums of the row-parallel passes: the four lanes of a wave that own the same columns
+// are summed by lane swaps, then the four waves through LDS scratch (the chunk region of A,
+// which these passes do not use), in a fixed order.
+template <int NM>
+__device__ __forceinline__ void col_reduce(const FitCtx& C, const double* acc, double* out) {
+  constexpr int CPT = NM / 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, sub = threadIdx.x & 15;
+#pragma unroll
+  for (int u = 0; u < CPT; ++u) {
+    const double v = pair_sum32(pair_sum16(acc[u]));
+    if (lane < 16) C.A[(w * CPT + u) * 16 + sub] = v;
+  }
+  __syncthreads();
+  const int j = threadIdx.x;
+  if (j < C.n) {
+    const int u = j >> 4, sj = j & 15;
+    out[j] = (C.A[(0 * CPT + u) * 16 + sj] + C.A[(1 * CPT + u) * 16 + sj]) +
+             (C.A[(2 * CPT + u) * 16 + sj] + C.A[(3 * CPT + u) * 16 + sj]);
+  }
+  __syncthreads();
+}
+
+// The refinement sweep of cg_pass (same modes and outputs) in the row-parallel form.
+template <int NM, int MODE, int VV>
+__device__ __forceinline__ double cg_rows(const FitArgs& a, const FitCtx& C, uint64_t sc, double* wsr, double* wsq,
+                                          bool upd, double alpha_prev) {
+  constexpr int CH = Chunk<NM>::CH;
+  constexpr int CPT = NM / 16;
+  constexpr int RPC = CH / 16;                      // rows per thread and chunk
+  static_assert(CH % 16 == 0 && NM % 16 == 0, "row groups");
+  const int sub = threadIdx.x & 15, rg = threadIdx.x >> 4;
+  RowCols<NM> cs;
+  cs.load(C, sub);
+  double accr[CPT], accq[CPT];
+#pragma unroll
+  for (int u = 0; u < CPT; ++u) accr[u] = accq[u] = 0.0;
+  double qq = 0.0;
+  RowLoad rl;
+  load_rows(a, C, 0, chunk_rows(C, 0, CH), rl);
+  for (int i0 = 0; i0 < C.m; i0 += CH) {
+    const int rows = chunk_rows(C, i0, CH);
+    put_rows(C, sc, rows, rl);
+    if (i0 + CH < C.m) load_rows(a, C, i0 + CH, chunk_rows(C, i0 + CH, CH), rl);
+    double rv[RPC], qv[RPC];
+#pragma unroll
+    for (int s2 = 0; s2 < RPC; ++s2) {
+      const int i = rg + 16 * s2;
+      rv[s2] = 0.0;
+      qv[s2] = 0.0;
+      if (MODE == kQ && i < rows) {
+        rv[s2] = wsr[C.r0 + i0 + i];
+        if (upd) qv[s2] = wsq[C.r0 + i0 + i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < RPC; ++s2) {
+      const int i = rg + 16 * s2;
+      const bool live = i < rows;
+      const double* pw = C.pt + (live ? i : 0) * 32;
+      const double fi = C.fch[live ? i : 0];
+      double mv[CPT];
+      double dsum = 0.0;
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const double mo = row_mono<VV>(pw, cs.o0[u], cs.o1[u]);
+        mv[u] = cs.num[u] ? mo : -fi * mo;
+        dsum += mv[u] * cs.tpj[u];
+      }
+      dsum = group_sum<16>(live ? dsum : 0.0);
+      if (live) {
+        const int64_t row = C.r0 + i0 + i;
+        double r, q = dsum;
+        if (MODE == kR0) {
+          r = fi - dsum;
+          if (sub == 0) wsr[row] = r;
+        } else {
+          r = rv[s2];
+          if (upd) {
+            r -= alpha_prev * qv[s2];
+            if (sub == 0) wsr[row] = r;
+          }
+          if (sub == 0) {
+            wsq[row] = q;
+            qq += q * q;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+          accr[u] += mv[u] * r;
+          if (MODE == kQ) accq[u] += mv[u] * q;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  col_reduce<NM>(C, accr, C.g);
+  if (MODE == kQ) {
+    col_reduce<NM>(C, accq, C.gq);
+    return block_sum(qq, C.red);
+  }
+  return 0.0;
+}
+
+// final_pass in the row-parallel form.
+template <int NM, int VV>
+__device__ __forceinline__ double final_rows(const FitArgs& a, const FitCtx& C, uint64_t sc, int* qneg_out) {
+  constexpr int CH = Chunk<NM>::CH;
+  constexpr int CPT = NM / 16;
+  constexpr int RPC = CH / 16;
+  const int sub = threadIdx.x & 15, rg = threadIdx.x >> 4;
+  RowCols<NM> cs;
+  cs.load(C, sub);
+  double acc = 0.0;
+  int qneg = 0;
+  RowLoad rl;
+  load_rows(a, C, 0, chunk_rows(C, 0, CH), rl);
+  for (int i0 = 0; i0 < C.m; i0 += CH) {
+    const int rows = chunk_rows(C, i0, CH);
+    put_rows(C, sc, rows, rl);
+    if (i0 + CH < C.m) load_rows(a, C, i0 + CH, chunk_rows(C, i0 + CH, CH), rl);
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < RPC; ++s2) {
+      const int i = rg + 16 * s2;
+      const bool live = i < rows;
+      const double* pw = C.pt + (live ? i : 0) * 32;
+      const double fi = C.fch[live ? i : 0];
+      double dsum = 0.0, qs = 0.0;
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const double mo = row_mono<VV>(pw, cs.o0[u], cs.o1[u]);
+        const double av = cs.num[u] ? mo : -fi * mo;
+        dsum += av * cs.tpj[u];
+        if (!cs.num[u]) qs += cs.tpj[u] * mo;
+      }
+      dsum = group_sum<16>(live ? dsum : 0.0);
+      qs = group_sum<16>(live ? qs : 0.0);
+      if (live && sub == 0) {
+        const double res = fi - dsum;
+        acc += res * res;
+        const double qv = 1.0 + qs;
+        if (!(qv > 0.0)) ++qneg;
+      }
+    }
+    __syncthreads();
+  }
+  const double qn = block_sum((double)qneg, C.red);
+  *qneg_out = (int)qn;
+  return block_sum(acc, C.red);
+}
+
+// Pass selection: the row-parallel form when every exponent is <= 3, else the chunked one.
+template <int NM, int MODE>
+__device__ __forceinline__ double cg_sweep(const FitArgs& a, const FitCtx& C, uint64_t sc, double* wsr, double* wsq,
+                                           bool upd, double alpha_prev) {
+  if (C.pow3) return C.v <= 4 ? cg_rows<NM, MODE, 4>(a, C, sc, wsr, wsq, upd, alpha_prev)
+                              : cg_rows<NM, MODE, 8>(a, C, sc, wsr, wsq, upd, alpha_prev);
+  return cg_pass<NM, MODE>(a, C, sc, wsr, wsq, upd, alpha_prev);
+}
+
+template <int NM>
+__device__ __forceinline__ double final_sweep(const FitArgs& a, const FitCtx& C, uint64_t sc, int* qneg_out) {
+  if (C.pow3) return C.v <= 4 ? final_rows<NM, 4>(a, C, sc, qneg_out) : final_rows<NM, 8>(a, C, sc, qneg_out);
+  return final_pass<NM>(a, C, sc, qneg_out);
+}
+
 // Equilibrate, shift and factor S.  Returns the numerical rank.  The factor is kept in pivot
 // order: at step k the rows and columns k and bi are swapped in place (the computed part of L
 // and the Schur complement alike), so element (i, j) of L is at rbase(i) + j and perm maps a
@@ -550,11 +788,25 @@ __device__ __forceinline__ int factor(const FitCtx& C, double unit) {
     C.perm[tid] = tid;
   }
   __syncthreads();
-  if (tid < n) {                       // row tid of the lower triangle
-    const double dj = C.D[tid];
-    const int rb = rbase(tid);
-    for (int k = 0; k <= tid; ++k) C.S[rb + k] *= dj * C.D[k];
-    C.c[tid] *= dj;
+  {                                    // rows over a 16 x 16 thread grid, loads before stores
+    const int ty = tid >> 4, tx = tid & 15;
+    for (int i = ty; i < n; i += 16) {
+      const int rb = rbase(i);
+      const double di = C.D[i];
+      double sv[8], dv[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int j = tx + 16 * b, jj = j <= i ? j : 0;
+        sv[b] = C.S[rb + jj];
+        dv[b] = C.D[jj];
+      }
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int j = tx + 16 * b;
+        if (j <= i) C.S[rb + j] = sv[b] * (di * dv[b]);
+      }
+    }
+    if (tid < n) C.c[tid] *= C.D[tid];
   }
   __syncthreads();
   if (tid < 64) {
@@ -643,13 +895,27 @@ __device__ __forceinline__ int factor(const FitCtx& C, double unit) {
       const int j = k + 1 + tx + 16 * b;
       lj[b] = j < n ? C.S[rbase(j) + k] : 0.0;
     }
-    for (int i = k + 1 + ty; i < n; i += 16) {
-      const int rb = rbase(i);
+    // two rows i, i + 16 at a time, every load issued before the stores (the elements are
+    // distinct, so the update is the same element by element; an out-of-triangle slot loads
+    // (i, k) instead and is not stored)
+    for (int i = k + 1 + ty; i < n; i += 32) {
+      const int i2 = i + 16;
+      const bool two = i2 < n;
+      const int rb = rbase(i), rb2 = two ? rbase(i2) : rb;
       const double lik = C.S[rb + k] * rinv;
+      const double lik2 = C.S[rb2 + k] * rinv;
+      double s1[8], s2[8];
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
         const int j = k + 1 + tx + 16 * b;
-        if (j <= i) C.S[rb + j] -= lik * lj[b];
+        s1[b] = C.S[rb + (j <= i ? j : k)];
+        s2[b] = C.S[rb2 + (j <= i2 ? j : k)];
+      }
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int j = k + 1 + tx + 16 * b;
+        if (j <= i) C.S[rb + j] = s1[b] - lik * lj[b];
+        if (two && j <= i2) C.S[rb2 + j] = s2[b] - lik2 * lj[b];
       }
     }
     lprev = lkk;
@@ -763,7 +1029,7 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, int fi, double* smem) 
     __syncthreads();
     if (tid < n) C.tp[tid] = C.D[tid] * C.z[tid];
     __syncthreads();
-    cg_pass<NM, kR0>(a, C, sc, wsr, wsq, false, 0.0);
+    cg_sweep<NM, kR0>(a, C, sc, wsr, wsq, false, 0.0);
     if (tid < n) C.g[tid] *= C.D[tid];
     __syncthreads();
     if (tid < 64) solve_fwd(C, C.g, C.s);
@@ -786,7 +1052,7 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, int fi, double* smem) 
       __syncthreads();
       if (tid < n) C.tp[tid] = C.D[tid] * C.t[tid];
       __syncthreads();
-      const double qq = cg_pass<NM, kQ>(a, C, sc, wsr, wsq, it > 0, alpha_prev);
+      const double qq = cg_sweep<NM, kQ>(a, C, sc, wsr, wsq, it > 0, alpha_prev);
       const double alpha = qq > 0.0 ? gamma / qq : 0.0;
       if (tid < n) C.z[tid] += alpha * C.t[tid];
       __syncthreads();
@@ -833,7 +1099,7 @@ __device__ __forceinline__ void fit_one(const FitArgs& a, int fi, double* smem) 
   if (tid < n) C.tp[tid] = C.D[tid] * C.z[tid];
   __syncthreads();
   int qneg = 0;
-  const double rr = final_pass<NM>(a, C, sc, &qneg);
+  const double rr = final_sweep<NM>(a, C, sc, &qneg);
   if (tid < n) a.coef[d.coef0 + tid] = C.tp[tid];
   if (tid == 0) {
     if (rank < n) info.status |= KLR_FIT_RANK_DEFICIENT;
