@@ -1258,49 +1258,78 @@ fit_persistent2(FitArgs a, Plan* pl, const int32_t* __restrict__ order, int cls)
 
 // Exclusive prefix of the sample counts of the fits that take a workgroup class (the one-
 // wavefront classes keep their residuals in registers): each such fit owns scratch rows
-// [rowoff[fi], rowoff[fi] + m).  One workgroup scans the batch in chunks of 1024 fits.
+// [rowoff[fi], rowoff[fi] + m).  Three launches: every workgroup of kScanBlock fits writes the
+// exclusive prefix within its block and the block total; one workgroup scans the totals; every
+// workgroup adds the total of the blocks before its own.  A block total is at most
+// kScanBlock * KLR_MAX_SAMPLES = 2^22, so the in-block sums stay in int32.
 constexpr int kScanBlock = 1024;
-__global__ void __launch_bounds__(kScanBlock) fit_rows_offsets(FitArgs a, int64_t* rowoff) {
-  __shared__ int32_t wsum[kScanBlock / 64];
-  __shared__ int64_t carry;
+
+__device__ __forceinline__ int32_t scratch_need(const FitArgs& a, int fi) {
+  if (fi >= a.n_fits) return 0;
+  const klr_fit_desc d = a.desc[fi];
+  const int cls = fit_class(a, d);
+  if (cls == kWaveClass || cls == kWaveClass16) return 0;
+  return d.m < 0 ? 0 : (d.m > KLR_MAX_SAMPLES ? KLR_MAX_SAMPLES : d.m);
+}
+
+// Exclusive scan of v over the workgroup (kScanBlock threads); *total gets the sum.
+template <typename T>
+__device__ __forceinline__ T block_exclusive(T v, T* wsum, T* total) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < a.n_fits; base += kScanBlock) {
-    const int fi = base + tid;
-    int32_t need = 0;
-    if (fi < a.n_fits) {
-      const klr_fit_desc d = a.desc[fi];
-      const int cls = fit_class(a, d);
-      if (cls != kWaveClass && cls != kWaveClass16)
-        need = d.m < 0 ? 0 : (d.m > KLR_MAX_SAMPLES ? KLR_MAX_SAMPLES : d.m);
-    }
-    int32_t inc = need;                        // inclusive scan within the wavefront
+  T inc = v;                                   // inclusive scan within the wavefront
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int32_t o = __shfl_up(inc, off);
-      if (lane >= off) inc += o;
-    }
-    if (lane == 63) wsum[wv] = inc;
-    __syncthreads();
-    int64_t before = carry;
-    for (int w = 0; w < wv; ++w) before += wsum[w];
-    if (fi < a.n_fits) rowoff[fi] = before + (inc - need);
-    __syncthreads();
-    if (tid == 0) {
-      int64_t t = carry;
-      for (int w = 0; w < kScanBlock / 64; ++w) t += wsum[w];
-      carry = t;
-    }
-    __syncthreads();
+  for (int off = 1; off < 64; off <<= 1) {
+    const T o = __shfl_up(inc, off);
+    if (lane >= off) inc += o;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  T before = 0;
+  for (int w = 0; w < wv; ++w) before += wsum[w];
+  T t = 0;
+  for (int w = 0; w < kScanBlock / 64; ++w) t += wsum[w];
+  *total = t;
+  __syncthreads();
+  return before + (inc - v);
+}
+
+__global__ void __launch_bounds__(kScanBlock) fit_rows_local(FitArgs a, int64_t* rowoff, int64_t* bsum) {
+  __shared__ int32_t wsum[kScanBlock / 64];
+  const int fi = blockIdx.x * kScanBlock + (int)threadIdx.x;
+  int32_t total;
+  const int32_t ex = block_exclusive<int32_t>(scratch_need(a, fi), wsum, &total);
+  if (fi < a.n_fits) rowoff[fi] = ex;
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanBlock) fit_rows_scan(int64_t* bsum, int nblk) {
+  __shared__ int64_t wsum[kScanBlock / 64];
+  int64_t carry = 0;
+  for (int b0 = 0; b0 < nblk; b0 += kScanBlock) {
+    const int b = b0 + (int)threadIdx.x;
+    int64_t total;
+    const int64_t ex = block_exclusive<int64_t>(b < nblk ? bsum[b] : 0, wsum, &total);
+    if (b < nblk) bsum[b] = carry + ex;
+    carry += total;
   }
 }
 
+__global__ void __launch_bounds__(kScanBlock) fit_rows_add(FitArgs a, int64_t* rowoff, const int64_t* bsum) {
+  const int fi = blockIdx.x * kScanBlock + (int)threadIdx.x;
+  if (fi < a.n_fits) rowoff[fi] += bsum[blockIdx.x];
+}
+
+__host__ __device__ inline int scan_blocks(int32_t n_fits) {
+  return n_fits > 0 ? (n_fits + kScanBlock - 1) / kScanBlock : 0;
+}
+
 // Workspace: the plan, the longest-first order and bucket keys (int32 per fit), the scratch
-// offsets (int64 per fit), then two FP64 scratch values per sample row (residual and A t).
+// offsets (int64 per fit) and the scan's block totals (int64 per kScanBlock fits), then two
+// FP64 scratch values per sample row (residual and A t).
 size_t head_bytes(int32_t n_fits) {
   const size_t nf = (size_t)(n_fits > 0 ? n_fits : 0);
-  return (sizeof(Plan) + nf * 2 * sizeof(int32_t) + nf * sizeof(int64_t) + 255) / 256 * 256;
+  return (sizeof(Plan) + nf * 2 * sizeof(int32_t) + (nf + (size_t)scan_blocks(n_fits)) * sizeof(int64_t) + 255) /
+         256 * 256;
 }
 
 // Two workgroups per CU when the dynamic LDS of a class leaves room for a second one (160 KB
@@ -1348,7 +1377,13 @@ hipError_t launch_all(const FitArgs& a, bool persistent) {
   Plan* pl = reinterpret_cast<Plan*>(a.ws);
   int32_t* order = reinterpret_cast<int32_t*>(pl + 1);
   int32_t* keys = order + (a.n_fits > 0 ? a.n_fits : 0);
-  hipLaunchKernelGGL(fit_rows_offsets, dim3(1), dim3(kScanBlock), 0, a.stream, a, a.rowoff);
+  const int nblk = scan_blocks(a.n_fits);
+  int64_t* bsum = a.rowoff + (a.n_fits > 0 ? a.n_fits : 0);
+  if (nblk > 0) {
+    hipLaunchKernelGGL(fit_rows_local, dim3((unsigned)nblk), dim3(kScanBlock), 0, a.stream, a, a.rowoff, bsum);
+    hipLaunchKernelGGL(fit_rows_scan, dim3(1), dim3(kScanBlock), 0, a.stream, bsum, nblk);
+    hipLaunchKernelGGL(fit_rows_add, dim3((unsigned)nblk), dim3(kScanBlock), 0, a.stream, a, a.rowoff, bsum);
+  }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && persistent) {
     const unsigned g = (unsigned)((a.n_fits + kFitBlock - 1) / kFitBlock);
