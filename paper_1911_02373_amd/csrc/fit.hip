@@ -833,7 +833,7 @@ __device__ __forceinline__ int factor(const FitCtx& C, double unit) {
       for (int i = k + tid; i < n; i += 64) {
         const double vv = C.S[rbase(i) + i];
         const double key = vv == vv ? vv : -INFINITY;
-        if (key > best || (key == best && i < bi)) { best = key; bi = i; }
+        argmax_take(best, bi, key, i);
       }
       wave_argmax(best, bi);
       if (tid == 0) {

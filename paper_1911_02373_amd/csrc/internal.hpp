@@ -244,7 +244,9 @@ __device__ __forceinline__ float pair_sum32_f(float v) {
 // Largest key over the 64 lanes, lowest index among equal keys (keys are never NaN); every
 // lane receives the same (key, index).  All lanes active.
 __device__ __forceinline__ void argmax_take(double& best, int& bi, double ob, int oi) {
-  if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  const bool take = (ob > best) | ((ob == best) & (oi < bi));   // selects, no branch
+  best = take ? ob : best;
+  bi = take ? oi : bi;
 }
 template <int CTRL>
 __device__ __forceinline__ void argmax_dpp(double& best, int& bi) {
