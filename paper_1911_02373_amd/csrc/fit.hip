@@ -588,6 +588,19 @@ __device__ __forceinline__ double row_mono(const double* pw, uint32_t o0, uint32
   return ((p[0] * p[1]) * (p[2] * p[3])) * ((p[4] * p[5]) * (p[6] * p[7]));
 }
 
+// The row-parallel passes stage kRowChunk rows at a time in the LDS span of the Gram pass's
+// chunk of A and its power table (free outside the Gram pass): tables from the start of the
+// span, targets after them.
+constexpr int kRowChunk = 64;
+template <int NM>
+__device__ __forceinline__ FitCtx row_staging(const FitCtx& C) {
+  static_assert((Lds<NM>::PT - Lds<NM>::A) + Lds<NM>::CH * 32 >= kRowChunk * 33, "row staging span");
+  FitCtx W = C;
+  W.pt = C.A;
+  W.fch = C.A + kRowChunk * 32;
+  return W;
+}
+
 // Per-thread column set of the row-parallel passes.
 template <int NM>
 struct RowCols {
@@ -632,11 +645,12 @@ __device__ __forceinline__ void col_reduce(const FitCtx& C, const double* acc, d
 template <int NM, int MODE, int VV>
 __device__ __forceinline__ double cg_rows(const FitArgs& a, const FitCtx& C, uint64_t sc, double* wsr, double* wsq,
                                           bool upd, double alpha_prev) {
-  constexpr int CH = Chunk<NM>::CH;
+  constexpr int CH = kRowChunk;
   constexpr int CPT = NM / 16;
   constexpr int RPC = CH / 16;                      // rows per thread and chunk
   static_assert(CH % 16 == 0 && NM % 16 == 0, "row groups");
   const int sub = threadIdx.x & 15, rg = threadIdx.x >> 4;
+  const FitCtx W = row_staging<NM>(C);
   RowCols<NM> cs;
   cs.load(C, sub);
   double accr[CPT], accq[CPT];
@@ -647,7 +661,7 @@ __device__ __forceinline__ double cg_rows(const FitArgs& a, const FitCtx& C, uin
   load_rows(a, C, 0, chunk_rows(C, 0, CH), rl);
   for (int i0 = 0; i0 < C.m; i0 += CH) {
     const int rows = chunk_rows(C, i0, CH);
-    put_rows(C, sc, rows, rl);
+    put_rows(W, sc, rows, rl);
     if (i0 + CH < C.m) load_rows(a, C, i0 + CH, chunk_rows(C, i0 + CH, CH), rl);
     double rv[RPC], qv[RPC];
 #pragma unroll
@@ -665,8 +679,8 @@ __device__ __forceinline__ double cg_rows(const FitArgs& a, const FitCtx& C, uin
     for (int s2 = 0; s2 < RPC; ++s2) {
       const int i = rg + 16 * s2;
       const bool live = i < rows;
-      const double* pw = C.pt + (live ? i : 0) * 32;
-      const double fi = C.fch[live ? i : 0];
+      const double* pw = W.pt + (live ? i : 0) * 32;
+      const double fi = W.fch[live ? i : 0];
       double mv[CPT];
       double dsum = 0.0;
 #pragma unroll
@@ -713,10 +727,11 @@ __device__ __forceinline__ double cg_rows(const FitArgs& a, const FitCtx& C, uin
 // final_pass in the row-parallel form.
 template <int NM, int VV>
 __device__ __forceinline__ double final_rows(const FitArgs& a, const FitCtx& C, uint64_t sc, int* qneg_out) {
-  constexpr int CH = Chunk<NM>::CH;
+  constexpr int CH = kRowChunk;
   constexpr int CPT = NM / 16;
   constexpr int RPC = CH / 16;
   const int sub = threadIdx.x & 15, rg = threadIdx.x >> 4;
+  const FitCtx W = row_staging<NM>(C);
   RowCols<NM> cs;
   cs.load(C, sub);
   double acc = 0.0;
@@ -725,15 +740,15 @@ __device__ __forceinline__ double final_rows(const FitArgs& a, const FitCtx& C, 
   load_rows(a, C, 0, chunk_rows(C, 0, CH), rl);
   for (int i0 = 0; i0 < C.m; i0 += CH) {
     const int rows = chunk_rows(C, i0, CH);
-    put_rows(C, sc, rows, rl);
+    put_rows(W, sc, rows, rl);
     if (i0 + CH < C.m) load_rows(a, C, i0 + CH, chunk_rows(C, i0 + CH, CH), rl);
     __syncthreads();
 #pragma unroll
     for (int s2 = 0; s2 < RPC; ++s2) {
       const int i = rg + 16 * s2;
       const bool live = i < rows;
-      const double* pw = C.pt + (live ? i : 0) * 32;
-      const double fi = C.fch[live ? i : 0];
+      const double* pw = W.pt + (live ? i : 0) * 32;
+      const double fi = W.fch[live ? i : 0];
       double dsum = 0.0, qs = 0.0;
 #pragma unroll
       for (int u = 0; u < CPT; ++u) {
