@@ -1394,8 +1394,9 @@ hipError_t launch_all(const FitArgs& a, bool persistent) {
   int32_t* keys = order + (a.n_fits > 0 ? a.n_fits : 0);
   const int nblk = scan_blocks(a.n_fits);
   int64_t* bsum = a.rowoff + (a.n_fits > 0 ? a.n_fits : 0);
-  if (nblk > 0) {
+  if (nblk > 0)       // one block: its in-block prefix is the whole prefix
     hipLaunchKernelGGL(fit_rows_local, dim3((unsigned)nblk), dim3(kScanBlock), 0, a.stream, a, a.rowoff, bsum);
+  if (nblk > 1) {
     hipLaunchKernelGGL(fit_rows_scan, dim3(1), dim3(kScanBlock), 0, a.stream, bsum, nblk);
     hipLaunchKernelGGL(fit_rows_add, dim3((unsigned)nblk), dim3(kScanBlock), 0, a.stream, a, a.rowoff, bsum);
   }
