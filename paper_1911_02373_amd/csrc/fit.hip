@@ -11,9 +11,11 @@
 // one wavefront go to fit_wave.hip.  Persistent workgroups pop fits of their class from a
 // longest-first order; the plain schedule launches one workgroup per fit, and workgroups whose
 // fit belongs to another class leave at once.  Per fit:
-//   1. the design matrix is built in LDS in chunks of CH rows from the staged samples
-//      (x~ = x 2^-s exact in FP64; A_ij = x~^e_j, or -f_i x~^e_j for denominator columns), the
-//      next chunk's samples being loaded into registers meanwhile;
+//   1. the samples are staged in chunks of rows as a table of x~_k^p (x~ = x 2^-s exact in
+//      FP64; A_ij = x~^e_j, or -f_i x~^e_j for denominator columns), the next chunk's samples
+//      being loaded into registers meanwhile; the Gram pass builds each chunk of A in LDS, the
+//      refinement and final passes form their elements from the table, sixteen threads per row
+//      (column sums in registers until the end of the pass) when every exponent is <= 3;
 //   2. Gram G = A^T A on MFMA (16-column tiles dealt to the waves as lower tile pairs; FP64, or
 //      FP32 / BF16-rounded inputs with FP32 accumulation) and c = A^T f in FP64;
 //   3. power-of-two column equilibration (exact), diagonal shift mu = 8 u tr/n;
