@@ -834,108 +834,134 @@ __device__ __forceinline__ int factor(const FitCtx& C, double unit) {
   }
   __syncthreads();
   const double mu = C.red[kFitBlock - 1];
-  if (tid < n) C.S[rbase(tid) + tid] += mu;
+  // the diagonal of the Schur complement, kept apart from S (C.t is free during the
+  // factorization) and updated column by column
+  double* const dg = C.t;
+  if (tid < n) {
+    const double dv = C.S[rbase(tid) + tid] + mu;
+    C.S[rbase(tid) + tid] = dv;
+    dg[tid] = dv;
+  }
   __syncthreads();
-  // Step k: (A) wave 0 picks the pivot while waves 1-3 divide column k-1 by its pivot's root;
-  // (B) symmetric swap; (C) trailing update from the unscaled column k, rows and columns dealt
-  // cyclically over a 16 x 16 thread grid so every thread has the same share of the triangle.
-  double lprev = 1.0;                  // root of the previous pivot
+  // Blocked, left-looking: panels of kPanel columns.  Step k of a panel: (A) wave 0 picks the
+  // largest remaining diagonal; (B) symmetric swap of positions k and bi (the computed part of
+  // L and the not yet updated trailing part alike, so L(i, j) sits at rbase(i) + j in pivot
+  // order); (C) column k of L: S(i, k) less the products of the panel's earlier columns, over
+  // L(k, k), one thread per row, and the diagonal loses its square.  After the panel the
+  // trailing triangle takes the panel's rank-kPanel product in one pass (16 x 16 thread grid).
+  constexpr int kPanel = 16;
   const int ty = tid >> 4, tx = tid & 15;
-  for (int k = 0; k < n; ++k) {
-    if (tid < 64) {
-      // largest remaining diagonal, lowest index on ties; NaN ranks below every number, so the
-      // pick is always one of the remaining positions k..n-1
-      double best = -INFINITY;
-      int bi = n;
-      for (int i = k + tid; i < n; i += 64) {
-        const double vv = C.S[rbase(i) + i];
-        const double key = vv == vv ? vv : -INFINITY;
-        argmax_take(best, bi, key, i);
-      }
-      wave_argmax(best, bi);
-      if (tid == 0) {
-        C.red[kFitBlock - 3] = best;
-        C.flags[2] = bi;
-      }
-    } else if (k > 0) {
-      const int i = k + tid - 64;      // rows k.. of column k-1
-      if (i < n) C.S[rbase(i) + k - 1] /= lprev;
-    }
-    __syncthreads();
-    const double best = C.red[kFitBlock - 3];
-    const int bi = C.flags[2];
-    if (!(best > 4.0 * mu)) {
-      // numerical rank reached: every remaining diagonal is at most 4 mu, i.e. the remaining
-      // Schur complement is rounding noise; the rest of the factor becomes sqrt(mu) I (the
-      // shift alone), so the noise is never divided by a tiny pivot
-      const double smu = sqrt(mu);
-      const int i = k + tid;
-      if (i < n) {
-        const int rb = rbase(i);
-        C.piv[i] = C.S[rb + i];
-        for (int j = k; j < i; ++j) C.S[rb + j] = 0.0;
-        C.S[rb + i] = smu;
+  bool stopped = false;
+  for (int k0 = 0; k0 < n && !stopped; k0 += kPanel) {
+    const int kend = k0 + kPanel < n ? k0 + kPanel : n;
+    for (int k = k0; k < kend; ++k) {
+      if (tid < 64) {
+        // largest remaining diagonal, lowest index on ties; NaN ranks below every number, so
+        // the pick is always one of the remaining positions k..n-1
+        double best = -INFINITY;
+        int bi = n;
+        for (int i = k + tid; i < n; i += 64) {
+          const double vv = dg[i];
+          const double key = vv == vv ? vv : -INFINITY;
+          argmax_take(best, bi, key, i);
+        }
+        wave_argmax(best, bi);
+        if (tid == 0) {
+          C.red[kFitBlock - 3] = best;
+          C.flags[2] = bi;
+        }
       }
       __syncthreads();
-      break;
-    }
-    if (bi != k) {                     // symmetric swap of positions k < bi
-      const int ba = rbase(k), bb = rbase(bi);
-      const int i = tid;
-      int p0 = -1, p1 = -1;
-      if (i < k) { p0 = ba + i; p1 = bb + i; }
-      else if (i == k) { p0 = ba + k; p1 = bb + bi; }
-      else if (i < bi) { p0 = rbase(i) + k; p1 = bb + i; }
-      else if (i > bi && i < n) { p0 = rbase(i) + k; p1 = rbase(i) + bi; }
-      if (p0 >= 0) {
-        const double t0 = C.S[p0], t1 = C.S[p1];
-        C.S[p0] = t1;
-        C.S[p1] = t0;
+      const double best = C.red[kFitBlock - 3];
+      const int bi = C.flags[2];
+      if (!(best > 4.0 * mu)) {
+        // numerical rank reached: every remaining diagonal is at most 4 mu, i.e. the remaining
+        // Schur complement is rounding noise; the rest of the factor becomes sqrt(mu) I (the
+        // shift alone), so the noise is never divided by a tiny pivot
+        const double smu = sqrt(mu);
+        const int i = k + tid;
+        if (i < n) {
+          const int rb = rbase(i);
+          C.piv[i] = dg[i];
+          for (int j = k; j < i; ++j) C.S[rb + j] = 0.0;
+          C.S[rb + i] = smu;
+        }
+        __syncthreads();
+        stopped = true;
+        break;
       }
-      if (tid == 0) {
-        const int t = C.perm[k];
-        C.perm[k] = C.perm[bi];
-        C.perm[bi] = t;
+      if (bi != k) {                   // symmetric swap of positions k < bi
+        const int ba = rbase(k), bb = rbase(bi);
+        const int i = tid;
+        int p0 = -1, p1 = -1;
+        if (i < k) { p0 = ba + i; p1 = bb + i; }
+        else if (i == k) { p0 = ba + k; p1 = bb + bi; }
+        else if (i < bi) { p0 = rbase(i) + k; p1 = bb + i; }
+        else if (i > bi && i < n) { p0 = rbase(i) + k; p1 = rbase(i) + bi; }
+        if (p0 >= 0) {
+          const double t0 = C.S[p0], t1 = C.S[p1];
+          C.S[p0] = t1;
+          C.S[p1] = t0;
+        }
+        if (tid == 0) {
+          const int t = C.perm[k];
+          C.perm[k] = C.perm[bi];
+          C.perm[bi] = t;
+          const double d = dg[k];
+          dg[k] = dg[bi];
+          dg[bi] = d;
+        }
+        __syncthreads();
+      }
+      const double lkk = sqrt(best);
+      if (tid == 0) {                  // nothing reads (k, k) in this step
+        C.piv[k] = best;
+        C.S[rbase(k) + k] = lkk;
+      }
+      {
+        const int i = k + 1 + tid;     // rows k+1.. (n <= 128)
+        if (i < n) {
+          const int rb = rbase(i), rk = rbase(k);
+          double lv[kPanel - 1], kv[kPanel - 1];
+#pragma unroll
+          for (int p = 0; p < kPanel - 1; ++p) {
+            const bool in = k0 + p < k;
+            lv[p] = in ? C.S[rb + k0 + p] : 0.0;
+            kv[p] = in ? C.S[rk + k0 + p] : 0.0;
+          }
+          double acc = C.S[rb + k];
+#pragma unroll
+          for (int p = 0; p < kPanel - 1; ++p)
+            if (k0 + p < k) acc -= lv[p] * kv[p];
+          const double l = acc / lkk;
+          C.S[rb + k] = l;
+          dg[i] -= l * l;
+        }
       }
       __syncthreads();
     }
-    const double lkk = sqrt(best);
-    const double rinv = 1.0 / best;
-    if (tid == 0) {                    // nothing reads (k, k) during the update
-      C.piv[k] = best;
-      C.S[rbase(k) + k] = lkk;
-    }
-    // S(i, j) -= S(i, k) S(j, k) / best for k < j <= i (n <= 128: at most 8 columns per thread)
-    double lj[8];
+    if (stopped || kend >= n) continue;
+    // trailing update: S(i, j) -= sum over the panel of L(i, p) L(j, p), kend <= j <= i
+    for (int i = kend + ty; i < n; i += 16) {
+      const int rb = rbase(i);
+      double li[kPanel];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int j = k + 1 + tx + 16 * b;
-      lj[b] = j < n ? C.S[rbase(j) + k] : 0.0;
-    }
-    // two rows i, i + 16 at a time, every load issued before the stores (the elements are
-    // distinct, so the update is the same element by element; an out-of-triangle slot loads
-    // (i, k) instead and is not stored)
-    for (int i = k + 1 + ty; i < n; i += 32) {
-      const int i2 = i + 16;
-      const bool two = i2 < n;
-      const int rb = rbase(i), rb2 = two ? rbase(i2) : rb;
-      const double lik = C.S[rb + k] * rinv;
-      const double lik2 = C.S[rb2 + k] * rinv;
-      double s1[8], s2[8];
+      for (int p = 0; p < kPanel; ++p) li[p] = k0 + p < kend ? C.S[rb + k0 + p] : 0.0;
+#pragma unroll 2
+      for (int c = 0; c < 8; ++c) {
+        const int j = kend + tx + 16 * c;
+        if (j <= i) {
+          const int rj = rbase(j);
+          double lj[kPanel];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const int j = k + 1 + tx + 16 * b;
-        s1[b] = C.S[rb + (j <= i ? j : k)];
-        s2[b] = C.S[rb2 + (j <= i2 ? j : k)];
-      }
+          for (int p = 0; p < kPanel; ++p) lj[p] = k0 + p < kend ? C.S[rj + k0 + p] : 0.0;
+          double acc = C.S[rb + j];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const int j = k + 1 + tx + 16 * b;
-        if (j <= i) C.S[rb + j] = s1[b] - lik * lj[b];
-        if (two && j <= i2) C.S[rb2 + j] = s2[b] - lik2 * lj[b];
+          for (int p = 0; p < kPanel; ++p) acc -= li[p] * lj[p];
+          C.S[rb + j] = acc;
+        }
       }
     }
-    lprev = lkk;
     __syncthreads();
   }
   int rank = 0;
