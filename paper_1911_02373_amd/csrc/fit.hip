@@ -843,8 +843,8 @@ __device__ __forceinline__ int factor(const FitCtx& C, double unit) {
     dg[tid] = dv;
   }
   __syncthreads();
-  // Blocked, left-looking: panels of kPanel columns.  Step k of a panel: (A) wave 0 picks the
-  // largest remaining diagonal; (B) symmetric swap of positions k and bi (the computed part of
+  // Blocked, left-looking: panels of kPanel columns.  Step k of a panel: (A) every wave picks
+  // the largest remaining diagonal; (B) symmetric swap of positions k and bi (the computed part of
   // L and the not yet updated trailing part alike, so L(i, j) sits at rbase(i) + j in pivot
   // order); (C) column k of L: S(i, k) less the products of the panel's earlier columns, over
   // L(k, k), one thread per row, and the diagonal loses its square.  After the panel the
@@ -855,25 +855,18 @@ __device__ __forceinline__ int factor(const FitCtx& C, double unit) {
   for (int k0 = 0; k0 < n && !stopped; k0 += kPanel) {
     const int kend = k0 + kPanel < n ? k0 + kPanel : n;
     for (int k = k0; k < kend; ++k) {
-      if (tid < 64) {
-        // largest remaining diagonal, lowest index on ties; NaN ranks below every number, so
-        // the pick is always one of the remaining positions k..n-1
-        double best = -INFINITY;
-        int bi = n;
-        for (int i = k + tid; i < n; i += 64) {
-          const double vv = dg[i];
-          const double key = vv == vv ? vv : -INFINITY;
-          argmax_take(best, bi, key, i);
-        }
-        wave_argmax(best, bi);
-        if (tid == 0) {
-          C.red[kFitBlock - 3] = best;
-          C.flags[2] = bi;
-        }
+      // every wave picks the pivot itself (the same pick in each: dg is written only in phase
+      // (C), behind a barrier): the largest remaining diagonal, lowest index on ties; NaN
+      // ranks below every number, so the pick is always one of the remaining positions k..n-1
+      double best = -INFINITY;
+      int bi = n;
+      for (int i = k + (tid & 63); i < n; i += 64) {
+        const double vv = dg[i];
+        const double key = vv == vv ? vv : -INFINITY;
+        argmax_take(best, bi, key, i);
       }
-      __syncthreads();
-      const double best = C.red[kFitBlock - 3];
-      const int bi = C.flags[2];
+      wave_argmax(best, bi);
+      bi = __builtin_amdgcn_readfirstlane(bi);
       if (!(best > 4.0 * mu)) {
         // numerical rank reached: every remaining diagonal is at most 4 mu, i.e. the remaining
         // Schur complement is rounding noise; the rest of the factor becomes sqrt(mu) I (the
@@ -907,12 +900,9 @@ __device__ __forceinline__ int factor(const FitCtx& C, double unit) {
           const int t = C.perm[k];
           C.perm[k] = C.perm[bi];
           C.perm[bi] = t;
-          const double d = dg[k];
-          dg[k] = dg[bi];
-          dg[bi] = d;
         }
-        __syncthreads();
       }
+      __syncthreads();
       const double lkk = sqrt(best);
       if (tid == 0) {                  // nothing reads (k, k) in this step
         C.piv[k] = best;
@@ -935,7 +925,7 @@ __device__ __forceinline__ int factor(const FitCtx& C, double unit) {
             if (k0 + p < k) acc -= lv[p] * kv[p];
           const double l = acc / lkk;
           C.S[rb + k] = l;
-          dg[i] -= l * l;
+          dg[i] = (i == bi ? dg[k] : dg[i]) - l * l;   // position bi now holds old position k
         }
       }
       __syncthreads();
