@@ -171,7 +171,7 @@ __device__ __forceinline__ double monomial(const FitCtx& C, int i, int j) {
 
 // Design-matrix chunk: A[i][j] for j < n, zero up to the 4-padded width.  Each thread owns one
 // column (its exponents are read once) and the rows i = g, g + G, ... of its row group g.
-template <int NM>
+template <int NM, int CHR = Chunk<NM>::CH>
 __device__ __forceinline__ void build_chunk(const FitCtx& C, int rows) {
   constexpr int G = kFitBlock / NM;
   const int j = threadIdx.x % NM, g = threadIdx.x / NM;
@@ -187,7 +187,7 @@ __device__ __forceinline__ void build_chunk(const FitCtx& C, int rows) {
     int off[KLR_MAX_VARS];
 #pragma unroll
     for (int k = 0; k < KLR_MAX_VARS; ++k) off[k] = k * 4 + (int)((w >> (2 * k)) & 3u);
-    constexpr int CH = Chunk<NM>::CH;
+    constexpr int CH = CHR;
     // all table loads of a row are issued before its products; full chunks skip the row guard
     auto row = [&](int i) {
       const double* pw = C.pt + i * 32;
@@ -235,6 +235,23 @@ __device__ __forceinline__ void build_chunk(const FitCtx& C, int rows) {
 // Row base of the packed lower triangle: element (i, j), j <= i, is at rbase(i) + j.
 __device__ __forceinline__ int rbase(int i) { return i * (i + 1) / 2; }
 
+// Rows per chunk of the Gram pass, which stages its chunks of A and the power table in the LDS
+// span of S (written only after the last chunk) and of the usual chunk: a multiple of 16 rows
+// whose staging fits in that span, with four rows per thread in each build step.
+template <int NM>
+struct GramChunk { static constexpr int CH = NM == 112 ? 48 : 64; };
+
+template <int NM>
+__device__ __forceinline__ FitCtx gram_staging(const FitCtx& C) {
+  constexpr int CH = GramChunk<NM>::CH;
+  static_assert(CH * (NM + 32 + 1) <= Lds<NM>::F && CH % 16 == 0, "Gram staging span");
+  FitCtx W = C;
+  W.A = C.S;                             // the span starts at S
+  W.pt = C.S + CH * NM;
+  W.fch = W.pt + CH * 32;
+  return W;
+}
+
 // Gram pass: S (packed lower, unscaled), c = A^T f and ||f||^2 (into *fnorm2).
 // GP: Gram precision.  Returns true if a target is not finite.
 // S is formed on the matrix cores: the 16-column tiles of A give nt (nt + 1) / 2 lower tile
@@ -245,7 +262,8 @@ template <int NM, int GP>
 __device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uint64_t sc, double* fnorm2) {
   using GT = GramTypes<GP>;
   using acc_t = typename GT::acc_t;
-  constexpr int CH = Chunk<NM>::CH;
+  constexpr int CH = GramChunk<NM>::CH;
+  const FitCtx Wc = gram_staging<NM>(C);
   constexpr int NT = NM / 16;                       // column tiles
   constexpr int W = kFitBlock / 64;                 // waves
   constexpr int PPW = (NT * (NT + 1) / 2 + W - 1) / W;
@@ -276,11 +294,11 @@ __device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uin
   for (int i0 = 0; i0 < C.m; i0 += CH) {
     const int rows = chunk_rows(C, i0, CH);
     const int rows4 = (rows + 3) & ~3;
-    bad |= put_rows(C, sc, rows, rl, &ff);
+    bad |= put_rows(Wc, sc, rows, rl, &ff);
     if (i0 + CH < C.m) load_rows(a, C, i0 + CH, chunk_rows(C, i0 + CH, CH), rl);
     __syncthreads();
-    build_chunk<NM>(C, rows);
-    for (int e = threadIdx.x; e < (rows4 - rows) * NM; e += kFitBlock) C.A[rows * NM + e] = 0.0;
+    build_chunk<NM, CH>(Wc, rows);
+    for (int e = threadIdx.x; e < (rows4 - rows) * NM; e += kFitBlock) Wc.A[rows * NM + e] = 0.0;
     __syncthreads();
     // blocks of 4 SUB rows: sub-step e gives reduction slot e the block's row 4 e + grp
     for (int i = 0; i < rows4; i += 4 * GT::SUB) {
@@ -290,7 +308,7 @@ __device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uin
 #pragma unroll
       for (int e = 0; e < GT::SUB; ++e) {
         if (i + 4 * e < rows4) {
-          const double* ar = C.A + (i + 4 * e + grp) * NM + col;
+          const double* ar = Wc.A + (i + 4 * e + grp) * NM + col;
 #pragma unroll
           for (int q = 0; q < PPW; ++q) {
             GT::put(xa[q], e, ar[16 * tj[q]]);
@@ -306,7 +324,7 @@ __device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uin
 #pragma unroll 4
       for (int u = 0; u < CH / TPC; ++u) {
         const int i = csub + u * TPC;
-        if (i < rows) cacc += C.A[i * NM + cj] * C.fch[i];
+        if (i < rows) cacc += Wc.A[i * NM + cj] * Wc.fch[i];
       }
     }
     __syncthreads();
