@@ -474,8 +474,11 @@ eval_kernel(const klr_program* __restrict__ progs, const float* __restrict__ coe
             const CfgRec* __restrict__ recs, const int32_t* __restrict__ queries,
             int32_t* __restrict__ argmin, float* __restrict__ best_cost,
             float* __restrict__ all_costs, EvalArgs a, Hw32 hw, int chunks) {
-  const int p = blockIdx.x / chunks;
-  const int qb = (blockIdx.x % chunks) * BLOCK * QPL;
+  // workgroup b runs on XCD b mod 8 (the dispatcher deals workgroups to the eight XCDs in
+  // turn): program p's chunks take the workgroups of XCD p mod 8, so one L2 holds its slots
+  const int xcd = (int)(blockIdx.x & 7u), j = (int)(blockIdx.x >> 3);
+  const int p = xcd + 8 * (j / chunks);
+  const int qb = (j % chunks) * BLOCK * QPL;
   if (p >= a.n_progs) return;
   const klr_program P = progs[p];
   if (!program_desc_ok(P, a) || qb >= P.n_q) return;
@@ -522,7 +525,8 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 template <int QPL, int BLOCK>
 hipError_t launch_variant(const EvalArgs& a, const Hw32& hw, const float* coefs, const CfgRec* recs) {
   const int chunks = (a.max_q + BLOCK * QPL - 1) / (BLOCK * QPL);
-  hipLaunchKernelGGL((eval_kernel<QPL, BLOCK>), dim3((unsigned)a.n_progs * chunks), dim3(BLOCK), 0, a.stream,
+  const unsigned groups = 8u * (unsigned)((a.n_progs + 7) / 8) * (unsigned)chunks;
+  hipLaunchKernelGGL((eval_kernel<QPL, BLOCK>), dim3(groups), dim3(BLOCK), 0, a.stream,
                      a.progs, coefs, recs, a.queries, a.argmin, a.best_cost, a.all_costs, a, hw, chunks);
   return hipGetLastError();
 }
