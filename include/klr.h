@@ -493,6 +493,17 @@ int64_t klr_selftest_divisors(uint32_t d_max);
  * divisor counts as one mismatch.  Returns the mismatch count. */
 int64_t klr_selftest_divisor_list(const uint64_t* ds, int32_t n_ds);
 
+/* [device, synchronous] Self-test of the short quotient the evaluation takes where the collapse
+ * encloses a metric's (or the cycle estimate's) numerator and denominator in [2^-40, 2^40]
+ * (paper: step 4, "Rational program evaluation"; the FP32 sequence is this library's): for each
+ * b mantissa in [b_first, b_first + b_count) of the 2^23 in [1, 2) and every a mantissa, the short
+ * quotient against the correctly rounded FP32 division, plus the reciprocal estimate's exact
+ * scaling with b's exponent (2^-60 .. 2^60) and sign.  Runs on the current device in slices of
+ * 2^16 b mantissas (the whole range, 2^46 pairs, takes about half a minute) and waits for them.
+ * Returns the mismatch count (0: the short quotient is the IEEE quotient for those b), or -1 if
+ * b_first < 0, b_count < 0, b_first + b_count > 2^23 or a HIP call failed. */
+int64_t klr_selftest_short_division(int32_t b_first, int32_t b_count);
+
 /* [host] ABI self-description for binding checks: writes up to n entries of
  * {sizeof(klr_fit_desc), sizeof(klr_fit_info), sizeof(klr_hw), sizeof(klr_program), ...}
  * and returns the number of entries available. */

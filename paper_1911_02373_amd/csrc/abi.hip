@@ -255,6 +255,10 @@ int64_t klr_selftest_divisor_list(const uint64_t* ds, int32_t n_ds) {
   return ds == nullptr || n_ds < 0 ? -1 : klr::selftest_divisor_list(ds, n_ds);
 }
 
+int64_t klr_selftest_short_division(int32_t b_first, int32_t b_count) {
+  return klr::selftest_short_division(b_first, b_count);
+}
+
 int32_t klr_abi_layout(int64_t* out, int32_t n) {
   const int64_t v[] = {
       (int64_t)sizeof(klr_fit_desc), (int64_t)sizeof(klr_fit_info), (int64_t)sizeof(klr_hw),

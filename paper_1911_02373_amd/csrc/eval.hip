@@ -652,6 +652,36 @@ fb_exact(const klr_program* __restrict__ progs, const float* __restrict__ coefs,
     sweep<KLR_GRID_2D>(slot0, rec0, queries, o, hw, P, qi, live);
 }
 
+// ---- self-test of the short quotient ---------------------------------------------------------
+// div_moderate against the correctly rounded division for every a mantissa in [1, 2) and the b
+// mantissas [b_first, b_first + nb); the first thread of each b also checks that the reciprocal
+// estimate of b 2^e is that of b times 2^-e, and that of -b 2^e its negation, for e in [-60, 60].
+constexpr int kSdA = 4096;                        // a mantissas per thread
+constexpr int kSdThreadsPerB = (1 << 23) / kSdA;  // 2048
+
+__global__ void __launch_bounds__(256) short_div_check(uint32_t b_first, uint32_t nb, unsigned long long* bad) {
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (uint64_t)nb * kSdThreadsPerB) return;
+  const uint32_t bm = b_first + (uint32_t)(g / kSdThreadsPerB);
+  const uint32_t a0 = (uint32_t)(g % kSdThreadsPerB) * kSdA;
+  const float b = __uint_as_float(0x3f800000u | bm);
+  uint32_t n = 0;
+  for (int i = 0; i < kSdA; ++i) {
+    const float a = __uint_as_float(0x3f800000u | (a0 + (uint32_t)i));
+    n += __float_as_uint(div_moderate(a, b)) != __float_as_uint(a / b) ? 1u : 0u;
+  }
+  if (g % kSdThreadsPerB == 0) {
+    const float r = __builtin_amdgcn_rcpf(b);
+    for (int e = -60; e <= 60; ++e) {
+      const float x = __builtin_ldexpf(b, e);
+      const uint32_t want = __float_as_uint(__builtin_ldexpf(r, -e));
+      n += __float_as_uint(__builtin_amdgcn_rcpf(x)) != want ? 1u : 0u;
+      n += __float_as_uint(__builtin_amdgcn_rcpf(-x)) != (want ^ 0x80000000u) ? 1u : 0u;
+    }
+  }
+  if (n) atomicAdd(bad, (unsigned long long)n);
+}
+
 }  // namespace
 
 size_t eval_workspace_bytes(int32_t n_progs, int32_t max_cfg) {
@@ -723,6 +753,26 @@ hipError_t launch_fallback(const EvalArgs& a, uint8_t* flags, float* best_cost, 
 }
 
 int eval_num_variants() { return kNumVariants; }
+
+int64_t selftest_short_division(int32_t b_first, int32_t b_count) {
+  if (b_first < 0 || b_count < 0 || (int64_t)b_first + b_count > (1 << 23)) return -1;
+  unsigned long long* d = nullptr;
+  if (hipMalloc(&d, sizeof *d) != hipSuccess) return -1;
+  bool ok = hipMemset(d, 0, sizeof *d) == hipSuccess;
+  // slices of 2^16 b mantissas (2^39 pairs, a fraction of a second each)
+  constexpr int32_t kSlice = 1 << 16;
+  for (int32_t b0 = b_first; ok && b0 < b_first + b_count; b0 += kSlice) {
+    const int32_t nb = b_first + b_count - b0 < kSlice ? b_first + b_count - b0 : kSlice;
+    const uint64_t threads = (uint64_t)nb * kSdThreadsPerB;
+    hipLaunchKernelGGL(short_div_check, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, nullptr,
+                       (uint32_t)b0, (uint32_t)nb, d);
+    ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  }
+  unsigned long long h = 0;
+  ok = ok && hipMemcpy(&h, d, sizeof h, hipMemcpyDeviceToHost) == hipSuccess;
+  const bool freed = hipFree(d) == hipSuccess;
+  return ok && freed ? (int64_t)h : -1;
+}
 
 int64_t selftest_divisor_list(const uint64_t* ds, int32_t n_ds) {
   // each listed divisor (up to 64 bits) against dividends at and around its multiples, small

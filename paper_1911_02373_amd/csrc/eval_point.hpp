@@ -83,13 +83,15 @@ __device__ __forceinline__ uint32_t udiv_magic(uint32_t n, uint32_t m, int32_t s
   return sh < 0 ? n : (__umulhi(n, m) >> sh);
 }
 
-// Quotient a / b by the steps of the correctly rounded FP32 division without its range
-// scaling and special-case fix-up: reciprocal estimate, one Newton step, then two corrections
-// of the quotient by its exact FMA remainder.  For finite a, b with |a| and |b| in
-// [2^-40, 2^40] the scaling steps of the full sequence leave both operands unchanged (the
-// exponents differ by less than 96, neither 1/b nor a/b is subnormal, a is far above the
-// subnormal range) and the fix-up returns the last correction unchanged, so the result is the
-// IEEE quotient bit for bit.
+// Quotient a / b for operands of moderate size: reciprocal estimate, one Newton step, then one
+// correction of the quotient by its exact FMA remainder (six instructions, against the eleven of
+// the correctly rounded FP32 division with its range scaling and special-case fix-up).  For
+// finite a, b with |a| and |b| in [2^-40, 2^40] the result is the IEEE quotient bit for bit:
+// klr_selftest_short_division compares the two over every pair of mantissas in [1, 2) and checks
+// that the reciprocal estimate scales exactly with b's exponent and sign.  In that range every
+// step's rounded result is a normal number or zero (a nonzero remainder is at least 2^-87 in
+// magnitude; the product inside an FMA is not rounded), so each step, and the correctly rounded
+// quotient, scale with the operands' exponents and signs.
 __device__ __forceinline__ float div_moderate(float a, float b) {
 #pragma clang fp contract(off)
   const float y0 = __builtin_amdgcn_rcpf(b);
@@ -97,9 +99,7 @@ __device__ __forceinline__ float div_moderate(float a, float b) {
   const float y1 = __builtin_fmaf(e0, y0, y0);
   const float q0 = a * y1;
   const float r0 = __builtin_fmaf(-b, q0, a);
-  const float q1 = __builtin_fmaf(r0, y1, q0);
-  const float r1 = __builtin_fmaf(-b, q1, a);
-  return __builtin_fmaf(r1, y1, q1);
+  return __builtin_fmaf(r0, y1, q0);
 }
 
 // Scaled query size per metric, x_j = N * 2^-s_j with s_j the scale exponent of metric j's fit.

@@ -97,6 +97,7 @@ hipError_t launch_eval(const EvalArgs& a);
 int eval_num_variants();
 int64_t selftest_divisors(uint32_t d_max);
 int64_t selftest_divisor_list(const uint64_t* ds, int32_t n_ds);
+int64_t selftest_short_division(int32_t b_first, int32_t b_count);
 
 // ---- fit ----------------------------------------------------------------------------------
 struct FitArgs {

@@ -37,13 +37,13 @@ EXPORTS = ("klr_create", "klr_destroy", "klr_last_error", "klr_fit_workspace", "
            "klr_eval_workspace", "klr_eval_argmin", "klr_abi_layout", "klr_profile_enable",
            "klr_profile_read", "klr_surrogate_param_bytes", "klr_surrogate_layout",
            "klr_surrogate_train_workspace", "klr_surrogate_train", "klr_surrogate_predict",
-           "klr_surrogate_step", "klr_surrogate_eval_workspace", "klr_surrogate_eval",
-           "klr_surrogate_init", "klr_set_option", "klr_capture_begin", "klr_capture_end",
-           "klr_graph_launch", "klr_graph_destroy", "klr_selftest_divisors",
-           "klr_selftest_divisor_list", "klr_eval_argmin_noalloc", "klr_service_workspace",
-           "klr_service_create", "klr_service_destroy", "klr_service_add_constraint", "klr_service_decide",
-           "klr_service_stats", "klr_service_set_history_limit", "klr_constraint_check",
-           "klr_collect_buffer", "klr_target_attributes", "klr_collect_times")
+           "klr_surrogate_step", "klr_surrogate_eval_workspace", "klr_surrogate_eval", "klr_surrogate_init",
+           "klr_set_option", "klr_capture_begin", "klr_capture_end", "klr_graph_launch", "klr_graph_destroy",
+           "klr_selftest_divisors", "klr_selftest_divisor_list", "klr_selftest_short_division",
+           "klr_eval_argmin_noalloc", "klr_service_workspace", "klr_service_create", "klr_service_destroy",
+           "klr_service_add_constraint", "klr_service_decide", "klr_service_stats",
+           "klr_service_set_history_limit", "klr_constraint_check", "klr_collect_buffer",
+           "klr_target_attributes", "klr_collect_times")
 TARGET_TRANSPOSE, TARGET_STENCIL = 0, 1
 OPT_FIT_PERSISTENT, OPT_EVAL_VARIANT, OPT_FIT_VARIANT, OPT_SURR_SHORTLIST = 0, 1, 2, 3
 K_COLLAPSE, K_EVAL, K_FIT_GRAM, K_FIT_SOLVE, K_MLP, K_SURR, K_FALLBACK = 0, 1, 2, 3, 4, 5, 6
@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.klr_selftest_divisors.restype = I64
     lib.klr_selftest_divisor_list.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     lib.klr_selftest_divisor_list.restype = I64
+    lib.klr_selftest_short_division.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.klr_selftest_short_division.restype = I64
     lib.klr_set_option.argtypes = [P, I32, I64]
     lib.klr_set_option.restype = I32
     lib.klr_surrogate_init.argtypes = [P, P, I32, P]

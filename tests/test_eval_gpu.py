@@ -139,6 +139,30 @@ def test_short_division_wide_exponents_bit_exact(klr):
         off += int(pb.n_cfg[p]) * int(pb.n_q[p])
 
 
+def test_short_quotient_is_ieee_sampled(klr):
+    """The short quotient (reciprocal, one Newton step, one remainder correction) equals the
+    correctly rounded FP32 division for every a mantissa against b mantissas at both ends of
+    [1, 2) and spread over it, and the reciprocal estimate scales exactly with b's exponent and
+    sign (the library's self-test kernel)."""
+    top = 1 << 23
+    slices = [(0, 1024), (top - 1024, 1024)] + [(k << 19, 128) for k in range(1, 16)]
+    for b0, nb in slices:
+        assert klr.lib.klr_selftest_short_division(b0, nb) == 0, (b0, nb)
+    assert klr.lib.klr_selftest_short_division(-1, 4) == -1
+    assert klr.lib.klr_selftest_short_division(top - 2, 4) == -1
+    assert klr.lib.klr_selftest_short_division(5, 0) == 0
+
+
+def test_short_quotient_is_ieee_exhaustive(klr):
+    """Every pair of mantissas (2^46 pairs, about half a minute): with the exponent and sign
+    scaling above this makes the short quotient the IEEE quotient for all operands in
+    [2^-40, 2^40], the range the collapse admits it for."""
+    step = 1 << 20
+    for b0 in range(0, 1 << 23, step):
+        assert klr.lib.klr_selftest_short_division(b0, step) == 0, b0
+        print(f"b mantissas [0, {b0 + step}) checked", flush=True)
+
+
 def test_mixed_uneven_programs_bit_exact(klr):
     """1-4 launch parameters, degree-3 metrics, 1-D and 2-D grids, uneven n_cfg and n_q,
     inadmissible configurations, tiny and huge N."""
