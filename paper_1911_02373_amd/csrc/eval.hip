@@ -437,21 +437,16 @@ __device__ __forceinline__ void sweep_cfgs(const klr_program& P, const float* __
   for (int c = 0; c < P.n_cfg; ++c) {
     const CfgRec r = rec0[c];
     const float* cf = slot0 + (int64_t)c * kSlotFloats;
-    if (KIND == KLR_COST_CYCLES && r.fast == 2) {     // wave-uniform
+    if (KIND == KLR_COST_CYCLES && r.fast >= 1) {     // wave-uniform
+      float cost[QPL];
+      if (r.fast == 2)
+        point_costs_short<QPL, GRID, DEG, 2>(N, xs, cf, r, hw, cost);
+      else
+        point_costs_short<QPL, GRID, DEG, 1>(N, xs, cf, r, hw, cost);
 #pragma unroll
       for (int u = 0; u < QPL; ++u) {
-        const float cost = point_cost<GRID, DEG, true, 2>(N[u], xs[u], cf, r, hw);
-        if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost;
-        if (cost < best[u]) { best[u] = cost; bi[u] = c; }
-      }
-      continue;
-    }
-    if (KIND == KLR_COST_CYCLES && r.fast == 1) {
-#pragma unroll
-      for (int u = 0; u < QPL; ++u) {
-        const float cost = point_cost<GRID, DEG, true, 1>(N[u], xs[u], cf, r, hw);
-        if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost;
-        if (cost < best[u]) { best[u] = cost; bi[u] = c; }
+        if (costs && live[u]) costs[(int64_t)c * P.n_q + qi[u]] = cost[u];
+        if (cost[u] < best[u]) { best[u] = cost[u]; bi[u] = c; }
       }
       continue;
     }

@@ -197,48 +197,16 @@ __device__ __forceinline__ bool point_admissible(int kind, int32_t N, const floa
   return ok & good5 & good6 & (resident_blocks(g5, good5, g6, good6, r, hw) >= 1.0f);
 }
 
-// Cost of one (query, configuration) point; +inf where inadmissible.  DEG: the program's highest
-// power of N~ (Horner from there; the normative sequence starts at power 3 with zero
-// coefficients above DEG, which gives bit-identical values because fma(0, x, a) = a exactly for
-// finite x and a != -0, and collapsed coefficients are sums that start from +0).
-// UNI: cf and r are the same in every lane (the coefficients then sit in scalar registers); a
-// per-lane configuration takes plain vector loads.  SHORT (the configuration record's `fast`):
-// 1 - every metric's numerator and denominator stay in [2^-40, 2^40] (denominators positive)
-// over the program's queries, so each metric quotient takes div_moderate (the same bits as the
-// IEEE division), every metric is defined and finite and nonzero, and the clamps reduce to
-// maxima; 2 - the four quotients of the cycle estimate take div_moderate as well.
-template <int GRID, int DEG = kNdeg, bool UNI = true, int SHORT = 0>
-__device__ __forceinline__ float point_cost(int32_t N, const float* xs, const float* __restrict__ cf,
-                                            const CfgRec& r, const Hw32& hw) {
+// The cycle estimate of one point from its metric values g (g[j] = p_j / q_j; good[j]: q > 0
+// and the value finite; ok: the point admissible so far), steps 2-6 of the normative sequence.
+// SHORT (the configuration record's `fast`): 1 - every metric is defined, finite and nonzero, so
+// the clamps reduce to maxima; 2 - besides, the four quotients of the cycle estimate have
+// operands in [2^-40, 2^40] and take div_moderate, so MWP's bounds are positive and finite and
+// its compare-select clamps equal the minimum and maximum.
+template <int GRID, int SHORT>
+__device__ __forceinline__ float cycle_cost(int32_t N, const float* g, const bool* good, bool ok, const CfgRec& r,
+                                            const Hw32& hw) {
 #pragma clang fp contract(off)
-  static_assert(DEG >= 1 && DEG <= kNdeg, "Horner degree");
-  bool ok = (r.ok != 0) & (N >= r.Lmax);
-  float g[KLR_N_METRICS];
-  bool good[KLR_N_METRICS];
-#pragma unroll
-  for (int j = 0; j < KLR_N_METRICS; ++j) {
-    const float* c = cf + j * 2 * (kNdeg + 1);     // c[2 d] numerator, c[2 d + 1] denominator
-    const float x = xs[j];
-    // First Horner step: both addends enter vector registers through one 64-bit move (the
-    // wave-uniform coefficients sit in scalar registers, and a VALU instruction reads at most
-    // one of them).
-    const float2 lo = UNI ? vgpr_pair(c + 2 * (DEG - 1)) : make_float2(c[2 * (DEG - 1)], c[2 * DEG - 1]);
-    float p = __builtin_fmaf(c[2 * DEG], x, lo.x);
-    float q = __builtin_fmaf(c[2 * DEG + 1], x, lo.y);
-#pragma unroll
-    for (int d = DEG - 2; d >= 0; --d) {
-      p = __builtin_fmaf(p, x, c[2 * d]);
-      q = __builtin_fmaf(q, x, c[2 * d + 1]);
-    }
-    if (SHORT) {
-      g[j] = div_moderate(p, q);
-      good[j] = true;
-    } else {
-      g[j] = p / q;
-      good[j] = (q > 0.0f) & (fabsf(g[j]) <= 3.402823466e38f);
-      ok = ok & good[j];
-    }
-  }
   // A metric failing the check is cleaned to +0 before its clamp; clean_max takes both steps.
   // The upper clamps of R (>= 1) and Z (>= -0) see no NaN, so fminf equals the compare-select.
   // (with SHORT every value is finite and nonzero, so the compare-select equals the maximum)
@@ -285,9 +253,9 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
   const float n2 = hw.bw * mem;
   const float d2 = Im * Bw;
   const float mwp_bw = SHORT == 2 ? div_moderate(n2, d2) : n2 / d2;
-  float mwp = sel_min(mwp_lat, mwp_bw);
-  mwp = sel_min(mwp, Nwf);
-  mwp = sel_max(mwp, 1.0f);
+  float mwp = SHORT == 2 ? fminf(mwp_lat, mwp_bw) : sel_min(mwp_lat, mwp_bw);
+  mwp = SHORT == 2 ? fminf(mwp, Nwf) : sel_min(mwp, Nwf);
+  mwp = SHORT == 2 ? fmaxf(mwp, 1.0f) : sel_max(mwp, 1.0f);
   const float tot = mem + comp;
   const bool cwp_full = tot >= Nwf * comp;
   const bool cwp_ge_mwp = tot >= mwp * comp;
@@ -313,6 +281,84 @@ __device__ __forceinline__ float point_cost(int32_t N, const float* xs, const fl
   const float cost = __builtin_fmaf(ex, repf, sy);                 // exec rep + sync
   ok = ok & (fabsf(cost) <= 3.402823466e38f);
   return ok ? cost : INFINITY;
+}
+
+// Cost of one (query, configuration) point; +inf where inadmissible.  DEG: the program's highest
+// power of N~ (Horner from there; the normative sequence starts at power 3 with zero
+// coefficients above DEG, which gives bit-identical values because fma(0, x, a) = a exactly for
+// finite x and a != -0, and collapsed coefficients are sums that start from +0).
+// UNI: cf and r are the same in every lane (the coefficients then sit in scalar registers); a
+// per-lane configuration takes plain vector loads.  SHORT (the configuration record's `fast`):
+// 1 - every metric's numerator and denominator stay in [2^-40, 2^40] (denominators positive)
+// over the program's queries, so each metric quotient takes div_moderate (the same bits as the
+// IEEE division), every metric is defined and finite and nonzero, and the clamps reduce to
+// maxima; 2 - the four quotients of the cycle estimate take div_moderate as well.
+template <int GRID, int DEG = kNdeg, bool UNI = true, int SHORT = 0>
+__device__ __forceinline__ float point_cost(int32_t N, const float* xs, const float* __restrict__ cf,
+                                            const CfgRec& r, const Hw32& hw) {
+#pragma clang fp contract(off)
+  static_assert(DEG >= 1 && DEG <= kNdeg, "Horner degree");
+  bool ok = (r.ok != 0) & (N >= r.Lmax);
+  float g[KLR_N_METRICS];
+  bool good[KLR_N_METRICS];
+#pragma unroll
+  for (int j = 0; j < KLR_N_METRICS; ++j) {
+    const float* c = cf + j * 2 * (kNdeg + 1);     // c[2 d] numerator, c[2 d + 1] denominator
+    const float x = xs[j];
+    // First Horner step: both addends enter vector registers through one 64-bit move (the
+    // wave-uniform coefficients sit in scalar registers, and a VALU instruction reads at most
+    // one of them).
+    const float2 lo = UNI ? vgpr_pair(c + 2 * (DEG - 1)) : make_float2(c[2 * (DEG - 1)], c[2 * DEG - 1]);
+    float p = __builtin_fmaf(c[2 * DEG], x, lo.x);
+    float q = __builtin_fmaf(c[2 * DEG + 1], x, lo.y);
+#pragma unroll
+    for (int d = DEG - 2; d >= 0; --d) {
+      p = __builtin_fmaf(p, x, c[2 * d]);
+      q = __builtin_fmaf(q, x, c[2 * d + 1]);
+    }
+    if (SHORT) {
+      g[j] = div_moderate(p, q);
+      good[j] = true;
+    } else {
+      g[j] = p / q;
+      good[j] = (q > 0.0f) & (fabsf(g[j]) <= 3.402823466e38f);
+      ok = ok & good[j];
+    }
+  }
+  return cycle_cost<GRID, SHORT>(N, g, good, ok, r, hw);
+}
+
+// Costs of QPL points (one configuration slot, wave-uniform, all of whose metric quotients take
+// the short form: SHORT = 1 or 2) by the same steps as point_cost: per metric the two
+// coefficients that enter vector registers do so once for all QPL queries.
+template <int QPL, int GRID, int DEG, int SHORT>
+__device__ __forceinline__ void point_costs_short(const int32_t* N, const float (*xs)[KLR_N_METRICS],
+                                                  const float* __restrict__ cf, const CfgRec& r, const Hw32& hw,
+                                                  float* cost) {
+#pragma clang fp contract(off)
+  static_assert(DEG >= 1 && DEG <= kNdeg && SHORT >= 1, "short metrics");
+  float g[QPL][KLR_N_METRICS];
+#pragma unroll
+  for (int j = 0; j < KLR_N_METRICS; ++j) {
+    const float* c = cf + j * 2 * (kNdeg + 1);
+    const float2 lo = vgpr_pair(c + 2 * (DEG - 1));
+#pragma unroll
+    for (int u = 0; u < QPL; ++u) {
+      const float x = xs[u][j];
+      float p = __builtin_fmaf(c[2 * DEG], x, lo.x);
+      float q = __builtin_fmaf(c[2 * DEG + 1], x, lo.y);
+#pragma unroll
+      for (int d = DEG - 2; d >= 0; --d) {
+        p = __builtin_fmaf(p, x, c[2 * d]);
+        q = __builtin_fmaf(q, x, c[2 * d + 1]);
+      }
+      g[u][j] = div_moderate(p, q);
+    }
+  }
+  const bool good[KLR_N_METRICS] = {true, true, true, true, true, true, true, true};
+#pragma unroll
+  for (int u = 0; u < QPL; ++u)
+    cost[u] = cycle_cost<GRID, SHORT>(N[u], g[u], good, (r.ok != 0) & (N[u] >= r.Lmax), r, hw);
 }
 
 // Cost of one point of a program whose one fitted function is the cost: p/q of metric 0 by the
