@@ -352,67 +352,112 @@ __device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uin
 }
 
 // Forward solve L u = in[perm[.]] by wave 0 (L in pivot order, see factor).  out is
-// pivot-indexed.
+// pivot-indexed.  A lane holds the right-hand side of rows lane and lane + 64.  Step k reads
+// b_k, forms u_k = b_k / L(k, k) (a product with the stored reciprocal) and subtracts
+// L(i, k) u_k from the rows i > k (the factor entry of rows i <= k is taken as zero, which
+// leaves them unchanged); row k keeps b_k, and every u_k is formed again at the end from the same
+// operands.  Rows past n hold values that are never read or stored.
 __device__ __forceinline__ void solve_fwd(const FitCtx& C, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
-  const int n = C.n;
-  const int b0r = rbase(lane), b1r = rbase(lane + 64);
+  const int n = __builtin_amdgcn_readfirstlane(C.n);
+  const int r1 = lane + 64;
+  const int b0r = rbase(lane < n ? lane : 0), b1r = rbase(r1 < n ? r1 : 0);
   double b0 = lane < n ? in[C.perm[lane]] : 0.0;
-  double b1 = lane + 64 < n ? in[C.perm[lane + 64]] : 0.0;
-  // steps in groups of 4: the factor entries of a group are loaded before its dependent chain
-  for (int k0 = 0; k0 < n; k0 += 4) {
+  double b1 = r1 < n ? in[C.perm[r1]] : 0.0;
+  const int n0 = n < 64 ? n : 64;
+  // steps 0 .. 63 update both rows of a lane; the factor entries of a group of four steps are
+  // loaded before its dependent chain
+  for (int k0 = 0; k0 < n0; k0 += 4) {
     double rp[4], s0[4], s1[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u < n0 ? k0 + u : n0 - 1;
+      rp[u] = C.piv[k];
+      s0[u] = lane > k ? C.S[b0r + k] : 0.0;
+      s1[u] = C.S[b1r + k];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
       const int k = k0 + u;
-      rp[u] = k < n ? C.piv[k] : 0.0;
-      s0[u] = (k < n && lane > k && lane < n) ? C.S[b0r + k] : 0.0;
-      s1[u] = (k < n && lane + 64 > k && lane + 64 < n) ? C.S[b1r + k] : 0.0;
+      if (k < n0) {
+        const double uk = readlane_d(b0, k) * rp[u];
+        b0 -= s0[u] * uk;
+        b1 -= s1[u] * uk;
+      }
+    }
+  }
+  // steps 64 .. n - 1: the first row of every lane is final
+  for (int k0 = 64; k0 < n; k0 += 4) {
+    double rp[4], s1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u < n ? k0 + u : n - 1;
+      rp[u] = C.piv[k];
+      s1[u] = r1 > k ? C.S[b1r + k] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = k0 + u;
       if (k < n) {
-        const double uk = readlane_d(k < 64 ? b0 : b1, k & 63) * rp[u];
-        if (lane == (k & 63)) { if (k < 64) b0 = uk; else b1 = uk; }
-        if (lane > k && lane < n) b0 -= s0[u] * uk;
-        if (lane + 64 > k && lane + 64 < n) b1 -= s1[u] * uk;
+        const double uk = readlane_d(b1, k - 64) * rp[u];
+        b1 -= s1[u] * uk;
       }
     }
   }
-  if (lane < n) out[lane] = b0;
-  if (lane + 64 < n) out[lane + 64] = b1;
+  if (lane < n) out[lane] = b0 * C.piv[lane];
+  if (r1 < n) out[r1] = b1 * C.piv[r1];
 }
 
-// Backward solve L^T v = in (pivot-indexed) by wave 0; out[perm[i]] = v_i.
+// Backward solve L^T v = in (pivot-indexed) by wave 0; out[perm[i]] = v_i.  Step k (from n - 1
+// down) forms v_k = b_k / L(k, k) and subtracts L(k, i) v_k from the rows i < k; as in the
+// forward solve, row k keeps b_k and the v_k are formed again at the end.
 __device__ __forceinline__ void solve_bwd(const FitCtx& C, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
-  const int n = C.n;
+  const int n = __builtin_amdgcn_readfirstlane(C.n);
+  const int r1 = lane + 64;
   double b0 = lane < n ? in[lane] : 0.0;
-  double b1 = lane + 64 < n ? in[lane + 64] : 0.0;
-  for (int k0 = n - 1; k0 >= 0; k0 -= 4) {
+  double b1 = r1 < n ? in[r1] : 0.0;
+  // steps n - 1 .. 64: every first row lies below k; second rows below k only
+  for (int k0 = n - 1; k0 >= 64; k0 -= 4) {
     double rp[4], s0[4], s1[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
+      const int k = k0 - u >= 64 ? k0 - u : 64;
+      const int rk = rbase(k);
+      rp[u] = C.piv[k];
+      s0[u] = C.S[rk + lane];
+      s1[u] = r1 < k ? C.S[rk + r1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
       const int k = k0 - u;
-      const int bk_row = k >= 0 ? rbase(k) : 0;
-      rp[u] = k >= 0 ? C.piv[k] : 0.0;
-      s0[u] = (k >= 0 && lane < k) ? C.S[bk_row + lane] : 0.0;
-      s1[u] = (k >= 0 && lane + 64 < k) ? C.S[bk_row + lane + 64] : 0.0;
+      if (k >= 64) {
+        const double vk = readlane_d(b1, k - 64) * rp[u];
+        b0 -= s0[u] * vk;
+        b1 -= s1[u] * vk;
+      }
+    }
+  }
+  // steps min(n, 64) - 1 .. 0: only first rows lie below k
+  for (int k0 = (n < 64 ? n : 64) - 1; k0 >= 0; k0 -= 4) {
+    double rp[4], s0[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 - u >= 0 ? k0 - u : 0;
+      rp[u] = C.piv[k];
+      s0[u] = lane < k ? C.S[rbase(k) + lane] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = k0 - u;
       if (k >= 0) {
-        const double vk = readlane_d(k < 64 ? b0 : b1, k & 63) * rp[u];
-        if (lane == (k & 63)) { if (k < 64) b0 = vk; else b1 = vk; }
-        if (lane < k) b0 -= s0[u] * vk;
-        if (lane + 64 < k) b1 -= s1[u] * vk;
+        const double vk = readlane_d(b0, k) * rp[u];
+        b0 -= s0[u] * vk;
       }
     }
   }
-  if (lane < n) out[C.perm[lane]] = b0;
-  if (lane + 64 < n) out[C.perm[lane + 64]] = b1;
+  if (lane < n) out[C.perm[lane]] = b0 * C.piv[lane];
+  if (r1 < n) out[C.perm[r1]] = b1 * C.piv[r1];
 }
 
 // sum_j x_j y_j over n entries, by wave 0 (valid in wave 0).

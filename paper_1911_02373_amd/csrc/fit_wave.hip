@@ -278,55 +278,61 @@ __device__ int factor_wave(WaveLds& L, int n, double unit) {
   return __popcll(full);
 }
 
-// L u = in[perm] (out pivot-indexed).
+// L u = in[perm] (out pivot-indexed).  Step k reads b_k, forms u_k = b_k / L(k, k) (a product
+// with the stored reciprocal) and subtracts L(i, k) u_k from the rows i > k (the factor entry of
+// rows i <= k is taken as zero, which leaves them unchanged); row k keeps b_k, and every u_k is
+// formed again at the end from the same operands.  Lanes past n hold values never stored.
 __device__ void fwd_wave(const WaveLds& L, int n, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
-  const int myb = rbase(lane);
+  n = __builtin_amdgcn_readfirstlane(n);
+  const int myb = rbase(lane < n ? lane : 0);
   double b = lane < n ? in[L.perm[lane]] : 0.0;
   // steps in groups of 4: the factor entries of a group are loaded before its dependent chain
   for (int k0 = 0; k0 < n; k0 += 4) {
     double rp[4], sv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int k = k0 + u;
-      rp[u] = k < n ? L.rd[k] : 0.0;
-      sv[u] = (k < n && lane > k && lane < n) ? L.S[myb + k] : 0.0;
+      const int k = k0 + u < n ? k0 + u : n - 1;
+      rp[u] = L.rd[k];
+      sv[u] = lane > k ? L.S[myb + k] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = k0 + u;
       if (k < n) {
         const double uk = readlane_d(b, k) * rp[u];
-        if (lane == k) b = uk;
-        if (lane > k && lane < n) b -= sv[u] * uk;
+        b -= sv[u] * uk;
       }
     }
   }
-  if (lane < n) out[lane] = b;
+  if (lane < n) out[lane] = b * L.rd[lane];
   wave_sync();
 }
+// L^T v = in (pivot-indexed); out[perm[i]] = v_i.  Step k (from n - 1 down) forms v_k = b_k /
+// L(k, k) and subtracts L(k, i) v_k from the rows i < k; row k keeps b_k and the v_k are formed
+// again at the end.
 __device__ void bwd_wave(const WaveLds& L, int n, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
+  n = __builtin_amdgcn_readfirstlane(n);
   double b = lane < n ? in[lane] : 0.0;
   for (int k0 = n - 1; k0 >= 0; k0 -= 4) {
     double rp[4], sv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int k = k0 - u;
-      rp[u] = k >= 0 ? L.rd[k] : 0.0;
-      sv[u] = (k >= 0 && lane < k) ? L.S[rbase(k) + lane] : 0.0;
+      const int k = k0 - u >= 0 ? k0 - u : 0;
+      rp[u] = L.rd[k];
+      sv[u] = lane < k ? L.S[rbase(k) + lane] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = k0 - u;
       if (k >= 0) {
         const double vk = readlane_d(b, k) * rp[u];
-        if (lane == k) b = vk;
-        if (lane < k) b -= sv[u] * vk;
+        b -= sv[u] * vk;
       }
     }
   }
-  if (lane < n) out[L.perm[lane]] = b;
+  if (lane < n) out[L.perm[lane]] = b * L.rd[lane];
   wave_sync();
 }
 
