@@ -67,6 +67,13 @@ def test_invariant_divisor_products_exact(lib):
     assert lib.klr_selftest_divisor_list(zero.ctypes.data, 1) == 1
 
 
+def test_short_division_selftest_rejects_bad_ranges_on_host(lib):
+    """The GPU self-test of the short quotient checks its b-mantissa range before any HIP call."""
+    assert lib.klr_selftest_short_division(-1, 4) == -1
+    assert lib.klr_selftest_short_division(0, -1) == -1
+    assert lib.klr_selftest_short_division((1 << 23) - 2, 4) == -1
+
+
 def test_program_samples_bookkeeping():
     """The (program, configuration, query) training samples of uneven two-launch-parameter
     programs, against a brute-force listing of the same points (host tensors)."""
