@@ -187,7 +187,8 @@ __global__ void __launch_bounds__(kRangeBlock) query_range_kernel(EvalArgs a) {
   const klr_program P = a.progs[p];
   int32_t lo = 0x7fffffff, hi = (int32_t)0x80000000;
   if (program_desc_ok(P, a))
-    for (int i = threadIdx.x; i < P.n_q; i += kRangeBlock) {
+#pragma unroll 8
+    for (int i = threadIdx.x; i < P.n_q; i += kRangeBlock) {     // eight loads in flight
       const int32_t N = a.queries[P.q0 + i];
       lo = N < lo ? N : lo;
       hi = N > hi ? N : hi;
