@@ -1326,8 +1326,14 @@ template <int NM, int PREC>
 __device__ __forceinline__ void fit_persistent_body(const FitArgs& a, Plan* pl, const int32_t* order, int cls,
                                                     double* smem, int* next) {
   const int total = pl->totals[cls], base = pl->base[cls];
+  if (total == 0) return;              // an empty class: no queue traffic at all
   for (;;) {
-    if (threadIdx.x == 0) *next = atomicAdd(&pl->queue[cls], 1);
+    // the counter only grows: once a plain read shows the queue exhausted, no atomic is needed
+    // (every workgroup of an exhausted class would otherwise meet at one address)
+    if (threadIdx.x == 0) {
+      const int seen = __hip_atomic_load(&pl->queue[cls], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      *next = seen >= total ? seen : atomicAdd(&pl->queue[cls], 1);
+    }
     __syncthreads();
     const int i = *next;
     __syncthreads();
