@@ -463,11 +463,12 @@ __device__ __forceinline__ void sweep_cfgs(const klr_program& P, const float* __
 }
 
 // QPL queries per lane, BLOCK lanes per workgroup: each lane carries QPL independent
-// (query, running minimum) chains through the same configuration loop.  The two-query shapes
-// are held to 80 VGPRs, six waves per SIMD (85 unconstrained, five waves): the sweep is bound by
-// instruction issue, and the extra wave hides more of its dependent latencies.
+// (query, running minimum) chains through the same configuration loop.  The sweep is bound by
+// instruction issue, and an extra wave per SIMD hides more of its dependent latencies: the
+// two-query shapes are held to 80 VGPRs (six waves; 85 unconstrained, five), the four-query
+// shape to 128 (four waves; 135 unconstrained, three).
 template <int QPL, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(QPL == 2 ? 6 : 1)))
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(QPL == 2 ? 6 : (QPL == 4 ? 4 : 1))))
 eval_kernel(const klr_program* __restrict__ progs, const float* __restrict__ coefs,
             const CfgRec* __restrict__ recs, const int32_t* __restrict__ queries,
             int32_t* __restrict__ argmin, float* __restrict__ best_cost,
