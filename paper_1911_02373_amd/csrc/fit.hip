@@ -352,10 +352,10 @@ __device__ __forceinline__ bool gram_pass(const FitArgs& a, const FitCtx& C, uin
 }
 
 // Forward solve L u = in[perm[.]] by wave 0 (L in pivot order, see factor).  out is
-// pivot-indexed.  A lane holds the right-hand side of rows lane and lane + 64.  Step k reads
-// b_k, forms u_k = b_k / L(k, k) (a product with the stored reciprocal) and subtracts
-// L(i, k) u_k from the rows i > k (the factor entry of rows i <= k is taken as zero, which
-// leaves them unchanged); row k keeps b_k, and every u_k is formed again at the end from the same
+// pivot-indexed.  A lane holds the right-hand side of rows lane and lane + 64.  Step k reads b_k,
+// forms u_k = b_k / L(k, k) (a product with the stored reciprocal) and subtracts L(i, k) u_k from
+// the rows i > k (the factor entry of rows i <= k is taken as zero, which leaves them unchanged
+// while u_k is finite); row k keeps b_k, and every u_k is formed again at the end from the same
 // operands.  Rows past n hold values that are never read or stored.
 __device__ __forceinline__ void solve_fwd(const FitCtx& C, const double* in, double* out) {
   const int lane = threadIdx.x & 63;

@@ -280,8 +280,9 @@ __device__ int factor_wave(WaveLds& L, int n, double unit) {
 
 // L u = in[perm] (out pivot-indexed).  Step k reads b_k, forms u_k = b_k / L(k, k) (a product
 // with the stored reciprocal) and subtracts L(i, k) u_k from the rows i > k (the factor entry of
-// rows i <= k is taken as zero, which leaves them unchanged); row k keeps b_k, and every u_k is
-// formed again at the end from the same operands.  Lanes past n hold values never stored.
+// rows i <= k is taken as zero, which leaves them unchanged while u_k is finite); row k keeps
+// b_k, and every u_k is formed again at the end from the same operands.  Lanes past n hold values
+// never stored.
 __device__ void fwd_wave(const WaveLds& L, int n, const double* in, double* out) {
   const int lane = threadIdx.x & 63;
   n = __builtin_amdgcn_readfirstlane(n);
